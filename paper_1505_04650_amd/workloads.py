@@ -1,0 +1,139 @@
+"""Seeded synthetic inputs shared by the oracle-side tests and the GPU side.
+
+This module holds no arithmetic of the method itself: it only draws the
+matrices that both sides receive (the data A, the Gaussian test matrices
+Omega, the initial factors), from NumPy's PCG64 with fixed seeds.  It
+imports nothing but NumPy, so the oracle tests can use it without touching
+the HIP library.
+
+Recipes (the paper's synthetic NMF experiment, Section 5.1 and its figure
+caption, with the dense density delta = 1):
+  * NMF data:   A = W H + N, W ~ U[0,1)^{m x r}, H ~ U[0,1)^{r x n},
+                N = |sigma Z|, Z standard normal (sigma is a standard
+                deviation; the absolute value keeps A >= 0).
+  * Separable:  A = W [I_r  H'] P + noise Z, W ~ U[0,1)^{m x r}, the columns
+                of H' are Dirichlet(1) draws scaled by s_j ~ U(0, 1], P a
+                seeded column permutation; the planted (extreme) columns are
+                where the identity columns land after P.
+  * Test matrices Omega: iid N(0, 1) (Section 2).
+  * Initial factors: c * U[0,1) with c = sqrt(4 mean(A) / r), so that
+    E[U V] = mean(A).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = ["Workload", "WORKLOADS", "nmf_matrix", "separable_matrix", "gaussian",
+           "init_factors", "make_inputs"]
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def nmf_matrix(m: int, n: int, r: int, sigma: float, seed: int, dtype=np.float64) -> np.ndarray:
+    """A = W H + |sigma Z| with W, H uniform on [0, 1).  Built in float64 and
+    rounded once to ``dtype``."""
+    g = _rng(seed)
+    W = g.random((m, r))
+    H = g.random((r, n))
+    A = W @ H
+    if sigma:
+        # draw the noise in row blocks to bound peak memory
+        for i0 in range(0, m, 8192):
+            blk = A[i0:i0 + 8192]
+            blk += np.abs(sigma * g.standard_normal(blk.shape))
+    return A.astype(dtype, copy=False)
+
+
+def separable_matrix(m: int, n: int, r: int, noise: float, seed: int, dtype=np.float64):
+    """Near-separable A = W [I_r H'] P + noise * Z.  Returns (A, planted) with
+    ``planted`` the sorted 0-based column indices of the identity columns."""
+    g = _rng(seed)
+    W = g.random((m, r))
+    Hp = g.dirichlet(np.ones(r), size=n - r).T          # r x (n - r), columns on the simplex
+    s = 1.0 - g.random(n - r)                            # U(0, 1]
+    Hp *= s[None, :]
+    Hfull = np.concatenate([np.eye(r), Hp], axis=1)      # r x n
+    perm = g.permutation(n)                              # column j of A is column perm[j] of W Hfull
+    A = (W @ Hfull)[:, perm]
+    if noise:
+        for i0 in range(0, m, 4096):
+            blk = A[i0:i0 + 4096]
+            blk += noise * g.standard_normal(blk.shape)
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    planted = np.sort(inv[:r])
+    return A.astype(dtype, copy=False), planted
+
+
+def gaussian(rows: int, cols: int, seed: int) -> np.ndarray:
+    """iid N(0, 1) test matrix (Section 2), float64."""
+    return _rng(seed).standard_normal((rows, cols))
+
+
+def init_factors(mean_a: float, m: int, n: int, r: int, seed: int):
+    """U1 (m x r), V1 (r x n) = c U[0,1) with c = sqrt(4 mean(A) / r)."""
+    g = _rng(seed)
+    c = math.sqrt(4.0 * float(mean_a) / r)
+    return c * g.random((m, r)), c * g.random((r, n))
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    index: int            # seed base: data 100*index, Omega 100*index+1, init 100*index+2
+    m: int
+    n: int
+    r: int
+    k: int
+    q: int
+    iters: int
+    dtype: str            # storage / pass precision of A on the GPU
+    sigma: float = 0.0    # |N(0, sigma)| additive noise for NMF data
+    separable: bool = False
+    sep_noise: float = 0.0
+    extra: dict = field(default_factory=dict)
+
+
+# Workload table.  The first entry is small enough for the oracle to run in
+# about a second; the others are the full-size cases.
+WORKLOADS = {
+    "plain_fp64_1000x500": Workload("plain_fp64_1000x500", 1, 1000, 500, 10, 20, 4, 100, "f64", sigma=0.01),
+    "nmf_fp32_20000x5000": Workload("nmf_fp32_20000x5000", 2, 20000, 5000, 50, 60, 4, 200, "f32", sigma=0.05),
+    "separable_fp32_10000x100000": Workload("separable_fp32_10000x100000", 3, 10000, 100000, 20, 30, 2, 0,
+                                            "f32", separable=True, sep_noise=1e-3),
+    "precision_100000x20000": Workload("precision_100000x20000", 4, 100000, 20000, 100, 120, 4, 0, "f32",
+                                       sigma=0.05),
+}
+
+
+def make_inputs(w: Workload, *, m=None, n=None, storage=None, two_sided=True, want_init=True):
+    """Draw every input of a workload (optionally at a reduced size).
+
+    Returns a dict with float64 arrays: A (rounded to the storage precision
+    and cast back, so both sides see the same values), Omega_L (n x k),
+    Omega_R (m x k), U1, V1, and for separable data the planted indices.
+    """
+    m = w.m if m is None else m
+    n = w.n if n is None else n
+    storage = storage or ("f64" if w.dtype == "f64" else "f32")
+    sdt = np.float64 if storage == "f64" else np.float32
+    out = {}
+    if w.separable:
+        A, planted = separable_matrix(m, n, w.r, w.sep_noise, 100 * w.index, dtype=sdt)
+        out["planted"] = planted
+    else:
+        A = nmf_matrix(m, n, w.r, w.sigma, 100 * w.index, dtype=sdt)
+    out["A"] = A
+    g = _rng(100 * w.index + 1)
+    out["Omega_L"] = g.standard_normal((n, w.k))
+    if two_sided:
+        out["Omega_R"] = g.standard_normal((m, w.k))
+    if want_init:
+        mean_a = float(np.mean(A, dtype=np.float64))
+        out["U1"], out["V1"] = init_factors(mean_a, m, n, w.r, 100 * w.index + 2)
+    return out
