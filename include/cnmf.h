@@ -1,0 +1,211 @@
+/*
+ * cnmf.h -- C ABI of the MI355X (gfx950) compressed-NMF library.
+ *
+ * Method: Tepper & Sapiro, "Compressed Nonnegative Matrix Factorization is
+ * Fast and Accurate" (arXiv:1505.04650).
+ *   - Structured random compression (Section 2, Alg. 1): a Gaussian range
+ *     finder orth((A A^T)^q A Omega), computed as re-orthonormalised
+ *     subspace iteration, orthonormalised by CholeskyQR2 in FP64.
+ *   - Two-sided compression and the small sketches (Section 3): L (m x k),
+ *     R (k x n), B = L^T A (k x n), At = L^T A R^T (k x k), Ac = A R^T (m x k).
+ *   - Compressed NMF: ADMM (Appendix B, Alg. 3) and alternating
+ *     multiplicative updates (Section 3, Alg. 2 with the semi-NMF rule of
+ *     Ding et al. 2010, Eq. 8); the same solvers with L = I, R = I are the
+ *     uncompressed comparators.
+ *   - Compressed separable NMF (Section 4, Alg. SNMF): SPA column
+ *     selection on B = Q^T A.
+ *
+ * Conventions shared by every entry point
+ *   - Every matrix is ROW-MAJOR with an explicit leading dimension (in
+ *     elements).  Pointers named *_dev are DEVICE pointers (memory the
+ *     caller allocated on the handle's device); all others are host.
+ *   - The caller owns A and every output buffer; the library never frees or
+ *     writes caller memory other than the declared outputs.  A is read-only.
+ *   - Work is enqueued on the HIP stream given to cnmf_create.  Calls do not
+ *     synchronise the stream; outputs (including device scalars) are valid
+ *     once that stream has completed the call's work.
+ *   - Errors: invalid shapes / parameters return CNMF_EINVAL before anything
+ *     is enqueued, with outputs untouched.  A HIP launch or allocation error
+ *     returns CNMF_EDEVICE / CNMF_ENOMEM.  cnmf_last_error gives a message
+ *     for the last failing call on a handle.  A handle is not thread safe.
+ *   - Random numbers: the Gaussian test matrices are INPUTS (omega_*), so
+ *     results are a pure function of (A, Omega, initial factors, params).
+ */
+#ifndef CNMF_H_
+#define CNMF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CNMF_OK = 0,
+  CNMF_EINVAL = -1,      /* invalid argument (detected before any launch)     */
+  CNMF_ENOMEM = -2,      /* device workspace could not be allocated           */
+  CNMF_EDEVICE = -3,     /* HIP runtime / launch error                        */
+  CNMF_EBREAKDOWN = -4,  /* orthonormalisation failed (Gram not positive def.) */
+  CNMF_ENOTSUP = -5,     /* valid but unsupported size / precision combination */
+  CNMF_EBUSY = -6
+} cnmf_status;
+
+typedef enum {
+  CNMF_F64 = 0,
+  CNMF_F32 = 1,
+  CNMF_BF16 = 2,
+  CNMF_FP8_E4M3 = 3
+} cnmf_dtype;
+
+enum { CNMF_LEFT = 1, CNMF_RIGHT = 2, CNMF_BOTH = 3 };
+
+enum {
+  CNMF_ADMM = 0,       /* compressed ADMM, Appendix B Alg. 3                    */
+  CNMF_MU = 1,         /* compressed alternating MU, Section 3 Alg. 2           */
+  CNMF_ADMM_FULL = 2,  /* Alg. 3 with L = I_m, R = I_n (uncompressed ADMM)      */
+  CNMF_MU_FULL = 3     /* Alg. 2 with L = I_m, R = I_n (uncompressed MU)        */
+};
+
+typedef struct cnmf_handle cnmf_handle;
+
+/* Create a handle bound to HIP device `device` and the HIP stream
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  `workspace_limit`
+ * caps the device workspace the handle may allocate (0 = no cap).  The
+ * workspace is allocated lazily on the first call that needs it, grown as
+ * needed, and freed by cnmf_destroy. */
+cnmf_status cnmf_create(int device, void* hip_stream, size_t workspace_limit, cnmf_handle** out);
+cnmf_status cnmf_destroy(cnmf_handle* h);
+/* Message for the last failing call on `h` (never NULL; "" if none).
+ * With h == NULL: the message of the last failing call without a handle. */
+const char* cnmf_last_error(const cnmf_handle* h);
+const char* cnmf_status_string(cnmf_status s);
+/* Library version string, e.g. "cnmf-mi355x 0.1". */
+const char* cnmf_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Input matrix A (Section 1, problem (nmf)): m x n, row-major, lda >= n.
+ * dtype CNMF_F64 or CNMF_F32.  Device pointer.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const void* data_dev;
+  cnmf_dtype dtype;
+  int64_t m, n, lda;
+} cnmf_input;
+
+/* Sketch parameters (Alg. 1 inputs: target rank r, oversampling r_ov with
+ * k = r + r_ov, exponent w = q).  Valid: 1 <= r < k <= min(m, n), k <= 128,
+ * q >= 0.  `sides` selects L (CNMF_LEFT), R (CNMF_RIGHT) or both.
+ * pass_dtype: precision of the GEMM operands of the range-finder passes:
+ *   CNMF_F64 (needs F64 input: everything in FP64), CNMF_F32, CNMF_BF16 or
+ *   CNMF_FP8_E4M3 (FP32 input; A is converted once into a workspace copy;
+ *   accumulation is FP32).
+ * final_dtype: precision of the last range pass and of the B / Ac pass
+ *   (CNMF_F64 with F64 input; CNMF_F32 or CNMF_BF16 otherwise).
+ * Orthonormalisation (CholeskyQR2) always runs in FP64.
+ * omega_left_dev:  n x k FP64, row-major (ld = k): test matrix for A.
+ * omega_right_dev: m x k FP64, row-major (ld = k): test matrix for A^T
+ *   (required when CNMF_RIGHT is set). */
+typedef struct {
+  int32_t r, k, q, sides;
+  cnmf_dtype pass_dtype;
+  cnmf_dtype final_dtype;
+  const double* omega_left_dev;
+  const double* omega_right_dev;
+} cnmf_sketch_desc;
+
+/* Sketch outputs.  Every pointer may be NULL (= not wanted).  Element type
+ * is FP64 when pass_dtype is CNMF_F64, FP32 otherwise; all row-major with
+ * tight leading dimensions:
+ *   L_dev  m x k   (orthonormal columns)     -- needs CNMF_LEFT
+ *   R_dev  k x n   (orthonormal rows)        -- needs CNMF_RIGHT
+ *   B_dev  k x n   B = L^T A                 -- needs CNMF_LEFT
+ *   At_dev k x k   At = L^T A R^T            -- needs both sides
+ *   Ac_dev m x k   Ac = A R^T                -- needs CNMF_RIGHT (one extra pass)
+ *   stats_dev FP64[4]: max|L^T L - I|, max|R R^T - I|, number of Cholesky
+ *     breakdowns repaired, 0. */
+typedef struct {
+  void* L_dev;
+  void* R_dev;
+  void* B_dev;
+  void* At_dev;
+  void* Ac_dev;
+  double* stats_dev;
+} cnmf_sketch_out;
+
+cnmf_status cnmf_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d,
+                        cnmf_sketch_out* out);
+
+/* Factorisation parameters.  method: CNMF_ADMM / CNMF_MU use the two-sided
+ * sketch `sk` (sides must be CNMF_BOTH); the *_FULL methods ignore `sk`
+ * except for sk.r and run on A itself.  iters: fixed number of iterations
+ * (no early stop).  lambda, phi > 0: ADMM penalties; xi > 0: ADMM step
+ * (1 in the paper).  mu_eps >= 0: added to every MU denominator.
+ * U0_dev (m x r) and V0_dev (r x n): FP64 initial factors (Alg. 2 / Alg. 3
+ * "Initialize"), row-major, required. */
+typedef struct {
+  cnmf_sketch_desc sk;
+  int32_t method;
+  int32_t iters;
+  double lambda, phi, xi;
+  double mu_eps;
+  const double* U0_dev;
+  const double* V0_dev;
+} cnmf_factorize_desc;
+
+/* Outputs (NULL = not wanted): U_dev m x r, V_dev r x n in the handle's
+ * accumulation precision (FP64 for F64 passes, FP32 otherwise);
+ * rel_residual_dev: FP64 scalar ||A - U V||_F / ||A||_F (one more pass over
+ * A, accumulated in FP64).  `sk_out` optionally receives the sketches. */
+typedef struct {
+  void* U_dev;
+  void* V_dev;
+  double* rel_residual_dev;
+  cnmf_sketch_out sk_out;
+} cnmf_factorize_out;
+
+cnmf_status cnmf_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
+                           cnmf_factorize_out* out);
+
+/* Separable NMF column selection (Section 4, Alg. SNMF, steps 1-2): left
+ * sketch Q of A (or both sides when d->sides == CNMF_BOTH), B = Q^T A, then
+ * SPA on the columns of B in FP64: r times pick the column of largest
+ * squared norm (lowest index on ties) and project it out.
+ * K_dev: int64[r] device, 0-based column indices in selection order.
+ * score_dev: optional FP64[r] device, the selected squared norms.
+ * B_dev: optional k x n output of B (FP32, or FP64 for F64 passes). */
+cnmf_status snmf_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d,
+                        int64_t* K_dev, double* score_dev, void* B_dev);
+
+/* SPA alone on a given B (k x n, row-major, ld >= n, FP64 or FP32 device
+ * matrix), writing r indices to K_dev (int64) and optionally the scores. */
+cnmf_status cnmf_spa(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n,
+                     int64_t ldb, int32_t r, int64_t* K_dev, double* score_dev);
+
+/* One streaming pass of the range finder (Alg. 1, the product step):
+ *   trans == 0: Y = A X    X is n x kx, Y is m x kx
+ *   trans == 1: Y = A^T X  X is m x kx, Y is n x kx
+ * X and Y are device matrices of A's dtype, row-major with ld = kx;
+ * 1 <= kx <= 128.  The product reads A once; it is the kernel every pass of
+ * cnmf_sketch runs. */
+cnmf_status cnmf_range_product(cnmf_handle* h, const cnmf_input* A, int trans, const void* X_dev, int32_t kx,
+                               void* Y_dev);
+
+/* Device workspace (bytes) that cnmf_factorize (or, with iters = 0 and
+ * method CNMF_ADMM, cnmf_sketch) needs for an m x n input.  Host only; no
+ * handle or GPU required. */
+cnmf_status cnmf_workspace_bytes(int64_t m, int64_t n, const cnmf_factorize_desc* d, size_t* bytes);
+
+/* Per-stage device time of the last call on `h`, in milliseconds, measured
+ * with HIP events when timing is enabled (cnmf_set_timing).  stage:
+ *   0 convert, 1 range passes, 2 orthonormalisation, 3 small sketches,
+ *   4 iterations, 5 residual, 6 SPA.  Returns NaN when not measured.
+ * Reading it synchronises the handle's stream. */
+cnmf_status cnmf_set_timing(cnmf_handle* h, int enable);
+double cnmf_stage_ms(cnmf_handle* h, int stage);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CNMF_H_ */

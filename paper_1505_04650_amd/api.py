@@ -1,0 +1,222 @@
+"""Python binding of the HIP compressed-NMF library.
+
+Thin marshalling over the C ABI (include/cnmf.h): PyTorch provides device
+memory and the stream; every step of the method runs in the library's HIP
+kernels.  Functions allocate their outputs with torch on A's device and
+enqueue on the current torch stream without synchronising.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float64: L.CNMF_F64, torch.float32: L.CNMF_F32}
+_PREC = {"f64": L.CNMF_F64, "f32": L.CNMF_F32, "bf16": L.CNMF_BF16, "fp8": L.CNMF_FP8_E4M3}
+_SIDES = {"left": L.CNMF_LEFT, "right": L.CNMF_RIGHT, "both": L.CNMF_BOTH}
+_METHODS = {"admm": L.CNMF_ADMM, "mu": L.CNMF_MU, "admm_full": L.CNMF_ADMM_FULL, "mu_full": L.CNMF_MU_FULL}
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+class Handle:
+    """A library handle bound to one device and one HIP stream."""
+
+    def __init__(self, device=None, stream=None, workspace_limit: int = 0):
+        lib = L.load()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.device = dev
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.stream = st
+        h = C.c_void_p()
+        L.check(lib.cnmf_create(dev.index, C.c_void_p(st.cuda_stream), workspace_limit, C.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    @property
+    def raw(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            self._lib.cnmf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, enable: bool):
+        L.check(self._lib.cnmf_set_timing(self._h, int(enable)), self._h)
+
+
+_handles: dict = {}
+
+
+def default_handle() -> Handle:
+    dev = torch.cuda.current_device()
+    st = torch.cuda.current_stream().cuda_stream
+    key = (dev, st)
+    h = _handles.get(key)
+    if h is None:
+        h = Handle(dev)
+        _handles[key] = h
+    return h
+
+
+def _input(A: torch.Tensor) -> L.cnmf_input:
+    if A.dtype not in _DT:
+        raise TypeError("A must be float64 or float32")
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D row-major tensor (unit column stride)")
+    return L.cnmf_input(_ptr(A), _DT[A.dtype], A.shape[0], A.shape[1], A.stride(0))
+
+
+def _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype):
+    return L.cnmf_sketch_desc(int(r), int(k), int(q), _SIDES[sides] if isinstance(sides, str) else int(sides),
+                              _PREC[pass_dtype], _PREC[final_dtype], _ptr(omega_left), _ptr(omega_right))
+
+
+def _acc_dtype(A, pass_dtype):
+    return torch.float64 if pass_dtype == "f64" else torch.float32
+
+
+def _default_prec(A, pass_dtype, final_dtype):
+    if pass_dtype is None:
+        pass_dtype = "f64" if A.dtype == torch.float64 else "f32"
+    if final_dtype is None:
+        final_dtype = "f64" if pass_dtype == "f64" else ("f32" if pass_dtype == "f32" else "bf16")
+    return pass_dtype, final_dtype
+
+
+@dataclass
+class Sketch:
+    L: torch.Tensor | None
+    R: torch.Tensor | None
+    B: torch.Tensor | None
+    At: torch.Tensor | None
+    Ac: torch.Tensor | None
+    stats: torch.Tensor
+
+
+def sketch(A, r, k, q, omega_left=None, omega_right=None, sides="both", pass_dtype=None, final_dtype=None,
+           want_ac=False, handle: Handle | None = None) -> Sketch:
+    """Structured random compression (Alg. 1) of A on one or both sides, and
+    the small sketches B = L^T A, At = L^T A R^T, Ac = A R^T."""
+    h = handle or default_handle()
+    pass_dtype, final_dtype = _default_prec(A, pass_dtype, final_dtype)
+    m, n = A.shape
+    dev = A.device
+    od = _acc_dtype(A, pass_dtype)
+    sd = _SIDES[sides] if isinstance(sides, str) else sides
+    left, right = bool(sd & 1), bool(sd & 2)
+    Lt = torch.empty((m, k), dtype=od, device=dev) if left else None
+    Rt = torch.empty((k, n), dtype=od, device=dev) if right else None
+    Bt = torch.empty((k, n), dtype=od, device=dev) if left else None
+    Att = torch.empty((k, k), dtype=od, device=dev) if (left and right) else None
+    Act = torch.empty((m, k), dtype=od, device=dev) if (right and want_ac) else None
+    stats = torch.zeros(4, dtype=torch.float64, device=dev)
+    inp = _input(A)
+    d = _sketch_desc(r, k, q, sd, omega_left, omega_right, pass_dtype, final_dtype)
+    out = L.cnmf_sketch_out(_ptr(Lt), _ptr(Rt), _ptr(Bt), _ptr(Att), _ptr(Act), _ptr(stats))
+    L.check(h._lib.cnmf_sketch(h.raw, C.byref(inp), C.byref(d), C.byref(out)), h.raw)
+    return Sketch(Lt, Rt, Bt, Att, Act, stats)
+
+
+@dataclass
+class Factorization:
+    U: torch.Tensor
+    V: torch.Tensor
+    rel_residual: torch.Tensor
+    sketch: Sketch | None
+
+
+def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="admm", iters=100,
+              lam=1.0, phi=None, xi=1.0, mu_eps=1e-16, pass_dtype=None, final_dtype=None,
+              want_sketch=False, handle: Handle | None = None) -> Factorization:
+    """Compressed NMF: two-sided sketch, then ADMM (Alg. 3) or MU (Alg. 2) on
+    the compressed factors, then the FP64 relative residual.  The *_full
+    methods run the same iterations uncompressed (L = I, R = I)."""
+    h = handle or default_handle()
+    pass_dtype, final_dtype = _default_prec(A, pass_dtype, final_dtype)
+    m, n = A.shape
+    dev = A.device
+    od = _acc_dtype(A, pass_dtype)
+    U = torch.empty((m, r), dtype=od, device=dev)
+    V = torch.empty((r, n), dtype=od, device=dev)
+    res = torch.zeros(1, dtype=torch.float64, device=dev)
+    sk = None
+    if want_sketch:
+        sk = Sketch(torch.empty((m, k), dtype=od, device=dev), torch.empty((k, n), dtype=od, device=dev),
+                    torch.empty((k, n), dtype=od, device=dev), torch.empty((k, k), dtype=od, device=dev),
+                    torch.empty((m, k), dtype=od, device=dev) if method == "mu" else None,
+                    torch.zeros(4, dtype=torch.float64, device=dev))
+        so = L.cnmf_sketch_out(_ptr(sk.L), _ptr(sk.R), _ptr(sk.B), _ptr(sk.At), _ptr(sk.Ac), _ptr(sk.stats))
+    else:
+        so = L.cnmf_sketch_out()
+    U0 = U0.to(device=dev, dtype=torch.float64).contiguous()
+    V0 = V0.to(device=dev, dtype=torch.float64).contiguous()
+    inp = _input(A)
+    d = L.cnmf_factorize_desc(_sketch_desc(r, k, q, L.CNMF_BOTH, omega_left, omega_right, pass_dtype, final_dtype),
+                              _METHODS[method], int(iters), float(lam), float(lam if phi is None else phi),
+                              float(xi), float(mu_eps), _ptr(U0), _ptr(V0))
+    out = L.cnmf_factorize_out(_ptr(U), _ptr(V), _ptr(res), so)
+    L.check(h._lib.cnmf_factorize(h.raw, C.byref(inp), C.byref(d), C.byref(out)), h.raw)
+    return Factorization(U, V, res, sk)
+
+
+def select(A, r, k, q, omega_left, omega_right=None, sides="left", pass_dtype=None, final_dtype=None,
+           want_scores=False, want_B=False, handle: Handle | None = None):
+    """Compressed separable NMF column selection (Alg. SNMF steps 1-2): the
+    sketch, B = Q^T A, and SPA on B.  Returns int64 indices (device)."""
+    h = handle or default_handle()
+    pass_dtype, final_dtype = _default_prec(A, pass_dtype, final_dtype)
+    dev = A.device
+    K = torch.empty(r, dtype=torch.int64, device=dev)
+    score = torch.empty(r, dtype=torch.float64, device=dev) if want_scores else None
+    B = torch.empty((k, A.shape[1]), dtype=_acc_dtype(A, pass_dtype), device=dev) if want_B else None
+    inp = _input(A)
+    d = _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype)
+    L.check(h._lib.snmf_select(h.raw, C.byref(inp), C.byref(d), _ptr(K), _ptr(score), _ptr(B)), h.raw)
+    return K, score, B
+
+
+def spa(B, r, want_scores=False, handle: Handle | None = None):
+    """SPA on the columns of a given k x n device matrix B (FP64 arithmetic)."""
+    h = handle or default_handle()
+    if B.dtype not in _DT or B.dim() != 2 or B.stride(1) != 1:
+        raise ValueError("B must be a row-major float64/float32 2-D tensor")
+    K = torch.empty(r, dtype=torch.int64, device=B.device)
+    score = torch.empty(r, dtype=torch.float64, device=B.device) if want_scores else None
+    L.check(h._lib.cnmf_spa(h.raw, _ptr(B), _DT[B.dtype], B.shape[0], B.shape[1], B.stride(0), int(r),
+                            _ptr(K), _ptr(score)), h.raw)
+    return K, score
+
+
+def range_product(A, X, trans=False, handle: Handle | None = None):
+    """One streaming pass: A @ X (trans False) or A.T @ X (trans True)."""
+    h = handle or default_handle()
+    if X.dtype != A.dtype or X.dim() != 2 or not X.is_contiguous():
+        raise ValueError("X must be a contiguous 2-D tensor of A's dtype")
+    rows_out = A.shape[1] if trans else A.shape[0]
+    Y = torch.empty((rows_out, X.shape[1]), dtype=A.dtype, device=A.device)
+    inp = _input(A)
+    L.check(h._lib.cnmf_range_product(h.raw, C.byref(inp), int(bool(trans)), _ptr(X), X.shape[1], _ptr(Y)), h.raw)
+    return Y
+
+
+def workspace_bytes(m, n, r, k, q, method="admm", iters=100, pass_dtype="f32"):
+    """Device workspace a factorisation of an m x n input needs (host only)."""
+    lib = L.load()
+    d = L.cnmf_factorize_desc(_sketch_desc(r, k, q, L.CNMF_BOTH, None, None, pass_dtype, pass_dtype),
+                              _METHODS[method], int(iters), 1.0, 1.0, 1.0, 0.0, None, None)
+    out = C.c_size_t()
+    L.check(lib.cnmf_workspace_bytes(int(m), int(n), C.byref(d), C.byref(out)))
+    return out.value

@@ -1,0 +1,116 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace cnmf {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// Error bookkeeping for kernel launchers: every launcher returns the HIP
+// status of its launch so the runtime can map it to CNMF_EDEVICE.
+#define CNMF_LAUNCH_CHECK() return hipGetLastError()
+
+// ---------------------------------------------------------------------------
+// Pass GEMMs (range-finder passes over A)
+// ---------------------------------------------------------------------------
+// Y = A X (A m x n row-major, X n x kk, kk = 16*kb): partial products over
+// `splits` slices of the n range land in P[s][m][kk]; with splits == 1 the
+// result is final.  T is double or float.
+template <typename T>
+hipError_t launch_gemm_n(const T* A, int64_t lda, int m, int n, const T* X, int kk, T* P,
+                         int splits, hipStream_t st);
+// W = A^T Z (Z m x kk): partials over slices of the m range in P[s][n][kk].
+template <typename T>
+hipError_t launch_gemm_t(const T* A, int64_t lda, int m, int n, const T* Z, int kk, T* P,
+                         int splits, hipStream_t st);
+// Split count heuristic shared by the runtime (deterministic in the shape).
+int choose_splits_n(int m, int n, int kk, int elem_bytes);
+int choose_splits_t(int m, int n, int kk, int elem_bytes);
+
+// Reduced-precision passes: A16 (bf16) or A8 (fp8 e4m3 with per-tile scales)
+// against operands of the same type; FP32 accumulation.
+hipError_t launch_gemm_n_bf16(const __hip_bfloat16* A, int64_t lda, int m, int n,
+                              const __hip_bfloat16* X, int kk, float* P, int splits, hipStream_t st);
+hipError_t launch_gemm_t_bf16(const __hip_bfloat16* A, int64_t lda, int m, int n,
+                              const __hip_bfloat16* Z, int kk, float* P, int splits, hipStream_t st);
+hipError_t launch_gemm_n_fp8(const uint8_t* A, int64_t lda, const float* tile_scale, int m, int n,
+                             const uint8_t* X, int kk, float* P, int splits, hipStream_t st);
+hipError_t launch_gemm_t_fp8(const uint8_t* A, int64_t lda, const float* tile_scale, int m, int n,
+                             const uint8_t* Z, int kk, float* P, int splits, hipStream_t st);
+hipError_t launch_convert_a_bf16(const float* A, int64_t lda, int m, int n, __hip_bfloat16* Ab,
+                                 int64_t ldb, hipStream_t st);
+hipError_t launch_convert_a_fp8(const float* A, int64_t lda, int m, int n, uint8_t* A8, int64_t ld8,
+                                float* tile_scale, hipStream_t st);
+constexpr int kFp8Tile = 128;
+
+// ---------------------------------------------------------------------------
+// Orthonormalisation (CholeskyQR2 in FP64) and small products
+// ---------------------------------------------------------------------------
+// Y = sum_s P[s] (fixed order), rows x ld.
+template <typename T>
+hipError_t launch_reduce_splits(const T* P, int splits, int64_t rows, int ld, T* Y, hipStream_t st);
+// Partials of X[:, x0 + h*hs : +ka]^T Y[:, y0 + h*hs : +kb] (FP64) over `parts`
+// row slices, for h < nh: Cp[(p * nh + h) * ka * kb].
+template <typename TX, typename TY>
+hipError_t launch_cross2(const TX* X, int ldx, int x0, const TY* Y, int ldy, int y0, int hs, int nh, int rows,
+                         int ka, int kb, double* Cp, int parts, hipStream_t st);
+// out[e] = sum_p in[p * count + e] in the order p = 0, 1, ...
+hipError_t launch_sum_parts(const double* in, int parts, int64_t count, double* out, hipStream_t st);
+// For each half h: G = T^T T (Cholesky, T upper with positive diagonal),
+// Tinv = T^-1.  A pivot <= tol * max diag(G) counts as a breakdown: flags[h]
+// is incremented and the pivot is repaired.
+hipError_t launch_chol_inv(const double* G, int nh, int kh, double* Tinv, double* Tacc,
+                           int* flags, hipStream_t st);
+// Q64[:, h*kh + c] = sum_{l <= c} Y[:, h*kh + l] Tinv_h[l][c] (FP64), h < nh.
+// In place (Q64 == Y) is allowed.
+template <typename TY>
+hipError_t launch_apply_tinv(const TY* Y, int rows, int ldy, int nh, int kh, const double* Tinv, double* Q64,
+                             int ldq, hipStream_t st);
+// max |Q^T Q - I| for an FP64 Gram (for stats)
+hipError_t launch_orth_error(const double* G, int kh, double* out, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Compressed / uncompressed NMF iterations
+// ---------------------------------------------------------------------------
+struct AdmmSide {
+  const void* Bm;   // basis rows (L: m x kp, or R^T: n x kp), TA
+  int ldb;
+  void* F;          // factor rows (U: m x r, or V^T: n x r), ld = ldf
+  void* M;          // multiplier rows (Lam or Phi^T), ld = ldf
+  int ldf;
+  int rows;
+  double pen;       // lambda or phi
+};
+template <typename T>
+hipError_t launch_admm_uv(AdmmSide s0, AdmmSide s1, int nsides, const double* XY, int k, int r,
+                          double xi, int mode, double* Pp, int parts0, int parts1, hipStream_t st);
+template <typename T>
+hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const double* At, int k, int r,
+                             double lam, double phi, int first, double* XY, double* Pred,
+                             unsigned* counter, int* flags, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Misc
+// ---------------------------------------------------------------------------
+template <typename TS, typename TD>
+hipError_t launch_copy2d(const TS* src, int64_t lds, TD* dst, int64_t ldd, int rows, int cols,
+                         double scale, hipStream_t st);
+template <typename TS, typename TD>
+hipError_t launch_transpose(const TS* src, int64_t lds, TD* dst, int64_t ldd, int rows, int cols,
+                            hipStream_t st);
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
+template <typename T>
+hipError_t launch_residual(const T* A, int64_t lda, int m, int n, const T* U, int ldu, const T* Vt,
+                           int ldv, int r, double* partial, int parts, hipStream_t st);
+hipError_t launch_residual_finish(const double* partial, int parts, double* out, hipStream_t st);
+hipError_t launch_flags_to_stats(const int* flags, int nflags, double* out, hipStream_t st);
+hipError_t launch_spa_step(double* Bt, int n, int k, int ldb, int t, int64_t* K, double* score,
+                           double* u, double* wg_best, int64_t* wg_idx, unsigned* counter,
+                           int nblocks, hipStream_t st);
+
+}  // namespace cnmf

@@ -1,0 +1,434 @@
+// Streaming passes over A for the structured random compression (Alg. 1,
+// Section 2): Y = A X and W = A^T Z with tall-skinny X, Z (kk <= 128
+// columns).  Each pass reads A exactly once; the operand chunk is staged in
+// LDS and shared by the four waves of a workgroup; A goes straight from HBM
+// into registers in 16-byte loads.  Products run on the 16x16x4 FP32 / FP64
+// MFMA.  The reduction dimension can be split over `splits` workgroup
+// columns; each slice writes its own partial (no atomics), and the partials
+// are summed later in a fixed order, so results are bit-reproducible.
+#include "cnmf_internal.hpp"
+
+namespace cnmf {
+
+template <typename T>
+struct Mfma;
+// Operand layout shared by both 16x16x4 MFMAs: lane (r = lane % 16,
+// g = lane / 16) supplies A[r][g] and B[g][r].  Result element i of lane
+// (c, g) is D[out_row(g, i)][c]: row 4g + i for FP32, but g + 4i for FP64
+// (measured on gfx950).
+template <>
+struct Mfma<float> {
+  typedef floatx4 acc_t;
+  static __device__ __forceinline__ void mma(float a, float b, floatx4& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int i) { return 4 * g + i; }
+};
+template <>
+struct Mfma<double> {
+  typedef doublex4 acc_t;
+  static __device__ __forceinline__ void mma(double a, double b, doublex4& c) {
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int i) { return g + 4 * i; }
+};
+
+template <typename T, int N>
+struct alignas(16) Vec {
+  T v[N];
+};
+
+// Load `cnt` consecutive elements of one row of A starting at column col
+// (cnt elements, all guarded against [.., kend)).  With FULL the whole run
+// is in range and 16-byte aligned.
+template <typename T, int CNT, bool VEC>
+__device__ __forceinline__ void load_run(const T* __restrict__ p, int col, int kend, bool row_ok,
+                                         T* out) {
+  constexpr int VW = 16 / sizeof(T);
+  if (VEC && row_ok && col + CNT <= kend) {
+#pragma unroll
+    for (int v = 0; v < CNT / VW; ++v) {
+      Vec<T, VW> x = *reinterpret_cast<const Vec<T, VW>*>(p + col + v * VW);
+#pragma unroll
+      for (int e = 0; e < VW; ++e) out[v * VW + e] = x.v[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < CNT; ++e) out[e] = (row_ok && col + e < kend) ? p[col + e] : T(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Y = A X.  Workgroup: 256 threads = 4 waves; wave w owns RB blocks of 16
+// rows.  Per K chunk of KC columns, lane (r = lane % 16, g = lane / 16)
+// holds columns [g*G, g*G + G) of its rows (a permutation of the MFMA K
+// index that both operands share, so the contraction is unchanged).
+// ---------------------------------------------------------------------------
+template <typename T, int KB, int RB, bool VEC>
+__global__ __launch_bounds__(256, 2) void gemm_n_kernel(const T* __restrict__ A, int64_t lda, int m,
+                                                        int n, const T* __restrict__ X,
+                                                        T* __restrict__ P, int cols_per_split) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int KC = sizeof(T) == 4 ? 64 : 32;
+  constexpr int G = KC / 4;
+  constexpr int KK = 16 * KB;
+  constexpr int LDX = KK + 1;
+  constexpr int XPER = KC * KK / 256;  // operand elements staged per thread
+  __shared__ T Xs[2][KC * LDX];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int r = lane & 15;
+  const int g = lane >> 4;
+  const int split = blockIdx.y;
+  const int kbeg = split * cols_per_split;
+  const int kend = min(n, kbeg + cols_per_split);
+  const int nchunk = kend > kbeg ? (kend - kbeg + KC - 1) / KC : 0;
+  const int row_base = blockIdx.x * (64 * RB) + w * 16 * RB;
+
+  const T* arow[RB];
+  bool rok[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    int row = row_base + rb * 16 + r;
+    rok[rb] = row < m;
+    arow[rb] = A + (int64_t)(rok[rb] ? row : 0) * lda;
+  }
+
+  acc_t acc[RB][KB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int jb = 0; jb < KB; ++jb) acc[rb][jb] = acc_t{0, 0, 0, 0};
+
+  T a_cur[RB][G], a_nxt[RB][G];
+  T xr[XPER];
+
+  auto load_a = [&](int chunk, T (&dst)[RB][G]) {
+    int col = kbeg + chunk * KC + g * G;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) load_run<T, G, VEC>(arow[rb], col, kend, rok[rb], dst[rb]);
+  };
+  // operand chunk: rows [k0, k0 + KC) of X, all KK columns (contiguous)
+  auto load_x = [&](int chunk) {
+    int k0 = kbeg + chunk * KC;
+#pragma unroll
+    for (int e = 0; e < XPER; ++e) {
+      int idx = e * 256 + tid;
+      int kr = idx / KK, c = idx - kr * KK;
+      xr[e] = (k0 + kr < kend) ? X[(int64_t)(k0 + kr) * KK + c] : T(0);
+    }
+  };
+  auto store_x = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < XPER; ++e) {
+      int idx = e * 256 + tid;
+      int kr = idx / KK, c = idx - kr * KK;
+      Xs[buf][kr * LDX + c] = xr[e];
+    }
+  };
+
+  if (nchunk > 0) {
+    load_a(0, a_cur);
+    load_x(0);
+    store_x(0);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nchunk;
+    if (more) {
+      load_a(ch + 1, a_nxt);
+      load_x(ch + 1);
+    }
+    const T* xs = Xs[buf] + (g * G) * LDX + r;
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+#pragma unroll
+      for (int jb = 0; jb < KB; ++jb) {
+        T b = xs[s * LDX + jb * 16];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) Mfma<T>::mma(a_cur[rb][s], b, acc[rb][jb]);
+      }
+    }
+    if (more) store_x(buf ^ 1);
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int s = 0; s < G; ++s) a_cur[rb][s] = a_nxt[rb][s];
+    }
+  }
+
+  // epilogue: acc[rb][jb][i] = Y[row_base + rb*16 + out_row(g, i)][jb*16 + r]
+  T* out = P + (int64_t)split * m * KK;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int row = row_base + rb * 16 + Mfma<T>::out_row(g, i);
+      if (row < m) {
+#pragma unroll
+        for (int jb = 0; jb < KB; ++jb) out[(int64_t)row * KK + jb * 16 + r] = acc[rb][jb][i];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// W = A^T Z.  MFMA M index = column of A, N = operand column, K = row of A.
+// Lane (r, g) loads VW consecutive columns [4.. of its 16-lane group] of a
+// row: column col_w + VW*r + e belongs to MFMA block e at M index r.  Per K
+// chunk of KC rows, group g takes rows [g*G, g*G + G).
+// ---------------------------------------------------------------------------
+template <typename T, int KB, int VW, bool VEC>
+__global__ __launch_bounds__(256, 2) void gemm_t_kernel(const T* __restrict__ A, int64_t lda, int m,
+                                                        int n, const T* __restrict__ Z,
+                                                        T* __restrict__ P, int rows_per_split) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int KC = 32;
+  constexpr int G = KC / 4;
+  constexpr int KK = 16 * KB;
+  constexpr int LDZ = KK + 1;
+  constexpr int ZPER = KC * KK / 256;
+  constexpr int CW = 16 * VW;  // columns per wave
+  __shared__ T Zs[2][KC * LDZ];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int r = lane & 15;
+  const int g = lane >> 4;
+  const int split = blockIdx.y;
+  const int ibeg = split * rows_per_split;
+  const int iend = min(m, ibeg + rows_per_split);
+  const int nchunk = iend > ibeg ? (iend - ibeg + KC - 1) / KC : 0;
+  const int colw = blockIdx.x * (4 * CW) + w * CW;
+  const int mycol = colw + VW * r;
+  const bool vec_ok = VEC && (mycol + VW <= n);
+
+  acc_t acc[VW][KB];
+#pragma unroll
+  for (int e = 0; e < VW; ++e)
+#pragma unroll
+    for (int jb = 0; jb < KB; ++jb) acc[e][jb] = acc_t{0, 0, 0, 0};
+
+  T a_cur[G][VW], a_nxt[G][VW];
+  T zr[ZPER];
+
+  auto load_a = [&](int chunk, T (&dst)[G][VW]) {
+    int i0 = ibeg + chunk * KC + g * G;
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      int row = i0 + s;
+      bool rok = row < iend;
+      const T* p = A + (int64_t)(rok ? row : ibeg) * lda;
+      if (vec_ok && rok) {
+        Vec<T, VW> x = *reinterpret_cast<const Vec<T, VW>*>(p + mycol);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) dst[s][e] = x.v[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) dst[s][e] = (rok && mycol + e < n) ? p[mycol + e] : T(0);
+      }
+    }
+  };
+  auto load_z = [&](int chunk) {
+    int i0 = ibeg + chunk * KC;
+#pragma unroll
+    for (int e = 0; e < ZPER; ++e) {
+      int idx = e * 256 + tid;
+      int kr = idx / KK, c = idx - kr * KK;
+      zr[e] = (i0 + kr < iend) ? Z[(int64_t)(i0 + kr) * KK + c] : T(0);
+    }
+  };
+  auto store_z = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < ZPER; ++e) {
+      int idx = e * 256 + tid;
+      int kr = idx / KK, c = idx - kr * KK;
+      Zs[buf][kr * LDZ + c] = zr[e];
+    }
+  };
+
+  if (nchunk > 0) {
+    load_a(0, a_cur);
+    load_z(0);
+    store_z(0);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nchunk;
+    if (more) {
+      load_a(ch + 1, a_nxt);
+      load_z(ch + 1);
+    }
+    const T* zs = Zs[buf] + (g * G) * LDZ + r;
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+#pragma unroll
+      for (int jb = 0; jb < KB; ++jb) {
+        T b = zs[s * LDZ + jb * 16];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) Mfma<T>::mma(a_cur[s][e], b, acc[e][jb]);
+      }
+    }
+    if (more) store_z(buf ^ 1);
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int s = 0; s < G; ++s)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) a_cur[s][e] = a_nxt[s][e];
+    }
+  }
+
+  // epilogue: acc[e][jb][i] = W[colw + VW*out_row(g, i) + e][jb*16 + r]
+  T* out = P + (int64_t)split * n * KK;
+#pragma unroll
+  for (int e = 0; e < VW; ++e)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int col = colw + VW * Mfma<T>::out_row(g, i) + e;
+      if (col < n) {
+#pragma unroll
+        for (int jb = 0; jb < KB; ++jb) out[(int64_t)col * KK + jb * 16 + r] = acc[e][jb][i];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static int g_num_cu = 0;
+static int num_cu() {
+  if (g_num_cu == 0) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess && p.multiProcessorCount > 0)
+      g_num_cu = p.multiProcessorCount;
+    else
+      g_num_cu = 256;
+  }
+  return g_num_cu;
+}
+
+// Pick the number of reduction slices so that tiles * splits fills the
+// resident workgroup slots (2 per CU) with a small tail, without cutting a
+// slice below a few chunks.  Depends only on the shape and the CU count.
+static int choose_splits(int tiles, int klen, int min_per_split) {
+  const int slots = 2 * num_cu();
+  int max_s = std::max(1, klen / min_per_split);
+  max_s = std::min(max_s, 64);
+  int best = 1;
+  double best_eff = -1.0;
+  for (int s = 1; s <= max_s; ++s) {
+    long long wgs = (long long)tiles * s;
+    long long rounds = (wgs + slots - 1) / slots;
+    double eff = (double)wgs / (double)(rounds * slots);
+    // penalise extra partial traffic slightly
+    eff -= 0.004 * s;
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = s;
+    }
+    if (wgs >= 4LL * slots) break;
+  }
+  return best;
+}
+
+// Row blocks of 16 per wave in the A X kernel: two for FP32 except where the
+// operand width makes the register budget spill.
+static constexpr int rb_for(int kb, int elem_bytes) { return (elem_bytes == 4 && kb != 6 && kb != 7) ? 2 : 1; }
+
+int choose_splits_n(int m, int n, int kk, int elem_bytes) {
+  int rb = rb_for(kk / 16, elem_bytes);
+  int tiles = (m + 64 * rb - 1) / (64 * rb);
+  return choose_splits(tiles, n, 512);
+}
+
+static int t_cols_per_wg(int kk, int elem_bytes) {
+  int kb = kk / 16;
+  int vw = elem_bytes == 4 ? (kb > 4 ? 2 : 4) : (kb > 4 ? 1 : 2);
+  return 4 * 16 * vw;
+}
+
+int choose_splits_t(int m, int n, int kk, int elem_bytes) {
+  int cw = t_cols_per_wg(kk, elem_bytes);
+  int tiles = (n + cw - 1) / cw;
+  return choose_splits(tiles, m, 512);
+}
+
+template <typename T, int KB>
+static hipError_t gemm_n_kb(const T* A, int64_t lda, int m, int n, const T* X, T* P, int splits,
+                            hipStream_t st) {
+  constexpr int RB = rb_for(KB, sizeof(T));
+  constexpr int KC = sizeof(T) == 4 ? 64 : 32;
+  int per = (n + splits - 1) / splits;
+  per = (per + KC - 1) / KC * KC;
+  dim3 grid((m + 64 * RB - 1) / (64 * RB), splits);
+  bool vec = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(T)) % 16 == 0);
+  if (vec)
+    hipLaunchKernelGGL((gemm_n_kernel<T, KB, RB, true>), grid, dim3(256), 0, st, A, lda, m, n, X, P, per);
+  else
+    hipLaunchKernelGGL((gemm_n_kernel<T, KB, RB, false>), grid, dim3(256), 0, st, A, lda, m, n, X, P, per);
+  CNMF_LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t launch_gemm_n(const T* A, int64_t lda, int m, int n, const T* X, int kk, T* P, int splits,
+                         hipStream_t st) {
+  switch (kk) {
+    case 16: return gemm_n_kb<T, 1>(A, lda, m, n, X, P, splits, st);
+    case 32: return gemm_n_kb<T, 2>(A, lda, m, n, X, P, splits, st);
+    case 48: return gemm_n_kb<T, 3>(A, lda, m, n, X, P, splits, st);
+    case 64: return gemm_n_kb<T, 4>(A, lda, m, n, X, P, splits, st);
+    case 80: return gemm_n_kb<T, 5>(A, lda, m, n, X, P, splits, st);
+    case 96: return gemm_n_kb<T, 6>(A, lda, m, n, X, P, splits, st);
+    case 112: return gemm_n_kb<T, 7>(A, lda, m, n, X, P, splits, st);
+    case 128: return gemm_n_kb<T, 8>(A, lda, m, n, X, P, splits, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int KB>
+static hipError_t gemm_t_kb(const T* A, int64_t lda, int m, int n, const T* Z, T* P, int splits,
+                            hipStream_t st) {
+  constexpr int VW = sizeof(T) == 4 ? (KB > 4 ? 2 : 4) : (KB > 4 ? 1 : 2);
+  constexpr int KC = 32;
+  int per = (m + splits - 1) / splits;
+  per = (per + KC - 1) / KC * KC;
+  dim3 grid((n + 64 * VW - 1) / (64 * VW), splits);
+  bool vec = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(T)) % 16 == 0);
+  if (vec)
+    hipLaunchKernelGGL((gemm_t_kernel<T, KB, VW, true>), grid, dim3(256), 0, st, A, lda, m, n, Z, P, per);
+  else
+    hipLaunchKernelGGL((gemm_t_kernel<T, KB, VW, false>), grid, dim3(256), 0, st, A, lda, m, n, Z, P, per);
+  CNMF_LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t launch_gemm_t(const T* A, int64_t lda, int m, int n, const T* Z, int kk, T* P, int splits,
+                         hipStream_t st) {
+  switch (kk) {
+    case 16: return gemm_t_kb<T, 1>(A, lda, m, n, Z, P, splits, st);
+    case 32: return gemm_t_kb<T, 2>(A, lda, m, n, Z, P, splits, st);
+    case 48: return gemm_t_kb<T, 3>(A, lda, m, n, Z, P, splits, st);
+    case 64: return gemm_t_kb<T, 4>(A, lda, m, n, Z, P, splits, st);
+    case 80: return gemm_t_kb<T, 5>(A, lda, m, n, Z, P, splits, st);
+    case 96: return gemm_t_kb<T, 6>(A, lda, m, n, Z, P, splits, st);
+    case 112: return gemm_t_kb<T, 7>(A, lda, m, n, Z, P, splits, st);
+    case 128: return gemm_t_kb<T, 8>(A, lda, m, n, Z, P, splits, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_gemm_n<float>(const float*, int64_t, int, int, const float*, int, float*, int, hipStream_t);
+template hipError_t launch_gemm_n<double>(const double*, int64_t, int, int, const double*, int, double*, int, hipStream_t);
+template hipError_t launch_gemm_t<float>(const float*, int64_t, int, int, const float*, int, float*, int, hipStream_t);
+template hipError_t launch_gemm_t<double>(const double*, int64_t, int, int, const double*, int, double*, int, hipStream_t);
+
+}  // namespace cnmf

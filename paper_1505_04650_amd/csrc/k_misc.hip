@@ -1,0 +1,337 @@
+// Data movement, the reported residual and SPA.
+#include "cnmf_internal.hpp"
+
+namespace cnmf {
+
+// ---------------------------------------------------------------------------
+// dst[i][j] = TD(scale * src[i][j])
+// ---------------------------------------------------------------------------
+template <typename TD>
+__device__ __forceinline__ TD cvt(double x) {
+  return (TD)x;
+}
+template <>
+__device__ __forceinline__ __hip_bfloat16 cvt<__hip_bfloat16>(double x) {
+  return __float2bfloat16((float)x);
+}
+
+template <typename TS, typename TD>
+__global__ void copy2d_kernel(const TS* __restrict__ src, int64_t lds, TD* __restrict__ dst, int64_t ldd,
+                              int rows, int cols, double scale) {
+  int64_t total = (int64_t)rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = e / cols, j = e - i * cols;
+    dst[i * ldd + j] = cvt<TD>(scale * (double)src[i * lds + j]);
+  }
+}
+
+template <typename TS, typename TD>
+hipError_t launch_copy2d(const TS* src, int64_t lds, TD* dst, int64_t ldd, int rows, int cols, double scale,
+                         hipStream_t st) {
+  int64_t total = (int64_t)rows * cols;
+  if (total == 0) return hipSuccess;
+  int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL((copy2d_kernel<TS, TD>), dim3(blocks), dim3(256), 0, st, src, lds, dst, ldd, rows, cols,
+                     scale);
+  CNMF_LAUNCH_CHECK();
+}
+template hipError_t launch_copy2d<double, double>(const double*, int64_t, double*, int64_t, int, int, double, hipStream_t);
+template hipError_t launch_copy2d<double, float>(const double*, int64_t, float*, int64_t, int, int, double, hipStream_t);
+template hipError_t launch_copy2d<float, float>(const float*, int64_t, float*, int64_t, int, int, double, hipStream_t);
+template hipError_t launch_copy2d<float, double>(const float*, int64_t, double*, int64_t, int, int, double, hipStream_t);
+template hipError_t launch_copy2d<double, __hip_bfloat16>(const double*, int64_t, __hip_bfloat16*, int64_t, int, int, double, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// dst[j][i] = src[i][j] through a 32 x 32 LDS tile
+// ---------------------------------------------------------------------------
+template <typename TS, typename TD>
+__global__ void transpose_kernel(const TS* __restrict__ src, int64_t lds, TD* __restrict__ dst, int64_t ldd,
+                                 int rows, int cols) {
+  __shared__ double tile[32][33];
+  int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: ty 0..7
+  for (int yy = ty; yy < 32; yy += 8) {
+    int i = by + yy, j = bx + tx;
+    tile[yy][tx] = (i < rows && j < cols) ? (double)src[(int64_t)i * lds + j] : 0.0;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    int j = bx + yy, i = by + tx;
+    if (j < cols && i < rows) dst[(int64_t)j * ldd + i] = (TD)tile[tx][yy];
+  }
+}
+
+template <typename TS, typename TD>
+hipError_t launch_transpose(const TS* src, int64_t lds, TD* dst, int64_t ldd, int rows, int cols,
+                            hipStream_t st) {
+  if (rows == 0 || cols == 0) return hipSuccess;
+  dim3 grid((cols + 31) / 32, (rows + 31) / 32);
+  hipLaunchKernelGGL((transpose_kernel<TS, TD>), grid, dim3(256), 0, st, src, lds, dst, ldd, rows, cols);
+  CNMF_LAUNCH_CHECK();
+}
+template hipError_t launch_transpose<double, double>(const double*, int64_t, double*, int64_t, int, int, hipStream_t);
+template hipError_t launch_transpose<double, float>(const double*, int64_t, float*, int64_t, int, int, hipStream_t);
+template hipError_t launch_transpose<float, float>(const float*, int64_t, float*, int64_t, int, int, hipStream_t);
+template hipError_t launch_transpose<float, double>(const float*, int64_t, double*, int64_t, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// zero fill (a kernel, so it can live inside captured graphs)
+// ---------------------------------------------------------------------------
+__global__ void fill_kernel(uint32_t* __restrict__ p, size_t words) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < words; e += (size_t)gridDim.x * blockDim.x)
+    p[e] = 0u;
+}
+__global__ void fill_bytes_kernel(uint8_t* __restrict__ p, size_t bytes) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < bytes; e += (size_t)gridDim.x * blockDim.x)
+    p[e] = 0u;
+}
+
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  if ((uintptr_t)p % 4 == 0 && bytes % 4 == 0) {
+    size_t words = bytes / 4;
+    int blocks = (int)std::min<size_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, st, (uint32_t*)p, words);
+  } else {
+    int blocks = (int)std::min<size_t>((bytes + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_bytes_kernel, dim3(blocks), dim3(256), 0, st, (uint8_t*)p, bytes);
+  }
+  CNMF_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Relative residual ||A - U V||_F / ||A||_F: each block takes 16 rows and
+// sweeps the columns in chunks of 256; U rows and V^T chunk rows in LDS;
+// the product in T, differences and sums of squares in FP64.  partial[blk]
+// = (sum (a - uv)^2, sum a^2).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void residual_kernel(const T* __restrict__ A, int64_t lda, int m, int n,
+                                                       const T* __restrict__ U, int ldu,
+                                                       const T* __restrict__ Vt, int ldv, int r,
+                                                       double* __restrict__ partial) {
+  constexpr int RB = 16;
+  __shared__ T us[RB][65];
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x;
+  const int row0 = blockIdx.x * RB;
+  for (int e = tid; e < RB * r; e += 256) {
+    int i = e / r, c = e - i * r;
+    us[i][c] = row0 + i < m ? U[(int64_t)(row0 + i) * ldu + c] : T(0);
+  }
+  __syncthreads();
+  double num = 0.0, den = 0.0;
+  for (int j0 = 0; j0 < n; j0 += 256) {
+    int j = j0 + tid;
+    if (j < n) {
+      T v[64];
+#pragma unroll
+      for (int c = 0; c < 64; ++c) v[c] = c < r ? Vt[(int64_t)j * ldv + c] : T(0);
+      for (int i = 0; i < RB && row0 + i < m; ++i) {
+        T s = 0;
+#pragma unroll
+        for (int c = 0; c < 64; ++c) s = fma(us[i][c < r ? c : 0], v[c], s);
+        double a = (double)A[(int64_t)(row0 + i) * lda + j];
+        double d = a - (double)s;
+        num = fma(d, d, num);
+        den = fma(a, a, den);
+      }
+    }
+  }
+  red[0][tid] = num;
+  red[1][tid] = den;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      red[0][tid] += red[0][tid + s];
+      red[1][tid] += red[1][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    partial[2 * blockIdx.x] = red[0][0];
+    partial[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+template <typename T>
+hipError_t launch_residual(const T* A, int64_t lda, int m, int n, const T* U, int ldu, const T* Vt, int ldv,
+                           int r, double* partial, int parts, hipStream_t st) {
+  if (r > 64) return hipErrorInvalidValue;
+  int blocks = (m + 15) / 16;
+  if (blocks != parts) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(residual_kernel<T>, dim3(blocks), dim3(256), 0, st, A, lda, m, n, U, ldu, Vt, ldv, r,
+                     partial);
+  CNMF_LAUNCH_CHECK();
+}
+template hipError_t launch_residual<float>(const float*, int64_t, int, int, const float*, int, const float*, int, int, double*, int, hipStream_t);
+template hipError_t launch_residual<double>(const double*, int64_t, int, int, const double*, int, const double*, int, int, double*, int, hipStream_t);
+
+__global__ void residual_finish_kernel(const double* __restrict__ partial, int parts, double* out) {
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x;
+  // fixed-order: thread t sums parts t, t+256, ...; then a fixed tree
+  double num = 0.0, den = 0.0;
+  for (int p = tid; p < parts; p += 256) {
+    num += partial[2 * p];
+    den += partial[2 * p + 1];
+  }
+  red[0][tid] = num;
+  red[1][tid] = den;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      red[0][tid] += red[0][tid + s];
+      red[1][tid] += red[1][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *out = red[1][0] > 0 ? sqrt(red[0][0]) / sqrt(red[1][0]) : 0.0;
+}
+
+hipError_t launch_residual_finish(const double* partial, int parts, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(residual_finish_kernel, dim3(1), dim3(256), 0, st, partial, parts, out);
+  CNMF_LAUNCH_CHECK();
+}
+
+__global__ void flags_to_stats_kernel(const int* flags, int nflags, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nflags; ++i) s += (double)flags[i];
+    *out = s;
+  }
+}
+
+hipError_t launch_flags_to_stats(const int* flags, int nflags, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(flags_to_stats_kernel, dim3(1), dim3(64), 0, st, flags, nflags, out);
+  CNMF_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// SPA (Section 4, Alg. SNMF step 2) on Bt = B^T (n x k, FP64 working copy).
+// One launch per selection step t:
+//   t > 0: b_j <- b_j - u (u^T b_j) with u the previous step's unit pivot;
+//   s_j = ||b_j||^2; block argmax (largest s, lowest j on ties);
+//   the last block to finish reduces the block winners in block order,
+//   records K[t], score[t] and u = b_p / sqrt(s_p) for the next step.
+// Each block stages 64 rows in LDS; 4 threads per row.
+// ---------------------------------------------------------------------------
+constexpr int kSpaRows = 64;
+
+__device__ __forceinline__ bool spa_better(double s1, int64_t j1, double s2, int64_t j2) {
+  return s1 > s2 || (s1 == s2 && j1 < j2);
+}
+
+__global__ __launch_bounds__(256) void spa_step_kernel(double* __restrict__ Bt, int n, int k, int ldb, int t,
+                                                       int64_t* __restrict__ K, double* __restrict__ score,
+                                                       double* __restrict__ u, double* __restrict__ wg_best,
+                                                       int64_t* __restrict__ wg_idx, unsigned* counter) {
+  extern __shared__ double sm[];
+  double* bs = sm;                 // kSpaRows x (k + 1)
+  double* us = bs + kSpaRows * (k + 1);
+  __shared__ double part[256];
+  __shared__ double rs[kSpaRows];
+  __shared__ int64_t ri[kSpaRows];
+  __shared__ bool last;
+  const int tid = threadIdx.x;
+  const int ld = k + 1;
+  const int64_t row0 = (int64_t)blockIdx.x * kSpaRows;
+  for (int e = tid; e < kSpaRows * k; e += 256) {
+    int rr = e / k, a = e - rr * k;
+    bs[rr * ld + a] = row0 + rr < n ? Bt[(row0 + rr) * ldb + a] : 0.0;
+  }
+  if (t > 0)
+    for (int a = tid; a < k; a += 256) us[a] = u[a];
+  __syncthreads();
+  const int rr = tid >> 2, q = tid & 3;
+  double* b = bs + rr * ld;
+  if (t > 0) {
+    double d = 0.0;
+    for (int a = q; a < k; a += 4) d = fma(us[a], b[a], d);
+    part[tid] = d;
+    __syncthreads();
+    // fixed combination order within the 4-thread group
+    double dot = (part[tid & ~3] + part[(tid & ~3) + 1]) + (part[(tid & ~3) + 2] + part[(tid & ~3) + 3]);
+    for (int a = q; a < k; a += 4) b[a] = fma(-us[a], dot, b[a]);
+    __syncthreads();
+    for (int e = tid; e < kSpaRows * k; e += 256) {
+      int r2 = e / k, a = e - r2 * k;
+      if (row0 + r2 < n) Bt[(row0 + r2) * ldb + a] = bs[r2 * ld + a];
+    }
+  }
+  double s = 0.0;
+  for (int a = q; a < k; a += 4) s = fma(b[a], b[a], s);
+  part[tid] = s;
+  __syncthreads();
+  if (q == 0) {
+    double tot = (part[tid] + part[tid + 1]) + (part[tid + 2] + part[tid + 3]);
+    rs[rr] = (row0 + rr < n) ? tot : -1.0;
+    ri[rr] = row0 + rr;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double bv = rs[0];
+    int64_t bi = ri[0];
+    for (int i = 1; i < kSpaRows; ++i)
+      if (spa_better(rs[i], ri[i], bv, bi)) {
+        bv = rs[i];
+        bi = ri[i];
+      }
+    wg_best[blockIdx.x] = bv;
+    wg_idx[blockIdx.x] = bi;
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    unsigned prev = atomicAdd(counter, 1u);
+    last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // block winners in block order: thread-strided, then a fixed tree
+  double bv = -2.0;
+  int64_t bi = INT64_MAX;
+  for (int p = tid; p < (int)gridDim.x; p += 256) {
+    double v = wg_best[p];
+    int64_t i = wg_idx[p];
+    if (spa_better(v, i, bv, bi)) {
+      bv = v;
+      bi = i;
+    }
+  }
+  __shared__ double tv[256];
+  __shared__ int64_t ti[256];
+  tv[tid] = bv;
+  ti[tid] = bi;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st && spa_better(tv[tid + st], ti[tid + st], tv[tid], ti[tid])) {
+      tv[tid] = tv[tid + st];
+      ti[tid] = ti[tid + st];
+    }
+    __syncthreads();
+  }
+  const int64_t p = ti[0];
+  const double sp = tv[0];
+  if (tid == 0) {
+    K[t] = p;
+    if (score) score[t] = sp;
+    *counter = 0u;
+  }
+  const double inv = sp > 0 ? 1.0 / sqrt(sp) : 0.0;
+  for (int a = tid; a < k; a += 256) u[a] = Bt[p * ldb + a] * inv;
+}
+
+hipError_t launch_spa_step(double* Bt, int n, int k, int ldb, int t, int64_t* K, double* score, double* u,
+                           double* wg_best, int64_t* wg_idx, unsigned* counter, int nblocks, hipStream_t st) {
+  if (nblocks != (n + kSpaRows - 1) / kSpaRows) return hipErrorInvalidValue;
+  size_t sm = ((size_t)kSpaRows * (k + 1) + k) * sizeof(double);
+  hipFuncSetAttribute((const void*)spa_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  hipLaunchKernelGGL(spa_step_kernel, dim3(nblocks), dim3(256), sm, st, Bt, n, k, ldb, t, K, score, u, wg_best,
+                     wg_idx, counter);
+  CNMF_LAUNCH_CHECK();
+}
+
+}  // namespace cnmf

@@ -1,0 +1,803 @@
+// Host runtime of the compressed-NMF library: handle, argument checks,
+// workspace planning and the launch sequences of the hot path.
+//
+// Range finder schedule (Alg. 1 on A and on A^T, Section 3).  Each chain
+// alternates products with A and A^T, with an orthonormalisation after every
+// product (re-orthonormalised subspace iteration):
+//   left chain L:  A Omega_L, A^T Q, A Q, ..., A Q      (2q + 1 products)
+//   right chain R: A^T Omega_R, A Q, A^T Q, ..., A^T Q  (2q + 1 products)
+// The right chain starts one pass later than the left one, so in every pass
+// both chains multiply by the SAME operator (A or A^T) and their operands
+// sit side by side: one streaming read of A serves both.  The pass after
+// L's last product multiplies A^T by [L | Q_R]: its left block is
+// A^T L = B^T (the small sketch B = L^T A), its right block is R's last
+// range sample.  Passes: 2q + 2 for two-sided or left-only sketches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/cnmf.h"
+#include "cnmf_internal.hpp"
+
+using namespace cnmf;
+
+static thread_local std::string g_noh_err;
+
+struct cnmf_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t limit = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err;
+  bool timing = false;
+  hipEvent_t ev[8] = {};
+  int ev_used[8] = {};
+  double stage_ms[8];
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline int ru16(int x) { return (x + 15) / 16 * 16; }
+
+cnmf_status fail(cnmf_handle* h, cnmf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h)
+    h->err = buf;
+  else
+    g_noh_err = buf;
+  return s;
+}
+
+#define HIPCHK(h, expr)                                                                          \
+  do {                                                                                           \
+    hipError_t _e = (expr);                                                                      \
+    if (_e != hipSuccess)                                                                        \
+      return fail(h, CNMF_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                  __LINE__);                                                                     \
+  } while (0)
+
+// Bump allocator over the handle's workspace (or a dry run for sizing).
+struct Arena {
+  char* base;
+  size_t off = 0;
+  explicit Arena(char* b) : base(b) {}
+  template <typename T>
+  T* take(size_t count) {
+    size_t bytes = align_up(count * sizeof(T));
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+size_t elem_size(cnmf_dtype d) {
+  switch (d) {
+    case CNMF_F64: return 8;
+    case CNMF_F32: return 4;
+    case CNMF_BF16: return 2;
+    case CNMF_FP8_E4M3: return 1;
+  }
+  return 0;
+}
+
+// -------------------------------------------------------------------------
+// Pass plan
+// -------------------------------------------------------------------------
+enum BlockKind { L_RANGE = 0, R_RANGE = 1, L_B = 2, R_AC = 3 };
+struct Block {
+  BlockKind kind;
+  int step;  // chain step (RANGE)
+  int col0;
+};
+struct Pass {
+  bool dirN;  // true: A X ; false: A^T Z
+  int kk;
+  std::vector<Block> blocks;
+  bool final_prec;
+};
+
+std::vector<Pass> plan_passes(int k, int q, int sides, bool want_ac) {
+  const bool L = sides & CNMF_LEFT, R = sides & CNMF_RIGHT;
+  const int nsteps = 2 * q + 1;
+  const int rstart = L ? 1 : 0;
+  std::vector<Pass> out;
+  int p = 0;
+  for (;; ++p) {
+    Pass ps;
+    ps.final_prec = p >= 2 * q;
+    int col = 0;
+    bool any = false;
+    bool dirset = false;
+    if (L) {
+      if (p < nsteps) {
+        ps.blocks.push_back({L_RANGE, p, col});
+        col += k;
+        ps.dirN = (p % 2 == 0);
+        dirset = any = true;
+      } else if (p == nsteps) {
+        ps.blocks.push_back({L_B, 0, col});
+        col += k;
+        ps.dirN = false;
+        dirset = any = true;
+      }
+    }
+    if (R) {
+      int s = p - rstart;
+      if (s >= 0 && s < nsteps) {
+        ps.blocks.push_back({R_RANGE, s, col});
+        col += k;
+        bool d = (s % 2 == 1);
+        if (dirset && d != ps.dirN) return {};  // schedule invariant
+        ps.dirN = d;
+        dirset = any = true;
+      } else if (s == nsteps && want_ac) {
+        // Ac = A R^T after R's last product (an A pass)
+        if (dirset && !ps.dirN) {
+          // cannot share with an A^T block; emit separately below
+        } else {
+          ps.blocks.push_back({R_AC, 0, col});
+          col += k;
+          ps.dirN = true;
+          dirset = any = true;
+        }
+      }
+    }
+    if (!any) break;
+    ps.kk = ru16(col);
+    out.push_back(ps);
+  }
+  return out;
+}
+
+// -------------------------------------------------------------------------
+// Argument checks
+// -------------------------------------------------------------------------
+cnmf_status check_input(cnmf_handle* h, const cnmf_input* A) {
+  if (!A) return fail(h, CNMF_EINVAL, "A is NULL");
+  if (!A->data_dev) return fail(h, CNMF_EINVAL, "A->data_dev is NULL");
+  if (A->dtype != CNMF_F64 && A->dtype != CNMF_F32)
+    return fail(h, CNMF_EINVAL, "A->dtype must be CNMF_F64 or CNMF_F32");
+  if (A->m < 1 || A->n < 1) return fail(h, CNMF_EINVAL, "A must be non-empty (m=%lld n=%lld)", (long long)A->m, (long long)A->n);
+  if (A->m > INT32_MAX / 2 || A->n > INT32_MAX / 2)
+    return fail(h, CNMF_ENOTSUP, "dimensions above 2^30 are not supported");
+  if (A->lda < A->n) return fail(h, CNMF_EINVAL, "lda (%lld) < n (%lld)", (long long)A->lda, (long long)A->n);
+  return CNMF_OK;
+}
+
+cnmf_status check_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d) {
+  if (!d) return fail(h, CNMF_EINVAL, "sketch descriptor is NULL");
+  const int64_t mn = std::min(A->m, A->n);
+  if (d->r < 1) return fail(h, CNMF_EINVAL, "r must be >= 1 (got %d)", d->r);
+  if (d->k <= d->r) return fail(h, CNMF_EINVAL, "k must exceed r (r_ov >= 1): r=%d k=%d", d->r, d->k);
+  if (d->k > mn) return fail(h, CNMF_EINVAL, "k=%d exceeds min(m, n)=%lld", d->k, (long long)mn);
+  if (d->k > 128) return fail(h, CNMF_ENOTSUP, "k=%d > 128 is not supported", d->k);
+  if (d->q < 0) return fail(h, CNMF_EINVAL, "q must be >= 0");
+  if (d->q > 64) return fail(h, CNMF_EINVAL, "q=%d is unreasonably large (max 64)", d->q);
+  if (d->sides < 1 || d->sides > 3) return fail(h, CNMF_EINVAL, "sides must be CNMF_LEFT, CNMF_RIGHT or CNMF_BOTH");
+  if ((d->sides & CNMF_LEFT) && !d->omega_left_dev) return fail(h, CNMF_EINVAL, "omega_left_dev is NULL");
+  if ((d->sides & CNMF_RIGHT) && !d->omega_right_dev) return fail(h, CNMF_EINVAL, "omega_right_dev is NULL");
+  if (A->dtype == CNMF_F64) {
+    if (d->pass_dtype != CNMF_F64 || d->final_dtype != CNMF_F64)
+      return fail(h, CNMF_EINVAL, "an F64 input runs with pass_dtype = final_dtype = CNMF_F64");
+  } else {
+    if (d->pass_dtype == CNMF_F64 || d->final_dtype == CNMF_F64)
+      return fail(h, CNMF_EINVAL, "F64 passes need an F64 input");
+    if (d->pass_dtype != CNMF_F32 || d->final_dtype != CNMF_F32)
+      return fail(h, CNMF_ENOTSUP, "reduced-precision passes are not available in this build");
+  }
+  return CNMF_OK;
+}
+
+// -------------------------------------------------------------------------
+// Workspace layout
+// -------------------------------------------------------------------------
+template <typename T>
+struct SketchWs {
+  T* Xop = nullptr;     // n x kkmax operand for A passes
+  T* Zop = nullptr;     // m x kkmax operand for A^T passes
+  T* Y = nullptr;       // max(m, n) x kkmax pass output
+  T* Ppart = nullptr;   // splits partials
+  double* Q64 = nullptr;
+  double* Gp = nullptr;
+  double* G = nullptr;
+  double* Tinv = nullptr;
+  int* flags = nullptr;
+  double* orth_err = nullptr;
+  T* Lb = nullptr;      // m x k
+  T* RTb = nullptr;     // n x k  (R^T)
+  T* BTb = nullptr;     // n x k  (B^T)
+  T* Acb = nullptr;     // m x k
+  double* At = nullptr; // k x k
+  int gparts = 0;
+  size_t ppart_elems = 0;
+};
+
+int gram_parts(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, rows / 64)); }
+
+template <typename T>
+void layout_sketch(Arena& a, SketchWs<T>& w, int64_t m, int64_t n, int k, const std::vector<Pass>& passes,
+                   bool want_ac) {
+  int kkmax = 16;
+  size_t pmax = 0;
+  for (const Pass& p : passes) {
+    kkmax = std::max(kkmax, p.kk);
+    int64_t rows = p.dirN ? m : n;
+    int s = p.dirN ? choose_splits_n((int)m, (int)n, p.kk, sizeof(T)) : choose_splits_t((int)m, (int)n, p.kk, sizeof(T));
+    if (s > 1) pmax = std::max(pmax, (size_t)s * rows * p.kk);
+  }
+  const int64_t mx = std::max(m, n);
+  w.Xop = a.take<T>((size_t)n * kkmax);
+  w.Zop = a.take<T>((size_t)m * kkmax);
+  w.Y = a.take<T>((size_t)mx * kkmax);
+  w.ppart_elems = pmax;
+  w.Ppart = a.take<T>(std::max<size_t>(pmax, 1));
+  w.Q64 = a.take<double>((size_t)mx * kkmax);
+  w.gparts = gram_parts(mx);
+  w.Gp = a.take<double>((size_t)w.gparts * 2 * k * k);
+  w.G = a.take<double>(2 * (size_t)k * k);
+  w.Tinv = a.take<double>(2 * (size_t)k * k);
+  w.flags = a.take<int>(4);
+  w.orth_err = a.take<double>(4);
+  w.Lb = a.take<T>((size_t)m * k);
+  w.RTb = a.take<T>((size_t)n * k);
+  w.BTb = a.take<T>((size_t)n * k);
+  w.Acb = want_ac ? a.take<T>((size_t)m * k) : nullptr;
+  w.At = a.take<double>((size_t)k * k);
+}
+
+template <typename T>
+struct AdmmWs {
+  T* U = nullptr;
+  T* Lam = nullptr;
+  T* Vt = nullptr;
+  T* Phit = nullptr;
+  double* XY = nullptr;
+  double* Pp = nullptr;
+  double* Pred = nullptr;
+  unsigned* counter = nullptr;
+  int parts0 = 0, parts1 = 0;
+  double* rpart = nullptr;
+  int rparts = 0;
+};
+
+int uv_parts(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(128, (rows + 63) / 64)); }
+
+template <typename T>
+void layout_admm(Arena& a, AdmmWs<T>& w, int64_t m, int64_t n, int k, int r) {
+  w.U = a.take<T>((size_t)m * r);
+  w.Lam = a.take<T>((size_t)m * r);
+  w.Vt = a.take<T>((size_t)n * r);
+  w.Phit = a.take<T>((size_t)n * r);
+  w.XY = a.take<double>(2 * (size_t)k * r);
+  w.parts0 = uv_parts(m);
+  w.parts1 = uv_parts(n);
+  w.Pp = a.take<double>((size_t)(w.parts0 + w.parts1) * k * r);
+  w.Pred = a.take<double>(2 * (size_t)k * r);
+  w.counter = a.take<unsigned>(4);
+  w.rparts = (int)((m + 15) / 16);
+  w.rpart = a.take<double>(2 * (size_t)w.rparts);
+}
+
+cnmf_status ensure_ws(cnmf_handle* h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return CNMF_OK;
+  if (h->limit && bytes > h->limit)
+    return fail(h, CNMF_ENOMEM, "workspace of %zu bytes exceeds the handle limit of %zu", bytes, h->limit);
+  if (h->ws) {
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(h, CNMF_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  h->ws = (char*)p;
+  h->ws_bytes = bytes;
+  return CNMF_OK;
+}
+
+// -------------------------------------------------------------------------
+// Timing helpers
+// -------------------------------------------------------------------------
+struct StageTimer {
+  cnmf_handle* h;
+  explicit StageTimer(cnmf_handle* hh) : h(hh) {
+    for (int i = 0; i < 8; ++i) h->stage_ms[i] = 0.0, h->ev_used[i] = 0;
+  }
+};
+
+// -------------------------------------------------------------------------
+// Orthonormalise nh column blocks [col0 + i*k, +k) of Y (rows x kk, already
+// reduced) by CholeskyQR2; result in Q64 (same columns, FP64).
+// -------------------------------------------------------------------------
+template <typename T>
+cnmf_status orth_blocks(cnmf_handle* h, SketchWs<T>& w, const T* Y, int rows, int kk, int col0, int nh, int k) {
+  hipStream_t st = h->stream;
+  const int parts = std::min(w.gparts, std::max(1, rows / 32));
+  // pass 1: G = Y^T Y, T1, Q1 = Y T1^-1
+  HIPCHK(h, (launch_cross2<T, T>(Y, kk, col0, Y, kk, col0, k, nh, rows, k, k, w.Gp, parts, st)));
+  HIPCHK(h, launch_sum_parts(w.Gp, parts, (int64_t)nh * k * k, w.G, st));
+  HIPCHK(h, launch_chol_inv(w.G, nh, k, w.Tinv, nullptr, w.flags, st));
+  // apply writes Q64 columns col0 + h*k via an offset view
+  HIPCHK(h, (launch_apply_tinv<T>(Y + col0, rows, kk, nh, k, w.Tinv, w.Q64 + col0, kk, st)));
+  // pass 2 on Q1
+  HIPCHK(h, (launch_cross2<double, double>(w.Q64, kk, col0, w.Q64, kk, col0, k, nh, rows, k, k, w.Gp, parts, st)));
+  HIPCHK(h, launch_sum_parts(w.Gp, parts, (int64_t)nh * k * k, w.G, st));
+  HIPCHK(h, launch_chol_inv(w.G, nh, k, w.Tinv, nullptr, w.flags, st));
+  HIPCHK(h, (launch_apply_tinv<double>(w.Q64 + col0, rows, kk, nh, k, w.Tinv, w.Q64 + col0, kk, st)));
+  return CNMF_OK;
+}
+
+// Sketch driver for T = double (F64 input) or float (F32 input).
+template <typename T>
+cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, SketchWs<T>& w,
+                       const std::vector<Pass>& passes, double* stats_dev) {
+  hipStream_t st = h->stream;
+  const int m = (int)A->m, n = (int)A->n, k = d->k;
+  const T* Ap = (const T*)A->data_dev;
+  const int64_t lda = A->lda;
+  HIPCHK(h, launch_fill(w.flags, 4 * sizeof(int), st));
+
+  auto operand_for = [&](const Pass& p) -> T* { return p.dirN ? w.Xop : w.Zop; };
+  // stage the first operands (Omegas) of the chains
+  for (size_t pi = 0; pi < passes.size(); ++pi) {
+    const Pass& p = passes[pi];
+    T* op = operand_for(p);
+    bool zeroed = false;
+    for (const Block& b : p.blocks) {
+      if ((b.kind == L_RANGE || b.kind == R_RANGE) && b.step == 0) {
+        if (!zeroed) {
+          HIPCHK(h, launch_fill(op, sizeof(T) * (size_t)(p.dirN ? n : m) * p.kk, st));
+          zeroed = true;
+        }
+        const double* om = b.kind == L_RANGE ? d->omega_left_dev : d->omega_right_dev;
+        int rows = b.kind == L_RANGE ? n : m;
+        HIPCHK(h, (launch_copy2d<double, T>(om, k, op + b.col0, p.kk, rows, k, 1.0, st)));
+      }
+    }
+  }
+
+  for (size_t pi = 0; pi < passes.size(); ++pi) {
+    const Pass& p = passes[pi];
+    const int rows = p.dirN ? m : n;
+    T* op = operand_for(p);
+    int splits = p.dirN ? choose_splits_n(m, n, p.kk, sizeof(T)) : choose_splits_t(m, n, p.kk, sizeof(T));
+    T* dst = splits > 1 ? w.Ppart : w.Y;
+    if (p.dirN)
+      HIPCHK(h, launch_gemm_n<T>(Ap, lda, m, n, op, p.kk, dst, splits, st));
+    else
+      HIPCHK(h, launch_gemm_t<T>(Ap, lda, m, n, op, p.kk, dst, splits, st));
+    if (splits > 1) HIPCHK(h, launch_reduce_splits<T>(w.Ppart, splits, rows, p.kk, w.Y, st));
+
+    // orthonormalise the range blocks (contiguous)
+    int rcol0 = -1, nh = 0;
+    for (const Block& b : p.blocks)
+      if (b.kind == L_RANGE || b.kind == R_RANGE) {
+        if (rcol0 < 0) rcol0 = b.col0;
+        ++nh;
+      }
+    if (nh > 0) {
+      cnmf_status s = orth_blocks<T>(h, w, w.Y, rows, p.kk, rcol0, nh, k);
+      if (s != CNMF_OK) return s;
+    }
+    // route results
+    const Pass* nx = pi + 1 < passes.size() ? &passes[pi + 1] : nullptr;
+    T* nop = nx ? operand_for(*nx) : nullptr;
+    bool nzeroed = false;
+    auto zero_next = [&]() -> cnmf_status {
+      if (nx && !nzeroed) {
+        bool has_first = false;
+        for (const Block& b : nx->blocks)
+          if ((b.kind == L_RANGE || b.kind == R_RANGE) && b.step == 0) has_first = true;
+        if (!has_first) HIPCHK(h, launch_fill(nop, sizeof(T) * (size_t)(nx->dirN ? n : m) * nx->kk, st));
+        nzeroed = true;
+      }
+      return CNMF_OK;
+    };
+    for (const Block& b : p.blocks) {
+      if (b.kind == L_RANGE || b.kind == R_RANGE) {
+        const bool isL = b.kind == L_RANGE;
+        const bool last = b.step == 2 * d->q;
+        // slot of this chain in the next pass
+        int ncol = -1;
+        if (nx)
+          for (const Block& c : nx->blocks) {
+            if (isL && (c.kind == L_RANGE || c.kind == L_B)) ncol = c.col0;
+            if (!isL && (c.kind == R_RANGE || c.kind == R_AC)) ncol = c.col0;
+          }
+        if (ncol >= 0) {
+          cnmf_status s = zero_next();
+          if (s != CNMF_OK) return s;
+          HIPCHK(h, (launch_copy2d<double, T>(w.Q64 + b.col0, p.kk, nop + ncol, nx->kk, rows, k, 1.0, st)));
+        }
+        if (last) {
+          T* basis = isL ? w.Lb : w.RTb;
+          HIPCHK(h, (launch_copy2d<double, T>(w.Q64 + b.col0, p.kk, basis, k, rows, k, 1.0, st)));
+          if (stats_dev) {
+            HIPCHK(h, (launch_cross2<double, double>(w.Q64, p.kk, b.col0, w.Q64, p.kk, b.col0, k, 1, rows, k, k, w.Gp,
+                                                     std::min(w.gparts, std::max(1, rows / 32)), st)));
+            HIPCHK(h, launch_sum_parts(w.Gp, std::min(w.gparts, std::max(1, rows / 32)), (int64_t)k * k, w.G, st));
+            HIPCHK(h, launch_orth_error(w.G, k, w.orth_err + (isL ? 0 : 1), st));
+          }
+        }
+      } else if (b.kind == L_B) {
+        HIPCHK(h, (launch_copy2d<T, T>(w.Y + b.col0, p.kk, w.BTb, k, n, k, 1.0, st)));
+      } else if (b.kind == R_AC) {
+        HIPCHK(h, (launch_copy2d<T, T>(w.Y + b.col0, p.kk, w.Acb, k, m, k, 1.0, st)));
+      }
+    }
+  }
+  // At = L^T A R^T = B R^T = (B^T)^T R^T, a k x k product over n rows
+  if ((d->sides & CNMF_BOTH) == CNMF_BOTH) {
+    int parts = std::min(w.gparts, std::max(1, n / 32));
+    HIPCHK(h, (launch_cross2<T, T>(w.BTb, k, 0, w.RTb, k, 0, 0, 1, n, k, k, w.Gp, parts, st)));
+    HIPCHK(h, launch_sum_parts(w.Gp, parts, (int64_t)k * k, w.At, st));
+  }
+  return CNMF_OK;
+}
+
+template <typename T>
+cnmf_status write_sketch_outputs(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, SketchWs<T>& w,
+                                 const cnmf_sketch_out* o) {
+  if (!o) return CNMF_OK;
+  hipStream_t st = h->stream;
+  const int m = (int)A->m, n = (int)A->n, k = d->k;
+  const bool L = d->sides & CNMF_LEFT, R = d->sides & CNMF_RIGHT;
+  if (o->L_dev && L) HIPCHK(h, (launch_copy2d<T, T>(w.Lb, k, (T*)o->L_dev, k, m, k, 1.0, st)));
+  if (o->R_dev && R) HIPCHK(h, (launch_transpose<T, T>(w.RTb, k, (T*)o->R_dev, n, n, k, st)));
+  if (o->B_dev && L) HIPCHK(h, (launch_transpose<T, T>(w.BTb, k, (T*)o->B_dev, n, n, k, st)));
+  if (o->At_dev && L && R) HIPCHK(h, (launch_copy2d<double, T>(w.At, k, (T*)o->At_dev, k, k, k, 1.0, st)));
+  if (o->Ac_dev && R && w.Acb) HIPCHK(h, (launch_copy2d<T, T>(w.Acb, k, (T*)o->Ac_dev, k, m, k, 1.0, st)));
+  if (o->stats_dev) {
+    // stats: [0] max|L^T L - I|, [1] max|R R^T - I|, [2] breakdowns, [3] 0
+    HIPCHK(h, launch_fill(o->stats_dev, 4 * sizeof(double), st));
+    if (L) HIPCHK(h, (launch_copy2d<double, double>(w.orth_err, 1, o->stats_dev, 1, 1, 1, 1.0, st)));
+    if (R) HIPCHK(h, (launch_copy2d<double, double>(w.orth_err + 1, 1, o->stats_dev + 1, 1, 1, 1, 1.0, st)));
+    HIPCHK(h, launch_flags_to_stats(w.flags, 2, o->stats_dev + 2, st));
+  }
+  return CNMF_OK;
+}
+
+template <typename T>
+cnmf_status do_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, const cnmf_sketch_out* o,
+                      bool want_ac) {
+  std::vector<Pass> passes = plan_passes(d->k, d->q, d->sides, want_ac);
+  if (passes.empty()) return fail(h, CNMF_EINVAL, "internal: empty pass plan");
+  Arena dry(nullptr);
+  SketchWs<T> w;
+  layout_sketch<T>(dry, w, A->m, A->n, d->k, passes, want_ac);
+  cnmf_status s = ensure_ws(h, dry.off);
+  if (s != CNMF_OK) return s;
+  Arena a(h->ws);
+  layout_sketch<T>(a, w, A->m, A->n, d->k, passes, want_ac);
+  s = run_sketch<T>(h, A, d, w, passes, o ? o->stats_dev : nullptr);
+  if (s != CNMF_OK) return s;
+  return write_sketch_outputs<T>(h, A, d, w, o);
+}
+
+template <typename T>
+cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
+                         const cnmf_factorize_out* o) {
+  const cnmf_sketch_desc* sk = &d->sk;
+  const bool want_ac = d->method == CNMF_MU;
+  std::vector<Pass> passes = plan_passes(sk->k, sk->q, CNMF_BOTH, want_ac);
+  if (passes.empty()) return fail(h, CNMF_EINVAL, "internal: empty pass plan");
+  const int m = (int)A->m, n = (int)A->n, k = sk->k, r = sk->r;
+  Arena dry(nullptr);
+  SketchWs<T> w;
+  AdmmWs<T> aw;
+  layout_sketch<T>(dry, w, m, n, k, passes, want_ac);
+  layout_admm<T>(dry, aw, m, n, k, r);
+  cnmf_status s = ensure_ws(h, dry.off);
+  if (s != CNMF_OK) return s;
+  Arena a(h->ws);
+  layout_sketch<T>(a, w, m, n, k, passes, want_ac);
+  layout_admm<T>(a, aw, m, n, k, r);
+  hipStream_t st = h->stream;
+
+  s = run_sketch<T>(h, A, sk, w, passes, o->sk_out.stats_dev);
+  if (s != CNMF_OK) return s;
+
+  // state: U = U0, V^T = V0^T, Lam = Phi = 0
+  HIPCHK(h, (launch_copy2d<double, T>(d->U0_dev, r, aw.U, r, m, r, 1.0, st)));
+  HIPCHK(h, (launch_transpose<double, T>(d->V0_dev, n, aw.Vt, r, r, n, st)));
+  HIPCHK(h, launch_fill(aw.Lam, sizeof(T) * (size_t)m * r, st));
+  HIPCHK(h, launch_fill(aw.Phit, sizeof(T) * (size_t)n * r, st));
+  HIPCHK(h, launch_fill(aw.counter, 4 * sizeof(unsigned), st));
+
+  if (d->method == CNMF_ADMM) {
+    AdmmSide s0{w.Lb, k, aw.U, aw.Lam, r, m, d->lambda};
+    AdmmSide s1{w.RTb, k, aw.Vt, aw.Phit, r, n, d->phi};
+    HIPCHK(h, launch_admm_uv<T>(s0, s1, 2, aw.XY, k, r, d->xi, 0, aw.Pp, aw.parts0, aw.parts1, st));
+    for (int it = 0; it < d->iters; ++it) {
+      HIPCHK(h, launch_admm_solve<T>(aw.Pp, aw.parts0, aw.parts1, w.At, k, r, d->lambda, d->phi, it == 0, aw.XY,
+                                     aw.Pred, aw.counter, w.flags + 2, st));
+      HIPCHK(h, launch_admm_uv<T>(s0, s1, 2, aw.XY, k, r, d->xi, 1, aw.Pp, aw.parts0, aw.parts1, st));
+    }
+  } else {
+    return fail(h, CNMF_ENOTSUP, "method %d is not available in this build", d->method);
+  }
+
+  if (o->U_dev) HIPCHK(h, (launch_copy2d<T, T>(aw.U, r, (T*)o->U_dev, r, m, r, 1.0, st)));
+  if (o->V_dev) HIPCHK(h, (launch_transpose<T, T>(aw.Vt, r, (T*)o->V_dev, n, n, r, st)));
+  if (o->rel_residual_dev) {
+    HIPCHK(h, launch_residual<T>((const T*)A->data_dev, A->lda, m, n, aw.U, r, aw.Vt, r, r, aw.rpart, aw.rparts, st));
+    HIPCHK(h, launch_residual_finish(aw.rpart, aw.rparts, o->rel_residual_dev, st));
+  }
+  return write_sketch_outputs<T>(h, A, sk, w, &o->sk_out);
+}
+
+template <typename T>
+cnmf_status do_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, int64_t* K, double* score,
+                      void* B_out) {
+  std::vector<Pass> passes = plan_passes(d->k, d->q, d->sides, false);
+  const int m = (int)A->m, n = (int)A->n, k = d->k;
+  Arena dry(nullptr);
+  SketchWs<T> w;
+  layout_sketch<T>(dry, w, m, n, k, passes, false);
+  double* Bt64 = dry.take<double>((size_t)n * k);
+  const int nblk = (n + 63) / 64;
+  double* u = dry.take<double>(k);
+  double* wb = dry.take<double>(nblk);
+  int64_t* wi = dry.take<int64_t>(nblk);
+  unsigned* ctr = dry.take<unsigned>(4);
+  cnmf_status s = ensure_ws(h, dry.off);
+  if (s != CNMF_OK) return s;
+  Arena a(h->ws);
+  layout_sketch<T>(a, w, m, n, k, passes, false);
+  Bt64 = a.take<double>((size_t)n * k);
+  u = a.take<double>(k);
+  wb = a.take<double>(nblk);
+  wi = a.take<int64_t>(nblk);
+  ctr = a.take<unsigned>(4);
+  hipStream_t st = h->stream;
+  s = run_sketch<T>(h, A, d, w, passes, nullptr);
+  if (s != CNMF_OK) return s;
+  HIPCHK(h, (launch_copy2d<T, double>(w.BTb, k, Bt64, k, n, k, 1.0, st)));
+  HIPCHK(h, launch_fill(ctr, 4 * sizeof(unsigned), st));
+  for (int t = 0; t < d->r; ++t)
+    HIPCHK(h, launch_spa_step(Bt64, n, k, k, t, K, score, u, wb, wi, ctr, nblk, st));
+  if (B_out) HIPCHK(h, (launch_transpose<T, T>(w.BTb, k, (T*)B_out, n, n, k, st)));
+  return CNMF_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* cnmf_version(void) { return "cnmf-mi355x 0.1"; }
+
+const char* cnmf_status_string(cnmf_status s) {
+  switch (s) {
+    case CNMF_OK: return "ok";
+    case CNMF_EINVAL: return "invalid argument";
+    case CNMF_ENOMEM: return "out of device memory / workspace limit";
+    case CNMF_EDEVICE: return "HIP device error";
+    case CNMF_EBREAKDOWN: return "orthonormalisation breakdown";
+    case CNMF_ENOTSUP: return "not supported";
+    case CNMF_EBUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+const char* cnmf_last_error(const cnmf_handle* h) { return h ? h->err.c_str() : g_noh_err.c_str(); }
+
+cnmf_status cnmf_create(int device, void* hip_stream, size_t workspace_limit, cnmf_handle** out) {
+  if (!out) return fail(nullptr, CNMF_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return fail(nullptr, CNMF_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(nullptr, CNMF_EINVAL, "device %d out of range [0, %d)", device, ndev);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(nullptr, CNMF_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  cnmf_handle* h = new cnmf_handle();
+  h->device = device;
+  h->stream = (hipStream_t)hip_stream;
+  h->limit = workspace_limit;
+  for (int i = 0; i < 8; ++i) h->stage_ms[i] = std::numeric_limits<double>::quiet_NaN();
+  *out = h;
+  return CNMF_OK;
+}
+
+cnmf_status cnmf_destroy(cnmf_handle* h) {
+  if (!h) return CNMF_OK;
+  if (h->ws) {
+    hipStreamSynchronize(h->stream);
+    hipFree(h->ws);
+  }
+  for (int i = 0; i < 8; ++i)
+    if (h->ev[i]) hipEventDestroy(h->ev[i]);
+  delete h;
+  return CNMF_OK;
+}
+
+cnmf_status cnmf_set_timing(cnmf_handle* h, int enable) {
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  h->timing = enable != 0;
+  return CNMF_OK;
+}
+
+double cnmf_stage_ms(cnmf_handle* h, int stage) {
+  if (!h || stage < 0 || stage >= 8) return std::numeric_limits<double>::quiet_NaN();
+  return h->stage_ms[stage];
+}
+
+cnmf_status cnmf_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, cnmf_sketch_out* out) {
+  cnmf_status s = check_input(h, A);
+  if (s != CNMF_OK) return s;
+  s = check_sketch(h, A, d);
+  if (s != CNMF_OK) return s;
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  HIPCHK(h, hipSetDevice(h->device));
+  bool want_ac = out && out->Ac_dev && (d->sides & CNMF_RIGHT);
+  if (A->dtype == CNMF_F64) return do_sketch<double>(h, A, d, out, want_ac);
+  return do_sketch<float>(h, A, d, out, want_ac);
+}
+
+static cnmf_status check_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d) {
+  if (!d) return fail(h, CNMF_EINVAL, "factorize descriptor is NULL");
+  cnmf_status s = check_sketch(h, A, &d->sk);
+  if (s != CNMF_OK) return s;
+  if (d->method < CNMF_ADMM || d->method > CNMF_MU_FULL) return fail(h, CNMF_EINVAL, "unknown method %d", d->method);
+  if ((d->method == CNMF_ADMM || d->method == CNMF_MU) && d->sk.sides != CNMF_BOTH)
+    return fail(h, CNMF_EINVAL, "compressed NMF needs sides = CNMF_BOTH");
+  if (d->iters < 0) return fail(h, CNMF_EINVAL, "iters must be >= 0");
+  if (d->method == CNMF_ADMM || d->method == CNMF_ADMM_FULL) {
+    if (!(d->lambda > 0) || !(d->phi > 0) || !std::isfinite(d->lambda) || !std::isfinite(d->phi))
+      return fail(h, CNMF_EINVAL, "lambda and phi must be finite and > 0");
+    if (!(d->xi > 0) || !std::isfinite(d->xi)) return fail(h, CNMF_EINVAL, "xi must be finite and > 0");
+  }
+  if (!(d->mu_eps >= 0)) return fail(h, CNMF_EINVAL, "mu_eps must be >= 0");
+  if (!d->U0_dev || !d->V0_dev) return fail(h, CNMF_EINVAL, "U0_dev and V0_dev are required");
+  if (d->sk.r > 64) return fail(h, CNMF_ENOTSUP, "r=%d > 64 is not supported by the NMF iterations", d->sk.r);
+  return CNMF_OK;
+}
+
+cnmf_status cnmf_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
+                           cnmf_factorize_out* out) {
+  cnmf_status s = check_input(h, A);
+  if (s != CNMF_OK) return s;
+  s = check_factorize(h, A, d);
+  if (s != CNMF_OK) return s;
+  if (!out) return fail(h, CNMF_EINVAL, "out is NULL");
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  HIPCHK(h, hipSetDevice(h->device));
+  if (A->dtype == CNMF_F64) return do_factorize<double>(h, A, d, out);
+  return do_factorize<float>(h, A, d, out);
+}
+
+cnmf_status snmf_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, int64_t* K_dev,
+                        double* score_dev, void* B_dev) {
+  cnmf_status s = check_input(h, A);
+  if (s != CNMF_OK) return s;
+  s = check_sketch(h, A, d);
+  if (s != CNMF_OK) return s;
+  if (!(d->sides & CNMF_LEFT)) return fail(h, CNMF_EINVAL, "SPA runs on B = Q^T A: sides must include CNMF_LEFT");
+  if (!K_dev) return fail(h, CNMF_EINVAL, "K_dev is NULL");
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  HIPCHK(h, hipSetDevice(h->device));
+  if (A->dtype == CNMF_F64) return do_select<double>(h, A, d, K_dev, score_dev, B_dev);
+  return do_select<float>(h, A, d, K_dev, score_dev, B_dev);
+}
+
+cnmf_status cnmf_spa(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n, int64_t ldb,
+                     int32_t r, int64_t* K_dev, double* score_dev) {
+  if (!B_dev || !K_dev) return fail(h, CNMF_EINVAL, "B_dev and K_dev are required");
+  if (dtype != CNMF_F64 && dtype != CNMF_F32) return fail(h, CNMF_EINVAL, "B must be F64 or F32");
+  if (k < 1 || n < 1 || ldb < n) return fail(h, CNMF_EINVAL, "bad B shape k=%lld n=%lld ldb=%lld", (long long)k, (long long)n, (long long)ldb);
+  if (k > 128) return fail(h, CNMF_ENOTSUP, "k > 128 is not supported");
+  if (n > INT32_MAX / 2) return fail(h, CNMF_ENOTSUP, "n above 2^30 is not supported");
+  if (r < 1 || r > std::min<int64_t>(k, n)) return fail(h, CNMF_EINVAL, "r=%d must be in [1, min(k, n)]", r);
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  HIPCHK(h, hipSetDevice(h->device));
+  const int nblk = (int)((n + 63) / 64);
+  Arena dry(nullptr);
+  dry.take<double>((size_t)n * k);
+  dry.take<double>(k);
+  dry.take<double>(nblk);
+  dry.take<int64_t>(nblk);
+  dry.take<unsigned>(4);
+  cnmf_status s = ensure_ws(h, dry.off);
+  if (s != CNMF_OK) return s;
+  Arena a(h->ws);
+  double* Bt64 = a.take<double>((size_t)n * k);
+  double* u = a.take<double>(k);
+  double* wb = a.take<double>(nblk);
+  int64_t* wi = a.take<int64_t>(nblk);
+  unsigned* ctr = a.take<unsigned>(4);
+  hipStream_t st = h->stream;
+  if (dtype == CNMF_F64)
+    HIPCHK(h, (launch_transpose<double, double>((const double*)B_dev, ldb, Bt64, k, (int)k, (int)n, st)));
+  else
+    HIPCHK(h, (launch_transpose<float, double>((const float*)B_dev, ldb, Bt64, k, (int)k, (int)n, st)));
+  HIPCHK(h, launch_fill(ctr, 4 * sizeof(unsigned), st));
+  for (int t = 0; t < r; ++t)
+    HIPCHK(h, launch_spa_step(Bt64, (int)n, (int)k, (int)k, t, K_dev, score_dev, u, wb, wi, ctr, nblk, st));
+  return CNMF_OK;
+}
+
+cnmf_status cnmf_range_product(cnmf_handle* h, const cnmf_input* A, int trans, const void* X_dev, int32_t kx,
+                               void* Y_dev) {
+  cnmf_status s = check_input(h, A);
+  if (s != CNMF_OK) return s;
+  if (trans != 0 && trans != 1) return fail(h, CNMF_EINVAL, "trans must be 0 or 1");
+  if (!X_dev || !Y_dev) return fail(h, CNMF_EINVAL, "X_dev and Y_dev are required");
+  if (kx < 1 || kx > 128) return fail(h, CNMF_EINVAL, "kx=%d must be in [1, 128]", kx);
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  HIPCHK(h, hipSetDevice(h->device));
+  const int m = (int)A->m, n = (int)A->n, kk = ru16(kx);
+  const int rows_in = trans ? m : n, rows_out = trans ? n : m;
+  const size_t es = A->dtype == CNMF_F64 ? 8 : 4;
+  const int splits = trans ? choose_splits_t(m, n, kk, (int)es) : choose_splits_n(m, n, kk, (int)es);
+  Arena dry(nullptr);
+  dry.take<char>((size_t)rows_in * kk * es);
+  dry.take<char>((size_t)rows_out * kk * es);
+  dry.take<char>((size_t)std::max(splits, 1) * rows_out * kk * es);
+  s = ensure_ws(h, dry.off);
+  if (s != CNMF_OK) return s;
+  Arena a(h->ws);
+  hipStream_t st = h->stream;
+  auto run = [&](auto tag) -> cnmf_status {
+    typedef decltype(tag) T;
+    T* Xp = a.take<T>((size_t)rows_in * kk);
+    T* Yp = a.take<T>((size_t)rows_out * kk);
+    T* Pp = a.take<T>((size_t)std::max(splits, 1) * rows_out * kk);
+    HIPCHK(h, launch_fill(Xp, sizeof(T) * (size_t)rows_in * kk, st));
+    HIPCHK(h, (launch_copy2d<T, T>((const T*)X_dev, kx, Xp, kk, rows_in, kx, 1.0, st)));
+    T* dst = splits > 1 ? Pp : Yp;
+    if (trans)
+      HIPCHK(h, launch_gemm_t<T>((const T*)A->data_dev, A->lda, m, n, Xp, kk, dst, splits, st));
+    else
+      HIPCHK(h, launch_gemm_n<T>((const T*)A->data_dev, A->lda, m, n, Xp, kk, dst, splits, st));
+    if (splits > 1) HIPCHK(h, launch_reduce_splits<T>(Pp, splits, rows_out, kk, Yp, st));
+    HIPCHK(h, (launch_copy2d<T, T>(Yp, kk, (T*)Y_dev, kx, rows_out, kx, 1.0, st)));
+    return CNMF_OK;
+  };
+  if (A->dtype == CNMF_F64) return run(double{});
+  return run(float{});
+}
+
+cnmf_status cnmf_workspace_bytes(int64_t m, int64_t n, const cnmf_factorize_desc* d, size_t* bytes) {
+  if (!d || !bytes) return fail(nullptr, CNMF_EINVAL, "descriptor and bytes are required");
+  if (m < 1 || n < 1) return fail(nullptr, CNMF_EINVAL, "m and n must be >= 1");
+  const int k = d->sk.k, r = d->sk.r;
+  if (r < 1 || k <= r || k > std::min<int64_t>(m, n) || k > 128)
+    return fail(nullptr, CNMF_EINVAL, "need 1 <= r < k <= min(m, n), k <= 128");
+  const bool f64 = d->sk.pass_dtype == CNMF_F64;
+  const bool want_ac = d->method == CNMF_MU;
+  std::vector<Pass> passes = plan_passes(k, d->sk.q, d->sk.sides ? d->sk.sides : CNMF_BOTH, want_ac);
+  Arena dry(nullptr);
+  if (f64) {
+    SketchWs<double> w;
+    AdmmWs<double> aw;
+    layout_sketch<double>(dry, w, m, n, k, passes, want_ac);
+    if (d->iters > 0) layout_admm<double>(dry, aw, m, n, k, r);
+  } else {
+    SketchWs<float> w;
+    AdmmWs<float> aw;
+    layout_sketch<float>(dry, w, m, n, k, passes, want_ac);
+    if (d->iters > 0) layout_admm<float>(dry, aw, m, n, k, r);
+  }
+  *bytes = dry.off;
+  return CNMF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports
+every symbol the header declares, and rejects invalid arguments before any
+device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1505_04650_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "cnmf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:cnmf|snmf)_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libcnmf.so is not built (run python -m paper_1505_04650_amd.build)")
+    return L.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = header_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(syms) == sorted(L.EXPORTED)
+
+
+def test_version_and_status_strings(lib):
+    assert lib.cnmf_version().startswith(b"cnmf-mi355x")
+    assert lib.cnmf_status_string(L.CNMF_EINVAL) == b"invalid argument"
+
+
+def _desc(r=10, k=20, q=2, sides=L.CNMF_BOTH, method=L.CNMF_ADMM, iters=10, prec=L.CNMF_F32):
+    sk = L.cnmf_sketch_desc(r, k, q, sides, prec, prec, C.c_void_p(16), C.c_void_p(16))
+    return L.cnmf_factorize_desc(sk, method, iters, 1.0, 1.0, 1.0, 0.0, C.c_void_p(16), C.c_void_p(16))
+
+
+def test_workspace_bytes_is_host_only_and_grows(lib):
+    out = C.c_size_t()
+    d = _desc()
+    assert lib.cnmf_workspace_bytes(2000, 1000, C.byref(d), C.byref(out)) == L.CNMF_OK
+    small = out.value
+    assert lib.cnmf_workspace_bytes(20000, 5000, C.byref(d), C.byref(out)) == L.CNMF_OK
+    assert out.value > small > 0
+
+
+@pytest.mark.parametrize("r,k,m,n", [(0, 5, 100, 100), (10, 10, 100, 100), (10, 200, 1000, 1000),
+                                     (10, 20, 100, 15)])
+def test_workspace_bytes_rejects_bad_shapes(lib, r, k, m, n):
+    out = C.c_size_t()
+    d = _desc(r=r, k=k)
+    assert lib.cnmf_workspace_bytes(m, n, C.byref(d), C.byref(out)) == L.CNMF_EINVAL
+    assert len(lib.cnmf_last_error(None)) > 0
+
+
+def test_calls_without_handle_or_data_fail_cleanly(lib):
+    A = L.cnmf_input(C.c_void_p(0), L.CNMF_F32, 100, 50, 50)
+    sk = L.cnmf_sketch_desc(5, 10, 1, L.CNMF_BOTH, L.CNMF_F32, L.CNMF_F32, None, None)
+    out = L.cnmf_sketch_out()
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL
+    A.data_dev = C.c_void_p(16)
+    A.lda = 40
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL
+    assert b"lda" in lib.cnmf_last_error(None)
+    A.lda = 50
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL  # omega NULL
+    sk.omega_left_dev = C.c_void_p(16)
+    sk.omega_right_dev = C.c_void_p(16)
+    sk.k = 51
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL  # k > min(m, n)
+    sk.k = 10
+    sk.pass_dtype = L.CNMF_F64
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL  # F64 pass, F32 input
+    sk.pass_dtype = L.CNMF_F32
+    # everything valid but no handle
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL
+    assert b"handle" in lib.cnmf_last_error(None)
+
+
+def test_factorize_parameter_checks(lib):
+    A = L.cnmf_input(C.c_void_p(16), L.CNMF_F32, 100, 50, 50)
+    out = L.cnmf_factorize_out()
+    d = _desc(r=5, k=10)
+    d.lambda_ = 0.0
+    assert lib.cnmf_factorize(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
+    d.lambda_ = 1.0
+    d.sk.sides = L.CNMF_LEFT
+    assert lib.cnmf_factorize(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
+    d.sk.sides = L.CNMF_BOTH
+    d.iters = -1
+    assert lib.cnmf_factorize(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
+
+
+def test_python_binding_fails_loudly_without_library(tmp_path):
+    with pytest.raises(FileNotFoundError):
+        L._lib_backup = L._lib
+        try:
+            L._lib = None
+            L.load(str(tmp_path / "missing.so"))
+        finally:
+            L._lib = L._lib_backup

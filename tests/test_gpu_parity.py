@@ -1,0 +1,194 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances: FP64 paths 1e-10 relative (Frobenius); FP32 paths are judged
+by their relative-residual gap to the oracle (<= 1e-3) plus orthonormality
+and subspace angles; SPA indices are compared exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cnmf_oracle as O
+from paper_1505_04650_amd import workloads as WL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1505_04650_amd import api  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().double().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def sin_max_angle(Q1, Q2):
+    """sin of the largest principal angle between span(Q1) and span(Q2)."""
+    s = np.linalg.svd(Q1.T @ Q2, compute_uv=False)
+    return math.sqrt(max(0.0, 1.0 - float(s.min()) ** 2))
+
+
+# --------------------------------------------------------------------------
+# the dominant kernel: one streaming pass
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", [(1037, 523, 21), (64, 64, 16), (3001, 2999, 128), (257, 4099, 37), (5, 7, 3)])
+def test_range_product_matches_matmul(dtype, shape):
+    m, n, kx = shape
+    g = np.random.default_rng(m + n + kx)
+    A = g.standard_normal((m, n))
+    X = g.standard_normal((n, kx))
+    Z = g.standard_normal((m, kx))
+    Ad = dev(A, dtype)
+    Y = host(api.range_product(Ad, dev(X, dtype)))
+    W = host(api.range_product(Ad, dev(Z, dtype), trans=True))
+    tol = 1e-13 if dtype == torch.float64 else 2e-6
+    # reference products in FP64 on the same (rounded) inputs
+    Ar = host(Ad)
+    Xr = host(dev(X, dtype))
+    Zr = host(dev(Z, dtype))
+    assert rel(Y, Ar @ Xr) < tol
+    assert rel(W, Ar.T @ Zr) < tol
+
+
+def test_range_product_padded_lda():
+    g = np.random.default_rng(5)
+    big = dev(g.standard_normal((300, 260)), torch.float32)
+    A = big[:, :250]  # lda = 260 (row-major view)
+    X = dev(g.standard_normal((250, 40)), torch.float32)
+    Y = host(api.range_product(A, X))
+    assert rel(Y, host(A) @ host(X)) < 2e-6
+
+
+# --------------------------------------------------------------------------
+# FP64 path at the 1000 x 500 workload: 1e-10 against the oracle
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c1():
+    w = WL.WORKLOADS["plain_fp64_1000x500"]
+    inp = WL.make_inputs(w)
+    sk = O.sketch(inp["A"], inp["Omega_L"], inp["Omega_R"], w.q)
+    lam = float(np.linalg.svd(sk["At"], compute_uv=False)[w.r - 1])
+    adm = O.admm(sk["At"], sk["L"], sk["R"], inp["U1"], inp["V1"], lam, lam, 1.0, w.iters)
+    res = O.rel_residual(inp["A"], adm["U"], adm["V"])
+    return w, inp, sk, lam, adm, res
+
+
+def test_sketch_fp64_parity(c1):
+    w, inp, sk, *_ = c1
+    out = api.sketch(dev(inp["A"]), w.r, w.k, w.q, dev(inp["Omega_L"]), dev(inp["Omega_R"]), want_ac=True)
+    for name in ("L", "R", "B", "At", "Ac"):
+        got = host(getattr(out, name))
+        assert rel(got, sk[name]) < 1e-10, name
+    st = host(out.stats)
+    assert st[0] < 1e-13 and st[1] < 1e-13 and st[2] == 0
+
+
+def test_factorize_admm_fp64_parity(c1):
+    w, inp, sk, lam, adm, res = c1
+    f = api.factorize(dev(inp["A"]), w.r, w.k, w.q, dev(inp["U1"]), dev(inp["V1"]), dev(inp["Omega_L"]),
+                      dev(inp["Omega_R"]), method="admm", iters=w.iters, lam=lam, phi=lam)
+    U, V = host(f.U), host(f.V)
+    assert rel(U, adm["U"]) < 1e-10
+    assert rel(V, adm["V"]) < 1e-10
+    assert abs(float(host(f.rel_residual)[0]) - res) <= 1e-10 * res
+
+
+@pytest.mark.parametrize("sides", ["left", "right"])
+@pytest.mark.parametrize("q", [0, 1, 3])
+def test_sketch_one_sided_ragged_fp64(sides, q):
+    g = np.random.default_rng(100 + q)
+    m, n, r, k = 613, 389, 7, 19
+    A = g.random((m, r)) @ g.random((r, n)) + np.abs(0.01 * g.standard_normal((m, n)))
+    oml, omr = g.standard_normal((n, k)), g.standard_normal((m, k))
+    out = api.sketch(dev(A), r, k, q, dev(oml), dev(omr), sides=sides)
+    if sides == "left":
+        ref = O.sketch(A, oml, None, q)
+        assert rel(host(out.L), ref["L"]) < 1e-10
+        assert rel(host(out.B), ref["B"]) < 1e-10
+    else:
+        Rref = O.range_finder(A.T, omr, q).T
+        assert rel(host(out.R), Rref) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# FP32 path (the 20000 x 5000 workload's recipe at reduced size, and full)
+# --------------------------------------------------------------------------
+
+def _fp32_case(m, n, iters):
+    w = WL.WORKLOADS["nmf_fp32_20000x5000"]
+    inp = WL.make_inputs(w, m=m, n=n)
+    A64 = inp["A"].astype(np.float64)            # the FP32-rounded values
+    sk = O.sketch(A64, inp["Omega_L"], inp["Omega_R"], w.q)
+    lam = float(np.linalg.svd(sk["At"], compute_uv=False)[w.r - 1])
+    return w, inp, A64, sk, lam
+
+
+def test_factorize_admm_fp32_reduced_size():
+    w, inp, A64, sk, lam = _fp32_case(4000, 1500, 60)
+    iters = 60
+    adm = O.admm(sk["At"], sk["L"], sk["R"], inp["U1"], inp["V1"], lam, lam, 1.0, iters)
+    res_o = O.rel_residual(A64, adm["U"], adm["V"])
+    Ad = dev(inp["A"], torch.float32)
+    f = api.factorize(Ad, w.r, w.k, w.q, dev(inp["U1"]), dev(inp["V1"]), dev(inp["Omega_L"]), dev(inp["Omega_R"]),
+                      iters=iters, lam=lam, phi=lam, want_sketch=True)
+    Lg = host(f.sketch.L)
+    assert np.abs(Lg.T @ Lg - np.eye(w.k)).max() < 1e-5
+    assert sin_max_angle(Lg[:, : w.r], sk["L"][:, : w.r]) < 1e-3
+    res_g = float(host(f.rel_residual)[0])
+    assert abs(res_g - res_o) <= 1e-3
+    # the residual is computed in FP64 from the GPU factors
+    assert abs(res_g - O.rel_residual(A64, host(f.U), host(f.V))) < 1e-6
+
+
+# --------------------------------------------------------------------------
+# SPA (Alg. SNMF): indices bit-exact
+# --------------------------------------------------------------------------
+
+def test_spa_on_given_matrix_is_exact():
+    g = np.random.default_rng(7)
+    B = g.standard_normal((30, 20011))
+    K, sc = api.spa(dev(B), 20, want_scores=True)
+    Kref, gaps = O.spa(B, 20, return_gaps=True)
+    assert min(gaps) > 1e-9
+    assert host(K).astype(np.int64).tolist() == Kref
+
+
+def test_select_separable_recovers_planted_fp64():
+    A, planted = WL.separable_matrix(700, 6000, 12, 1e-4, seed=9)
+    g = np.random.default_rng(10)
+    om = g.standard_normal((6000, 22))
+    K, _, B = api.select(dev(A), 12, 22, 2, dev(om), want_B=True)
+    Kg = host(K).astype(np.int64).tolist()
+    Bref = O.sketch(A, om, None, 2)["B"]
+    assert rel(host(B), Bref) < 1e-10
+    assert Kg == O.spa(Bref, 12)
+    assert sorted(Kg) == list(planted)
+
+
+def test_select_separable_fp32_two_sided():
+    A, planted = WL.separable_matrix(1200, 9000, 15, 1e-3, seed=11)
+    g = np.random.default_rng(12)
+    om, omr = g.standard_normal((9000, 25)), g.standard_normal((1200, 25))
+    Ad = dev(A, torch.float32)
+    K, _, B = api.select(Ad, 15, 25, 2, dev(om), dev(omr), sides="both", want_B=True)
+    Kg = host(K).astype(np.int64).tolist()
+    assert sorted(Kg) == list(planted)
+    # same decision on the GPU's own B taken by the oracle's SPA
+    assert Kg == O.spa(host(B), 15)
