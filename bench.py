@@ -1,0 +1,171 @@
+"""Benchmark of the compressed-NMF hot path on one MI355X.
+
+A step is one cnmf_factorize call on the FP32 20000 x 5000 workload
+(A = W H + |N(0, 0.05)|, r = 50, k = 60, q = 4, two-sided structured
+compression, 200 compressed-ADMM iterations, FP64 relative residual), with
+A, the test matrices and the initial factors resident in HBM before the
+clock starts.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1505_04650_amd import workloads as WL  # noqa: E402
+
+METRIC = "sketch TFLOP/s + NMF solves/s at stated rel. residual; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(inp, w, lam, budget_s=15.0):
+    """The FP64 oracle, as it stands, on the host: full solves of the same
+    workload (sketch + 200 ADMM iterations + residual) until ~budget_s."""
+    from oracle import cnmf_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count() or 1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    A64 = inp["A"].astype(np.float64)
+    done, t0, res = 0, time.perf_counter(), None
+    while True:
+        sk = O.sketch(A64, inp["Omega_L"], inp["Omega_R"], w.q)
+        adm = O.admm(sk["At"], sk["L"], sk["R"], inp["U1"], inp["V1"], lam, lam, 1.0, w.iters)
+        res = O.rel_residual(A64, adm["U"], adm["V"])
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or el / done * (done + 1) > 2.5 * budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} full solve(s) of the same 20000x5000 workload (FP64 NumPy, "
+                      f"sketch q=4 + {w.iters} ADMM iterations + residual) in {el:.1f} s"}, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="nmf_fp32_20000x5000")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes on "
+              "sharding); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1505_04650_amd import api
+
+    w = WL.WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"workload {w.name}: generating inputs")
+    inp = WL.make_inputs(w)
+    A = torch.as_tensor(inp["A"], device=dev)
+    t = lambda x: torch.as_tensor(x, dtype=torch.float64, device=dev)
+    oml, omr, U1, V1 = t(inp["Omega_L"]), t(inp["Omega_R"]), t(inp["U1"]), t(inp["V1"])
+    h = api.default_handle()
+
+    # penalty: sigma_r of the compressed core (fixed before timing)
+    sk = api.sketch(A, w.r, w.k, w.q, oml, omr)
+    torch.cuda.synchronize()
+    lam = float(np.linalg.svd(sk.At.double().cpu().numpy(), compute_uv=False)[w.r - 1])
+    log(f"lambda = phi = sigma_r(At) = {lam:.6g}")
+
+    def step():
+        return api.factorize(A, w.r, w.k, w.q, U1, V1, oml, omr, method="admm", iters=w.iters, lam=lam, phi=lam,
+                             handle=h)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    h.set_timing(True)
+    st = h.stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    agg = {}
+    torch.cuda.synchronize()
+    ev0.record(st)
+    t0 = time.perf_counter()
+    f = None
+    for _ in range(args.steps):
+        f = step()
+        for name, (ms, fl, n) in h.stages().items():  # waits on the step's own events
+            a = agg.setdefault(name, [0.0, 0.0, 0])
+            if not math.isnan(ms):
+                a[0] += ms
+            a[1] += fl
+            a[2] += n
+    ev1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    h.set_timing(False)
+    ms_per_step = gpu_ms / args.steps
+    res_gpu = float(f.rel_residual.item())
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f} ms/step)")
+
+    # sketch alone (TFLOP/s on the algorithmic 2 m n k x 19 flops)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        api.sketch(A, w.r, w.k, w.q, oml, omr, handle=h)
+    e1.record(st)
+    torch.cuda.synchronize()
+    sketch_ms = e0.elapsed_time(e1) / args.steps
+    sketch_flops = 2.0 * w.m * w.n * w.k * (2 * (1 + 2 * w.q) + 1)
+    sketch_tflops = sketch_flops / (sketch_ms * 1e-3) / 1e12
+
+    stages = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[2] / args.steps,
+                  "gflop_per_step": v[1] / args.steps / 1e9} for k, v in agg.items() if v[2]}
+    # dominant kernel: the range-finder pass kernels (A X and A^T Z launches)
+    pn, pt = agg.get("pass_AX", [0, 0, 0]), agg.get("pass_ATZ", [0, 0, 0])
+    pass_ms = pn[0] + pt[0]
+    pass_fl = pn[1] + pt[1]
+    pass_n = pn[2] + pt[2]
+    achieved = pass_fl / (pass_ms * 1e-3) / 1e12 if pass_ms > 0 else None
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": (achieved / FP32_PEAK_TFLOPS) if achieved else None, "traffic": None,
+                "kernel": "gemm_n_kernel + gemm_t_kernel (range-finder passes, FP32 16x16x4 MFMA)",
+                "avg_launch_ms": pass_ms / pass_n if pass_n else None,
+                "gflop_per_launch": pass_fl / pass_n / 1e9 if pass_n else None}
+
+    out = {"metric": METRIC, "value": 1000.0 / ms_per_step, "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": w.name, "m": w.m, "n": w.n, "r": w.r, "k": w.k, "q": w.q, "iters": w.iters,
+                      "method": "compressed ADMM (two-sided)", "lambda": lam, "rel_residual": res_gpu},
+           "sketch_tflops": sketch_tflops, "sketch_ms": sketch_ms, "stages": stages, "roofline": roofline}
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline: running the FP64 oracle on the host")
+        cb, res_o = cpu_baseline(inp, w, lam)
+        out["cpu_baseline"] = cb
+        out["config"]["rel_residual_oracle"] = res_o
+        out["config"]["rel_residual_gap"] = abs(res_gpu - res_o)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

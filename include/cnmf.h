@@ -196,13 +196,22 @@ cnmf_status cnmf_range_product(cnmf_handle* h, const cnmf_input* A, int trans, c
  * handle or GPU required. */
 cnmf_status cnmf_workspace_bytes(int64_t m, int64_t n, const cnmf_factorize_desc* d, size_t* bytes);
 
-/* Per-stage device time of the last call on `h`, in milliseconds, measured
- * with HIP events when timing is enabled (cnmf_set_timing).  stage:
- *   0 convert, 1 range passes, 2 orthonormalisation, 3 small sketches,
- *   4 iterations, 5 residual, 6 SPA.  Returns NaN when not measured.
- * Reading it synchronises the handle's stream. */
+/* Per-stage accounting of the last call on `h`.  Stages:
+ *   0 precision conversion of A, 1 A X range passes, 2 A^T Z range passes,
+ *   3 orthonormalisation and small sketches, 4 NMF iterations, 5 residual,
+ *   6 SPA.
+ * cnmf_stage_ms: device time in milliseconds from HIP events recorded on the
+ *   handle's stream around each span (only while timing is enabled with
+ *   cnmf_set_timing; NaN otherwise or if the stage did not run).  Reading it
+ *   waits for the events of the last call.
+ * cnmf_stage_flops: algorithmic flop count of the stage (for the range passes
+ *   2 m n k per chain block, padding excluded).
+ * cnmf_stage_launches: number of spans (for the range passes: kernel
+ *   launches). */
 cnmf_status cnmf_set_timing(cnmf_handle* h, int enable);
 double cnmf_stage_ms(cnmf_handle* h, int stage);
+double cnmf_stage_flops(cnmf_handle* h, int stage);
+int cnmf_stage_launches(cnmf_handle* h, int stage);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "CNMF_OK", -1: "CNMF_EINVAL", -2: "CNMF_ENOMEM", -3: "CNMF_ED
 EXPORTED = [
     "cnmf_create", "cnmf_destroy", "cnmf_last_error", "cnmf_status_string", "cnmf_version",
     "cnmf_sketch", "cnmf_factorize", "snmf_select", "cnmf_spa", "cnmf_workspace_bytes",
-    "cnmf_set_timing", "cnmf_stage_ms", "cnmf_range_product",
+    "cnmf_set_timing", "cnmf_stage_ms", "cnmf_range_product", "cnmf_stage_flops", "cnmf_stage_launches",
 ]
 
 
@@ -100,6 +100,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.cnmf_set_timing.restype = st
     lib.cnmf_stage_ms.argtypes = [vp, C.c_int]
     lib.cnmf_stage_ms.restype = C.c_double
+    lib.cnmf_stage_flops.argtypes = [vp, C.c_int]
+    lib.cnmf_stage_flops.restype = C.c_double
+    lib.cnmf_stage_launches.argtypes = [vp, C.c_int]
+    lib.cnmf_stage_launches.restype = C.c_int
     _lib = lib
     return lib
 

@@ -56,6 +56,16 @@ class Handle:
     def set_timing(self, enable: bool):
         L.check(self._lib.cnmf_set_timing(self._h, int(enable)), self._h)
 
+    STAGES = ("convert", "pass_AX", "pass_ATZ", "orth", "iterations", "residual", "spa")
+
+    def stages(self):
+        """Per-stage (ms, flops, launches) of the last call (ms needs timing on)."""
+        out = {}
+        for i, name in enumerate(self.STAGES):
+            out[name] = (self._lib.cnmf_stage_ms(self._h, i), self._lib.cnmf_stage_flops(self._h, i),
+                         self._lib.cnmf_stage_launches(self._h, i))
+        return out
+
 
 _handles: dict = {}
 

@@ -61,11 +61,14 @@ hipError_t launch_cross2(const TX* X, int ldx, int x0, const TY* Y, int ldy, int
                          int ka, int kb, double* Cp, int parts, hipStream_t st);
 // out[e] = sum_p in[p * count + e] in the order p = 0, 1, ...
 hipError_t launch_sum_parts(const double* in, int parts, int64_t count, double* out, hipStream_t st);
-// For each half h: G = T^T T (Cholesky, T upper with positive diagonal),
-// Tinv = T^-1.  A pivot <= tol * max diag(G) counts as a breakdown: flags[h]
-// is incremented and the pivot is repaired.
-hipError_t launch_chol_inv(const double* G, int nh, int kh, double* Tinv, double* Tacc,
-                           int* flags, hipStream_t st);
+// For each half h: G_h = fixed-order sum of the Gram partials, then
+// G_h = T^T T (Cholesky, T upper with positive diagonal).  Output per half
+// (kh x kh): for kh <= 64 the factor T itself, otherwise Tinv = T^-1; the
+// matching launch_apply_tinv consumes either form.  A
+// pivot <= 1e-20 max diag(G_h) counts as a breakdown in flags[h] and is
+// repaired.  counters: nh zero-initialised words, left zero on return.
+hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double* G, double* Tinv, int* flags,
+                            unsigned* counters, hipStream_t st);
 // Q64[:, h*kh + c] = sum_{l <= c} Y[:, h*kh + l] Tinv_h[l][c] (FP64), h < nh.
 // In place (Q64 == Y) is allowed.
 template <typename TY>

@@ -12,269 +12,348 @@
 // matrices are read once per iteration.  admm_solve_kernel reduces those
 // partials in a fixed order and does the r x r solves by Cholesky in FP64.
 #include "cnmf_internal.hpp"
+#include "small_dense.hpp"
 
 namespace cnmf {
 
-constexpr int kUvRows = 32;   // rows staged per sweep
-constexpr int kMaxK16 = 8;    // k <= 128
-constexpr int kMaxR16 = 4;    // r <= 64
+// MFMA helpers (16x16x4; see k_gemm.hip for the measured result layout).
+template <typename T>
+struct Mf;
+template <>
+struct Mf<float> {
+  typedef floatx4 acc_t;
+  static __device__ __forceinline__ void mma(float a, float b, floatx4& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int i) { return 4 * g + i; }
+};
+template <>
+struct Mf<double> {
+  typedef doublex4 acc_t;
+  static __device__ __forceinline__ void mma(double a, double b, doublex4& c) {
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int i) { return g + 4 * i; }
+};
 
 // mode 0: only partials of basis^T (pen F - M)  (initialisation)
 // mode 1: update F, M, then partials
-template <typename T>
+// Per sweep of CH rows: the basis rows go to LDS; LX = basis * C on the
+// MFMA (wave w owns rows 16w..16w+15); the row update is applied in the
+// MFMA's result layout; then the k x r partial basis^T (pen F - M) is
+// accumulated on the MFMA in registers across sweeps (wave w owns M-blocks
+// w and w + 4).  KP, RP: k, r padded to 16.
+template <typename T, int CH>
 __global__ __launch_bounds__(256) void admm_uv_kernel(AdmmSide s0, AdmmSide s1, int nblk0,
                                                       const double* __restrict__ XY, int k, int r,
                                                       double xi, int mode, double* __restrict__ Pp,
                                                       int rows_per_blk0, int rows_per_blk1) {
+  typedef typename Mf<T>::acc_t acc_t;
   const bool side1 = (int)blockIdx.x >= nblk0;
   const AdmmSide S = side1 ? s1 : s0;
   const int blk = side1 ? blockIdx.x - nblk0 : blockIdx.x;
   const int rpb = side1 ? rows_per_blk1 : rows_per_blk0;
   const double* C = XY + (side1 ? (int64_t)k * r : 0);
   double* out = Pp + (int64_t)blockIdx.x * k * r;   // partial slot = global block index
-  const T* Bm = (const T*)S.Bm;
-  T* F = (T*)S.F;
-  T* M = (T*)S.M;
+  const T* __restrict__ Bm = (const T*)S.Bm;
+  T* __restrict__ F = (T*)S.F;
+  T* __restrict__ M = (T*)S.M;
   const T pen = (T)S.pen;
   const T inv_pen = (T)(1.0 / S.pen);
   const T xpen = (T)(xi * S.pen);
+  const int KP16 = (k + 15) >> 4, RP16 = (r + 15) >> 4;
+  const int KP = KP16 * 16, RP = RP16 * 16;
+  const int ldb = KP + 1, ldc = RP + 1;
 
-  __shared__ T cs[128 * 64];             // C: k x r
-  __shared__ T bs[kUvRows][129];         // basis rows
-  __shared__ T ws[kUvRows][65];          // pen F - M for the staged rows
+  extern __shared__ char smraw[];
+  T* cs = reinterpret_cast<T*>(smraw);   // KP x ldc
+  T* bs = cs + KP * ldc;                 // CH x ldb
+  T* ws = bs + CH * ldb;                 // CH x ldc
   const int tid = threadIdx.x;
-  for (int e = tid; e < k * r; e += 256) cs[e] = (T)C[e];
-  const int ta = tid >> 4, tb = tid & 15;
-  double acc[kMaxK16][kMaxR16];
+  const int lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, g = lane >> 4;
+  for (int e = tid; e < KP * RP; e += 256) {
+    int a = e / RP, c = e - a * RP;
+    cs[a * ldc + c] = (a < k && c < r) ? (T)C[a * r + c] : T(0);
+  }
+  acc_t pacc[2][4];
 #pragma unroll
-  for (int i = 0; i < kMaxK16; ++i)
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int j = 0; j < kMaxR16; ++j) acc[i][j] = 0.0;
+    for (int v = 0; v < 4; ++v) pacc[u][v] = acc_t{0, 0, 0, 0};
 
   const int i0 = blk * rpb;
   const int i1 = min(S.rows, i0 + rpb);
-  __syncthreads();
-  for (int base = i0; base < i1; base += kUvRows) {
-    const int nr = min(kUvRows, i1 - base);
-    for (int e = tid; e < kUvRows * k; e += 256) {
-      int rr = e / k, a = e - rr * k;
-      bs[rr][a] = rr < nr ? Bm[(int64_t)(base + rr) * S.ldb + a] : T(0);
+  for (int base = i0; base < i1; base += CH) {
+    const int nr = min(CH, i1 - base);
+    // prefetch this lane's F / M entries of the sweep (MFMA result layout)
+    T fv[CH / 64 > 0 ? CH / 64 : 1][4][4], mv[CH / 64 > 0 ? CH / 64 : 1][4][4];
+#pragma unroll
+    for (int q = 0; q < (CH / 64 > 0 ? CH / 64 : 1); ++q) {
+      const int rg = w + 4 * q;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * rg + Mf<T>::out_row(g, i), col = 16 * cb + lr;
+          const bool ok = rg < CH / 16 && cb < RP16 && row < nr && col < r;
+          const int64_t off = (int64_t)(base + row) * S.ldf + col;
+          fv[q][cb][i] = ok ? F[off] : T(0);
+          mv[q][cb][i] = ok ? M[off] : T(0);
+        }
     }
     __syncthreads();
-    for (int e = tid; e < nr * r; e += 256) {
-      int rr = e / r, c = e - rr * r;
-      int64_t off = (int64_t)(base + rr) * S.ldf + c;
-      T f = F[off];
-      T mu = M[off];
-      if (mode == 1) {
-        T lx = 0;
-        for (int a = 0; a < k; ++a) lx = fma(bs[rr][a], cs[a * r + c], lx);
-        T t = lx + mu * inv_pen;
-        f = t > T(0) ? t : T(0);
-        mu = mu + xpen * (lx - f);
-        F[off] = f;
-        M[off] = mu;
-      }
-      ws[rr][c] = pen * f - mu;
+    for (int e = tid; e < CH * KP; e += 256) {
+      int rr = e / KP, a = e - rr * KP;
+      bs[rr * ldb + a] = (rr < nr && a < k) ? Bm[(int64_t)(base + rr) * S.ldb + a] : T(0);
     }
     __syncthreads();
-    for (int rr = 0; rr < nr; ++rr) {
+    // ---- LX and the row update (waves own 16-row groups) ----
 #pragma unroll
-      for (int i = 0; i < kMaxK16; ++i) {
-        int a = ta + 16 * i;
-        double b = a < k ? (double)bs[rr][a] : 0.0;
+    for (int q = 0; q < (CH / 64 > 0 ? CH / 64 : 1); ++q) {
+      const int rg = w + 4 * q;
+      if (rg >= CH / 16) continue;
 #pragma unroll
-        for (int j = 0; j < kMaxR16; ++j) {
-          int c = tb + 16 * j;
-          double w = c < r ? (double)ws[rr][c] : 0.0;
-          acc[i][j] = fma(b, w, acc[i][j]);
+      for (int cb = 0; cb < 4; ++cb) {
+        if (cb >= RP16) continue;
+        acc_t acc = acc_t{0, 0, 0, 0};
+        if (mode == 1) {
+          const T* ap = bs + (16 * rg + lr) * ldb + g;
+          const T* bp = cs + g * ldc + 16 * cb + lr;
+          for (int ks = 0; ks < KP / 4; ++ks) Mf<T>::mma(ap[4 * ks], bp[4 * ks * ldc], acc);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * rg + Mf<T>::out_row(g, i), col = 16 * cb + lr;
+          const bool ok = row < nr && col < r;
+          T f = fv[q][cb][i], mu = mv[q][cb][i];
+          if (ok && mode == 1) {
+            const T lx = acc[i];
+            const T t = lx + mu * inv_pen;
+            f = t > T(0) ? t : T(0);
+            mu = mu + xpen * (lx - f);
+            const int64_t off = (int64_t)(base + row) * S.ldf + col;
+            F[off] = f;
+            M[off] = mu;
+          }
+          ws[row * ldc + col] = ok ? pen * f - mu : T(0);
         }
       }
     }
     __syncthreads();
+    // ---- partial: P (KP x RP) += bs^T (KP x CH) * ws (CH x RP) ----
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int mb = w + 4 * u;
+      if (mb < KP16) {
+        for (int ks = 0; ks < CH / 4; ++ks) {
+          const T a = bs[(4 * ks + g) * ldb + 16 * mb + lr];
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (v < RP16) Mf<T>::mma(a, ws[(4 * ks + g) * ldc + 16 * v + lr], pacc[u][v]);
+        }
+      }
+    }
   }
 #pragma unroll
-  for (int i = 0; i < kMaxK16; ++i)
+  for (int u = 0; u < 2; ++u) {
+    const int mb = w + 4 * u;
+    if (mb < KP16) {
 #pragma unroll
-    for (int j = 0; j < kMaxR16; ++j) {
-      int a = ta + 16 * i, c = tb + 16 * j;
-      if (a < k && c < r) out[a * r + c] = acc[i][j];
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int a = 16 * mb + Mf<T>::out_row(g, i), c = 16 * v + lr;
+          if (v < RP16 && a < k && c < r) out[a * r + c] = (double)pacc[u][v][i];
+        }
     }
+  }
 }
 
 template <typename T>
 hipError_t launch_admm_uv(AdmmSide s0, AdmmSide s1, int nsides, const double* XY, int k, int r, double xi,
                           int mode, double* Pp, int parts0, int parts1, hipStream_t st) {
   if (k > 128 || r > 64) return hipErrorInvalidValue;
+  const int KP = (k + 15) / 16 * 16, RP = (r + 15) / 16 * 16;
   int rpb0 = (s0.rows + parts0 - 1) / parts0;
   int rpb1 = nsides > 1 ? (s1.rows + parts1 - 1) / parts1 : 1;
   int nb = parts0 + (nsides > 1 ? parts1 : 0);
-  hipLaunchKernelGGL(admm_uv_kernel<T>, dim3(nb), dim3(256), 0, st, s0, s1, parts0, XY, k, r, xi, mode, Pp,
-                     rpb0, rpb1);
+  auto lds = [&](int ch) { return ((size_t)KP * (RP + 1) + (size_t)ch * (KP + 1) + (size_t)ch * (RP + 1)) * sizeof(T); };
+  if (lds(64) <= 160 * 1024) {
+    hipFuncSetAttribute((const void*)admm_uv_kernel<T, 64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds(64));
+    hipLaunchKernelGGL((admm_uv_kernel<T, 64>), dim3(nb), dim3(256), lds(64), st, s0, s1, parts0, XY, k, r, xi, mode,
+                       Pp, rpb0, rpb1);
+  } else {
+    hipFuncSetAttribute((const void*)admm_uv_kernel<T, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds(32));
+    hipLaunchKernelGGL((admm_uv_kernel<T, 32>), dim3(nb), dim3(256), lds(32), st, s0, s1, parts0, XY, k, r, xi, mode,
+                       Pp, rpb0, rpb1);
+  }
   CNMF_LAUNCH_CHECK();
 }
 template hipError_t launch_admm_uv<float>(AdmmSide, AdmmSide, int, const double*, int, int, double, int, double*, int, int, hipStream_t);
 template hipError_t launch_admm_uv<double>(AdmmSide, AdmmSide, int, const double*, int, int, double, int, double*, int, int, hipStream_t);
 
-// ---------------------------------------------------------------------------
-// Small dense helpers for one workgroup (NT threads), FP64 in LDS.
-// ---------------------------------------------------------------------------
-template <int NT>
-__device__ void wg_chol_inv(double* Mm, int r, double* Ci, int* flag) {
-  // Mm (r x r, row-major, SPD) -> upper Cholesky factor in place (Mm = C^T C),
-  // then Ci = C^-1 (upper).
-  const int tid = threadIdx.x;
-  for (int j = 0; j < r; ++j) {
-    __syncthreads();
-    double d = Mm[j * r + j];
-    if (!(d > 0.0) || !isfinite(d)) {
-      if (tid == 0 && flag) atomicAdd(flag, 1);
-      d = 1e-300;
-    }
-    const double t = sqrt(d);
-    __syncthreads();
-    if (tid == 0) Mm[j * r + j] = t;
-    for (int c = j + 1 + tid; c < r; c += NT) Mm[j * r + c] /= t;
-    __syncthreads();
-    const int rem = r - j - 1;
-    for (int e = tid; e < rem * rem; e += NT) {
-      int a = e / rem, b = e - a * rem;
-      if (b >= a) Mm[(j + 1 + a) * r + (j + 1 + b)] -= Mm[j * r + j + 1 + a] * Mm[j * r + j + 1 + b];
-    }
-  }
-  __syncthreads();
-  for (int i = r - 1; i >= 0; --i) {
-    const double tii = Mm[i * r + i];
-    for (int j = i + tid; j < r; j += NT) {
-      if (j == i) {
-        Ci[i * r + i] = 1.0 / tii;
-      } else {
-        double s = 0.0;
-        for (int l = i + 1; l <= j; ++l) s = fma(Mm[i * r + l], Ci[l * r + j], s);
-        Ci[i * r + j] = -s / tii;
-      }
-    }
-    for (int j = tid; j < i; j += NT) Ci[i * r + j] = 0.0;
-    __syncthreads();
-  }
+// Fixed-order sums of the partials: P_U over the parts0 blocks of the U
+// side and P_V over the parts1 blocks of the V side, into Pred[0], Pred[1].
+// Blocks [0, nbh) reduce P_U, blocks [nbh, 2 nbh) reduce P_V.
+constexpr int kRedNT = 256;
+constexpr int kRedEPB = 32;
+
+__global__ __launch_bounds__(kRedNT) void admm_reduce_kernel(const double* __restrict__ Pp, int parts0,
+                                                             int parts1, int64_t kr, double* __restrict__ Pred) {
+  __shared__ double red[kRedNT];
+  const int nbh = gridDim.x / 2;
+  const bool vside = (int)blockIdx.x >= nbh;
+  const int64_t e0 = (int64_t)(vside ? blockIdx.x - nbh : blockIdx.x) * kRedEPB;
+  if (!vside)
+    block_sum_parts<kRedNT, kRedEPB>(Pp, parts0, kr, kr, e0, Pred, red);
+  else
+    block_sum_parts<kRedNT, kRedEPB>(Pp + (int64_t)parts0 * kr, parts1, kr, kr, e0, Pred + kr, red);
 }
 
-// X (rows x r) <- X C^-1 C^-T  (solve X M = RHS for M = C^T C), in place,
-// using tmp (rows x r).
-template <int NT>
-__device__ void wg_right_solve(double* X, int rows, int r, const double* Ci, double* tmp) {
-  const int tid = threadIdx.x;
-  // tmp = X Ci   (Ci upper: tmp[i][c] = sum_{l <= c} X[i][l] Ci[l][c])
-  for (int e = tid; e < rows * r; e += NT) {
-    int i = e / r, c = e - i * r;
-    double s = 0.0;
-    for (int l = 0; l <= c; ++l) s = fma(X[i * r + l], Ci[l * r + c], s);
-    tmp[e] = s;
-  }
-  __syncthreads();
-  // X = tmp Ci^T  (X[i][c] = sum_{l >= c} tmp[i][l] Ci[c][l])
-  for (int e = tid; e < rows * r; e += NT) {
-    int i = e / r, c = e - i * r;
-    double s = 0.0;
-    for (int l = c; l < r; ++l) s = fma(tmp[i * r + l], Ci[c * r + l], s);
-    X[e] = s;
-  }
-  __syncthreads();
-}
+// The two r x r solves of one iteration in one workgroup.  XY: [0] Xt
+// (k x r), [1] Yt^T (k x r), FP64.  first != 0: Yt^T = P_V / phi before the
+// Xt solve (Alg. 3 initialisation Yt = V R^T, the partial having been
+// formed as R (phi V^T)).  The systems are padded to N = 16 ceil(r / 16)
+// with an identity block and solved by the blocked Cholesky in LDS.
+constexpr int kSolveNT = 256;
 
-// Reduce the partials (blocks of the first phase), then one workgroup does
-// the two solves.  Pp: [parts0] k x r for P_U then [parts1] k x r for P_V.
-// XY: [0] Xt (k x r), [1] Yt^T (k x r), FP64.  first != 0: Yt^T = P_V / phi
-// before the Xt solve (Alg. 3 initialisation Yt = V R^T, with the partial
-// computed as R (phi V^T)).
-template <int NT>
-__global__ __launch_bounds__(NT) void admm_solve_kernel(const double* __restrict__ Pp, int parts0,
-                                                        int parts1, const double* __restrict__ At, int k,
-                                                        int r, double lam, double phi, int first,
-                                                        double* __restrict__ XY, double* __restrict__ Pred,
-                                                        unsigned* counter, int* flags) {
+__global__ __launch_bounds__(kSolveNT) void admm_solve_kernel(const double* __restrict__ Pred,
+                                                              const double* __restrict__ At, int k, int r,
+                                                              double lam, double phi, int first,
+                                                              double* __restrict__ XY, int* flags, int at_in_lds) {
+  constexpr int NT = kSolveNT;
   const int tid = threadIdx.x;
   const int64_t kr = (int64_t)k * r;
-  // phase 1: Pred[0] = sum P_U partials, Pred[1] = sum P_V partials
-  for (int64_t e = blockIdx.x * (int64_t)NT + tid; e < 2 * kr; e += (int64_t)gridDim.x * NT) {
-    const bool v = e >= kr;
-    const int64_t ee = v ? e - kr : e;
-    const int p0 = v ? parts0 : 0;
-    const int np = v ? parts1 : parts0;
-    double s = 0.0;
-    for (int p = 0; p < np; ++p) s += Pp[(int64_t)(p0 + p) * kr + ee];
-    Pred[e] = s;
-  }
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+  const int NB = (r + 15) / 16, N = 16 * NB, ld = N + 1;
   extern __shared__ double sm[];
-  double* Y = sm;                // Yt^T, k x r
-  double* X = Y + kr;            // Xt / RHS, k x r
-  double* Mm = X + kr;           // r x r
-  double* Ci = Mm + r * r;       // r x r
+  double* Y = sm;                  // Yt^T, k x ld
+  double* X = Y + k * ld;          // Xt / RHS, k x ld
+  double* Mm = X + k * ld;         // N x ld: system matrix, then its factor
+  double* TI = Mm + N * ld;        // NB x 16 x 17
+  double* PN = TI + NB * 272;      // 16 x ld
+  double* Rs = PN + 16 * ld;       // k x 17
+  double* Ats = Rs + k * 17;       // k x k when at_in_lds
+  const double* Aa = at_in_lds ? Ats : At;
   const double* PU = Pred;
   const double* PV = Pred + kr;
-  for (int e = tid; e < kr; e += NT) Y[e] = first ? PV[e] / phi : XY[kr + e];
+  for (int e = tid; e < k * N; e += NT) {
+    int i = e / N, c = e - i * N;
+    Y[i * ld + c] = c < r ? (first ? PV[i * r + c] / phi : XY[kr + i * r + c]) : 0.0;
+  }
+  if (at_in_lds)
+    for (int e = tid; e < k * k; e += NT) Ats[e] = At[e];
   __syncthreads();
-  // M1 = Yt Yt^T + lam I = Y^T Y + lam I (r x r)
-  for (int e = tid; e < r * r; e += NT) {
-    int a = e / r, b = e - a * r;
-    double s = 0.0;
-    for (int l = 0; l < k; ++l) s = fma(Y[l * r + a], Y[l * r + b], s);
-    Mm[e] = s + (a == b ? lam : 0.0);
+  // pass 0: Xt from (At, Yt, P_U, lam); pass 1: Yt^T from (At^T, Xt, P_V, phi)
+  for (int pass = 0; pass < 2; ++pass) {
+    const double* S = pass ? X : Y;     // k x ld (the other factor)
+    double* D = pass ? Y : X;           // RHS, then the solution
+    const double* P = pass ? PV : PU;
+    const double pen = pass ? phi : lam;
+    // system matrix S^T S + pen I (padded with I), 4 x 4 tiles of the upper
+    // block triangle
+    const int NQ = N / 4;
+    for (int e = tid; e < NQ * NQ; e += NT) {
+      const int ta = e / NQ, tb = e - ta * NQ;
+      if (tb < ta) continue;
+      double acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
+      for (int l = 0; l < k; ++l) {
+        const double* sl = S + l * ld;
+        double x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          x[u] = sl[4 * ta + u];
+          y[u] = sl[4 * tb + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = fma(x[u], y[v], acc[u][v]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 4 * ta + u, b = 4 * tb + v;
+          if (b < a) continue;
+          const double val = acc[u][v] + (a == b ? (a < r ? pen : 1.0) : 0.0);
+          Mm[a * ld + b] = val;
+          Mm[b * ld + a] = val;
+        }
+    }
+    // RHS = At S + P (pass 0) or At^T S + P (pass 1), zero padding; 4 x 4 tiles
+    const int KQ = (k + 3) / 4;
+    for (int e = tid; e < KQ * NQ; e += NT) {
+      const int ta = e / NQ, tc = e - ta * NQ;
+      double acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
+      for (int l = 0; l < k; ++l) {
+        double x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int a = min(4 * ta + u, k - 1);
+          x[u] = pass == 0 ? Aa[a * k + l] : Aa[l * k + a];
+          y[u] = S[l * ld + 4 * tc + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = fma(x[u], y[v], acc[u][v]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 4 * ta + u, c = 4 * tc + v;
+          if (a < k) D[a * ld + c] = c < r ? acc[u][v] + P[a * r + c] : 0.0;
+        }
+    }
+    __syncthreads();
+    double mx = 0.0;
+    for (int i = 0; i < r; ++i) mx = fmax(mx, Mm[i * ld + i]);
+    wg_chol_blocked<NT>(Mm, ld, NB, TI, PN, 1e-300 * mx, flags);
+    wg_right_solve_blocked<NT>(D, k, ld, NB, Mm, ld, TI, Rs);
+    double* out = XY + (pass ? kr : 0);
+    for (int e = tid; e < kr; e += NT) {
+      int i = e / r, c = e - i * r;
+      out[e] = D[i * ld + c];
+    }
   }
-  // RHS1 = At Y + P_U (k x r)
-  for (int e = tid; e < kr; e += NT) {
-    int a = e / r, c = e - a * r;
-    double s = 0.0;
-    for (int l = 0; l < k; ++l) s = fma(At[a * k + l], Y[l * r + c], s);
-    X[e] = s + PU[e];
-  }
-  __syncthreads();
-  wg_chol_inv<NT>(Mm, r, Ci, flags);
-  wg_right_solve<NT>(X, k, r, Ci, Y);     // X = Xt (Y is scratch here)
-  // M2 = Xt^T Xt + phi I
-  for (int e = tid; e < r * r; e += NT) {
-    int a = e / r, b = e - a * r;
-    double s = 0.0;
-    for (int l = 0; l < k; ++l) s = fma(X[l * r + a], X[l * r + b], s);
-    Mm[e] = s + (a == b ? phi : 0.0);
-  }
-  // RHS2 = At^T Xt + P_V (k x r)
-  for (int e = tid; e < kr; e += NT) {
-    int a = e / r, c = e - a * r;
-    double s = 0.0;
-    for (int l = 0; l < k; ++l) s = fma(At[l * k + a], X[l * r + c], s);
-    Y[e] = s + PV[e];
-  }
-  __syncthreads();
-  for (int e = tid; e < kr; e += NT) XY[e] = X[e];
-  wg_chol_inv<NT>(Mm, r, Ci, flags);
-  wg_right_solve<NT>(Y, k, r, Ci, X);     // Y = Yt^T (X is scratch here)
-  for (int e = tid; e < kr; e += NT) XY[kr + e] = Y[e];
-  if (tid == 0) *counter = 0u;
+}
+
+static size_t admm_solve_lds(int k, int r, bool with_at) {
+  const int NB = (r + 15) / 16, N = 16 * NB, ld = N + 1;
+  size_t d = 2 * (size_t)k * ld + (size_t)N * ld + (size_t)NB * 272 + 16 * (size_t)ld + (size_t)k * 17;
+  if (with_at) d += (size_t)k * k;
+  return d * sizeof(double);
 }
 
 template <typename T>
 hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const double* At, int k, int r,
-                             double lam, double phi, int first, double* XY, double* Pred, unsigned* counter,
+                             double lam, double phi, int first, double* XY, double* Pred, unsigned* /*counter*/,
                              int* flags, hipStream_t st) {
-  constexpr int NT = 512;
-  size_t sm = (2 * (size_t)k * r + 2 * (size_t)r * r) * sizeof(double);
-  if (sm > 160 * 1024) return hipErrorInvalidValue;
-  int64_t kr2 = 2LL * k * r;
-  int nb = (int)std::max<int64_t>(1, std::min<int64_t>(64, (kr2 + NT - 1) / NT));
-  hipFuncSetAttribute((const void*)admm_solve_kernel<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  hipLaunchKernelGGL(admm_solve_kernel<NT>, dim3(nb), dim3(NT), sm, st, Pp, parts0, parts1, At, k, r, lam, phi,
-                     first, XY, Pred, counter, flags);
+  if (r > 64 || k > 128) return hipErrorInvalidValue;
+  const size_t cap = 160 * 1024;
+  int at_in_lds = admm_solve_lds(k, r, true) <= cap;
+  size_t sm = admm_solve_lds(k, r, at_in_lds);
+  if (sm > cap) return hipErrorInvalidValue;
+  int64_t kr = (int64_t)k * r;
+  int nbh = (int)((kr + kRedEPB - 1) / kRedEPB);
+  hipLaunchKernelGGL(admm_reduce_kernel, dim3(2 * nbh), dim3(kRedNT), 0, st, Pp, parts0, parts1, kr, Pred);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipFuncSetAttribute((const void*)admm_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  hipLaunchKernelGGL(admm_solve_kernel, dim3(1), dim3(kSolveNT), sm, st, Pred, At, k, r, lam, phi, first, XY, flags,
+                     at_in_lds);
   CNMF_LAUNCH_CHECK();
 }
 template hipError_t launch_admm_solve<float>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, unsigned*, int*, hipStream_t);

@@ -210,12 +210,13 @@ hipError_t launch_flags_to_stats(const int* flags, int nflags, double* out, hipS
 
 // ---------------------------------------------------------------------------
 // SPA (Section 4, Alg. SNMF step 2) on Bt = B^T (n x k, FP64 working copy).
-// One launch per selection step t:
-//   t > 0: b_j <- b_j - u (u^T b_j) with u the previous step's unit pivot;
-//   s_j = ||b_j||^2; block argmax (largest s, lowest j on ties);
-//   the last block to finish reduces the block winners in block order,
-//   records K[t], score[t] and u = b_p / sqrt(s_p) for the next step.
-// Each block stages 64 rows in LDS; 4 threads per row.
+// Selection step t is two launches:
+//   spa_norms (all rows): t > 0: b_j <- b_j - u (u^T b_j) with u the previous
+//     step's unit pivot; s_j = ||b_j||^2; block argmax (largest s, lowest j on
+//     ties) into wg_best / wg_idx;
+//   spa_pick (one block): argmax over the block winners, records K[t],
+//     score[t] and u = b_p / sqrt(s_p) for the next step.
+// Each norms block stages 64 rows in LDS; 4 threads per row.
 // ---------------------------------------------------------------------------
 constexpr int kSpaRows = 64;
 
@@ -223,17 +224,15 @@ __device__ __forceinline__ bool spa_better(double s1, int64_t j1, double s2, int
   return s1 > s2 || (s1 == s2 && j1 < j2);
 }
 
-__global__ __launch_bounds__(256) void spa_step_kernel(double* __restrict__ Bt, int n, int k, int ldb, int t,
-                                                       int64_t* __restrict__ K, double* __restrict__ score,
-                                                       double* __restrict__ u, double* __restrict__ wg_best,
-                                                       int64_t* __restrict__ wg_idx, unsigned* counter) {
+__global__ __launch_bounds__(256) void spa_norms_kernel(double* __restrict__ Bt, int n, int k, int ldb, int t,
+                                                        const double* __restrict__ u, double* __restrict__ wg_best,
+                                                        int64_t* __restrict__ wg_idx) {
   extern __shared__ double sm[];
   double* bs = sm;                 // kSpaRows x (k + 1)
   double* us = bs + kSpaRows * (k + 1);
   __shared__ double part[256];
   __shared__ double rs[kSpaRows];
   __shared__ int64_t ri[kSpaRows];
-  __shared__ bool last;
   const int tid = threadIdx.x;
   const int ld = k + 1;
   const int64_t row0 = (int64_t)blockIdx.x * kSpaRows;
@@ -252,7 +251,8 @@ __global__ __launch_bounds__(256) void spa_step_kernel(double* __restrict__ Bt, 
     part[tid] = d;
     __syncthreads();
     // fixed combination order within the 4-thread group
-    double dot = (part[tid & ~3] + part[(tid & ~3) + 1]) + (part[(tid & ~3) + 2] + part[(tid & ~3) + 3]);
+    const int g0 = tid & ~3;
+    const double dot = (part[g0] + part[g0 + 1]) + (part[g0 + 2] + part[g0 + 3]);
     for (int a = q; a < k; a += 4) b[a] = fma(-us[a], dot, b[a]);
     __syncthreads();
     for (int e = tid; e < kSpaRows * k; e += 256) {
@@ -262,6 +262,7 @@ __global__ __launch_bounds__(256) void spa_step_kernel(double* __restrict__ Bt, 
   }
   double s = 0.0;
   for (int a = q; a < k; a += 4) s = fma(b[a], b[a], s);
+  __syncthreads();
   part[tid] = s;
   __syncthreads();
   if (q == 0) {
@@ -281,19 +282,20 @@ __global__ __launch_bounds__(256) void spa_step_kernel(double* __restrict__ Bt, 
     wg_best[blockIdx.x] = bv;
     wg_idx[blockIdx.x] = bi;
   }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+}
+
+__global__ __launch_bounds__(256) void spa_pick_kernel(const double* __restrict__ Bt, int k, int ldb, int t,
+                                                       int nblocks, int64_t* __restrict__ K,
+                                                       double* __restrict__ score, double* __restrict__ u,
+                                                       const double* __restrict__ wg_best,
+                                                       const int64_t* __restrict__ wg_idx) {
+  __shared__ double tv[256];
+  __shared__ int64_t ti[256];
+  const int tid = threadIdx.x;
   // block winners in block order: thread-strided, then a fixed tree
   double bv = -2.0;
   int64_t bi = INT64_MAX;
-  for (int p = tid; p < (int)gridDim.x; p += 256) {
+  for (int p = tid; p < nblocks; p += 256) {
     double v = wg_best[p];
     int64_t i = wg_idx[p];
     if (spa_better(v, i, bv, bi)) {
@@ -301,15 +303,13 @@ __global__ __launch_bounds__(256) void spa_step_kernel(double* __restrict__ Bt, 
       bi = i;
     }
   }
-  __shared__ double tv[256];
-  __shared__ int64_t ti[256];
   tv[tid] = bv;
   ti[tid] = bi;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (tid < st && spa_better(tv[tid + st], ti[tid + st], tv[tid], ti[tid])) {
-      tv[tid] = tv[tid + st];
-      ti[tid] = ti[tid + st];
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w && spa_better(tv[tid + w], ti[tid + w], tv[tid], ti[tid])) {
+      tv[tid] = tv[tid + w];
+      ti[tid] = ti[tid + w];
     }
     __syncthreads();
   }
@@ -318,19 +318,21 @@ __global__ __launch_bounds__(256) void spa_step_kernel(double* __restrict__ Bt, 
   if (tid == 0) {
     K[t] = p;
     if (score) score[t] = sp;
-    *counter = 0u;
   }
   const double inv = sp > 0 ? 1.0 / sqrt(sp) : 0.0;
   for (int a = tid; a < k; a += 256) u[a] = Bt[p * ldb + a] * inv;
 }
 
 hipError_t launch_spa_step(double* Bt, int n, int k, int ldb, int t, int64_t* K, double* score, double* u,
-                           double* wg_best, int64_t* wg_idx, unsigned* counter, int nblocks, hipStream_t st) {
+                           double* wg_best, int64_t* wg_idx, unsigned* /*counter*/, int nblocks, hipStream_t st) {
   if (nblocks != (n + kSpaRows - 1) / kSpaRows) return hipErrorInvalidValue;
   size_t sm = ((size_t)kSpaRows * (k + 1) + k) * sizeof(double);
-  hipFuncSetAttribute((const void*)spa_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  hipLaunchKernelGGL(spa_step_kernel, dim3(nblocks), dim3(256), sm, st, Bt, n, k, ldb, t, K, score, u, wg_best,
-                     wg_idx, counter);
+  hipFuncSetAttribute((const void*)spa_norms_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  hipLaunchKernelGGL(spa_norms_kernel, dim3(nblocks), dim3(256), sm, st, Bt, n, k, ldb, t, u, wg_best, wg_idx);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(spa_pick_kernel, dim3(1), dim3(256), 0, st, Bt, k, ldb, t, nblocks, K, score, u, wg_best,
+                     wg_idx);
   CNMF_LAUNCH_CHECK();
 }
 

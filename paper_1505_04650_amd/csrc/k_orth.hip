@@ -7,6 +7,7 @@
 // With diag(T) > 0 this Q is the same basis as the Householder QR with a
 // nonnegative diagonal for full-column-rank Y.
 #include "cnmf_internal.hpp"
+#include "small_dense.hpp"
 
 namespace cnmf {
 
@@ -132,108 +133,152 @@ template hipError_t launch_cross2<float, double>(const float*, int, int, const d
 // ---------------------------------------------------------------------------
 // out[e] = sum_p in[p * count + e], p increasing.
 // ---------------------------------------------------------------------------
-__global__ void sum_parts_kernel(const double* __restrict__ in, int parts, int64_t count,
-                                 double* __restrict__ out) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int p = 0; p < parts; ++p) acc += in[p * count + e];
-    out[e] = acc;
-  }
+__global__ __launch_bounds__(256) void sum_parts_kernel(const double* __restrict__ in, int parts, int64_t count,
+                                                        double* __restrict__ out) {
+  __shared__ double red[256];
+  block_sum_parts<256, 32>(in, parts, count, count, (int64_t)blockIdx.x * 32, out, red);
 }
 
 hipError_t launch_sum_parts(const double* in, int parts, int64_t count, double* out, hipStream_t st) {
-  int blocks = (int)std::min<int64_t>((count + 255) / 256, 1024);
+  int blocks = (int)((count + 31) / 32);
   hipLaunchKernelGGL(sum_parts_kernel, dim3(blocks), dim3(256), 0, st, in, parts, count, out);
   CNMF_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky G = T^T T (T upper, positive diagonal) and Tinv = T^-1, one
-// workgroup per half.  Upper triangles are packed in LDS:
-//   idx(i, j) = i*kh - i*(i-1)/2 + (j - i), j >= i.
-// A pivot <= tol * max_i G_ii (or not finite) is a breakdown: flags[h] += 1
-// and the pivot is replaced by tol * max_i G_ii so the factor stays finite.
+// G_h = sum of the Gram partials (fixed order; sum_parts kernel), then one
+// workgroup per half: G_h = T^T T (Cholesky, T upper with positive diagonal)
+// and Tinv_h = T^-1 written to global memory (upper, zero lower triangle).
+// Partials: Gp[(p * nh + h) * kh * kh].  A pivot <= 1e-20 max_i G_ii (or
+// not finite) counts as a breakdown in flags[h] and is replaced by that floor.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int pk(int i, int j, int kh) { return i * kh - (i * (i - 1)) / 2 + (j - i); }
+constexpr int kCholNT = 512;
 
-__global__ __launch_bounds__(256) void chol_inv_kernel(const double* __restrict__ G, int kh,
-                                                       double* __restrict__ Tinv, int* flags,
-                                                       double tol) {
-  extern __shared__ double sm[];
-  const int np = kh * (kh + 1) / 2;
-  double* S = sm;        // packed T
-  double* Ti = sm + np;  // packed Tinv
-  __shared__ double s_piv;
-  __shared__ double s_maxd;
+// kh > 64: LDS factorisation by the whole workgroup.
+__global__ __launch_bounds__(kCholNT) void chol_kernel(const double* __restrict__ G, int kh,
+                                                       double* __restrict__ Tinv, int* flags) {
+  constexpr int NT = kCholNT;
   const int h = blockIdx.x;
-  const double* Gh = G + (int64_t)h * kh * kh;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kh * kh; e += 256) {
+  const int64_t cnt = (int64_t)kh * kh;
+  extern __shared__ double sm[];
+  const int ld = kh + 1;
+  double* M = sm;
+  double* Td = sm + kh * ld;
+  const double* Gh = G + h * cnt;
+  for (int e = threadIdx.x; e < kh * kh; e += NT) {
     int i = e / kh, j = e - i * kh;
-    if (j >= i) S[pk(i, j, kh)] = 0.5 * (Gh[i * kh + j] + Gh[j * kh + i]);
+    if (j >= i) M[i * ld + j] = 0.5 * (Gh[i * kh + j] + Gh[j * kh + i]);
   }
   __syncthreads();
-  if (tid == 0) {
-    double md = 0.0;
-    for (int i = 0; i < kh; ++i) md = fmax(md, S[pk(i, i, kh)]);
-    s_maxd = md;
-  }
-  __syncthreads();
-  const double floor_piv = tol * s_maxd;
-  for (int j = 0; j < kh; ++j) {
-    if (tid == 0) {
-      double d = S[pk(j, j, kh)];
-      if (!(d > floor_piv) || !isfinite(d)) {
-        d = floor_piv > 0 ? floor_piv : 1.0;
-        if (flags) atomicAdd(&flags[h], 1);
-      }
-      s_piv = sqrt(d);
-      S[pk(j, j, kh)] = s_piv;
-    }
-    __syncthreads();
-    const double t = s_piv;
-    for (int c = j + 1 + tid; c < kh; c += 256) S[pk(j, c, kh)] /= t;
-    __syncthreads();
-    // trailing update: S[a][b] -= S[j][a] S[j][b], j < a <= b
-    const int rem = kh - j - 1;
-    for (int e = tid; e < rem * rem; e += 256) {
-      int a = e / rem, b = e - a * rem;
-      if (b >= a) {
-        a += j + 1;
-        b += j + 1;
-        S[pk(a, b, kh)] -= S[pk(j, a, kh)] * S[pk(j, b, kh)];
-      }
-    }
-    __syncthreads();
-  }
-  // Tinv by rows from the bottom: Ti[i][i] = 1/T_ii,
-  // Ti[i][j] = -(sum_{l=i+1..j} T[i][l] Ti[l][j]) / T_ii.
-  for (int i = kh - 1; i >= 0; --i) {
-    const double tii = S[pk(i, i, kh)];
-    for (int j = i + tid; j < kh; j += 256) {
-      if (j == i) {
-        Ti[pk(i, i, kh)] = 1.0 / tii;
-      } else {
-        double s = 0.0;
-        for (int l = i + 1; l <= j; ++l) s = fma(S[pk(i, l, kh)], Ti[pk(l, j, kh)], s);
-        Ti[pk(i, j, kh)] = -s / tii;
-      }
-    }
-    __syncthreads();
-  }
-  double* out = Tinv + (int64_t)h * kh * kh;
-  for (int e = tid; e < kh * kh; e += 256) {
+  double mx = 0.0;
+  for (int i = 0; i < kh; ++i) mx = fmax(mx, M[i * ld + i]);
+  wg_cholesky_inverse<NT>(M, kh, ld, Td, 1e-20 * mx, flags ? flags + h : nullptr);
+  double* out = Tinv + h * cnt;
+  for (int e = threadIdx.x; e < kh * kh; e += NT) {
     int i = e / kh, j = e - i * kh;
-    out[e] = (j >= i) ? Ti[pk(i, j, kh)] : 0.0;
+    out[e] = j >= i ? M[i * ld + j] : 0.0;
   }
 }
 
-hipError_t launch_chol_inv(const double* G, int nh, int kh, double* Tinv, double* /*Tacc*/, int* flags,
-                           hipStream_t st) {
-  size_t sm = (size_t)kh * (kh + 1) * sizeof(double);  // two packed triangles
-  hipFuncSetAttribute((const void*)chol_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(nh), dim3(256), sm, st, G, kh, Tinv, flags, 1e-28);
+// kh <= 64: factor only (blocked, padded to 16 ceil(kh / 16) with I);
+// Tf_h = T (upper, zero lower) for the substitution in apply_tri_kernel.
+constexpr int kFacNT = 256;
+__global__ __launch_bounds__(kFacNT) void chol_fac_kernel(const double* __restrict__ G, int kh,
+                                                          double* __restrict__ Tf, int* flags) {
+  const int h = blockIdx.x;
+  const int64_t cnt = (int64_t)kh * kh;
+  const int NB = (kh + 15) / 16, N = 16 * NB, ld = N + 1;
+  extern __shared__ double sm[];
+  double* M = sm;              // N x ld
+  double* TI = M + N * ld;     // NB x 272
+  double* PN = TI + NB * 272;  // 16 x ld
+  const double* Gh = G + h * cnt;
+  for (int e = threadIdx.x; e < N * N; e += kFacNT) {
+    int i = e / N, j = e - i * N;
+    double v;
+    if (i < kh && j < kh)
+      v = 0.5 * (Gh[i * kh + j] + Gh[j * kh + i]);
+    else
+      v = (i == j) ? 1.0 : 0.0;
+    M[i * ld + j] = v;
+  }
+  __syncthreads();
+  double mx = 0.0;
+  for (int i = 0; i < kh; ++i) mx = fmax(mx, M[i * ld + i]);
+  wg_chol_blocked<kFacNT>(M, ld, NB, TI, PN, 1e-20 * mx, flags ? flags + h : nullptr);
+  double* out = Tf + h * cnt;
+  for (int e = threadIdx.x; e < kh * kh; e += kFacNT) {
+    int i = e / kh, j = e - i * kh;
+    out[e] = j >= i ? M[i * ld + j] : 0.0;
+  }
+}
+
+// Q[i][h*kh + c] for one row per thread: forward substitution z T = y with
+// the upper factor T (staged in LDS, read uniformly), z in registers.
+template <typename TY, int KH>
+__global__ __launch_bounds__(256) void apply_tri_kernel(const TY* __restrict__ Y, int rows, int ldy, int kh,
+                                                        const double* __restrict__ Tf, double* __restrict__ Q,
+                                                        int ldq) {
+  const int h = blockIdx.y;
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  __shared__ double T[KH * KH];
+  const double* __restrict__ Tg = Tf + (int64_t)h * kh * kh;
+  for (int e = threadIdx.x; e < kh * kh; e += 256) T[e] = Tg[e];
+  __syncthreads();
+  if (row >= rows) return;
+  const TY* y = Y + (int64_t)row * ldy + h * kh;
+  double z[KH];
+#pragma unroll
+  for (int c = 0; c < KH; ++c) z[c] = c < kh ? (double)y[c] : 0.0;
+#pragma unroll
+  for (int c = 0; c < KH; ++c) {
+    if (c < kh) {
+      double s0 = z[c], s1 = 0.0;
+#pragma unroll
+      for (int l = 0; l < c; l += 2) {
+        s0 = fma(-z[l], T[l * kh + c], s0);
+        if (l + 1 < c) s1 = fma(-z[l + 1], T[(l + 1) * kh + c], s1);
+      }
+      z[c] = (s0 + s1) / T[c * kh + c];
+    }
+  }
+  double* q = Q + (int64_t)row * ldq + h * kh;
+#pragma unroll
+  for (int c = 0; c < KH; ++c)
+    if (c < kh) q[c] = z[c];
+}
+
+template <typename TY>
+hipError_t launch_apply_tri(const TY* Y, int rows, int ldy, int nh, int kh, const double* Tf, double* Q64, int ldq,
+                            hipStream_t st) {
+  dim3 grid((rows + 255) / 256, nh);
+  if (kh <= 16)
+    hipLaunchKernelGGL((apply_tri_kernel<TY, 16>), grid, dim3(256), 0, st, Y, rows, ldy, kh, Tf, Q64, ldq);
+  else if (kh <= 32)
+    hipLaunchKernelGGL((apply_tri_kernel<TY, 32>), grid, dim3(256), 0, st, Y, rows, ldy, kh, Tf, Q64, ldq);
+  else if (kh <= 48)
+    hipLaunchKernelGGL((apply_tri_kernel<TY, 48>), grid, dim3(256), 0, st, Y, rows, ldy, kh, Tf, Q64, ldq);
+  else if (kh <= 64)
+    hipLaunchKernelGGL((apply_tri_kernel<TY, 64>), grid, dim3(256), 0, st, Y, rows, ldy, kh, Tf, Q64, ldq);
+  else
+    return hipErrorInvalidValue;
+  CNMF_LAUNCH_CHECK();
+}
+
+hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double* G, double* Tinv, int* flags,
+                            unsigned* /*counters*/, hipStream_t st) {
+  hipError_t e = launch_sum_parts(Gp, parts, (int64_t)nh * kh * kh, G, st);
+  if (e != hipSuccess) return e;
+  if (kh <= 64) {
+    const int NB = (kh + 15) / 16, N = 16 * NB, ld = N + 1;
+    size_t sm = ((size_t)N * ld + (size_t)NB * 272 + 16 * (size_t)ld) * sizeof(double);
+    hipFuncSetAttribute((const void*)chol_fac_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    hipLaunchKernelGGL(chol_fac_kernel, dim3(nh), dim3(kFacNT), sm, st, G, kh, Tinv, flags);
+  } else {
+    size_t sm = ((size_t)kh * (kh + 1) + kh) * sizeof(double);
+    hipFuncSetAttribute((const void*)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    hipLaunchKernelGGL(chol_kernel, dim3(nh), dim3(kCholNT), sm, st, G, kh, Tinv, flags);
+  }
   CNMF_LAUNCH_CHECK();
 }
 
@@ -241,50 +286,55 @@ hipError_t launch_chol_inv(const double* G, int nh, int kh, double* Tinv, double
 // Q64[i][h*kh + c] = sum_{l <= c} Y[i][h*kh + l] Tinv_h[l][c]   (FP64)
 // ---------------------------------------------------------------------------
 template <typename TY>
-__global__ __launch_bounds__(256) void apply_tinv_kernel(const TY* __restrict__ Y, int rows, int ldy,
-                                                         int kh, const double* __restrict__ Tinv,
-                                                         double* __restrict__ Q, int ldq,
-                                                         int rows_per_block) {
+__global__ __launch_bounds__(256) void apply_tinv_kernel(const TY* __restrict__ Y, int rows, int ldy, int kh,
+                                                         const double* __restrict__ Tinv,
+                                                         double* __restrict__ Q, int ldq, int rows_per_block,
+                                                         int rb) {
   extern __shared__ double sm[];
-  double* Ti = sm;               // kh x kh (full, upper part used)
-  double* ys = sm + kh * kh;     // RB x kh rows
+  double* Ti = sm;               // kh x kh (upper part used)
+  double* ys = sm + kh * kh;     // rb x kh rows
   const int h = blockIdx.y;
   const int tid = threadIdx.x;
   const double* Th = Tinv + (int64_t)h * kh * kh;
   for (int e = tid; e < kh * kh; e += 256) Ti[e] = Th[e];
-  const int RBK = 256 / kh > 0 ? 256 / kh : 1;  // rows per sweep
   const int i0 = blockIdx.x * rows_per_block;
   const int i1 = min(rows, i0 + rows_per_block);
-  __syncthreads();
-  for (int base = i0; base < i1; base += RBK) {
-    for (int e = tid; e < RBK * kh; e += 256) {
+  for (int base = i0; base < i1; base += rb) {
+    const int nr = min(rb, i1 - base);
+    __syncthreads();
+    for (int e = tid; e < nr * kh; e += 256) {
       int rr = e / kh, c = e - rr * kh;
-      int row = base + rr;
-      ys[e] = row < i1 ? (double)Y[(int64_t)row * ldy + h * kh + c] : 0.0;
+      ys[e] = (double)Y[(int64_t)(base + rr) * ldy + h * kh + c];
     }
     __syncthreads();
-    if (tid < RBK * kh) {
-      int rr = tid / kh, c = tid - rr * kh;
-      int row = base + rr;
+    for (int e = tid; e < nr * kh; e += 256) {
+      int rr = e / kh, c = e - rr * kh;
       const double* y = ys + rr * kh;
-      double s = 0.0;
-      for (int l = 0; l <= c; ++l) s = fma(y[l], Ti[l * kh + c], s);
-      if (row < i1) Q[(int64_t)row * ldq + h * kh + c] = s;
+      double s0 = 0.0, s1 = 0.0;
+      int l = 0;
+      for (; l + 1 <= c; l += 2) {
+        s0 = fma(y[l], Ti[l * kh + c], s0);
+        s1 = fma(y[l + 1], Ti[(l + 1) * kh + c], s1);
+      }
+      if (l <= c) s0 = fma(y[l], Ti[l * kh + c], s0);
+      Q[(int64_t)(base + rr) * ldq + h * kh + c] = s0 + s1;
     }
-    __syncthreads();
   }
 }
 
 template <typename TY>
 hipError_t launch_apply_tinv(const TY* Y, int rows, int ldy, int nh, int kh, const double* Tinv,
                              double* Q64, int ldq, hipStream_t st) {
-  int blocks = std::max(1, std::min(1024, (rows + 63) / 64));
+  if (kh <= 64) return launch_apply_tri<TY>(Y, rows, ldy, nh, kh, Tinv, Q64, ldq, st);
+  const size_t cap = 160 * 1024;
+  int rb = (int)std::min<size_t>(64, (cap - (size_t)kh * kh * 8) / ((size_t)kh * 8));
+  rb = std::max(rb, 1);
+  int blocks = std::max(1, std::min(512, (rows + 2 * rb - 1) / (2 * rb)));
   int rpb = (rows + blocks - 1) / blocks;
-  int rbk = std::max(1, 256 / kh);
-  size_t sm = ((size_t)kh * kh + (size_t)rbk * kh) * sizeof(double);
+  size_t sm = ((size_t)kh * kh + (size_t)rb * kh) * sizeof(double);
   hipFuncSetAttribute((const void*)apply_tinv_kernel<TY>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  hipLaunchKernelGGL(apply_tinv_kernel<TY>, dim3(blocks, nh), dim3(256), sm, st, Y, rows, ldy, kh, Tinv,
-                     Q64, ldq, rpb);
+  hipLaunchKernelGGL(apply_tinv_kernel<TY>, dim3(blocks, nh), dim3(256), sm, st, Y, rows, ldy, kh, Tinv, Q64,
+                     ldq, rpb, rb);
   CNMF_LAUNCH_CHECK();
 }
 template hipError_t launch_apply_tinv<float>(const float*, int, int, int, int, const double*, double*, int, hipStream_t);

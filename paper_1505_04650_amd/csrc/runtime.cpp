@@ -30,6 +30,8 @@ using namespace cnmf;
 
 static thread_local std::string g_noh_err;
 
+constexpr int kStages = 8;
+
 struct cnmf_handle {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -37,10 +39,19 @@ struct cnmf_handle {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   std::string err;
+  // per-stage timing of the last call (HIP events on the handle's stream)
   bool timing = false;
-  hipEvent_t ev[8] = {};
-  int ev_used[8] = {};
-  double stage_ms[8];
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_next = 0;
+  struct Span {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Span> spans;
+  bool resolved = true;
+  double stage_ms[kStages];
+  double stage_flops[kStages];
+  int stage_count[kStages];
 };
 
 namespace {
@@ -216,6 +227,7 @@ struct SketchWs {
   double* G = nullptr;
   double* Tinv = nullptr;
   int* flags = nullptr;
+  unsigned* counters = nullptr;
   double* orth_err = nullptr;
   T* Lb = nullptr;      // m x k
   T* RTb = nullptr;     // n x k  (R^T)
@@ -251,6 +263,7 @@ void layout_sketch(Arena& a, SketchWs<T>& w, int64_t m, int64_t n, int k, const 
   w.G = a.take<double>(2 * (size_t)k * k);
   w.Tinv = a.take<double>(2 * (size_t)k * k);
   w.flags = a.take<int>(4);
+  w.counters = a.take<unsigned>(4);
   w.orth_err = a.take<double>(4);
   w.Lb = a.take<T>((size_t)m * k);
   w.RTb = a.take<T>((size_t)n * k);
@@ -274,7 +287,7 @@ struct AdmmWs {
   int rparts = 0;
 };
 
-int uv_parts(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(128, (rows + 63) / 64)); }
+int uv_parts(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (rows + 63) / 64)); }
 
 template <typename T>
 void layout_admm(Arena& a, AdmmWs<T>& w, int64_t m, int64_t n, int k, int r) {
@@ -311,14 +324,65 @@ cnmf_status ensure_ws(cnmf_handle* h, size_t bytes) {
 }
 
 // -------------------------------------------------------------------------
-// Timing helpers
+// Timing: stages 0 convert, 1 A X passes, 2 A^T Z passes, 3 orthonormalisation
+// and small sketches, 4 iterations, 5 residual, 6 SPA.  With timing enabled
+// every span is bracketed by two HIP events on the handle's stream.
 // -------------------------------------------------------------------------
-struct StageTimer {
+enum { ST_CONVERT = 0, ST_PASS_N = 1, ST_PASS_T = 2, ST_ORTH = 3, ST_ITER = 4, ST_RESID = 5, ST_SPA = 6 };
+
+void timing_reset(cnmf_handle* h) {
+  h->spans.clear();
+  h->ev_next = 0;
+  h->resolved = true;
+  for (int i = 0; i < kStages; ++i) {
+    h->stage_ms[i] = 0.0;
+    h->stage_flops[i] = 0.0;
+    h->stage_count[i] = 0;
+  }
+}
+
+hipEvent_t next_event(cnmf_handle* h) {
+  if (h->ev_next == h->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_next++];
+}
+
+struct Span {
   cnmf_handle* h;
-  explicit StageTimer(cnmf_handle* hh) : h(hh) {
-    for (int i = 0; i < 8; ++i) h->stage_ms[i] = 0.0, h->ev_used[i] = 0;
+  int stage;
+  hipEvent_t a = nullptr;
+  Span(cnmf_handle* hh, int st, double flops = 0.0) : h(hh), stage(st) {
+    h->stage_flops[st] += flops;
+    h->stage_count[st] += 1;
+    if (h->timing) {
+      a = next_event(h);
+      if (a) hipEventRecord(a, h->stream);
+    }
+  }
+  ~Span() {
+    if (a) {
+      hipEvent_t b = next_event(h);
+      if (b) {
+        hipEventRecord(b, h->stream);
+        h->spans.push_back({stage, a, b});
+        h->resolved = false;
+      }
+    }
   }
 };
+
+void timing_resolve(cnmf_handle* h) {
+  if (h->resolved) return;
+  if (!h->spans.empty()) hipEventSynchronize(h->spans.back().b);
+  for (const auto& sp : h->spans) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) h->stage_ms[sp.stage] += ms;
+  }
+  h->resolved = true;
+}
 
 // -------------------------------------------------------------------------
 // Orthonormalise nh column blocks [col0 + i*k, +k) of Y (rows x kk, already
@@ -330,14 +394,12 @@ cnmf_status orth_blocks(cnmf_handle* h, SketchWs<T>& w, const T* Y, int rows, in
   const int parts = std::min(w.gparts, std::max(1, rows / 32));
   // pass 1: G = Y^T Y, T1, Q1 = Y T1^-1
   HIPCHK(h, (launch_cross2<T, T>(Y, kk, col0, Y, kk, col0, k, nh, rows, k, k, w.Gp, parts, st)));
-  HIPCHK(h, launch_sum_parts(w.Gp, parts, (int64_t)nh * k * k, w.G, st));
-  HIPCHK(h, launch_chol_inv(w.G, nh, k, w.Tinv, nullptr, w.flags, st));
+  HIPCHK(h, launch_gram_chol(w.Gp, parts, nh, k, w.G, w.Tinv, w.flags, w.counters, st));
   // apply writes Q64 columns col0 + h*k via an offset view
   HIPCHK(h, (launch_apply_tinv<T>(Y + col0, rows, kk, nh, k, w.Tinv, w.Q64 + col0, kk, st)));
   // pass 2 on Q1
   HIPCHK(h, (launch_cross2<double, double>(w.Q64, kk, col0, w.Q64, kk, col0, k, nh, rows, k, k, w.Gp, parts, st)));
-  HIPCHK(h, launch_sum_parts(w.Gp, parts, (int64_t)nh * k * k, w.G, st));
-  HIPCHK(h, launch_chol_inv(w.G, nh, k, w.Tinv, nullptr, w.flags, st));
+  HIPCHK(h, launch_gram_chol(w.Gp, parts, nh, k, w.G, w.Tinv, w.flags, w.counters, st));
   HIPCHK(h, (launch_apply_tinv<double>(w.Q64 + col0, rows, kk, nh, k, w.Tinv, w.Q64 + col0, kk, st)));
   return CNMF_OK;
 }
@@ -351,6 +413,7 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
   const T* Ap = (const T*)A->data_dev;
   const int64_t lda = A->lda;
   HIPCHK(h, launch_fill(w.flags, 4 * sizeof(int), st));
+  HIPCHK(h, launch_fill(w.counters, 4 * sizeof(unsigned), st));
 
   auto operand_for = [&](const Pass& p) -> T* { return p.dirN ? w.Xop : w.Zop; };
   // stage the first operands (Omegas) of the chains
@@ -377,10 +440,15 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
     T* op = operand_for(p);
     int splits = p.dirN ? choose_splits_n(m, n, p.kk, sizeof(T)) : choose_splits_t(m, n, p.kk, sizeof(T));
     T* dst = splits > 1 ? w.Ppart : w.Y;
-    if (p.dirN)
-      HIPCHK(h, launch_gemm_n<T>(Ap, lda, m, n, op, p.kk, dst, splits, st));
-    else
-      HIPCHK(h, launch_gemm_t<T>(Ap, lda, m, n, op, p.kk, dst, splits, st));
+    {
+      const double flops = 2.0 * m * n * (double)(k * (int)p.blocks.size());
+      Span sp(h, p.dirN ? ST_PASS_N : ST_PASS_T, flops);
+      if (p.dirN)
+        HIPCHK(h, launch_gemm_n<T>(Ap, lda, m, n, op, p.kk, dst, splits, st));
+      else
+        HIPCHK(h, launch_gemm_t<T>(Ap, lda, m, n, op, p.kk, dst, splits, st));
+    }
+    Span orth_span(h, ST_ORTH);
     if (splits > 1) HIPCHK(h, launch_reduce_splits<T>(w.Ppart, splits, rows, p.kk, w.Y, st));
 
     // orthonormalise the range blocks (contiguous)
@@ -443,6 +511,7 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
   }
   // At = L^T A R^T = B R^T = (B^T)^T R^T, a k x k product over n rows
   if ((d->sides & CNMF_BOTH) == CNMF_BOTH) {
+    Span sp(h, ST_ORTH);
     int parts = std::min(w.gparts, std::max(1, n / 32));
     HIPCHK(h, (launch_cross2<T, T>(w.BTb, k, 0, w.RTb, k, 0, 0, 1, n, k, k, w.Gp, parts, st)));
     HIPCHK(h, launch_sum_parts(w.Gp, parts, (int64_t)k * k, w.At, st));
@@ -520,6 +589,7 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
   HIPCHK(h, launch_fill(aw.counter, 4 * sizeof(unsigned), st));
 
   if (d->method == CNMF_ADMM) {
+    Span sp(h, ST_ITER, (double)d->iters * 4.0 * (double)(m + n) * k * r);
     AdmmSide s0{w.Lb, k, aw.U, aw.Lam, r, m, d->lambda};
     AdmmSide s1{w.RTb, k, aw.Vt, aw.Phit, r, n, d->phi};
     HIPCHK(h, launch_admm_uv<T>(s0, s1, 2, aw.XY, k, r, d->xi, 0, aw.Pp, aw.parts0, aw.parts1, st));
@@ -535,6 +605,7 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
   if (o->U_dev) HIPCHK(h, (launch_copy2d<T, T>(aw.U, r, (T*)o->U_dev, r, m, r, 1.0, st)));
   if (o->V_dev) HIPCHK(h, (launch_transpose<T, T>(aw.Vt, r, (T*)o->V_dev, n, n, r, st)));
   if (o->rel_residual_dev) {
+    Span sp(h, ST_RESID, 2.0 * m * n * (double)r);
     HIPCHK(h, launch_residual<T>((const T*)A->data_dev, A->lda, m, n, aw.U, r, aw.Vt, r, r, aw.rpart, aw.rparts, st));
     HIPCHK(h, launch_residual_finish(aw.rpart, aw.rparts, o->rel_residual_dev, st));
   }
@@ -568,9 +639,12 @@ cnmf_status do_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_des
   s = run_sketch<T>(h, A, d, w, passes, nullptr);
   if (s != CNMF_OK) return s;
   HIPCHK(h, (launch_copy2d<T, double>(w.BTb, k, Bt64, k, n, k, 1.0, st)));
-  HIPCHK(h, launch_fill(ctr, 4 * sizeof(unsigned), st));
-  for (int t = 0; t < d->r; ++t)
-    HIPCHK(h, launch_spa_step(Bt64, n, k, k, t, K, score, u, wb, wi, ctr, nblk, st));
+  {
+    Span sp(h, ST_SPA);
+    HIPCHK(h, launch_fill(ctr, 4 * sizeof(unsigned), st));
+    for (int t = 0; t < d->r; ++t)
+      HIPCHK(h, launch_spa_step(Bt64, n, k, k, t, K, score, u, wb, wi, ctr, nblk, st));
+  }
   if (B_out) HIPCHK(h, (launch_transpose<T, T>(w.BTb, k, (T*)B_out, n, n, k, st)));
   return CNMF_OK;
 }
@@ -612,7 +686,7 @@ cnmf_status cnmf_create(int device, void* hip_stream, size_t workspace_limit, cn
   h->device = device;
   h->stream = (hipStream_t)hip_stream;
   h->limit = workspace_limit;
-  for (int i = 0; i < 8; ++i) h->stage_ms[i] = std::numeric_limits<double>::quiet_NaN();
+  timing_reset(h);
   *out = h;
   return CNMF_OK;
 }
@@ -623,8 +697,7 @@ cnmf_status cnmf_destroy(cnmf_handle* h) {
     hipStreamSynchronize(h->stream);
     hipFree(h->ws);
   }
-  for (int i = 0; i < 8; ++i)
-    if (h->ev[i]) hipEventDestroy(h->ev[i]);
+  for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
   delete h;
   return CNMF_OK;
 }
@@ -636,8 +709,19 @@ cnmf_status cnmf_set_timing(cnmf_handle* h, int enable) {
 }
 
 double cnmf_stage_ms(cnmf_handle* h, int stage) {
-  if (!h || stage < 0 || stage >= 8) return std::numeric_limits<double>::quiet_NaN();
-  return h->stage_ms[stage];
+  if (!h || stage < 0 || stage >= kStages || !h->timing) return std::numeric_limits<double>::quiet_NaN();
+  timing_resolve(h);
+  return h->stage_count[stage] ? h->stage_ms[stage] : std::numeric_limits<double>::quiet_NaN();
+}
+
+double cnmf_stage_flops(cnmf_handle* h, int stage) {
+  if (!h || stage < 0 || stage >= kStages) return 0.0;
+  return h->stage_flops[stage];
+}
+
+int cnmf_stage_launches(cnmf_handle* h, int stage) {
+  if (!h || stage < 0 || stage >= kStages) return 0;
+  return h->stage_count[stage];
 }
 
 cnmf_status cnmf_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, cnmf_sketch_out* out) {
@@ -647,6 +731,7 @@ cnmf_status cnmf_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_d
   if (s != CNMF_OK) return s;
   if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
   HIPCHK(h, hipSetDevice(h->device));
+  timing_reset(h);
   bool want_ac = out && out->Ac_dev && (d->sides & CNMF_RIGHT);
   if (A->dtype == CNMF_F64) return do_sketch<double>(h, A, d, out, want_ac);
   return do_sketch<float>(h, A, d, out, want_ac);
@@ -680,6 +765,7 @@ cnmf_status cnmf_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_facto
   if (!out) return fail(h, CNMF_EINVAL, "out is NULL");
   if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
   HIPCHK(h, hipSetDevice(h->device));
+  timing_reset(h);
   if (A->dtype == CNMF_F64) return do_factorize<double>(h, A, d, out);
   return do_factorize<float>(h, A, d, out);
 }
@@ -694,6 +780,7 @@ cnmf_status snmf_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_d
   if (!K_dev) return fail(h, CNMF_EINVAL, "K_dev is NULL");
   if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
   HIPCHK(h, hipSetDevice(h->device));
+  timing_reset(h);
   if (A->dtype == CNMF_F64) return do_select<double>(h, A, d, K_dev, score_dev, B_dev);
   return do_select<float>(h, A, d, K_dev, score_dev, B_dev);
 }
