@@ -97,6 +97,34 @@ hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const dou
                              double lam, double phi, int first, double* XY, double* Pred,
                              unsigned* counter, int* flags, hipStream_t st);
 
+// Generic row update for MU and the uncompressed comparators (k_nmf.hip).
+struct RowArgs {
+  int rows, k1, r, k2;
+  const void* B1;
+  int ldb1;
+  const double* C;
+  void* F;
+  int ldf;
+  void* Mu;
+  const double* Gp;
+  const double* Gm;
+  const double* Minv;
+  double pen, xi, eps;
+  int method;  // 0 MU, 1 ADMM (uncompressed), 2 partials only
+  const void* B2;
+  int ldb2;
+  void* Op;
+  int ldop;
+  double* Pp;
+  int rows_per_block;
+};
+template <typename T>
+hipError_t launch_nmf_row(const RowArgs& a, int blocks, hipStream_t st);
+// mode 0: G = C^T C (C = S, k x r) -> G+, G-; mode 1: G = S (r x r) -> G+, G-;
+// mode 2: Gp = (S + pen I)^-1 (S the r x r Gram).
+hipError_t launch_nmf_small(const double* S, int k, int r, int mode, double pen, double* Gp, double* Gm, int* flags,
+                            hipStream_t st);
+
 // ---------------------------------------------------------------------------
 // Misc
 // ---------------------------------------------------------------------------

@@ -558,28 +558,103 @@ cnmf_status do_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_des
   return write_sketch_outputs<T>(h, A, d, w, o);
 }
 
+// Buffers of the multiplicative / uncompressed iterations.
+template <typename T>
+struct IterWs {
+  T* Xop = nullptr;    // n x kk operand (Y^T rows) for A passes
+  T* Zop = nullptr;    // m x kk operand (X rows) for A^T passes
+  T* Pn = nullptr;     // m x kk pass output
+  T* Pt = nullptr;     // n x kk pass output
+  T* Ppart = nullptr;  // split partials
+  double* PpX = nullptr;
+  double* PpY = nullptr;
+  double* S = nullptr;
+  double* Gp = nullptr;
+  double* Gm = nullptr;
+  int kk = 16, bx = 1, by = 1;
+};
+
+int row_blocks(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(512, (rows + 63) / 64)); }
+
+template <typename T>
+void layout_iter(Arena& a, IterWs<T>& w, int64_t m, int64_t n, int k, int r, bool full) {
+  w.kk = ru16(r);
+  w.bx = row_blocks(m);
+  w.by = row_blocks(n);
+  const int k2 = full ? r : k;
+  if (full) {
+    w.Xop = a.take<T>((size_t)n * w.kk);
+    w.Zop = a.take<T>((size_t)m * w.kk);
+    w.Pn = a.take<T>((size_t)m * w.kk);
+    w.Pt = a.take<T>((size_t)n * w.kk);
+    int sn = choose_splits_n((int)m, (int)n, w.kk, sizeof(T)), stt = choose_splits_t((int)m, (int)n, w.kk, sizeof(T));
+    size_t pm = std::max((size_t)(sn > 1 ? sn : 0) * m, (size_t)(stt > 1 ? stt : 0) * n) * w.kk;
+    w.Ppart = a.take<T>(std::max<size_t>(pm, 1));
+  }
+  w.PpX = a.take<double>((size_t)w.bx * k2 * r);
+  w.PpY = a.take<double>((size_t)w.by * k2 * r);
+  w.S = a.take<double>((size_t)std::max(k2, r) * r);
+  w.Gp = a.take<double>((size_t)r * r);
+  w.Gm = a.take<double>((size_t)r * r);
+}
+
+template <typename T>
+cnmf_status pass_full(cnmf_handle* h, const cnmf_input* A, bool dirN, const T* op, int kk, T* out, T* ppart) {
+  hipStream_t st = h->stream;
+  const int m = (int)A->m, n = (int)A->n;
+  const T* Ap = (const T*)A->data_dev;
+  const int splits = dirN ? choose_splits_n(m, n, kk, sizeof(T)) : choose_splits_t(m, n, kk, sizeof(T));
+  T* dst = splits > 1 ? ppart : out;
+  {
+    Span sp(h, dirN ? ST_PASS_N : ST_PASS_T, 2.0 * m * n * (double)kk);
+    if (dirN)
+      HIPCHK(h, launch_gemm_n<T>(Ap, A->lda, m, n, op, kk, dst, splits, st));
+    else
+      HIPCHK(h, launch_gemm_t<T>(Ap, A->lda, m, n, op, kk, dst, splits, st));
+  }
+  if (splits > 1) HIPCHK(h, launch_reduce_splits<T>(ppart, splits, dirN ? m : n, kk, out, st));
+  return CNMF_OK;
+}
+
 template <typename T>
 cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
                          const cnmf_factorize_out* o) {
   const cnmf_sketch_desc* sk = &d->sk;
+  const bool full = d->method == CNMF_ADMM_FULL || d->method == CNMF_MU_FULL;
   const bool want_ac = d->method == CNMF_MU;
-  std::vector<Pass> passes = plan_passes(sk->k, sk->q, CNMF_BOTH, want_ac);
-  if (passes.empty()) return fail(h, CNMF_EINVAL, "internal: empty pass plan");
+  std::vector<Pass> passes;
+  if (!full) {
+    passes = plan_passes(sk->k, sk->q, CNMF_BOTH, want_ac);
+    if (passes.empty()) return fail(h, CNMF_EINVAL, "internal: empty pass plan");
+  }
   const int m = (int)A->m, n = (int)A->n, k = sk->k, r = sk->r;
   Arena dry(nullptr);
   SketchWs<T> w;
   AdmmWs<T> aw;
-  layout_sketch<T>(dry, w, m, n, k, passes, want_ac);
+  IterWs<T> iw;
+  if (!full) layout_sketch<T>(dry, w, m, n, k, passes, want_ac);
+  else {
+    w.flags = dry.take<int>(4);
+  }
   layout_admm<T>(dry, aw, m, n, k, r);
+  if (d->method != CNMF_ADMM) layout_iter<T>(dry, iw, m, n, k, r, full);
   cnmf_status s = ensure_ws(h, dry.off);
   if (s != CNMF_OK) return s;
   Arena a(h->ws);
-  layout_sketch<T>(a, w, m, n, k, passes, want_ac);
+  if (!full) layout_sketch<T>(a, w, m, n, k, passes, want_ac);
+  else {
+    w.flags = a.take<int>(4);
+  }
   layout_admm<T>(a, aw, m, n, k, r);
+  if (d->method != CNMF_ADMM) layout_iter<T>(a, iw, m, n, k, r, full);
   hipStream_t st = h->stream;
 
-  s = run_sketch<T>(h, A, sk, w, passes, o->sk_out.stats_dev);
-  if (s != CNMF_OK) return s;
+  if (!full) {
+    s = run_sketch<T>(h, A, sk, w, passes, o->sk_out.stats_dev);
+    if (s != CNMF_OK) return s;
+  } else {
+    HIPCHK(h, launch_fill(w.flags, 4 * sizeof(int), st));
+  }
 
   // state: U = U0, V^T = V0^T, Lam = Phi = 0
   HIPCHK(h, (launch_copy2d<double, T>(d->U0_dev, r, aw.U, r, m, r, 1.0, st)));
@@ -587,6 +662,41 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
   HIPCHK(h, launch_fill(aw.Lam, sizeof(T) * (size_t)m * r, st));
   HIPCHK(h, launch_fill(aw.Phit, sizeof(T) * (size_t)n * r, st));
   HIPCHK(h, launch_fill(aw.counter, 4 * sizeof(unsigned), st));
+
+  auto row = [&](int rows, int blocks, const void* B1, int ldb1, const double* C, int k1, T* F, T* Mu,
+                 const double* Gp, const double* Gm, const double* Minv, double pen, int method, const void* B2,
+                 int k2, T* Op, double* Pp) -> cnmf_status {
+    RowArgs ra{};
+    ra.rows = rows;
+    ra.k1 = k1;
+    ra.r = r;
+    ra.k2 = k2;
+    ra.B1 = B1;
+    ra.ldb1 = ldb1;
+    ra.C = C;
+    ra.F = F;
+    ra.ldf = r;
+    ra.Mu = Mu;
+    ra.Gp = Gp;
+    ra.Gm = Gm;
+    ra.Minv = Minv;
+    ra.pen = pen;
+    ra.xi = d->xi;
+    ra.eps = d->mu_eps;
+    ra.method = method;
+    ra.B2 = B2;
+    ra.ldb2 = k;
+    ra.Op = Op;
+    ra.ldop = iw.kk;
+    ra.Pp = Pp;
+    HIPCHK(h, launch_nmf_row<T>(ra, blocks, st));
+    return CNMF_OK;
+  };
+#define RUN(expr)                        \
+  do {                                   \
+    cnmf_status _s = (expr);             \
+    if (_s != CNMF_OK) return _s;        \
+  } while (0)
 
   if (d->method == CNMF_ADMM) {
     Span sp(h, ST_ITER, (double)d->iters * 4.0 * (double)(m + n) * k * r);
@@ -598,9 +708,45 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
                                      aw.Pred, aw.counter, w.flags + 2, st));
       HIPCHK(h, launch_admm_uv<T>(s0, s1, 2, aw.XY, k, r, d->xi, 1, aw.Pp, aw.parts0, aw.parts1, st));
     }
+  } else if (d->method == CNMF_MU) {
+    Span sp(h, ST_ITER, (double)d->iters * (4.0 * (double)(m + n) * k * r + 4.0 * (double)(m + n) * r * r));
+    // initial Yc^T = R V0^T
+    RUN(row(n, iw.by, nullptr, 0, nullptr, k, aw.Vt, nullptr, nullptr, nullptr, nullptr, 0.0, 2, w.RTb, k, nullptr,
+            iw.PpY));
+    for (int it = 0; it < d->iters; ++it) {
+      HIPCHK(h, launch_sum_parts(iw.PpY, iw.by, (int64_t)k * r, iw.S, st));
+      HIPCHK(h, launch_nmf_small(iw.S, k, r, 0, 0.0, iw.Gp, iw.Gm, nullptr, st));
+      RUN(row(m, iw.bx, w.Acb, k, iw.S, k, aw.U, nullptr, iw.Gp, iw.Gm, nullptr, 0.0, 0, w.Lb, k, nullptr, iw.PpX));
+      HIPCHK(h, launch_sum_parts(iw.PpX, iw.bx, (int64_t)k * r, iw.S, st));
+      HIPCHK(h, launch_nmf_small(iw.S, k, r, 0, 0.0, iw.Gp, iw.Gm, nullptr, st));
+      RUN(row(n, iw.by, w.BTb, k, iw.S, k, aw.Vt, nullptr, iw.Gp, iw.Gm, nullptr, 0.0, 0, w.RTb, k, nullptr,
+              iw.PpY));
+    }
   } else {
-    return fail(h, CNMF_ENOTSUP, "method %d is not available in this build", d->method);
+    // uncompressed comparators: L = I, R = I, two streaming passes per iteration
+    const bool admm = d->method == CNMF_ADMM_FULL;
+    const int kk = iw.kk;
+    Span sp(h, ST_ITER, (double)d->iters * 4.0 * (double)m * n * r);
+    HIPCHK(h, launch_fill(iw.Xop, sizeof(T) * (size_t)n * kk, st));
+    HIPCHK(h, launch_fill(iw.Zop, sizeof(T) * (size_t)m * kk, st));
+    HIPCHK(h, (launch_copy2d<T, T>(aw.Vt, r, iw.Xop, kk, n, r, 1.0, st)));
+    // initial Gram of V0^T (= Yt^T for ADMM)
+    RUN(row(n, iw.by, nullptr, 0, nullptr, r, aw.Vt, nullptr, nullptr, nullptr, nullptr, 0.0, 2, nullptr, r, nullptr,
+            iw.PpY));
+    for (int it = 0; it < d->iters; ++it) {
+      HIPCHK(h, launch_sum_parts(iw.PpY, iw.by, (int64_t)r * r, iw.S, st));
+      HIPCHK(h, launch_nmf_small(iw.S, r, r, admm ? 2 : 1, d->lambda, iw.Gp, iw.Gm, w.flags + 2, st));
+      RUN(pass_full<T>(h, A, true, iw.Xop, kk, iw.Pn, iw.Ppart));
+      RUN(row(m, iw.bx, iw.Pn, kk, nullptr, r, aw.U, admm ? aw.Lam : nullptr, iw.Gp, iw.Gm, iw.Gp, d->lambda,
+              admm ? 1 : 0, nullptr, r, iw.Zop, iw.PpX));
+      HIPCHK(h, launch_sum_parts(iw.PpX, iw.bx, (int64_t)r * r, iw.S, st));
+      HIPCHK(h, launch_nmf_small(iw.S, r, r, admm ? 2 : 1, d->phi, iw.Gp, iw.Gm, w.flags + 2, st));
+      RUN(pass_full<T>(h, A, false, iw.Zop, kk, iw.Pt, iw.Ppart));
+      RUN(row(n, iw.by, iw.Pt, kk, nullptr, r, aw.Vt, admm ? aw.Phit : nullptr, iw.Gp, iw.Gm, iw.Gp, d->phi,
+              admm ? 1 : 0, nullptr, r, iw.Xop, iw.PpY));
+    }
   }
+#undef RUN
 
   if (o->U_dev) HIPCHK(h, (launch_copy2d<T, T>(aw.U, r, (T*)o->U_dev, r, m, r, 1.0, st)));
   if (o->V_dev) HIPCHK(h, (launch_transpose<T, T>(aw.Vt, r, (T*)o->V_dev, n, n, r, st)));
@@ -609,6 +755,7 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
     HIPCHK(h, launch_residual<T>((const T*)A->data_dev, A->lda, m, n, aw.U, r, aw.Vt, r, r, aw.rpart, aw.rparts, st));
     HIPCHK(h, launch_residual_finish(aw.rpart, aw.rparts, o->rel_residual_dev, st));
   }
+  if (full) return CNMF_OK;
   return write_sketch_outputs<T>(h, A, sk, w, &o->sk_out);
 }
 
@@ -739,8 +886,19 @@ cnmf_status cnmf_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_d
 
 static cnmf_status check_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d) {
   if (!d) return fail(h, CNMF_EINVAL, "factorize descriptor is NULL");
-  cnmf_status s = check_sketch(h, A, &d->sk);
-  if (s != CNMF_OK) return s;
+  if (d->method == CNMF_ADMM_FULL || d->method == CNMF_MU_FULL) {
+    cnmf_sketch_desc sk = d->sk;  // only r and the precision matter
+    sk.k = sk.r + 1 <= std::min(A->m, A->n) ? sk.r + 1 : sk.r;
+    sk.sides = CNMF_LEFT;
+    sk.q = 0;
+    sk.omega_left_dev = (const double*)1;
+    cnmf_status s = check_sketch(h, A, &sk);
+    if (s != CNMF_OK) return s;
+  } else {
+    cnmf_status s = check_sketch(h, A, &d->sk);
+    if (s != CNMF_OK) return s;
+  }
+  cnmf_status s = CNMF_OK;
   if (d->method < CNMF_ADMM || d->method > CNMF_MU_FULL) return fail(h, CNMF_EINVAL, "unknown method %d", d->method);
   if ((d->method == CNMF_ADMM || d->method == CNMF_MU) && d->sk.sides != CNMF_BOTH)
     return fail(h, CNMF_EINVAL, "compressed NMF needs sides = CNMF_BOTH");
@@ -870,19 +1028,25 @@ cnmf_status cnmf_workspace_bytes(int64_t m, int64_t n, const cnmf_factorize_desc
     return fail(nullptr, CNMF_EINVAL, "need 1 <= r < k <= min(m, n), k <= 128");
   const bool f64 = d->sk.pass_dtype == CNMF_F64;
   const bool want_ac = d->method == CNMF_MU;
+  const bool full = d->method == CNMF_ADMM_FULL || d->method == CNMF_MU_FULL;
   std::vector<Pass> passes = plan_passes(k, d->sk.q, d->sk.sides ? d->sk.sides : CNMF_BOTH, want_ac);
   Arena dry(nullptr);
-  if (f64) {
-    SketchWs<double> w;
-    AdmmWs<double> aw;
-    layout_sketch<double>(dry, w, m, n, k, passes, want_ac);
-    if (d->iters > 0) layout_admm<double>(dry, aw, m, n, k, r);
-  } else {
-    SketchWs<float> w;
-    AdmmWs<float> aw;
-    layout_sketch<float>(dry, w, m, n, k, passes, want_ac);
-    if (d->iters > 0) layout_admm<float>(dry, aw, m, n, k, r);
-  }
+  auto go = [&](auto tag) {
+    typedef decltype(tag) T;
+    SketchWs<T> w;
+    AdmmWs<T> aw;
+    IterWs<T> iw;
+    if (!full)
+      layout_sketch<T>(dry, w, m, n, k, passes, want_ac);
+    else
+      dry.take<int>(4);
+    if (d->iters > 0 || full) layout_admm<T>(dry, aw, m, n, k, r);
+    if (d->method != CNMF_ADMM) layout_iter<T>(dry, iw, m, n, k, r, full);
+  };
+  if (f64)
+    go(double{});
+  else
+    go(float{});
   *bytes = dry.off;
   return CNMF_OK;
 }

@@ -192,3 +192,66 @@ def test_select_separable_fp32_two_sided():
     assert sorted(Kg) == list(planted)
     # same decision on the GPU's own B taken by the oracle's SPA
     assert Kg == O.spa(host(B), 15)
+
+
+# --------------------------------------------------------------------------
+# Alg. 2 (compressed MU) and the uncompressed comparators
+# --------------------------------------------------------------------------
+
+def test_factorize_mu_fp64_parity(c1):
+    w, inp, sk, *_ = c1
+    iters = 60
+    ref = O.mu(sk["Ac"], sk["B"], sk["L"], sk["R"], inp["U1"], inp["V1"], iters, 1e-16)
+    f = api.factorize(dev(inp["A"]), w.r, w.k, w.q, dev(inp["U1"]), dev(inp["V1"]), dev(inp["Omega_L"]),
+                      dev(inp["Omega_R"]), method="mu", iters=iters, mu_eps=1e-16)
+    assert rel(host(f.U), ref["X"]) < 1e-10
+    assert rel(host(f.V), ref["Y"]) < 1e-10
+    res = O.rel_residual(inp["A"], ref["X"], ref["Y"])
+    assert abs(float(host(f.rel_residual)[0]) - res) <= 1e-10 * res
+
+
+@pytest.fixture(scope="module")
+def small_full():
+    g = np.random.default_rng(200)
+    m, n, r = 613, 389, 7
+    A = g.random((m, r)) @ g.random((r, n)) + np.abs(0.01 * g.standard_normal((m, n)))
+    U1, V1 = WL.init_factors(A.mean(), m, n, r, 201)
+    lam = float(np.linalg.svd(A, compute_uv=False)[r - 1])
+    return A, U1, V1, r, lam
+
+
+def test_factorize_admm_full_fp64_parity(small_full):
+    A, U1, V1, r, lam = small_full
+    ref = O.admm_uncompressed(A, U1, V1, lam, 1.3 * lam, 1.0, 40)
+    f = api.factorize(dev(A), r, r + 1, 0, dev(U1), dev(V1), method="admm_full", iters=40, lam=lam, phi=1.3 * lam)
+    assert rel(host(f.U), ref["U"]) < 1e-10
+    assert rel(host(f.V), ref["V"]) < 1e-10
+
+
+def test_factorize_mu_full_fp64_parity(small_full):
+    A, U1, V1, r, _ = small_full
+    ref = O.mu_uncompressed(A, U1, V1, 40, 1e-16)
+    f = api.factorize(dev(A), r, r + 1, 0, dev(U1), dev(V1), method="mu_full", iters=40, mu_eps=1e-16)
+    assert rel(host(f.U), ref["X"]) < 1e-10
+    assert rel(host(f.V), ref["Y"]) < 1e-10
+
+
+@pytest.mark.parametrize("method", ["mu", "admm_full", "mu_full"])
+def test_factorize_fp32_methods_residual_gap(method):
+    w, inp, A64, sk, lam = _fp32_case(3000, 1200, 30)
+    iters = 30
+    if method == "mu":
+        ref = O.mu(sk["Ac"], sk["B"], sk["L"], sk["R"], inp["U1"], inp["V1"], iters, 1e-16)
+        U, V = ref["X"], ref["Y"]
+    elif method == "admm_full":
+        ref = O.admm_uncompressed(A64, inp["U1"], inp["V1"], lam, lam, 1.0, iters)
+        U, V = ref["U"], ref["V"]
+    else:
+        ref = O.mu_uncompressed(A64, inp["U1"], inp["V1"], iters, 1e-16)
+        U, V = ref["X"], ref["Y"]
+    res_o = O.rel_residual(A64, U, V)
+    f = api.factorize(dev(inp["A"], torch.float32), w.r, w.k, w.q, dev(inp["U1"]), dev(inp["V1"]),
+                      dev(inp["Omega_L"]), dev(inp["Omega_R"]), method=method, iters=iters, lam=lam, phi=lam,
+                      mu_eps=1e-16)
+    res_g = float(host(f.rel_residual)[0])
+    assert abs(res_g - res_o) <= 1e-3
