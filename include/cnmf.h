@@ -96,12 +96,20 @@ typedef struct {
 /* Sketch parameters (Alg. 1 inputs: target rank r, oversampling r_ov with
  * k = r + r_ov, exponent w = q).  Valid: 1 <= r < k <= min(m, n), k <= 128,
  * q >= 0.  `sides` selects L (CNMF_LEFT), R (CNMF_RIGHT) or both.
- * pass_dtype: precision of the GEMM operands of the range-finder passes:
+ * pass_dtype: precision of the GEMM operands of the power-iteration passes
+ *   (the 2q passes before the last range product of each chain):
  *   CNMF_F64 (needs F64 input: everything in FP64), CNMF_F32, CNMF_BF16 or
- *   CNMF_FP8_E4M3 (FP32 input; A is converted once into a workspace copy;
- *   accumulation is FP32).
- * final_dtype: precision of the last range pass and of the B / Ac pass
- *   (CNMF_F64 with F64 input; CNMF_F32 or CNMF_BF16 otherwise).
+ *   CNMF_FP8_E4M3 (FP32 input; accumulation is FP32).  For BF16 / FP8, A
+ *   is converted once per call into workspace copies of A and A^T (round
+ *   to nearest even; FP8 E4M3 with one FP32 scale max|tile| / 448 per
+ *   128 x 128 tile of A, each tile's partial product rescaled in FP32), and
+ *   each pass operand column is rounded to the pass type (FP8: after
+ *   scaling by a power of two, which the orthonormalisation absorbs).
+ * final_dtype: precision of the last range pass of each chain and of the
+ *   B / Ac pass (CNMF_F64 with F64 input; CNMF_F32 or CNMF_BF16 otherwise;
+ *   CNMF_FP8_E4M3 returns CNMF_ENOTSUP: B and Ac are used unscaled).
+ *   The workspace grows by 4 m n bytes for BF16 copies and 2 m n bytes
+ *   for FP8 copies.
  * Orthonormalisation (CholeskyQR2) always runs in FP64.
  * omega_left_dev:  n x k FP64, row-major (ld = k): test matrix for A.
  * omega_right_dev: m x k FP64, row-major (ld = k): test matrix for A^T
@@ -190,6 +198,18 @@ cnmf_status cnmf_spa(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_
  * cnmf_sketch runs. */
 cnmf_status cnmf_range_product(cnmf_handle* h, const cnmf_input* A, int trans, const void* X_dev, int32_t kx,
                                void* Y_dev);
+
+/* The same pass with reduced-precision operands (Alg. 1 product step in the
+ * precision form of the passes): A (F32 input) is converted to BF16 or FP8
+ * E4M3 exactly as cnmf_sketch converts it, X_dev (FP64, cols x kx, ld = kx,
+ * cols = n for trans == 0, m for trans == 1) is rounded per column as a pass
+ * operand (FP8: scaled by the largest power of two s_c with
+ * max|X[:, c]| s_c <= 256, then rounded), the product is accumulated in
+ * FP32 and Y_dev (FP32, rows_out x kx, ld = kx) is returned with the FP8
+ * column scales divided out.  pass_dtype must be CNMF_BF16 or
+ * CNMF_FP8_E4M3. */
+cnmf_status cnmf_range_product_lowp(cnmf_handle* h, const cnmf_input* A, int trans, cnmf_dtype pass_dtype,
+                                    const double* X_dev, int32_t kx, float* Y_dev);
 
 /* Device workspace (bytes) that cnmf_factorize (or, with iters = 0 and
  * method CNMF_ADMM, cnmf_sketch) needs for an m x n input.  Host only; no

@@ -23,6 +23,7 @@ EXPORTED = [
     "cnmf_create", "cnmf_destroy", "cnmf_last_error", "cnmf_status_string", "cnmf_version",
     "cnmf_sketch", "cnmf_factorize", "snmf_select", "cnmf_spa", "cnmf_workspace_bytes",
     "cnmf_set_timing", "cnmf_stage_ms", "cnmf_range_product", "cnmf_stage_flops", "cnmf_stage_launches",
+    "cnmf_range_product_lowp",
 ]
 
 
@@ -96,6 +97,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.cnmf_workspace_bytes.restype = st
     lib.cnmf_range_product.argtypes = [vp, C.POINTER(cnmf_input), C.c_int, vp, i32, vp]
     lib.cnmf_range_product.restype = st
+    lib.cnmf_range_product_lowp.argtypes = [vp, C.POINTER(cnmf_input), C.c_int, C.c_int, vp, i32, vp]
+    lib.cnmf_range_product_lowp.restype = st
     lib.cnmf_set_timing.argtypes = [vp, C.c_int]
     lib.cnmf_set_timing.restype = st
     lib.cnmf_stage_ms.argtypes = [vp, C.c_int]

@@ -222,10 +222,30 @@ def range_product(A, X, trans=False, handle: Handle | None = None):
     return Y
 
 
-def workspace_bytes(m, n, r, k, q, method="admm", iters=100, pass_dtype="f32"):
+def range_product_lowp(A, X, trans=False, pass_dtype="bf16", handle: Handle | None = None):
+    """One pass with BF16 / FP8 operands: A @ X or A.T @ X, FP32 result.
+
+    A: FP32 device matrix; X: FP64, (n or m) x kx.  FP8 operand column scales
+    are divided out of the result."""
+    h = handle or default_handle()
+    if A.dtype != torch.float32:
+        raise ValueError("reduced-precision passes need an FP32 A")
+    if X.dtype != torch.float64 or X.dim() != 2 or not X.is_contiguous():
+        raise ValueError("X must be a contiguous 2-D FP64 tensor")
+    rows_out = A.shape[1] if trans else A.shape[0]
+    Y = torch.empty((rows_out, X.shape[1]), dtype=torch.float32, device=A.device)
+    inp = _input(A)
+    L.check(h._lib.cnmf_range_product_lowp(h.raw, C.byref(inp), int(bool(trans)), _PREC[pass_dtype], _ptr(X),
+                                           X.shape[1], _ptr(Y)), h.raw)
+    return Y
+
+
+def workspace_bytes(m, n, r, k, q, method="admm", iters=100, pass_dtype="f32", final_dtype=None):
     """Device workspace a factorisation of an m x n input needs (host only)."""
     lib = L.load()
-    d = L.cnmf_factorize_desc(_sketch_desc(r, k, q, L.CNMF_BOTH, None, None, pass_dtype, pass_dtype),
+    if final_dtype is None:
+        final_dtype = pass_dtype if pass_dtype in ("f64", "f32") else "bf16"
+    d = L.cnmf_factorize_desc(_sketch_desc(r, k, q, L.CNMF_BOTH, None, None, pass_dtype, final_dtype),
                               _METHODS[method], int(iters), 1.0, 1.0, 1.0, 0.0, None, None)
     out = C.c_size_t()
     L.check(lib.cnmf_workspace_bytes(int(m), int(n), C.byref(d), C.byref(out)))

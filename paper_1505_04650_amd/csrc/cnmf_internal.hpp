@@ -32,21 +32,29 @@ hipError_t launch_gemm_t(const T* A, int64_t lda, int m, int n, const T* Z, int 
 int choose_splits_n(int m, int n, int kk, int elem_bytes);
 int choose_splits_t(int m, int n, int kk, int elem_bytes);
 
-// Reduced-precision passes: A16 (bf16) or A8 (fp8 e4m3 with per-tile scales)
-// against operands of the same type; FP32 accumulation.
-hipError_t launch_gemm_n_bf16(const __hip_bfloat16* A, int64_t lda, int m, int n,
-                              const __hip_bfloat16* X, int kk, float* P, int splits, hipStream_t st);
-hipError_t launch_gemm_t_bf16(const __hip_bfloat16* A, int64_t lda, int m, int n,
-                              const __hip_bfloat16* Z, int kk, float* P, int splits, hipStream_t st);
-hipError_t launch_gemm_n_fp8(const uint8_t* A, int64_t lda, const float* tile_scale, int m, int n,
-                             const uint8_t* X, int kk, float* P, int splits, hipStream_t st);
-hipError_t launch_gemm_t_fp8(const uint8_t* A, int64_t lda, const float* tile_scale, int m, int n,
-                             const uint8_t* Z, int kk, float* P, int splits, hipStream_t st);
-hipError_t launch_convert_a_bf16(const float* A, int64_t lda, int m, int n, __hip_bfloat16* Ab,
-                                 int64_t ldb, hipStream_t st);
-hipError_t launch_convert_a_fp8(const float* A, int64_t lda, int m, int n, uint8_t* A8, int64_t ld8,
-                                float* tile_scale, hipStream_t st);
+// Reduced-precision passes (k_lowp.hip).  A copy of A (m x n) and of A^T
+// (n x m) in BF16 or FP8 E4M3; FP8 copies carry one FP32 scale per
+// kFp8Tile x kFp8Tile tile of A (scale[ti * ntj + tj], ntj column tiles),
+// shared by the A^T copy.  Either output pointer may be NULL.
 constexpr int kFp8Tile = 128;
+hipError_t launch_convert_lowp(const float* A, int64_t lda, int m, int n, __hip_bfloat16* A16, __hip_bfloat16* At16,
+                               uint8_t* A8, uint8_t* At8, int64_t ldo, int64_t ldt, float* scale, hipStream_t st);
+// P[s][rows][kk] (FP32) = M (rows x cols, element size es: 2 BF16, 1 FP8,
+// ld ldm) times Xt^T (Xt kk x cols, same type, ld ldx), partial sums over
+// `splits` slices of the column range.  FP8: scale as above; scale_t = 1
+// when M is the A^T copy.
+hipError_t launch_gemm_lowp(int es, const void* M, int64_t ldm, int rows, int cols, const void* Xt, int64_t ldx,
+                            int kk, float* P, int splits, const float* scale, int scale_ld, int scale_t,
+                            hipStream_t st);
+int choose_splits_lowp(int rows, int cols, int kk);
+// Columns [c0, c0 + k) of Q (rows x ldq, FP64) -> rows [dr0, dr0 + k) of the
+// transposed operand Xt (ld ldx) in BF16 (es 2) or FP8 (es 1); FP8 columns
+// are scaled by a power of two (colscale[scol0 + c]) chosen from the column
+// maximum so that they use the E4M3 range.
+hipError_t launch_store_lowp(int es, const double* Q, int rows, int ldq, int c0, int k, void* Xt, int64_t ldx,
+                             int dr0, float* colscale, int scol0, hipStream_t st);
+// Y[:, c] /= colscale[c], c < k (FP32, rows x ld).
+hipError_t launch_unscale_cols(float* Y, int rows, int ld, int k, const float* colscale, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Orthonormalisation (CholeskyQR2 in FP64) and small products

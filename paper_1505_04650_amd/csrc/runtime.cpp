@@ -21,6 +21,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/cnmf.h"
@@ -119,9 +120,16 @@ struct Pass {
   int kk;
   std::vector<Block> blocks;
   bool final_prec;
+  cnmf_dtype prec;  // precision of the pass GEMM inputs
 };
 
-std::vector<Pass> plan_passes(int k, int q, int sides, bool want_ac) {
+inline bool is_lowp(cnmf_dtype d) { return d == CNMF_BF16 || d == CNMF_FP8_E4M3; }
+inline int lowp_es(cnmf_dtype d) { return d == CNMF_BF16 ? 2 : 1; }
+
+// Passes before 2q are power-iteration passes and run in pass_dtype; the last
+// range product of each chain, B = L^T A and Ac = A R^T run in final_dtype.
+std::vector<Pass> plan_passes(int k, int q, int sides, bool want_ac, cnmf_dtype pass_dtype,
+                              cnmf_dtype final_dtype) {
   const bool L = sides & CNMF_LEFT, R = sides & CNMF_RIGHT;
   const int nsteps = 2 * q + 1;
   const int rstart = L ? 1 : 0;
@@ -169,6 +177,7 @@ std::vector<Pass> plan_passes(int k, int q, int sides, bool want_ac) {
     }
     if (!any) break;
     ps.kk = ru16(col);
+    ps.prec = ps.final_prec ? final_dtype : pass_dtype;
     out.push_back(ps);
   }
   return out;
@@ -207,8 +216,12 @@ cnmf_status check_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_
   } else {
     if (d->pass_dtype == CNMF_F64 || d->final_dtype == CNMF_F64)
       return fail(h, CNMF_EINVAL, "F64 passes need an F64 input");
-    if (d->pass_dtype != CNMF_F32 || d->final_dtype != CNMF_F32)
-      return fail(h, CNMF_ENOTSUP, "reduced-precision passes are not available in this build");
+    if (d->pass_dtype != CNMF_F32 && d->pass_dtype != CNMF_BF16 && d->pass_dtype != CNMF_FP8_E4M3)
+      return fail(h, CNMF_EINVAL, "unknown pass_dtype %d", (int)d->pass_dtype);
+    if (d->final_dtype == CNMF_FP8_E4M3)
+      return fail(h, CNMF_ENOTSUP, "the last range pass and B = L^T A need at least BF16 (final_dtype)");
+    if (d->final_dtype != CNMF_F32 && d->final_dtype != CNMF_BF16)
+      return fail(h, CNMF_EINVAL, "unknown final_dtype %d", (int)d->final_dtype);
   }
   return CNMF_OK;
 }
@@ -236,6 +249,23 @@ struct SketchWs {
   double* At = nullptr; // k x k
   int gparts = 0;
   size_t ppart_elems = 0;
+  // reduced-precision passes: copies of A (m x ldo) and A^T (n x ldt),
+  // FP8 tile scales, transposed operands (kkmax x ldo / kkmax x ldt, 2-byte
+  // slots) and their FP8 column scales (A passes [0, 128), A^T [128, 256))
+  __hip_bfloat16* A16 = nullptr;
+  __hip_bfloat16* At16 = nullptr;
+  uint8_t* A8 = nullptr;
+  uint8_t* At8 = nullptr;
+  float* tscale = nullptr;
+  int ntj = 0;
+  int64_t ldo = 0, ldt = 0;
+  uint8_t* XtN = nullptr;
+  uint8_t* XtT = nullptr;
+  float* cscale = nullptr;
+  // FP32 / FP64 passes wider than 128 columns run one launch per chain
+  // block through these tight buffers (max(m, n) x 128)
+  T* Xg = nullptr;
+  T* Yg = nullptr;
 };
 
 int gram_parts(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, rows / 64)); }
@@ -245,11 +275,23 @@ void layout_sketch(Arena& a, SketchWs<T>& w, int64_t m, int64_t n, int k, const 
                    bool want_ac) {
   int kkmax = 16;
   size_t pmax = 0;
+  bool need16 = false, need8 = false, wide = false;
   for (const Pass& p : passes) {
     kkmax = std::max(kkmax, p.kk);
-    int64_t rows = p.dirN ? m : n;
-    int s = p.dirN ? choose_splits_n((int)m, (int)n, p.kk, sizeof(T)) : choose_splits_t((int)m, (int)n, p.kk, sizeof(T));
-    if (s > 1) pmax = std::max(pmax, (size_t)s * rows * p.kk);
+    int64_t rows = p.dirN ? m : n, cols = p.dirN ? n : m;
+    int s;
+    int kl = p.kk;
+    if (is_lowp(p.prec)) {
+      s = choose_splits_lowp((int)rows, (int)cols, p.kk);
+      (p.prec == CNMF_BF16 ? need16 : need8) = true;
+    } else {
+      if (p.kk > 128) {
+        kl = ru16(k);
+        wide = true;
+      }
+      s = p.dirN ? choose_splits_n((int)m, (int)n, kl, sizeof(T)) : choose_splits_t((int)m, (int)n, kl, sizeof(T));
+    }
+    if (s > 1) pmax = std::max(pmax, (size_t)s * rows * kl);
   }
   const int64_t mx = std::max(m, n);
   w.Xop = a.take<T>((size_t)n * kkmax);
@@ -270,6 +312,27 @@ void layout_sketch(Arena& a, SketchWs<T>& w, int64_t m, int64_t n, int k, const 
   w.BTb = a.take<T>((size_t)n * k);
   w.Acb = want_ac ? a.take<T>((size_t)m * k) : nullptr;
   w.At = a.take<double>((size_t)k * k);
+  if (need16 || need8) {
+    w.ldo = (n + 63) / 64 * 64;
+    w.ldt = (m + 63) / 64 * 64;
+    if (need16) {
+      w.A16 = a.take<__hip_bfloat16>((size_t)m * w.ldo);
+      w.At16 = a.take<__hip_bfloat16>((size_t)n * w.ldt);
+    }
+    if (need8) {
+      w.A8 = a.take<uint8_t>((size_t)m * w.ldo);
+      w.At8 = a.take<uint8_t>((size_t)n * w.ldt);
+      w.ntj = (int)((n + kFp8Tile - 1) / kFp8Tile);
+      w.tscale = a.take<float>((size_t)w.ntj * ((m + kFp8Tile - 1) / kFp8Tile));
+    }
+    w.XtN = a.take<uint8_t>((size_t)kkmax * w.ldo * 2);
+    w.XtT = a.take<uint8_t>((size_t)kkmax * w.ldt * 2);
+    w.cscale = a.take<float>(512);
+  }
+  if (wide) {
+    w.Xg = a.take<T>((size_t)mx * 128);
+    w.Yg = a.take<T>((size_t)mx * 128);
+  }
 }
 
 template <typename T>
@@ -415,21 +478,57 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
   HIPCHK(h, launch_fill(w.flags, 4 * sizeof(int), st));
   HIPCHK(h, launch_fill(w.counters, 4 * sizeof(unsigned), st));
 
+  // A pass multiplies an operand with one row per column of the matrix it
+  // reads: FP32/FP64 operands are row-major (cols x kk), reduced-precision
+  // operands transposed (kk x ld) in the pass type.
   auto operand_for = [&](const Pass& p) -> T* { return p.dirN ? w.Xop : w.Zop; };
+  auto xt_for = [&](const Pass& p) -> uint8_t* { return p.dirN ? w.XtN : w.XtT; };
+  auto xt_ld = [&](const Pass& p) -> int64_t { return p.dirN ? w.ldo : w.ldt; };
+  auto scol_for = [&](const Pass& p) -> int { return p.dirN ? 0 : 256; };
+  auto clear_operand = [&](const Pass& p) -> cnmf_status {
+    const size_t cols = p.dirN ? n : m;
+    if (is_lowp(p.prec))
+      HIPCHK(h, launch_fill(xt_for(p), (size_t)lowp_es(p.prec) * p.kk * xt_ld(p), st));
+    else
+      HIPCHK(h, launch_fill(operand_for(p), sizeof(T) * cols * p.kk, st));
+    return CNMF_OK;
+  };
+  // Q64 columns [c0, c0 + k) (rows x ldq) -> operand slot col of pass p
+  auto store_operand = [&](const Pass& p, const double* Q, int rows, int ldq, int c0, int col) -> cnmf_status {
+    if (is_lowp(p.prec))
+      HIPCHK(h, launch_store_lowp(lowp_es(p.prec), Q + 0, rows, ldq, c0, k, xt_for(p), xt_ld(p), col, w.cscale,
+                                  scol_for(p) + col, st));
+    else
+      HIPCHK(h, (launch_copy2d<double, T>(Q + c0, ldq, operand_for(p) + col, p.kk, rows, k, 1.0, st)));
+    return CNMF_OK;
+  };
+#define RUN(expr)                 \
+  do {                            \
+    cnmf_status _s = (expr);      \
+    if (_s != CNMF_OK) return _s; \
+  } while (0)
+
+  if (w.A16 || w.A8) {
+    if constexpr (std::is_same<T, float>::value) {
+      Span sp(h, ST_CONVERT);
+      HIPCHK(h, launch_convert_lowp(Ap, lda, m, n, w.A16, w.At16, w.A8, w.At8, w.ldo, w.ldt, w.tscale, st));
+    } else {
+      return fail(h, CNMF_EINVAL, "internal: reduced-precision passes need an F32 input");
+    }
+  }
   // stage the first operands (Omegas) of the chains
   for (size_t pi = 0; pi < passes.size(); ++pi) {
     const Pass& p = passes[pi];
-    T* op = operand_for(p);
     bool zeroed = false;
     for (const Block& b : p.blocks) {
       if ((b.kind == L_RANGE || b.kind == R_RANGE) && b.step == 0) {
         if (!zeroed) {
-          HIPCHK(h, launch_fill(op, sizeof(T) * (size_t)(p.dirN ? n : m) * p.kk, st));
+          RUN(clear_operand(p));
           zeroed = true;
         }
         const double* om = b.kind == L_RANGE ? d->omega_left_dev : d->omega_right_dev;
         int rows = b.kind == L_RANGE ? n : m;
-        HIPCHK(h, (launch_copy2d<double, T>(om, k, op + b.col0, p.kk, rows, k, 1.0, st)));
+        RUN(store_operand(p, om, rows, k, 0, b.col0));
       }
     }
   }
@@ -438,15 +537,43 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
     const Pass& p = passes[pi];
     const int rows = p.dirN ? m : n;
     T* op = operand_for(p);
-    int splits = p.dirN ? choose_splits_n(m, n, p.kk, sizeof(T)) : choose_splits_t(m, n, p.kk, sizeof(T));
+    const bool lp = is_lowp(p.prec);
+    const bool wide = !lp && p.kk > 128;
+    int splits = lp ? choose_splits_lowp(rows, p.dirN ? n : m, p.kk)
+                    : (p.dirN ? choose_splits_n(m, n, p.kk, sizeof(T)) : choose_splits_t(m, n, p.kk, sizeof(T)));
+    if (wide) splits = 1;  // reduced per block below
     T* dst = splits > 1 ? w.Ppart : w.Y;
     {
       const double flops = 2.0 * m * n * (double)(k * (int)p.blocks.size());
       Span sp(h, p.dirN ? ST_PASS_N : ST_PASS_T, flops);
-      if (p.dirN)
+      if (lp) {
+        if constexpr (std::is_same<T, float>::value) {
+          const int es = lowp_es(p.prec);
+          const void* M = es == 2 ? (p.dirN ? (const void*)w.A16 : (const void*)w.At16)
+                                  : (p.dirN ? (const void*)w.A8 : (const void*)w.At8);
+          HIPCHK(h, launch_gemm_lowp(es, M, p.dirN ? w.ldo : w.ldt, rows, p.dirN ? n : m, xt_for(p), xt_ld(p), p.kk,
+                                     dst, splits, w.tscale, w.ntj, p.dirN ? 0 : 1, st));
+        }
+      } else if (wide) {
+        // one product per chain block (k <= 128 columns each)
+        const int kb = ru16(k), in_rows = p.dirN ? n : m;
+        const int sb = p.dirN ? choose_splits_n(m, n, kb, sizeof(T)) : choose_splits_t(m, n, kb, sizeof(T));
+        for (const Block& b : p.blocks) {
+          if (kb != k) HIPCHK(h, launch_fill(w.Xg, sizeof(T) * (size_t)in_rows * kb, st));
+          HIPCHK(h, (launch_copy2d<T, T>(op + b.col0, p.kk, w.Xg, kb, in_rows, k, 1.0, st)));
+          T* db = sb > 1 ? w.Ppart : w.Yg;
+          if (p.dirN)
+            HIPCHK(h, launch_gemm_n<T>(Ap, lda, m, n, w.Xg, kb, db, sb, st));
+          else
+            HIPCHK(h, launch_gemm_t<T>(Ap, lda, m, n, w.Xg, kb, db, sb, st));
+          if (sb > 1) HIPCHK(h, launch_reduce_splits<T>(w.Ppart, sb, rows, kb, w.Yg, st));
+          HIPCHK(h, (launch_copy2d<T, T>(w.Yg, kb, w.Y + b.col0, p.kk, rows, k, 1.0, st)));
+        }
+      } else if (p.dirN) {
         HIPCHK(h, launch_gemm_n<T>(Ap, lda, m, n, op, p.kk, dst, splits, st));
-      else
+      } else {
         HIPCHK(h, launch_gemm_t<T>(Ap, lda, m, n, op, p.kk, dst, splits, st));
+      }
     }
     Span orth_span(h, ST_ORTH);
     if (splits > 1) HIPCHK(h, launch_reduce_splits<T>(w.Ppart, splits, rows, p.kk, w.Y, st));
@@ -464,14 +591,13 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
     }
     // route results
     const Pass* nx = pi + 1 < passes.size() ? &passes[pi + 1] : nullptr;
-    T* nop = nx ? operand_for(*nx) : nullptr;
     bool nzeroed = false;
     auto zero_next = [&]() -> cnmf_status {
       if (nx && !nzeroed) {
         bool has_first = false;
         for (const Block& b : nx->blocks)
           if ((b.kind == L_RANGE || b.kind == R_RANGE) && b.step == 0) has_first = true;
-        if (!has_first) HIPCHK(h, launch_fill(nop, sizeof(T) * (size_t)(nx->dirN ? n : m) * nx->kk, st));
+        if (!has_first) RUN(clear_operand(*nx));
         nzeroed = true;
       }
       return CNMF_OK;
@@ -490,7 +616,7 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
         if (ncol >= 0) {
           cnmf_status s = zero_next();
           if (s != CNMF_OK) return s;
-          HIPCHK(h, (launch_copy2d<double, T>(w.Q64 + b.col0, p.kk, nop + ncol, nx->kk, rows, k, 1.0, st)));
+          RUN(store_operand(*nx, w.Q64, rows, p.kk, b.col0, ncol));
         }
         if (last) {
           T* basis = isL ? w.Lb : w.RTb;
@@ -516,6 +642,7 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
     HIPCHK(h, (launch_cross2<T, T>(w.BTb, k, 0, w.RTb, k, 0, 0, 1, n, k, k, w.Gp, parts, st)));
     HIPCHK(h, launch_sum_parts(w.Gp, parts, (int64_t)k * k, w.At, st));
   }
+#undef RUN
   return CNMF_OK;
 }
 
@@ -544,7 +671,7 @@ cnmf_status write_sketch_outputs(cnmf_handle* h, const cnmf_input* A, const cnmf
 template <typename T>
 cnmf_status do_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, const cnmf_sketch_out* o,
                       bool want_ac) {
-  std::vector<Pass> passes = plan_passes(d->k, d->q, d->sides, want_ac);
+  std::vector<Pass> passes = plan_passes(d->k, d->q, d->sides, want_ac, d->pass_dtype, d->final_dtype);
   if (passes.empty()) return fail(h, CNMF_EINVAL, "internal: empty pass plan");
   Arena dry(nullptr);
   SketchWs<T> w;
@@ -624,7 +751,7 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
   const bool want_ac = d->method == CNMF_MU;
   std::vector<Pass> passes;
   if (!full) {
-    passes = plan_passes(sk->k, sk->q, CNMF_BOTH, want_ac);
+    passes = plan_passes(sk->k, sk->q, CNMF_BOTH, want_ac, sk->pass_dtype, sk->final_dtype);
     if (passes.empty()) return fail(h, CNMF_EINVAL, "internal: empty pass plan");
   }
   const int m = (int)A->m, n = (int)A->n, k = sk->k, r = sk->r;
@@ -762,7 +889,7 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
 template <typename T>
 cnmf_status do_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, int64_t* K, double* score,
                       void* B_out) {
-  std::vector<Pass> passes = plan_passes(d->k, d->q, d->sides, false);
+  std::vector<Pass> passes = plan_passes(d->k, d->q, d->sides, false, d->pass_dtype, d->final_dtype);
   const int m = (int)A->m, n = (int)A->n, k = d->k;
   Arena dry(nullptr);
   SketchWs<T> w;
@@ -1020,6 +1147,58 @@ cnmf_status cnmf_range_product(cnmf_handle* h, const cnmf_input* A, int trans, c
   return run(float{});
 }
 
+cnmf_status cnmf_range_product_lowp(cnmf_handle* h, const cnmf_input* A, int trans, cnmf_dtype pass_dtype,
+                                    const double* X_dev, int32_t kx, float* Y_dev) {
+  cnmf_status s = check_input(h, A);
+  if (s != CNMF_OK) return s;
+  if (A->dtype != CNMF_F32) return fail(h, CNMF_EINVAL, "reduced-precision passes need an F32 input");
+  if (pass_dtype != CNMF_BF16 && pass_dtype != CNMF_FP8_E4M3)
+    return fail(h, CNMF_EINVAL, "pass_dtype must be CNMF_BF16 or CNMF_FP8_E4M3");
+  if (trans != 0 && trans != 1) return fail(h, CNMF_EINVAL, "trans must be 0 or 1");
+  if (!X_dev || !Y_dev) return fail(h, CNMF_EINVAL, "X_dev and Y_dev are required");
+  if (kx < 1 || kx > 128) return fail(h, CNMF_EINVAL, "kx=%d must be in [1, 128]", kx);
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  HIPCHK(h, hipSetDevice(h->device));
+  const int m = (int)A->m, n = (int)A->n, kk = ru16(kx);
+  const int rows_out = trans ? n : m, cols = trans ? m : n;
+  const int es = lowp_es(pass_dtype);
+  const int64_t ldo = (n + 63) / 64 * 64, ldt = (m + 63) / 64 * 64;
+  const int64_t ldm = trans ? ldt : ldo;
+  const int ntj = (n + kFp8Tile - 1) / kFp8Tile, nti = (m + kFp8Tile - 1) / kFp8Tile;
+  const int splits = choose_splits_lowp(rows_out, cols, kk);
+  auto layout = [&](Arena& a, uint8_t** Mc, float** tsc, uint8_t** Xt, float** cs, float** Yp, float** Pp) {
+    *Mc = a.take<uint8_t>((size_t)es * (trans ? n : m) * ldm);
+    *tsc = a.take<float>((size_t)ntj * nti);
+    *Xt = a.take<uint8_t>((size_t)es * kk * ldm);
+    *cs = a.take<float>(128);
+    *Yp = a.take<float>((size_t)rows_out * kk);
+    *Pp = a.take<float>((size_t)std::max(splits, 1) * rows_out * kk);
+  };
+  uint8_t *Mc, *Xt;
+  float *tsc, *cs, *Yp, *Pp;
+  Arena dry(nullptr);
+  layout(dry, &Mc, &tsc, &Xt, &cs, &Yp, &Pp);
+  s = ensure_ws(h, dry.off);
+  if (s != CNMF_OK) return s;
+  Arena a(h->ws);
+  layout(a, &Mc, &tsc, &Xt, &cs, &Yp, &Pp);
+  hipStream_t st = h->stream;
+  const float* Ap = (const float*)A->data_dev;
+  // only the copy this direction reads is written
+  __hip_bfloat16* c16 = es == 2 ? (__hip_bfloat16*)Mc : nullptr;
+  uint8_t* c8 = es == 1 ? Mc : nullptr;
+  HIPCHK(h, launch_convert_lowp(Ap, A->lda, m, n, trans ? nullptr : c16, trans ? c16 : nullptr, trans ? nullptr : c8,
+                                trans ? c8 : nullptr, ldo, ldt, tsc, st));
+  HIPCHK(h, launch_fill(Xt, (size_t)es * kk * ldm, st));
+  HIPCHK(h, launch_store_lowp(es, X_dev, cols, kx, 0, kx, Xt, ldm, 0, cs, 0, st));
+  float* dst = splits > 1 ? Pp : Yp;
+  HIPCHK(h, launch_gemm_lowp(es, Mc, ldm, rows_out, cols, Xt, ldm, kk, dst, splits, tsc, ntj, trans, st));
+  if (splits > 1) HIPCHK(h, launch_reduce_splits<float>(Pp, splits, rows_out, kk, Yp, st));
+  if (es == 1) HIPCHK(h, launch_unscale_cols(Yp, rows_out, kk, kx, cs, st));
+  HIPCHK(h, (launch_copy2d<float, float>(Yp, kk, Y_dev, kx, rows_out, kx, 1.0, st)));
+  return CNMF_OK;
+}
+
 cnmf_status cnmf_workspace_bytes(int64_t m, int64_t n, const cnmf_factorize_desc* d, size_t* bytes) {
   if (!d || !bytes) return fail(nullptr, CNMF_EINVAL, "descriptor and bytes are required");
   if (m < 1 || n < 1) return fail(nullptr, CNMF_EINVAL, "m and n must be >= 1");
@@ -1029,7 +1208,8 @@ cnmf_status cnmf_workspace_bytes(int64_t m, int64_t n, const cnmf_factorize_desc
   const bool f64 = d->sk.pass_dtype == CNMF_F64;
   const bool want_ac = d->method == CNMF_MU;
   const bool full = d->method == CNMF_ADMM_FULL || d->method == CNMF_MU_FULL;
-  std::vector<Pass> passes = plan_passes(k, d->sk.q, d->sk.sides ? d->sk.sides : CNMF_BOTH, want_ac);
+  std::vector<Pass> passes = plan_passes(k, d->sk.q, d->sk.sides ? d->sk.sides : CNMF_BOTH, want_ac,
+                                         d->sk.pass_dtype, d->sk.final_dtype);
   Arena dry(nullptr);
   auto go = [&](auto tag) {
     typedef decltype(tag) T;
@@ -1040,7 +1220,7 @@ cnmf_status cnmf_workspace_bytes(int64_t m, int64_t n, const cnmf_factorize_desc
       layout_sketch<T>(dry, w, m, n, k, passes, want_ac);
     else
       dry.take<int>(4);
-    if (d->iters > 0 || full) layout_admm<T>(dry, aw, m, n, k, r);
+    layout_admm<T>(dry, aw, m, n, k, r);
     if (d->method != CNMF_ADMM) layout_iter<T>(dry, iw, m, n, k, r, full);
   };
   if (f64)

@@ -107,3 +107,44 @@ def test_python_binding_fails_loudly_without_library(tmp_path):
             L.load(str(tmp_path / "missing.so"))
         finally:
             L._lib = L._lib_backup
+
+
+def test_precision_combinations(lib):
+    """Reduced-precision passes need an FP32 input; B and the last range
+    pass need at least BF16; the workspace grows by the A / A^T copies."""
+    A = L.cnmf_input(C.c_void_p(16), L.CNMF_F32, 100, 50, 50)
+    sk = L.cnmf_sketch_desc(5, 10, 1, L.CNMF_BOTH, L.CNMF_FP8_E4M3, L.CNMF_FP8_E4M3, C.c_void_p(16),
+                            C.c_void_p(16))
+    out = L.cnmf_sketch_out()
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_ENOTSUP
+    assert b"BF16" in lib.cnmf_last_error(None)
+    sk.final_dtype = L.CNMF_BF16
+    # valid combination: fails only for the missing handle
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL
+    assert b"handle" in lib.cnmf_last_error(None)
+    A64 = L.cnmf_input(C.c_void_p(16), L.CNMF_F64, 100, 50, 50)
+    assert lib.cnmf_sketch(None, C.byref(A64), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL
+    sizes = {}
+    for name, p, f in (("f32", L.CNMF_F32, L.CNMF_F32), ("bf16", L.CNMF_BF16, L.CNMF_BF16),
+                       ("fp8", L.CNMF_FP8_E4M3, L.CNMF_BF16), ("fp8f32", L.CNMF_FP8_E4M3, L.CNMF_F32)):
+        d = _desc(r=50, k=60, q=4)
+        d.sk.pass_dtype, d.sk.final_dtype = p, f
+        o = C.c_size_t()
+        assert lib.cnmf_workspace_bytes(20000, 5000, C.byref(d), C.byref(o)) == L.CNMF_OK
+        sizes[name] = o.value
+    mn = 20000 * 5000
+    assert sizes["bf16"] - sizes["f32"] >= 4 * mn          # BF16 A and A^T copies
+    assert sizes["fp8"] - sizes["f32"] >= 6 * mn           # FP8 copies + the BF16 ones for the final passes
+    assert sizes["fp8f32"] - sizes["f32"] >= 2 * mn
+
+
+def test_lowp_range_product_argument_checks(lib):
+    A = L.cnmf_input(C.c_void_p(16), L.CNMF_F32, 100, 50, 50)
+    X = C.c_void_p(16)
+    assert lib.cnmf_range_product_lowp(None, C.byref(A), 0, L.CNMF_F32, X, 8, X) == L.CNMF_EINVAL
+    assert lib.cnmf_range_product_lowp(None, C.byref(A), 0, L.CNMF_BF16, X, 0, X) == L.CNMF_EINVAL
+    assert lib.cnmf_range_product_lowp(None, C.byref(A), 2, L.CNMF_BF16, X, 8, X) == L.CNMF_EINVAL
+    A64 = L.cnmf_input(C.c_void_p(16), L.CNMF_F64, 100, 50, 50)
+    assert lib.cnmf_range_product_lowp(None, C.byref(A64), 0, L.CNMF_BF16, X, 8, X) == L.CNMF_EINVAL
+    assert lib.cnmf_range_product_lowp(None, C.byref(A), 0, L.CNMF_FP8_E4M3, X, 8, X) == L.CNMF_EINVAL
+    assert b"handle" in lib.cnmf_last_error(None)
