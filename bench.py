@@ -7,6 +7,13 @@ A, the test matrices and the initial factors resident in HBM before the
 clock starts.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-precision]
+
+The line also carries a "precision" object: the two-sided sketch of the
+100000 x 20000 FP32 workload (r = 100, k = 120, q = 4) with FP32, BF16 and
+FP8 E4M3 (+ BF16 final pass) range-finder passes, each with its projection
+residual ||A - L L^T A||_F / ||A||_F accumulated in FP64.  That input is
+generated on the device (torch's seeded generator, same recipe).
 """
 from __future__ import annotations
 
@@ -59,12 +66,81 @@ def cpu_baseline(inp, w, lam, budget_s=15.0):
                       f"sketch q=4 + {w.iters} ADMM iterations + residual) in {el:.1f} s"}, res
 
 
+def _proj_residual(A, L, norm_a):
+    """||A - L L^T A||_F / ||A||_F = sqrt(||A||^2 - ||L^T A||^2) / ||A|| for
+    orthonormal L, with L^T A accumulated in FP64 over row blocks."""
+    import torch
+    k, n = L.shape[1], A.shape[1]
+    B = torch.zeros(k, n, dtype=torch.float64, device=A.device)
+    for i in range(0, A.shape[0], 8192):
+        B += L[i:i + 8192].double().T @ A[i:i + 8192].double()
+    return math.sqrt(max(0.0, norm_a ** 2 - float((B * B).sum()))) / norm_a
+
+
+def precision_section(h, steps, warmup):
+    """Sketch of the 100000 x 20000 precision workload in FP32, BF16 and FP8."""
+    import torch
+    from paper_1505_04650_amd import api
+    w = WL.WORKLOADS["precision_100000x20000"]
+    dev = torch.device("cuda", 0)
+    g = torch.Generator(device=dev)
+    g.manual_seed(100 * w.index)
+    A = torch.rand(w.m, w.r, device=dev, generator=g) @ torch.rand(w.r, w.n, device=dev, generator=g)
+    for i in range(0, w.m, 8192):
+        A[i:i + 8192] += (w.sigma * torch.randn(A[i:i + 8192].shape, device=dev, generator=g)).abs_()
+    oml = torch.randn(w.n, w.k, device=dev, dtype=torch.float64, generator=g)
+    omr = torch.randn(w.m, w.k, device=dev, dtype=torch.float64, generator=g)
+    norm_a = math.sqrt(sum(float((A[i:i + 8192].double() ** 2).sum()) for i in range(0, w.m, 8192)))
+    flops = 2.0 * w.m * w.n * w.k * (2 * (1 + 2 * w.q) + 1)  # two chains of 2q + 1 products, and B
+    out = {"workload": w.name, "m": w.m, "n": w.n, "r": w.r, "k": w.k, "q": w.q, "sides": "both",
+           "data": "synthetic, generated on the device"}
+    st = h.stream
+    for pd, fd in (("f32", "f32"), ("bf16", "bf16"), ("fp8", "bf16")):
+        for _ in range(warmup):
+            api.sketch(A, w.r, w.k, w.q, oml, omr, pass_dtype=pd, final_dtype=fd, handle=h)
+        torch.cuda.synchronize()
+        h.set_timing(True)
+        agg = {}
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        sk = None
+        for _ in range(steps):
+            sk = api.sketch(A, w.r, w.k, w.q, oml, omr, pass_dtype=pd, final_dtype=fd, handle=h)
+            for name, (ms, fl, nl) in h.stages().items():
+                a = agg.setdefault(name, [0.0, 0.0, 0])
+                if not math.isnan(ms):
+                    a[0] += ms
+                a[1] += fl
+                a[2] += nl
+        e1.record(st)
+        torch.cuda.synchronize()
+        h.set_timing(False)
+        ms = e0.elapsed_time(e1) / steps
+        pn, pt = agg.get("pass_AX", [0, 0, 0]), agg.get("pass_ATZ", [0, 0, 0])
+        pass_ms = (pn[0] + pt[0]) / steps
+        out[pd] = {"final_dtype": fd, "sketch_ms": ms, "sketch_tflops": flops / (ms * 1e-3) / 1e12,
+                   "pass_ms": pass_ms, "pass_tflops": flops / (pass_ms * 1e-3) / 1e12,
+                   "stages_ms": {k: v[0] / steps for k, v in agg.items() if v[2]},
+                   "proj_residual": _proj_residual(A, sk.L, norm_a)}
+        log(f"precision {pd}/{fd}: {ms:.3f} ms per sketch, projection residual {out[pd]['proj_residual']:.6e}")
+    ref = out["f32"]["proj_residual"]
+    for pd in ("bf16", "fp8"):
+        out[pd]["proj_residual_gap_vs_f32"] = abs(out[pd]["proj_residual"] - ref)
+        out[pd]["speedup_vs_f32"] = out["f32"]["sketch_ms"] / out[pd]["sketch_ms"]
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--precision-only", action="store_true",
+                    help="only the precision sketches (for kernel profiles); prints that object")
     ap.add_argument("--workload", default="nmf_fp32_20000x5000")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -78,6 +154,10 @@ def main():
     w = WL.WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.precision_only:
+        print(json.dumps({"precision": precision_section(api.default_handle(), max(1, args.steps), args.warmup)}),
+              flush=True)
+        return
     log(f"workload {w.name}: generating inputs")
     inp = WL.make_inputs(w)
     A = torch.as_tensor(inp["A"], device=dev)
@@ -157,6 +237,9 @@ def main():
            "config": {"workload": w.name, "m": w.m, "n": w.n, "r": w.r, "k": w.k, "q": w.q, "iters": w.iters,
                       "method": "compressed ADMM (two-sided)", "lambda": lam, "rel_residual": res_gpu},
            "sketch_tflops": sketch_tflops, "sketch_ms": sketch_ms, "stages": stages, "roofline": roofline}
+
+    if not args.no_precision:
+        out["precision"] = precision_section(h, max(2, min(args.steps, 5)), 1)
 
     if not args.no_cpu_baseline:
         log("cpu baseline: running the FP64 oracle on the host")
