@@ -233,6 +233,90 @@ double cnmf_stage_ms(cnmf_handle* h, int stage);
 double cnmf_stage_flops(cnmf_handle* h, int stage);
 int cnmf_stage_launches(cnmf_handle* h, int stage);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of factorisation requests on one GPU.
+ *
+ * cnmf_server_start creates a server with a device arena of
+ * hbm_budget_bytes (allocated once) from which every admitted request gets
+ * its workspace block, `workers` worker streams (1..3) for the per-request
+ * phases and one stream for the batched iterations, and a dispatcher thread
+ * that owns all of the server's launches.
+ *
+ * A request is what cnmf_factorize takes.  Lifecycle: queued (arrival
+ * order) -> admitted when its workspace footprint fits in the arena and one
+ * of max_batch + 2 workers in-flight slots is free (a waiting head of the
+ * queue may be passed by smaller requests only while the free bytes left
+ * still cover it, at most 64 times) -> prologue on a worker stream (Alg. 1
+ * sketch, small sketches, initial state) -> for FP32 compressed ADMM
+ * (CNMF_ADMM, F32 input, iters > 0): member of the batch, where one step
+ * advances every member by one iteration of Appendix B Alg. 3 with three
+ * launches covering all members (at most max_batch) -> epilogue (U, V, FP64
+ * residual, sketch outputs) on a worker stream -> done.  Other requests
+ * (MU, uncompressed, FP64) run whole on a worker stream.  Each member runs
+ * the same per-request code as cnmf_factorize, so its results equal those of
+ * cnmf_factorize on the same inputs, whatever else is in the batch.
+ *
+ * Ownership: A and every output buffer belong to the caller and must stay
+ * valid until the ticket is done.  The inputs may be produced on
+ * `producer_stream` (a hipStream_t, NULL = null stream): the request's work
+ * is ordered after the work enqueued there before the submit call.
+ * Errors: cnmf_server_submit validates like cnmf_factorize (CNMF_EINVAL
+ * before anything is enqueued) and returns CNMF_ENOMEM for a footprint
+ * above the whole budget; a failure later in the request is reported by
+ * cnmf_server_poll (status, message).  cnmf_server_last_error gives the text
+ * of the calling thread's last failing server call.  All calls are thread
+ * safe; cnmf_server_stop drains every queued and in-flight request, then
+ * frees the server (tickets are invalid afterwards).
+ * ------------------------------------------------------------------------- */
+typedef struct cnmf_server cnmf_server;
+
+typedef struct {
+  int32_t device;
+  int32_t max_batch;          /* members of a batched step, 1..4096          */
+  int32_t workers;            /* worker streams, 1..3                        */
+  int32_t reserved;
+  uint64_t hbm_budget_bytes;  /* device arena for request workspaces         */
+} cnmf_server_config;
+
+typedef struct {
+  int32_t state;              /* 0 queued, 1 prologue, 2 ready, 3 in batch,
+                                 4 epilogue, 5 done                          */
+  int32_t done;               /* state == 5                                  */
+  cnmf_status status;         /* result once done                            */
+  int32_t reserved;
+  double queue_ms;            /* submit -> admission (so far if queued)      */
+  double total_ms;            /* submit -> done (so far if not done)         */
+  char message[192];          /* error text when status != CNMF_OK           */
+} cnmf_ticket_info;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int64_t batch_steps;        /* batched launches of the iteration step      */
+  int64_t batched_iterations; /* request-iterations they advanced            */
+  int64_t max_batch_seen;     /* largest batch                               */
+  int64_t queued, in_flight;
+  uint64_t arena_bytes, arena_free_bytes, peak_arena_bytes;
+} cnmf_server_stats;
+
+cnmf_status cnmf_server_start(const cnmf_server_config* cfg, cnmf_server** out);
+cnmf_status cnmf_server_submit(cnmf_server* s, const cnmf_input* A, const cnmf_factorize_desc* d,
+                               const cnmf_factorize_out* out, void* producer_stream, uint64_t* ticket);
+cnmf_status cnmf_server_poll(cnmf_server* s, uint64_t ticket, cnmf_ticket_info* info);
+/* Forget a done ticket (CNMF_EBUSY if it is not done). */
+cnmf_status cnmf_server_release(cnmf_server* s, uint64_t ticket);
+cnmf_status cnmf_server_get_stats(cnmf_server* s, cnmf_server_stats* out);
+cnmf_status cnmf_server_stop(cnmf_server* s);
+const char* cnmf_server_last_error(void);
+
+/* Host-only replay of the server's admission policy (no GPU needed):
+ * request i arrives at arrival_ms[i] (sorted), needs bytes[i] of the arena
+ * and, once admitted, holds its slot and block for service_ms[i].  Writes
+ * admit_ms[i] and done_ms[i] (-1 for a request above the budget) and the
+ * peak arena use.  For testing and capacity planning. */
+cnmf_status cnmf_server_simulate(int32_t nreq, const double* arrival_ms, const uint64_t* bytes,
+                                 const double* service_ms, uint64_t budget, int32_t max_inflight,
+                                 double* admit_ms, double* done_ms, uint64_t* peak_bytes);
+
 #ifdef __cplusplus
 }
 #endif

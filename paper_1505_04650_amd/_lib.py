@@ -24,6 +24,8 @@ EXPORTED = [
     "cnmf_sketch", "cnmf_factorize", "snmf_select", "cnmf_spa", "cnmf_workspace_bytes",
     "cnmf_set_timing", "cnmf_stage_ms", "cnmf_range_product", "cnmf_stage_flops", "cnmf_stage_launches",
     "cnmf_range_product_lowp",
+    "cnmf_server_start", "cnmf_server_submit", "cnmf_server_poll", "cnmf_server_release",
+    "cnmf_server_get_stats", "cnmf_server_stop", "cnmf_server_last_error", "cnmf_server_simulate",
 ]
 
 
@@ -52,6 +54,23 @@ class cnmf_factorize_desc(C.Structure):
 class cnmf_factorize_out(C.Structure):
     _fields_ = [("U_dev", C.c_void_p), ("V_dev", C.c_void_p), ("rel_residual_dev", C.c_void_p),
                 ("sk_out", cnmf_sketch_out)]
+
+
+class cnmf_server_config(C.Structure):
+    _fields_ = [("device", C.c_int32), ("max_batch", C.c_int32), ("workers", C.c_int32), ("reserved", C.c_int32),
+                ("hbm_budget_bytes", C.c_uint64)]
+
+
+class cnmf_ticket_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("done", C.c_int32), ("status", C.c_int), ("reserved", C.c_int32),
+                ("queue_ms", C.c_double), ("total_ms", C.c_double), ("message", C.c_char * 192)]
+
+
+class cnmf_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("batch_steps", C.c_int64), ("batched_iterations", C.c_int64), ("max_batch_seen", C.c_int64),
+                ("queued", C.c_int64), ("in_flight", C.c_int64), ("arena_bytes", C.c_uint64),
+                ("arena_free_bytes", C.c_uint64), ("peak_arena_bytes", C.c_uint64)]
 
 
 class CnmfError(RuntimeError):
@@ -107,6 +126,24 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.cnmf_stage_flops.restype = C.c_double
     lib.cnmf_stage_launches.argtypes = [vp, C.c_int]
     lib.cnmf_stage_launches.restype = C.c_int
+    lib.cnmf_server_start.argtypes = [C.POINTER(cnmf_server_config), C.POINTER(vp)]
+    lib.cnmf_server_start.restype = st
+    lib.cnmf_server_submit.argtypes = [vp, C.POINTER(cnmf_input), C.POINTER(cnmf_factorize_desc),
+                                       C.POINTER(cnmf_factorize_out), vp, C.POINTER(C.c_uint64)]
+    lib.cnmf_server_submit.restype = st
+    lib.cnmf_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(cnmf_ticket_info)]
+    lib.cnmf_server_poll.restype = st
+    lib.cnmf_server_release.argtypes = [vp, C.c_uint64]
+    lib.cnmf_server_release.restype = st
+    lib.cnmf_server_get_stats.argtypes = [vp, C.POINTER(cnmf_server_stats)]
+    lib.cnmf_server_get_stats.restype = st
+    lib.cnmf_server_stop.argtypes = [vp]
+    lib.cnmf_server_stop.restype = st
+    lib.cnmf_server_last_error.argtypes = []
+    lib.cnmf_server_last_error.restype = C.c_char_p
+    dp, u64p = C.POINTER(C.c_double), C.POINTER(C.c_uint64)
+    lib.cnmf_server_simulate.argtypes = [i32, dp, u64p, dp, C.c_uint64, i32, dp, dp, u64p]
+    lib.cnmf_server_simulate.restype = st
     _lib = lib
     return lib
 
@@ -115,3 +152,8 @@ def check(status: int, handle=None):
     if status != CNMF_OK:
         msg = load().cnmf_last_error(handle).decode()
         raise CnmfError(status, msg)
+
+
+def check_server(status: int):
+    if status != CNMF_OK:
+        raise CnmfError(status, load().cnmf_server_last_error().decode())

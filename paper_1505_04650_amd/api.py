@@ -250,3 +250,108 @@ def workspace_bytes(m, n, r, k, q, method="admm", iters=100, pass_dtype="f32", f
     out = C.c_size_t()
     L.check(lib.cnmf_workspace_bytes(int(m), int(n), C.byref(d), C.byref(out)))
     return out.value
+
+
+# --------------------------------------------------------------------------
+# Serving (continuous batching; see cnmf_server_* in include/cnmf.h)
+# --------------------------------------------------------------------------
+
+@dataclass
+class Ticket:
+    id: int
+    U: torch.Tensor
+    V: torch.Tensor
+    rel_residual: torch.Tensor
+    keep: tuple  # inputs kept alive until the request is done
+
+
+class Server:
+    """A request server on one GPU.  submit() returns at once; poll() /
+    wait() report completion; outputs are device tensors of the ticket."""
+
+    STATES = ("queued", "prologue", "ready", "batch", "epilogue", "done")
+
+    def __init__(self, hbm_budget_bytes: int, max_batch: int = 128, workers: int = 3, device: int = 0):
+        self._lib = L.load()
+        cfg = L.cnmf_server_config(int(device), int(max_batch), int(workers), 0, int(hbm_budget_bytes))
+        raw = C.c_void_p()
+        L.check_server(self._lib.cnmf_server_start(C.byref(cfg), C.byref(raw)))
+        self.raw = raw
+        self.device = torch.device("cuda", device)
+
+    def submit(self, A, r, k, q, U0, V0, omega_left, omega_right, method="admm", iters=100, lam=1.0, phi=None,
+               xi=1.0, mu_eps=1e-16, pass_dtype=None, final_dtype=None, stream=None) -> Ticket:
+        pass_dtype, final_dtype = _default_prec(A, pass_dtype, final_dtype)
+        m, n = A.shape
+        od = _acc_dtype(A, pass_dtype)
+        U = torch.empty((m, r), dtype=od, device=A.device)
+        V = torch.empty((r, n), dtype=od, device=A.device)
+        res = torch.zeros(1, dtype=torch.float64, device=A.device)
+        U0 = U0.to(device=A.device, dtype=torch.float64).contiguous()
+        V0 = V0.to(device=A.device, dtype=torch.float64).contiguous()
+        inp = _input(A)
+        d = L.cnmf_factorize_desc(_sketch_desc(r, k, q, L.CNMF_BOTH, omega_left, omega_right, pass_dtype,
+                                               final_dtype),
+                                  _METHODS[method], int(iters), float(lam), float(lam if phi is None else phi),
+                                  float(xi), float(mu_eps), _ptr(U0), _ptr(V0))
+        out = L.cnmf_factorize_out(_ptr(U), _ptr(V), _ptr(res), L.cnmf_sketch_out())
+        st = stream if stream is not None else torch.cuda.current_stream(A.device)
+        t = C.c_uint64()
+        L.check_server(self._lib.cnmf_server_submit(self.raw, C.byref(inp), C.byref(d), C.byref(out),
+                                                    C.c_void_p(st.cuda_stream), C.byref(t)))
+        return Ticket(t.value, U, V, res, (A, U0, V0, omega_left, omega_right))
+
+    def poll(self, ticket: Ticket) -> dict:
+        info = L.cnmf_ticket_info()
+        L.check_server(self._lib.cnmf_server_poll(self.raw, ticket.id, C.byref(info)))
+        return {"state": self.STATES[info.state], "done": bool(info.done), "status": info.status,
+                "queue_ms": info.queue_ms, "total_ms": info.total_ms, "message": info.message.decode()}
+
+    def wait(self, ticket: Ticket, timeout_s: float = 120.0, sleep_s: float = 2e-4) -> dict:
+        import time
+        t0 = time.perf_counter()
+        while True:
+            info = self.poll(ticket)
+            if info["done"]:
+                if info["status"] != L.CNMF_OK:
+                    raise L.CnmfError(info["status"], info["message"])
+                return info
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"ticket {ticket.id} not done after {timeout_s} s ({info['state']})")
+            time.sleep(sleep_s)
+
+    def release(self, ticket: Ticket):
+        L.check_server(self._lib.cnmf_server_release(self.raw, ticket.id))
+
+    def stats(self) -> dict:
+        s = L.cnmf_server_stats()
+        L.check_server(self._lib.cnmf_server_get_stats(self.raw, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in L.cnmf_server_stats._fields_}
+
+    def stop(self):
+        if self.raw:
+            L.check_server(self._lib.cnmf_server_stop(self.raw))
+            self.raw = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()
+
+
+def simulate_admission(arrival_ms, nbytes, service_ms, budget, max_inflight):
+    """Host-only replay of the server's admission policy (no GPU)."""
+    import numpy as np
+    lib = L.load()
+    a = np.ascontiguousarray(arrival_ms, dtype=np.float64)
+    b = np.ascontiguousarray(nbytes, dtype=np.uint64)
+    s = np.ascontiguousarray(service_ms, dtype=np.float64)
+    n = len(a)
+    adm = np.empty(n, dtype=np.float64)
+    done = np.empty(n, dtype=np.float64)
+    peak = C.c_uint64()
+    dp = lambda x: x.ctypes.data_as(C.POINTER(C.c_double))
+    L.check_server(lib.cnmf_server_simulate(n, dp(a), b.ctypes.data_as(C.POINTER(C.c_uint64)), dp(s), int(budget),
+                                            int(max_inflight), dp(adm), dp(done), C.byref(peak)))
+    return adm, done, peak.value

@@ -105,6 +105,32 @@ hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const dou
                              double lam, double phi, int first, double* XY, double* Pred,
                              unsigned* counter, int* flags, hipStream_t st);
 
+// One request of a batched ADMM step (FP32 factors): its two sides, the
+// FP64 solve state and its partial buffers, all in its own workspace.
+struct AdmmJob {
+  AdmmSide s0, s1;        // U / Lam with L, and V^T / Phi^T with R^T
+  const double* At;       // k x k
+  double* XY;             // Xt, Yt^T (k x r each)
+  double* Pp;             // (parts0 + parts1) k x r partials
+  double* Pred;           // 2 k x r reduced partials
+  int* flags;             // breakdown flag word
+  double lam, phi, xi;
+  int k, r, parts0, parts1;
+  int rpb0, rpb1;         // rows per uv block (filled by admm_job_prepare)
+  int first;              // 1 for the request's first iteration
+  int at_in_lds;          // filled by admm_job_prepare
+};
+void admm_job_prepare(AdmmJob& J);
+int admm_job_uv_blocks(const AdmmJob& J);
+int admm_job_red_blocks(const AdmmJob& J);
+size_t admm_job_solve_lds(const AdmmJob& J);
+// jobs_dev: njobs descriptors; uv_first_dev / red_first_dev: first block of
+// each job in the uv / reduce launch (ascending, from 0), uv_blocks /
+// red_blocks the totals; solve_lds = max admm_job_solve_lds over the jobs.
+hipError_t launch_admm_step_batch(const AdmmJob* jobs_dev, const int* uv_first_dev, const int* red_first_dev,
+                                  int njobs, int uv_blocks, int red_blocks, int max_k, int max_r, size_t solve_lds,
+                                  hipStream_t st);
+
 // Generic row update for MU and the uncompressed comparators (k_nmf.hip).
 struct RowArgs {
   int rows, k1, r, k2;

@@ -44,17 +44,17 @@ struct Mf<double> {
 // accumulated on the MFMA in registers across sweeps (wave w owns M-blocks
 // w and w + 4).  KP, RP: k, r padded to 16.
 template <typename T, int CH>
-__global__ __launch_bounds__(256) void admm_uv_kernel(AdmmSide s0, AdmmSide s1, int nblk0,
-                                                      const double* __restrict__ XY, int k, int r,
-                                                      double xi, int mode, double* __restrict__ Pp,
-                                                      int rows_per_blk0, int rows_per_blk1) {
+__device__ __forceinline__ void admm_uv_body(const AdmmSide& s0, const AdmmSide& s1, int nblk0, int bid,
+                                             const double* __restrict__ XY, int k, int r, double xi, int mode,
+                                             double* __restrict__ Pp, int rows_per_blk0, int rows_per_blk1,
+                                             char* smraw) {
   typedef typename Mf<T>::acc_t acc_t;
-  const bool side1 = (int)blockIdx.x >= nblk0;
+  const bool side1 = bid >= nblk0;
   const AdmmSide S = side1 ? s1 : s0;
-  const int blk = side1 ? blockIdx.x - nblk0 : blockIdx.x;
+  const int blk = side1 ? bid - nblk0 : bid;
   const int rpb = side1 ? rows_per_blk1 : rows_per_blk0;
   const double* C = XY + (side1 ? (int64_t)k * r : 0);
-  double* out = Pp + (int64_t)blockIdx.x * k * r;   // partial slot = global block index
+  double* out = Pp + (int64_t)bid * k * r;   // partial slot = block index within the request
   const T* __restrict__ Bm = (const T*)S.Bm;
   T* __restrict__ F = (T*)S.F;
   T* __restrict__ M = (T*)S.M;
@@ -65,7 +65,6 @@ __global__ __launch_bounds__(256) void admm_uv_kernel(AdmmSide s0, AdmmSide s1, 
   const int KP = KP16 * 16, RP = RP16 * 16;
   const int ldb = KP + 1, ldc = RP + 1;
 
-  extern __shared__ char smraw[];
   T* cs = reinterpret_cast<T*>(smraw);   // KP x ldc
   T* bs = cs + KP * ldc;                 // CH x ldb
   T* ws = bs + CH * ldb;                 // CH x ldc
@@ -170,6 +169,38 @@ __global__ __launch_bounds__(256) void admm_uv_kernel(AdmmSide s0, AdmmSide s1, 
   }
 }
 
+template <typename T, int CH>
+__global__ __launch_bounds__(256) void admm_uv_kernel(AdmmSide s0, AdmmSide s1, int nblk0,
+                                                      const double* __restrict__ XY, int k, int r,
+                                                      double xi, int mode, double* __restrict__ Pp,
+                                                      int rows_per_blk0, int rows_per_blk1) {
+  extern __shared__ char smraw[];
+  admm_uv_body<T, CH>(s0, s1, nblk0, blockIdx.x, XY, k, r, xi, mode, Pp, rows_per_blk0, rows_per_blk1, smraw);
+}
+
+// Job of global block b in a batched launch: the last job whose first
+// block is <= b (first blocks ascending, jobs[0].first == 0).
+__device__ __forceinline__ int batch_job(const int* __restrict__ first, int njobs, int b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One ADMM row update (mode 1) for every job of a batch: the blocks of job j
+// are [uv_first[j], uv_first[j + 1]).
+template <typename T, int CH>
+__global__ __launch_bounds__(256) void admm_uv_batch_kernel(const AdmmJob* __restrict__ jobs,
+                                                            const int* __restrict__ uv_first, int njobs) {
+  extern __shared__ char smraw[];
+  const int j = batch_job(uv_first, njobs, blockIdx.x);
+  const AdmmJob& J = jobs[j];
+  admm_uv_body<T, CH>(J.s0, J.s1, J.parts0, (int)blockIdx.x - uv_first[j], J.XY, J.k, J.r, J.xi, 1, J.Pp,
+                      J.rpb0, J.rpb1, smraw);
+}
+
 template <typename T>
 hipError_t launch_admm_uv(AdmmSide s0, AdmmSide s1, int nsides, const double* XY, int k, int r, double xi,
                           int mode, double* Pp, int parts0, int parts1, hipStream_t st) {
@@ -199,16 +230,32 @@ template hipError_t launch_admm_uv<double>(AdmmSide, AdmmSide, int, const double
 constexpr int kRedNT = 256;
 constexpr int kRedEPB = 32;
 
-__global__ __launch_bounds__(kRedNT) void admm_reduce_kernel(const double* __restrict__ Pp, int parts0,
-                                                             int parts1, int64_t kr, double* __restrict__ Pred) {
-  __shared__ double red[kRedNT];
-  const int nbh = gridDim.x / 2;
-  const bool vside = (int)blockIdx.x >= nbh;
-  const int64_t e0 = (int64_t)(vside ? blockIdx.x - nbh : blockIdx.x) * kRedEPB;
+__device__ __forceinline__ void admm_reduce_body(const double* __restrict__ Pp, int parts0, int parts1, int64_t kr,
+                                                 double* __restrict__ Pred, int nbh, int bid, double* red) {
+  const bool vside = bid >= nbh;
+  const int64_t e0 = (int64_t)(vside ? bid - nbh : bid) * kRedEPB;
   if (!vside)
     block_sum_parts<kRedNT, kRedEPB>(Pp, parts0, kr, kr, e0, Pred, red);
   else
     block_sum_parts<kRedNT, kRedEPB>(Pp + (int64_t)parts0 * kr, parts1, kr, kr, e0, Pred + kr, red);
+}
+
+__global__ __launch_bounds__(kRedNT) void admm_reduce_kernel(const double* __restrict__ Pp, int parts0,
+                                                             int parts1, int64_t kr, double* __restrict__ Pred) {
+  __shared__ double red[kRedNT];
+  admm_reduce_body(Pp, parts0, parts1, kr, Pred, gridDim.x / 2, blockIdx.x, red);
+}
+
+int admm_reduce_blocks(int k, int r) { return 2 * (int)(((int64_t)k * r + kRedEPB - 1) / kRedEPB); }
+
+__global__ __launch_bounds__(kRedNT) void admm_reduce_batch_kernel(const AdmmJob* __restrict__ jobs,
+                                                                   const int* __restrict__ red_first, int njobs) {
+  __shared__ double red[kRedNT];
+  const int j = batch_job(red_first, njobs, blockIdx.x);
+  const AdmmJob& J = jobs[j];
+  const int64_t kr = (int64_t)J.k * J.r;
+  const int nbh = (int)((kr + kRedEPB - 1) / kRedEPB);
+  admm_reduce_body(J.Pp, J.parts0, J.parts1, kr, J.Pred, nbh, (int)blockIdx.x - red_first[j], red);
 }
 
 // The two r x r solves of one iteration in one workgroup.  XY: [0] Xt
@@ -218,15 +265,13 @@ __global__ __launch_bounds__(kRedNT) void admm_reduce_kernel(const double* __res
 // with an identity block and solved by the blocked Cholesky in LDS.
 constexpr int kSolveNT = 256;
 
-__global__ __launch_bounds__(kSolveNT) void admm_solve_kernel(const double* __restrict__ Pred,
-                                                              const double* __restrict__ At, int k, int r,
-                                                              double lam, double phi, int first,
-                                                              double* __restrict__ XY, int* flags, int at_in_lds) {
+__device__ __forceinline__ void admm_solve_body(const double* __restrict__ Pred, const double* __restrict__ At,
+                                                int k, int r, double lam, double phi, int first,
+                                                double* __restrict__ XY, int* flags, int at_in_lds, double* sm) {
   constexpr int NT = kSolveNT;
   const int tid = threadIdx.x;
   const int64_t kr = (int64_t)k * r;
   const int NB = (r + 15) / 16, N = 16 * NB, ld = N + 1;
-  extern __shared__ double sm[];
   double* Y = sm;                  // Yt^T, k x ld
   double* X = Y + k * ld;          // Xt / RHS, k x ld
   double* Mm = X + k * ld;         // N x ld: system matrix, then its factor
@@ -330,6 +375,21 @@ __global__ __launch_bounds__(kSolveNT) void admm_solve_kernel(const double* __re
   }
 }
 
+__global__ __launch_bounds__(kSolveNT) void admm_solve_kernel(const double* __restrict__ Pred,
+                                                              const double* __restrict__ At, int k, int r,
+                                                              double lam, double phi, int first,
+                                                              double* __restrict__ XY, int* flags, int at_in_lds) {
+  extern __shared__ double sm[];
+  admm_solve_body(Pred, At, k, r, lam, phi, first, XY, flags, at_in_lds, sm);
+}
+
+// One workgroup per job.
+__global__ __launch_bounds__(kSolveNT) void admm_solve_batch_kernel(const AdmmJob* __restrict__ jobs) {
+  extern __shared__ double sm[];
+  const AdmmJob& J = jobs[blockIdx.x];
+  admm_solve_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.flags, J.at_in_lds, sm);
+}
+
 static size_t admm_solve_lds(int k, int r, bool with_at) {
   const int NB = (r + 15) / 16, N = 16 * NB, ld = N + 1;
   size_t d = 2 * (size_t)k * ld + (size_t)N * ld + (size_t)NB * 272 + 16 * (size_t)ld + (size_t)k * 17;
@@ -358,5 +418,45 @@ hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const dou
 }
 template hipError_t launch_admm_solve<float>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, unsigned*, int*, hipStream_t);
 template hipError_t launch_admm_solve<double>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, unsigned*, int*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Batched ADMM step (serving): for every job, the fixed-order partial sums,
+// the two r x r solves and the mode-1 row update, as three launches over all
+// jobs.  Each job runs exactly the per-request code above, so its result does
+// not depend on which other jobs share the launch.
+// ---------------------------------------------------------------------------
+void admm_job_prepare(AdmmJob& J) {
+  J.rpb0 = (J.s0.rows + J.parts0 - 1) / J.parts0;
+  J.rpb1 = (J.s1.rows + J.parts1 - 1) / J.parts1;
+  J.at_in_lds = admm_solve_lds(J.k, J.r, true) <= 160 * 1024;
+}
+
+int admm_job_uv_blocks(const AdmmJob& J) { return J.parts0 + J.parts1; }
+int admm_job_red_blocks(const AdmmJob& J) { return admm_reduce_blocks(J.k, J.r); }
+
+hipError_t launch_admm_step_batch(const AdmmJob* jobs_dev, const int* uv_first_dev, const int* red_first_dev,
+                                  int njobs, int uv_blocks, int red_blocks, int max_k, int max_r, size_t solve_lds,
+                                  hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  if (max_r > 64 || max_k > 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(admm_reduce_batch_kernel, dim3(red_blocks), dim3(kRedNT), 0, st, jobs_dev, red_first_dev, njobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (solve_lds > 160 * 1024) return hipErrorInvalidValue;
+  hipFuncSetAttribute((const void*)admm_solve_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)solve_lds);
+  hipLaunchKernelGGL(admm_solve_batch_kernel, dim3(njobs), dim3(kSolveNT), solve_lds, st, jobs_dev);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int KP = (max_k + 15) / 16 * 16, RP = (max_r + 15) / 16 * 16;
+  const size_t lds = ((size_t)KP * (RP + 1) + 64 * (size_t)(KP + 1) + 64 * (size_t)(RP + 1)) * sizeof(float);
+  hipFuncSetAttribute((const void*)admm_uv_batch_kernel<float, 64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds);
+  hipLaunchKernelGGL((admm_uv_batch_kernel<float, 64>), dim3(uv_blocks), dim3(256), lds, st, jobs_dev, uv_first_dev,
+                     njobs);
+  CNMF_LAUNCH_CHECK();
+}
+
+size_t admm_job_solve_lds(const AdmmJob& J) { return admm_solve_lds(J.k, J.r, J.at_in_lds != 0); }
 
 }  // namespace cnmf

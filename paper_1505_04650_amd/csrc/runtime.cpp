@@ -39,6 +39,7 @@ struct cnmf_handle {
   size_t limit = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  bool ext_ws = false;  // ws belongs to the caller (serving arena): never freed or grown
   std::string err;
   // per-stage timing of the last call (HIP events on the handle's stream)
   bool timing = false;
@@ -370,6 +371,8 @@ void layout_admm(Arena& a, AdmmWs<T>& w, int64_t m, int64_t n, int k, int r) {
 
 cnmf_status ensure_ws(cnmf_handle* h, size_t bytes) {
   if (bytes <= h->ws_bytes) return CNMF_OK;
+  if (h->ext_ws)
+    return fail(h, CNMF_ENOMEM, "internal: request needs %zu workspace bytes, its block has %zu", bytes, h->ws_bytes);
   if (h->limit && bytes > h->limit)
     return fail(h, CNMF_ENOMEM, "workspace of %zu bytes exceeds the handle limit of %zu", bytes, h->limit);
   if (h->ws) {
@@ -743,53 +746,96 @@ cnmf_status pass_full(cnmf_handle* h, const cnmf_input* A, bool dirN, const T* o
   return CNMF_OK;
 }
 
+// A factorisation in four phases (the serving loop drives them separately):
+// layout of the workspace, prologue (sketch, initial state and, for ADMM,
+// the first partials), the iterations, and the epilogue (outputs, residual).
 template <typename T>
-cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
-                         const cnmf_factorize_out* o) {
-  const cnmf_sketch_desc* sk = &d->sk;
-  const bool full = d->method == CNMF_ADMM_FULL || d->method == CNMF_MU_FULL;
-  const bool want_ac = d->method == CNMF_MU;
+struct FactState {
   std::vector<Pass> passes;
-  if (!full) {
-    passes = plan_passes(sk->k, sk->q, CNMF_BOTH, want_ac, sk->pass_dtype, sk->final_dtype);
-    if (passes.empty()) return fail(h, CNMF_EINVAL, "internal: empty pass plan");
-  }
-  const int m = (int)A->m, n = (int)A->n, k = sk->k, r = sk->r;
-  Arena dry(nullptr);
+  bool full = false, want_ac = false;
   SketchWs<T> w;
   AdmmWs<T> aw;
   IterWs<T> iw;
-  if (!full) layout_sketch<T>(dry, w, m, n, k, passes, want_ac);
-  else {
-    w.flags = dry.take<int>(4);
-  }
-  layout_admm<T>(dry, aw, m, n, k, r);
-  if (d->method != CNMF_ADMM) layout_iter<T>(dry, iw, m, n, k, r, full);
-  cnmf_status s = ensure_ws(h, dry.off);
-  if (s != CNMF_OK) return s;
-  Arena a(h->ws);
-  if (!full) layout_sketch<T>(a, w, m, n, k, passes, want_ac);
-  else {
-    w.flags = a.take<int>(4);
-  }
-  layout_admm<T>(a, aw, m, n, k, r);
-  if (d->method != CNMF_ADMM) layout_iter<T>(a, iw, m, n, k, r, full);
-  hipStream_t st = h->stream;
+};
 
-  if (!full) {
-    s = run_sketch<T>(h, A, sk, w, passes, o->sk_out.stats_dev);
+template <typename T>
+cnmf_status fact_plan(cnmf_handle* h, const cnmf_factorize_desc* d, FactState<T>& f) {
+  const cnmf_sketch_desc* sk = &d->sk;
+  f.full = d->method == CNMF_ADMM_FULL || d->method == CNMF_MU_FULL;
+  f.want_ac = d->method == CNMF_MU;
+  if (!f.full) {
+    f.passes = plan_passes(sk->k, sk->q, CNMF_BOTH, f.want_ac, sk->pass_dtype, sk->final_dtype);
+    if (f.passes.empty()) return fail(h, CNMF_EINVAL, "internal: empty pass plan");
+  }
+  return CNMF_OK;
+}
+
+template <typename T>
+void fact_layout(Arena& a, FactState<T>& f, int64_t m, int64_t n, const cnmf_factorize_desc* d) {
+  const int k = d->sk.k, r = d->sk.r;
+  if (!f.full)
+    layout_sketch<T>(a, f.w, m, n, k, f.passes, f.want_ac);
+  else
+    f.w.flags = a.take<int>(4);
+  layout_admm<T>(a, f.aw, m, n, k, r);
+  if (d->method != CNMF_ADMM) layout_iter<T>(a, f.iw, m, n, k, r, f.full);
+}
+
+template <typename T>
+AdmmJob admm_job_of(FactState<T>& f, const cnmf_input* A, const cnmf_factorize_desc* d) {
+  const int m = (int)A->m, n = (int)A->n, k = d->sk.k, r = d->sk.r;
+  AdmmJob J{};
+  J.s0 = AdmmSide{f.w.Lb, k, f.aw.U, f.aw.Lam, r, m, d->lambda};
+  J.s1 = AdmmSide{f.w.RTb, k, f.aw.Vt, f.aw.Phit, r, n, d->phi};
+  J.At = f.w.At;
+  J.XY = f.aw.XY;
+  J.Pp = f.aw.Pp;
+  J.Pred = f.aw.Pred;
+  J.flags = f.w.flags + 2;
+  J.lam = d->lambda;
+  J.phi = d->phi;
+  J.xi = d->xi;
+  J.k = k;
+  J.r = r;
+  J.parts0 = f.aw.parts0;
+  J.parts1 = f.aw.parts1;
+  J.first = 1;
+  return J;
+}
+
+template <typename T>
+cnmf_status fact_prologue(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
+                          const cnmf_factorize_out* o, FactState<T>& f) {
+  const int m = (int)A->m, n = (int)A->n, k = d->sk.k, r = d->sk.r;
+  hipStream_t st = h->stream;
+  if (!f.full) {
+    cnmf_status s = run_sketch<T>(h, A, &d->sk, f.w, f.passes, o->sk_out.stats_dev);
     if (s != CNMF_OK) return s;
   } else {
-    HIPCHK(h, launch_fill(w.flags, 4 * sizeof(int), st));
+    HIPCHK(h, launch_fill(f.w.flags, 4 * sizeof(int), st));
   }
-
+  AdmmWs<T>& aw = f.aw;
   // state: U = U0, V^T = V0^T, Lam = Phi = 0
   HIPCHK(h, (launch_copy2d<double, T>(d->U0_dev, r, aw.U, r, m, r, 1.0, st)));
   HIPCHK(h, (launch_transpose<double, T>(d->V0_dev, n, aw.Vt, r, r, n, st)));
   HIPCHK(h, launch_fill(aw.Lam, sizeof(T) * (size_t)m * r, st));
   HIPCHK(h, launch_fill(aw.Phit, sizeof(T) * (size_t)n * r, st));
   HIPCHK(h, launch_fill(aw.counter, 4 * sizeof(unsigned), st));
+  if (d->method == CNMF_ADMM) {
+    AdmmJob J = admm_job_of(f, A, d);
+    Span sp(h, ST_ITER);
+    HIPCHK(h, launch_admm_uv<T>(J.s0, J.s1, 2, aw.XY, k, r, d->xi, 0, aw.Pp, aw.parts0, aw.parts1, st));
+  }
+  return CNMF_OK;
+}
 
+template <typename T>
+cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d, FactState<T>& f) {
+  const int m = (int)A->m, n = (int)A->n, k = d->sk.k, r = d->sk.r;
+  hipStream_t st = h->stream;
+  SketchWs<T>& w = f.w;
+  AdmmWs<T>& aw = f.aw;
+  IterWs<T>& iw = f.iw;
   auto row = [&](int rows, int blocks, const void* B1, int ldb1, const double* C, int k1, T* F, T* Mu,
                  const double* Gp, const double* Gm, const double* Minv, double pen, int method, const void* B2,
                  int k2, T* Op, double* Pp) -> cnmf_status {
@@ -827,13 +873,11 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
 
   if (d->method == CNMF_ADMM) {
     Span sp(h, ST_ITER, (double)d->iters * 4.0 * (double)(m + n) * k * r);
-    AdmmSide s0{w.Lb, k, aw.U, aw.Lam, r, m, d->lambda};
-    AdmmSide s1{w.RTb, k, aw.Vt, aw.Phit, r, n, d->phi};
-    HIPCHK(h, launch_admm_uv<T>(s0, s1, 2, aw.XY, k, r, d->xi, 0, aw.Pp, aw.parts0, aw.parts1, st));
+    AdmmJob J = admm_job_of(f, A, d);
     for (int it = 0; it < d->iters; ++it) {
       HIPCHK(h, launch_admm_solve<T>(aw.Pp, aw.parts0, aw.parts1, w.At, k, r, d->lambda, d->phi, it == 0, aw.XY,
                                      aw.Pred, aw.counter, w.flags + 2, st));
-      HIPCHK(h, launch_admm_uv<T>(s0, s1, 2, aw.XY, k, r, d->xi, 1, aw.Pp, aw.parts0, aw.parts1, st));
+      HIPCHK(h, launch_admm_uv<T>(J.s0, J.s1, 2, aw.XY, k, r, d->xi, 1, aw.Pp, aw.parts0, aw.parts1, st));
     }
   } else if (d->method == CNMF_MU) {
     Span sp(h, ST_ITER, (double)d->iters * (4.0 * (double)(m + n) * k * r + 4.0 * (double)(m + n) * r * r));
@@ -874,7 +918,15 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
     }
   }
 #undef RUN
+  return CNMF_OK;
+}
 
+template <typename T>
+cnmf_status fact_epilogue(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
+                          const cnmf_factorize_out* o, FactState<T>& f) {
+  const int m = (int)A->m, n = (int)A->n, r = d->sk.r;
+  hipStream_t st = h->stream;
+  AdmmWs<T>& aw = f.aw;
   if (o->U_dev) HIPCHK(h, (launch_copy2d<T, T>(aw.U, r, (T*)o->U_dev, r, m, r, 1.0, st)));
   if (o->V_dev) HIPCHK(h, (launch_transpose<T, T>(aw.Vt, r, (T*)o->V_dev, n, n, r, st)));
   if (o->rel_residual_dev) {
@@ -882,8 +934,27 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
     HIPCHK(h, launch_residual<T>((const T*)A->data_dev, A->lda, m, n, aw.U, r, aw.Vt, r, r, aw.rpart, aw.rparts, st));
     HIPCHK(h, launch_residual_finish(aw.rpart, aw.rparts, o->rel_residual_dev, st));
   }
-  if (full) return CNMF_OK;
-  return write_sketch_outputs<T>(h, A, sk, w, &o->sk_out);
+  if (f.full) return CNMF_OK;
+  return write_sketch_outputs<T>(h, A, &d->sk, f.w, &o->sk_out);
+}
+
+template <typename T>
+cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
+                         const cnmf_factorize_out* o) {
+  FactState<T> f;
+  cnmf_status s = fact_plan<T>(h, d, f);
+  if (s != CNMF_OK) return s;
+  Arena dry(nullptr);
+  fact_layout<T>(dry, f, A->m, A->n, d);
+  s = ensure_ws(h, dry.off);
+  if (s != CNMF_OK) return s;
+  Arena a(h->ws);
+  fact_layout<T>(a, f, A->m, A->n, d);
+  s = fact_prologue<T>(h, A, d, o, f);
+  if (s != CNMF_OK) return s;
+  s = fact_iterations<T>(h, A, d, f);
+  if (s != CNMF_OK) return s;
+  return fact_epilogue<T>(h, A, d, o, f);
 }
 
 template <typename T>
@@ -924,6 +995,87 @@ cnmf_status do_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_des
 }
 
 }  // namespace
+
+// ===========================================================================
+// Hooks of the serving loop (server.cpp): one request run in phases inside a
+// workspace block that the server owns.
+// ===========================================================================
+namespace cnmf {
+
+cnmf_status serve_check(const cnmf_input* A, const cnmf_factorize_desc* d, const cnmf_factorize_out* o);
+
+size_t serve_footprint(const cnmf_input* A, const cnmf_factorize_desc* d) {
+  auto go = [&](auto tag) -> size_t {
+    typedef decltype(tag) T;
+    FactState<T> f;
+    if (fact_plan<T>(nullptr, d, f) != CNMF_OK) return 0;
+    Arena dry(nullptr);
+    fact_layout<T>(dry, f, A->m, A->n, d);
+    return dry.off;
+  };
+  return A->dtype == CNMF_F64 ? go(double{}) : go(float{});
+}
+
+cnmf_status serve_handle_create(int device, hipStream_t st, cnmf_handle** out) {
+  cnmf_handle* h = new cnmf_handle();
+  h->device = device;
+  h->stream = st;
+  h->ext_ws = true;
+  timing_reset(h);
+  *out = h;
+  return CNMF_OK;
+}
+
+void serve_handle_destroy(cnmf_handle* h) {
+  if (!h) return;
+  for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
+  delete h;
+}
+
+const char* serve_handle_error(const cnmf_handle* h) { return h->err.c_str(); }
+
+// Batched (FP32 compressed ADMM with iterations): runs the prologue and
+// fills *job; otherwise runs the whole request.  *batched says which.
+cnmf_status serve_begin(cnmf_handle* h, char* ws, size_t ws_bytes, const cnmf_input* A, const cnmf_factorize_desc* d,
+                        const cnmf_factorize_out* o, AdmmJob* job, bool* batched) {
+  h->ws = ws;
+  h->ws_bytes = ws_bytes;
+  timing_reset(h);
+  *batched = d->method == CNMF_ADMM && A->dtype == CNMF_F32 && d->iters > 0;
+  if (!*batched) {
+    if (A->dtype == CNMF_F64) return do_factorize<double>(h, A, d, o);
+    return do_factorize<float>(h, A, d, o);
+  }
+  FactState<float> f;
+  cnmf_status s = fact_plan<float>(h, d, f);
+  if (s != CNMF_OK) return s;
+  Arena dry(nullptr);
+  fact_layout<float>(dry, f, A->m, A->n, d);
+  s = ensure_ws(h, dry.off);
+  if (s != CNMF_OK) return s;
+  Arena a(h->ws);
+  fact_layout<float>(a, f, A->m, A->n, d);
+  s = fact_prologue<float>(h, A, d, o, f);
+  if (s != CNMF_OK) return s;
+  *job = admm_job_of(f, A, d);
+  admm_job_prepare(*job);
+  return CNMF_OK;
+}
+
+cnmf_status serve_end(cnmf_handle* h, char* ws, size_t ws_bytes, const cnmf_input* A, const cnmf_factorize_desc* d,
+                      const cnmf_factorize_out* o) {
+  h->ws = ws;
+  h->ws_bytes = ws_bytes;
+  FactState<float> f;
+  cnmf_status s = fact_plan<float>(h, d, f);
+  if (s != CNMF_OK) return s;
+  Arena a(h->ws);
+  fact_layout<float>(a, f, A->m, A->n, d);
+  if (a.off > ws_bytes) return fail(h, CNMF_ENOMEM, "internal: workspace block too small");
+  return fact_epilogue<float>(h, A, d, o, f);
+}
+
+}  // namespace cnmf
 
 // ===========================================================================
 // C ABI
@@ -1040,6 +1192,19 @@ static cnmf_status check_factorize(cnmf_handle* h, const cnmf_input* A, const cn
   if (d->sk.r > 64) return fail(h, CNMF_ENOTSUP, "r=%d > 64 is not supported by the NMF iterations", d->sk.r);
   return CNMF_OK;
 }
+
+}  // extern "C"
+
+cnmf_status cnmf::serve_check(const cnmf_input* A, const cnmf_factorize_desc* d, const cnmf_factorize_out* o) {
+  cnmf_status s = check_input(nullptr, A);
+  if (s != CNMF_OK) return s;
+  s = check_factorize(nullptr, A, d);
+  if (s != CNMF_OK) return s;
+  if (!o) return fail(nullptr, CNMF_EINVAL, "out is NULL");
+  return CNMF_OK;
+}
+
+extern "C" {
 
 cnmf_status cnmf_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
                            cnmf_factorize_out* out) {
