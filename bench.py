@@ -132,6 +132,111 @@ def precision_section(h, steps, warmup):
     return out
 
 
+def serving_section(n_req, qps, max_batch=128, workers=3, budget_bytes=8 << 30, baseline_n=40):
+    """The serving workload: n_req uneven compressed-ADMM requests (FP32,
+    k = r + 10, q = 2, 100 iterations) with Poisson arrivals at `qps`,
+    generated on the device at their arrival, through the continuous-
+    batching server.  Beside it: the first `baseline_n` requests run one at a
+    time through cnmf_factorize (the plain FP32 path), whose factors the
+    served ones equal bit for bit."""
+    import torch
+    from paper_1505_04650_amd import api
+    S = WL.SERVING
+    m, n, r, k, t_arr = WL.serving_requests(n_req, qps)
+    dev = torch.device("cuda", 0)
+    noise_mean = S["sigma"] * math.sqrt(2.0 / math.pi)
+
+    def gen(i):
+        g = torch.Generator(device=dev)
+        g.manual_seed(10_000 + i)
+        mi, ni, ri, ki = int(m[i]), int(n[i]), int(r[i]), int(k[i])
+        A = torch.rand(mi, ri, device=dev, generator=g) @ torch.rand(ri, ni, device=dev, generator=g)
+        A += (S["sigma"] * torch.randn(mi, ni, device=dev, generator=g)).abs_()
+        oml = torch.randn(ni, ki, device=dev, dtype=torch.float64, generator=g)
+        omr = torch.randn(mi, ki, device=dev, dtype=torch.float64, generator=g)
+        c = math.sqrt(4.0 * (ri / 4.0 + noise_mean) / ri)
+        U0 = c * torch.rand(mi, ri, device=dev, dtype=torch.float64, generator=g)
+        V0 = c * torch.rand(ri, ni, device=dev, dtype=torch.float64, generator=g)
+        lam = WL.expected_rms(ri, S["sigma"]) * math.sqrt(min(mi, ni))
+        return dict(A=A, r=ri, k=ki, q=S["q"], U0=U0, V0=V0, omega_left=oml, omega_right=omr, lam=lam)
+
+    # the plain path: one request at a time through cnmf_factorize
+    h = api.default_handle()
+    base = []
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    for i in range(baseline_n):
+        q = gen(i)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        f = api.factorize(q["A"], q["r"], q["k"], q["q"], q["U0"], q["V0"], q["omega_left"], q["omega_right"],
+                          iters=S["iters"], lam=q["lam"], phi=q["lam"], handle=h)
+        torch.cuda.synchronize()
+        base.append(((time.perf_counter() - t1) * 1e3, f.U, f.V, float(f.rel_residual.item())))
+    base_wall = time.perf_counter() - tb0
+    base_ms = np.array([b[0] for b in base])
+
+    lat, queue, res, same = [], [], [], []
+    with api.Server(budget_bytes, max_batch=max_batch, workers=workers) as srv:
+        outstanding = {}
+
+        def drain(block=False):
+            while outstanding:
+                done_any = False
+                for i in list(outstanding):
+                    t = outstanding[i]
+                    info = srv.poll(t)
+                    if info["done"]:
+                        if info["status"] != 0:
+                            raise RuntimeError(f"request {i} failed: {info['message']}")
+                        lat.append(info["total_ms"])
+                        queue.append(info["queue_ms"])
+                        res.append(float(t.rel_residual.item()))
+                        if i < baseline_n:
+                            same.append(bool(torch.equal(t.U, base[i][1]) and torch.equal(t.V, base[i][2])))
+                        srv.release(t)
+                        del outstanding[i]
+                        done_any = True
+                if not block or not outstanding:
+                    return
+                if not done_any:
+                    time.sleep(2e-4)
+
+        t0 = time.perf_counter()
+        for i in range(n_req):
+            while time.perf_counter() - t0 < t_arr[i]:
+                drain()
+                time.sleep(1e-4)
+            q = gen(i)
+            outstanding[i] = srv.submit(q["A"], q["r"], q["k"], q["q"], q["U0"], q["V0"], q["omega_left"],
+                                        q["omega_right"], iters=S["iters"], lam=q["lam"], phi=q["lam"])
+            if i % 64 == 63:
+                drain()
+        t_sub = time.perf_counter() - t0
+        drain(block=True)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    lat = np.array(lat)
+    out = {"workload": f"serving_{n_req}", "requests": n_req, "qps_offered": qps or None,
+           "qps_submitted": n_req / t_sub if t_sub > 0 else None,
+           "m": list(S["m"]), "n": list(S["n"]), "r": list(S["r"]), "q": S["q"], "iters": S["iters"],
+           "max_batch": max_batch, "workers": workers, "hbm_budget_bytes": budget_bytes,
+           "solves_per_s": n_req / wall, "wall_s": wall,
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                          "mean": float(lat.mean()), "max": float(lat.max())},
+           "queue_ms_p50": float(np.percentile(queue, 50)),
+           "rel_residual_mean": float(np.mean(res)), "rel_residual_max": float(np.max(res)),
+           "server": {k2: st[k2] for k2 in ("batch_steps", "batched_iterations", "max_batch_seen",
+                                            "peak_arena_bytes")},
+           "plain_path": {"requests": baseline_n, "solves_per_s": baseline_n / base_wall,
+                          "latency_ms_p50": float(np.percentile(base_ms, 50)),
+                          "latency_ms_p99": float(np.percentile(base_ms, 99)),
+                          "served_results_identical": bool(all(same)) if same else None}}
+    log(f"serving: {out['solves_per_s']:.1f} solves/s, p50 {out['latency_ms']['p50']:.1f} ms, "
+        f"p99 {out['latency_ms']['p99']:.1f} ms (plain path {out['plain_path']['solves_per_s']:.1f} solves/s)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +246,10 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--precision-only", action="store_true",
                     help="only the precision sketches (for kernel profiles); prints that object")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving run; prints that object")
+    ap.add_argument("--serving-requests", type=int, default=WL.SERVING["count"])
+    ap.add_argument("--serving-qps", type=float, default=400.0, help="Poisson arrival rate (0: all at once)")
     ap.add_argument("--workload", default="nmf_fp32_20000x5000")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -157,6 +266,9 @@ def main():
     if args.precision_only:
         print(json.dumps({"precision": precision_section(api.default_handle(), max(1, args.steps), args.warmup)}),
               flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_section(args.serving_requests, args.serving_qps)}), flush=True)
         return
     log(f"workload {w.name}: generating inputs")
     inp = WL.make_inputs(w)
@@ -240,6 +352,8 @@ def main():
 
     if not args.no_precision:
         out["precision"] = precision_section(h, max(2, min(args.steps, 5)), 1)
+    if not args.no_serving:
+        out["serving"] = serving_section(args.serving_requests, args.serving_qps)
 
     if not args.no_cpu_baseline:
         log("cpu baseline: running the FP64 oracle on the host")

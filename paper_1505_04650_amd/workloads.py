@@ -137,3 +137,30 @@ def make_inputs(w: Workload, *, m=None, n=None, storage=None, two_sided=True, wa
         mean_a = float(np.mean(A, dtype=np.float64))
         out["U1"], out["V1"] = init_factors(mean_a, m, n, w.r, 100 * w.index + 2)
     return out
+
+
+# Serving workload: a stream of uneven factorisation requests.
+SERVING = dict(count=2000, m=(500, 20000), n=(200, 8000), r=(5, 64), oversample=10, q=2, iters=100, sigma=0.05)
+
+
+def serving_requests(count: int = SERVING["count"], qps: float = 0.0, seed: int = 500):
+    """Shapes and arrival times of the serving workload: m and n log-uniform
+    on their ranges, r uniform on [5, 64], k = r + 10; Poisson arrivals at
+    `qps` requests per second (all at t = 0 when qps == 0).  Returns int64
+    arrays m, n, r, k and float64 arrival times in seconds."""
+    g = _rng(seed)
+    lo_m, hi_m = SERVING["m"]
+    lo_n, hi_n = SERVING["n"]
+    m = np.rint(np.exp(g.uniform(math.log(lo_m), math.log(hi_m), count))).astype(np.int64)
+    n = np.rint(np.exp(g.uniform(math.log(lo_n), math.log(hi_n), count))).astype(np.int64)
+    r = g.integers(SERVING["r"][0], SERVING["r"][1] + 1, count).astype(np.int64)
+    k = r + SERVING["oversample"]
+    t = np.cumsum(g.exponential(1.0 / qps, count)) if qps > 0 else np.zeros(count)
+    return m, n, r, k, t
+
+
+def expected_rms(r: int, sigma: float) -> float:
+    """Root mean square of an entry of W H + |sigma Z| with W, H uniform on
+    [0, 1): E[(sum_l w_l h_l)^2] = r / 9 + r (r - 1) / 16, plus the noise's
+    second moment sigma^2 (cross terms neglected)."""
+    return math.sqrt(r / 9.0 + r * (r - 1) / 16.0 + sigma * sigma)
