@@ -147,51 +147,21 @@ hipError_t launch_sum_parts(const double* in, int parts, int64_t count, double* 
 
 // ---------------------------------------------------------------------------
 // G_h = sum of the Gram partials (fixed order; sum_parts kernel), then one
-// workgroup per half: G_h = T^T T (Cholesky, T upper with positive diagonal)
-// and Tinv_h = T^-1 written to global memory (upper, zero lower triangle).
-// Partials: Gp[(p * nh + h) * kh * kh].  A pivot <= 1e-20 max_i G_ii (or
-// not finite) counts as a breakdown in flags[h] and is replaced by that floor.
+// workgroup per half: G_h (padded to N = 16 ceil(kh / 16) with an identity
+// block) = T^T T by the blocked Cholesky in LDS (T upper, positive
+// diagonal), then Tinv_h = T^-1 by block columns, written to global memory
+// (kh x kh, zero below the diagonal).  A pivot <= 1e-20 max_i G_ii (or not
+// finite) counts as a breakdown in flags[h] and is replaced by that floor.
 // ---------------------------------------------------------------------------
-constexpr int kCholNT = 512;
-
-// kh > 64: LDS factorisation by the whole workgroup.
-__global__ __launch_bounds__(kCholNT) void chol_kernel(const double* __restrict__ G, int kh,
-                                                       double* __restrict__ Tinv, int* flags) {
-  constexpr int NT = kCholNT;
-  const int h = blockIdx.x;
-  const int64_t cnt = (int64_t)kh * kh;
-  extern __shared__ double sm[];
-  const int ld = kh + 1;
-  double* M = sm;
-  double* Td = sm + kh * ld;
-  const double* Gh = G + h * cnt;
-  for (int e = threadIdx.x; e < kh * kh; e += NT) {
-    int i = e / kh, j = e - i * kh;
-    if (j >= i) M[i * ld + j] = 0.5 * (Gh[i * kh + j] + Gh[j * kh + i]);
-  }
-  __syncthreads();
-  double mx = 0.0;
-  for (int i = 0; i < kh; ++i) mx = fmax(mx, M[i * ld + i]);
-  wg_cholesky_inverse<NT>(M, kh, ld, Td, 1e-20 * mx, flags ? flags + h : nullptr);
-  double* out = Tinv + h * cnt;
-  for (int e = threadIdx.x; e < kh * kh; e += NT) {
-    int i = e / kh, j = e - i * kh;
-    out[e] = j >= i ? M[i * ld + j] : 0.0;
-  }
-}
-
-// kh <= 64: factor only (blocked, padded to 16 ceil(kh / 16) with I);
-// Tf_h = T (upper, zero lower) for the substitution in apply_tri_kernel.
 constexpr int kFacNT = 256;
-__global__ __launch_bounds__(kFacNT) void chol_fac_kernel(const double* __restrict__ G, int kh,
-                                                          double* __restrict__ Tf, int* flags) {
+__global__ __launch_bounds__(kFacNT) void chol_tinv_kernel(const double* __restrict__ G, int kh,
+                                                           double* __restrict__ Tinv, int* flags) {
   const int h = blockIdx.x;
   const int64_t cnt = (int64_t)kh * kh;
   const int NB = (kh + 15) / 16, N = 16 * NB, ld = N + 1;
   extern __shared__ double sm[];
   double* M = sm;              // N x ld
   double* TI = M + N * ld;     // NB x 272
-  double* PN = TI + NB * 272;  // 16 x ld
   const double* Gh = G + h * cnt;
   for (int e = threadIdx.x; e < N * N; e += kFacNT) {
     int i = e / N, j = e - i * N;
@@ -205,119 +175,80 @@ __global__ __launch_bounds__(kFacNT) void chol_fac_kernel(const double* __restri
   __syncthreads();
   double mx = 0.0;
   for (int i = 0; i < kh; ++i) mx = fmax(mx, M[i * ld + i]);
-  wg_chol_blocked<kFacNT>(M, ld, NB, TI, PN, 1e-20 * mx, flags ? flags + h : nullptr);
-  double* out = Tf + h * cnt;
+  wg_chol_blocked_ip<kFacNT>(M, ld, NB, TI, 1e-20 * mx, flags ? flags + h : nullptr);
+  wg_tinv_blocked<kFacNT>(M, ld, NB, TI);
+  double* out = Tinv + h * cnt;
   for (int e = threadIdx.x; e < kh * kh; e += kFacNT) {
-    int i = e / kh, j = e - i * kh;
-    out[e] = j >= i ? M[i * ld + j] : 0.0;
+    const int i = e / kh, j = e - i * kh;
+    const int bi = i >> 4, bj = j >> 4, r = i & 15, c = j & 15;
+    double v = 0.0;
+    if (j >= i) v = bi == bj ? TI[bi * 272 + r * 17 + c] : M[j * ld + 16 * bi + r];
+    out[e] = v;
   }
-}
-
-// Q[i][h*kh + c] for one row per thread: forward substitution z T = y with
-// the upper factor T (staged in LDS, read uniformly), z in registers.
-template <typename TY, int KH>
-__global__ __launch_bounds__(256) void apply_tri_kernel(const TY* __restrict__ Y, int rows, int ldy, int kh,
-                                                        const double* __restrict__ Tf, double* __restrict__ Q,
-                                                        int ldq) {
-  const int h = blockIdx.y;
-  const int row = blockIdx.x * 256 + threadIdx.x;
-  __shared__ double T[KH * KH];
-  const double* __restrict__ Tg = Tf + (int64_t)h * kh * kh;
-  for (int e = threadIdx.x; e < kh * kh; e += 256) T[e] = Tg[e];
-  __syncthreads();
-  if (row >= rows) return;
-  const TY* y = Y + (int64_t)row * ldy + h * kh;
-  double z[KH];
-#pragma unroll
-  for (int c = 0; c < KH; ++c) z[c] = c < kh ? (double)y[c] : 0.0;
-#pragma unroll
-  for (int c = 0; c < KH; ++c) {
-    if (c < kh) {
-      double s0 = z[c], s1 = 0.0;
-#pragma unroll
-      for (int l = 0; l < c; l += 2) {
-        s0 = fma(-z[l], T[l * kh + c], s0);
-        if (l + 1 < c) s1 = fma(-z[l + 1], T[(l + 1) * kh + c], s1);
-      }
-      z[c] = (s0 + s1) / T[c * kh + c];
-    }
-  }
-  double* q = Q + (int64_t)row * ldq + h * kh;
-#pragma unroll
-  for (int c = 0; c < KH; ++c)
-    if (c < kh) q[c] = z[c];
-}
-
-template <typename TY>
-hipError_t launch_apply_tri(const TY* Y, int rows, int ldy, int nh, int kh, const double* Tf, double* Q64, int ldq,
-                            hipStream_t st) {
-  dim3 grid((rows + 255) / 256, nh);
-  if (kh <= 16)
-    hipLaunchKernelGGL((apply_tri_kernel<TY, 16>), grid, dim3(256), 0, st, Y, rows, ldy, kh, Tf, Q64, ldq);
-  else if (kh <= 32)
-    hipLaunchKernelGGL((apply_tri_kernel<TY, 32>), grid, dim3(256), 0, st, Y, rows, ldy, kh, Tf, Q64, ldq);
-  else if (kh <= 48)
-    hipLaunchKernelGGL((apply_tri_kernel<TY, 48>), grid, dim3(256), 0, st, Y, rows, ldy, kh, Tf, Q64, ldq);
-  else if (kh <= 64)
-    hipLaunchKernelGGL((apply_tri_kernel<TY, 64>), grid, dim3(256), 0, st, Y, rows, ldy, kh, Tf, Q64, ldq);
-  else
-    return hipErrorInvalidValue;
-  CNMF_LAUNCH_CHECK();
 }
 
 hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double* G, double* Tinv, int* flags,
                             unsigned* /*counters*/, hipStream_t st) {
+  if (kh > 128) return hipErrorInvalidValue;
   hipError_t e = launch_sum_parts(Gp, parts, (int64_t)nh * kh * kh, G, st);
   if (e != hipSuccess) return e;
-  if (kh <= 64) {
-    const int NB = (kh + 15) / 16, N = 16 * NB, ld = N + 1;
-    size_t sm = ((size_t)N * ld + (size_t)NB * 272 + 16 * (size_t)ld) * sizeof(double);
-    hipFuncSetAttribute((const void*)chol_fac_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    hipLaunchKernelGGL(chol_fac_kernel, dim3(nh), dim3(kFacNT), sm, st, G, kh, Tinv, flags);
-  } else {
-    size_t sm = ((size_t)kh * (kh + 1) + kh) * sizeof(double);
-    hipFuncSetAttribute((const void*)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    hipLaunchKernelGGL(chol_kernel, dim3(nh), dim3(kCholNT), sm, st, G, kh, Tinv, flags);
-  }
+  const int NB = (kh + 15) / 16, N = 16 * NB, ld = N + 1;
+  size_t sm = ((size_t)N * ld + (size_t)NB * 272) * sizeof(double);
+  hipFuncSetAttribute((const void*)chol_tinv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  hipLaunchKernelGGL(chol_tinv_kernel, dim3(nh), dim3(kFacNT), sm, st, G, kh, Tinv, flags);
   CNMF_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
-// Q64[i][h*kh + c] = sum_{l <= c} Y[i][h*kh + l] Tinv_h[l][c]   (FP64)
+// Q64[i][h*kh + c] = sum_{l <= c} Y[i][h*kh + l] Tinv_h[l][c] on the FP64
+// MFMA (16x16x4).  Workgroup: 64 rows (wave w: rows 16 w .. 16 w + 15) of
+// one half; each lane first loads its K values of Y (lane (r, g) supplies
+// Y[row r][4 s + g]), then the 64-column slabs of Tinv_h are staged in LDS
+// one after the other.  All reads of a row precede the writes of that row,
+// so Q64 == Y (in place) is allowed.
 // ---------------------------------------------------------------------------
 template <typename TY>
-__global__ __launch_bounds__(256) void apply_tinv_kernel(const TY* __restrict__ Y, int rows, int ldy, int kh,
-                                                         const double* __restrict__ Tinv,
-                                                         double* __restrict__ Q, int ldq, int rows_per_block,
-                                                         int rb) {
-  extern __shared__ double sm[];
-  double* Ti = sm;               // kh x kh (upper part used)
-  double* ys = sm + kh * kh;     // rb x kh rows
+__global__ __launch_bounds__(256, 2) void apply_mfma_kernel(const TY* __restrict__ Y, int rows, int ldy, int kh,
+                                                            const double* __restrict__ Tinv, double* Q, int ldq) {
+  constexpr int SL = 64, LDT = SL + 4, KS = 32;   // kh <= 128: at most 32 K steps of 4
+  __shared__ double Ts[4 * KS * LDT];
   const int h = blockIdx.y;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int row0 = blockIdx.x * 64 + w * 16;
+  const int row = row0 + r;
+  const int nsteps = (kh + 3) >> 2;
   const double* Th = Tinv + (int64_t)h * kh * kh;
-  for (int e = tid; e < kh * kh; e += 256) Ti[e] = Th[e];
-  const int i0 = blockIdx.x * rows_per_block;
-  const int i1 = min(rows, i0 + rows_per_block);
-  for (int base = i0; base < i1; base += rb) {
-    const int nr = min(rb, i1 - base);
+  double yv[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int l = 4 * s + g;
+    yv[s] = (s < nsteps && row < rows && l < kh) ? (double)Y[(int64_t)row * ldy + h * kh + l] : 0.0;
+  }
+  const int nslab = (kh + SL - 1) / SL;
+  for (int sl = 0; sl < nslab; ++sl) {
+    const int c0 = sl * SL;
     __syncthreads();
-    for (int e = tid; e < nr * kh; e += 256) {
-      int rr = e / kh, c = e - rr * kh;
-      ys[e] = (double)Y[(int64_t)(base + rr) * ldy + h * kh + c];
+    for (int e = tid; e < 4 * nsteps * SL; e += 256) {
+      const int l = e / SL, c = e - l * SL;
+      Ts[l * LDT + c] = (l < kh && c0 + c < kh) ? Th[l * kh + c0 + c] : 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < nr * kh; e += 256) {
-      int rr = e / kh, c = e - rr * kh;
-      const double* y = ys + rr * kh;
-      double s0 = 0.0, s1 = 0.0;
-      int l = 0;
-      for (; l + 1 <= c; l += 2) {
-        s0 = fma(y[l], Ti[l * kh + c], s0);
-        s1 = fma(y[l + 1], Ti[(l + 1) * kh + c], s1);
+#pragma unroll
+    for (int cb = 0; cb < SL / 16; ++cb) {
+      const int cbase = c0 + 16 * cb;
+      if (cbase >= kh) break;
+      // Tinv is upper triangular: rows l <= cbase + 15 contribute
+      const int smax = min(nsteps, (cbase + 16 + 3) >> 2);
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        if (s < smax) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[s], Ts[(4 * s + g) * LDT + 16 * cb + r], acc, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int orow = row0 + g + 4 * i, col = cbase + r;
+        if (orow < rows && col < kh) Q[(int64_t)orow * ldq + h * kh + col] = acc[i];
       }
-      if (l <= c) s0 = fma(y[l], Ti[l * kh + c], s0);
-      Q[(int64_t)(base + rr) * ldq + h * kh + c] = s0 + s1;
     }
   }
 }
@@ -325,16 +256,9 @@ __global__ __launch_bounds__(256) void apply_tinv_kernel(const TY* __restrict__ 
 template <typename TY>
 hipError_t launch_apply_tinv(const TY* Y, int rows, int ldy, int nh, int kh, const double* Tinv,
                              double* Q64, int ldq, hipStream_t st) {
-  if (kh <= 64) return launch_apply_tri<TY>(Y, rows, ldy, nh, kh, Tinv, Q64, ldq, st);
-  const size_t cap = 160 * 1024;
-  int rb = (int)std::min<size_t>(64, (cap - (size_t)kh * kh * 8) / ((size_t)kh * 8));
-  rb = std::max(rb, 1);
-  int blocks = std::max(1, std::min(512, (rows + 2 * rb - 1) / (2 * rb)));
-  int rpb = (rows + blocks - 1) / blocks;
-  size_t sm = ((size_t)kh * kh + (size_t)rb * kh) * sizeof(double);
-  hipFuncSetAttribute((const void*)apply_tinv_kernel<TY>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  hipLaunchKernelGGL(apply_tinv_kernel<TY>, dim3(blocks, nh), dim3(256), sm, st, Y, rows, ldy, kh, Tinv, Q64,
-                     ldq, rpb, rb);
+  if (kh > 128) return hipErrorInvalidValue;
+  dim3 grid((rows + 63) / 64, nh);
+  hipLaunchKernelGGL(apply_mfma_kernel<TY>, grid, dim3(256), 0, st, Y, rows, ldy, kh, Tinv, Q64, ldq);
   CNMF_LAUNCH_CHECK();
 }
 template hipError_t launch_apply_tinv<float>(const float*, int, int, int, int, const double*, double*, int, hipStream_t);

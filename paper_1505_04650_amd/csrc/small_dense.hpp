@@ -246,6 +246,109 @@ __device__ void wave_diag16(double* D, int ldd, double* TI, double floor_piv, in
   __builtin_amdgcn_wave_barrier();
 }
 
+// 1 / sqrt(d) for d > 0: the hardware estimate refined by two Newton steps
+// y <- y (3/2 - d y^2 / 2) (each step squares the relative error).
+__device__ __forceinline__ double rsqrt_refined(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// x from lane `src` (any lane; every lane may name a different source).
+__device__ __forceinline__ double bperm_d(double x, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+// The same contract as wave_diag16 with a quad layout: lane 4 i + q holds
+// D[i][4q .. 4q + 3].  Step j: the pivot comes by readlane, 1/sqrt by a
+// refined reciprocal square root, column j within each quad by DPP and row
+// j by bpermute, so each step is a short dependent chain.  T^-1 follows
+// column by column, S[:, j] = (e_j - S[:, <j] T[<j, j]) / T[j][j], with the
+// row sums reduced inside the quads.
+template <int J>
+__device__ __forceinline__ double quad_bcast_d(double x) {
+  constexpr int ctrl = J | (J << 2) | (J << 4) | (J << 6);
+  return dpp_d<ctrl>(x);
+}
+
+__device__ void wave_diag16_quad(double* D, int ldd, double* TI, double floor_piv, int* flag) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane >> 2, q = lane & 3;
+  double a[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) a[e] = D[i * ldd + 4 * q + e];
+  double ys[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int jq = j >> 2, je = j & 3;
+    double d = readlane_d(a[je], 4 * j + jq);
+    if (!(d > floor_piv) || !isfinite(d)) {
+      if (lane == 0 && flag) atomicAdd(flag, 1);
+      d = floor_piv > 0.0 ? floor_piv : 1.0;
+    }
+    const double y = rsqrt_refined(d);
+    ys[j] = y;
+    double mij;
+    switch (jq) {
+      case 0: mij = quad_bcast_d<0>(a[je]); break;
+      case 1: mij = quad_bcast_d<1>(a[je]); break;
+      case 2: mij = quad_bcast_d<2>(a[je]); break;
+      default: mij = quad_bcast_d<3>(a[je]); break;
+    }
+    double rj[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rj[e] = bperm_d(a[e], 4 * j + q);
+    const double f = mij * (y * y);
+    if (i > j) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (4 * q + e > j) a[e] = fma(-f, rj[e], a[e]);
+    } else if (i == j) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 4 * q + e;
+        if (c > j) a[e] *= y;
+        else if (c == j) a[e] = d * y;
+      }
+    }
+  }
+  // T (upper, zeros below) back to D
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int c = 4 * q + e;
+    D[i * ldd + c] = c >= i ? a[e] : 0.0;
+  }
+  // S = T^-1, column by column
+  double sv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int jq = j >> 2, je = j & 3;
+    double p = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int l = 4 * q + e;
+      const double tlj = bperm_d(a[je], 4 * l + jq);   // T[l][j], held by lane (l, jq)
+      if (l < j) p = fma(sv[e], tlj, p);
+    }
+    p += dpp_d<0xB1>(p);
+    p += dpp_d<0x4E>(p);
+    const double sij = i <= j ? ((i == j ? 1.0 : 0.0) - p) * ys[j] : 0.0;
+    if (q == jq) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (e == je) sv[e] = sij;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) TI[i * 17 + 4 * q + e] = sv[e];
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+}
+
 // M (N x N, LDS, row stride ldm, full symmetric) = T^T T.  On return the
 // upper block triangle of M holds T (diagonal blocks upper triangular),
 // TI[jb] (16 x 17 each) the inverses of the diagonal blocks.  PN: 16 x ldm
@@ -296,6 +399,129 @@ __device__ void wg_chol_blocked(double* M, int ldm, int NB, double* TI, double* 
       }
       __syncthreads();
     }
+  }
+}
+
+// Blocked factorisation for N = 16 NB <= 128 without panel scratch (LDS:
+// M, N x ldm, and TI, NB x 272): M = T^T T as in wg_chol_blocked.  The panel
+// is formed in place one column per thread; the trailing update (both
+// triangles) uses 4 x 4 register tiles.  Starts and ends with a barrier.
+template <int NT>
+__device__ void wg_chol_blocked_ip(double* M, int ldm, int NB, double* TI, double floor_piv, int* flag) {
+  const int tid = threadIdx.x;
+  const int N = 16 * NB;
+  __syncthreads();
+  for (int jb = 0; jb < NB; ++jb) {
+    const int j0 = 16 * jb, c0 = j0 + 16, rem = N - c0;
+    if (tid < 64) wave_diag16(M + j0 * ldm + j0, ldm, TI + jb * 272, floor_piv, flag);
+    __syncthreads();
+    if (rem <= 0) break;
+    const double* ti = TI + jb * 272;
+    // panel T[j0 + i][c] = sum_{l <= i} Tinv[l][i] M[j0 + l][c], in place
+    for (int c = c0 + tid; c < N; c += NT) {
+      double v[16], o[16];
+#pragma unroll
+      for (int l = 0; l < 16; ++l) v[l] = M[(j0 + l) * ldm + c];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l <= i; ++l) acc = fma(ti[l * 17 + i], v[l], acc);
+        o[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) M[(j0 + i) * ldm + c] = o[i];
+    }
+    __syncthreads();
+    // trailing update M[x][y] -= sum_i P[i][x] P[i][y] over 4 x 4 tiles of the
+    // upper tile triangle, mirrored to the lower one
+    const int RQ = rem / 4;
+    for (int e = tid; e < RQ * RQ; e += NT) {
+      const int ta = e / RQ, tb = e - ta * RQ;
+      if (tb < ta) continue;
+      const int x0 = c0 + 4 * ta, y0 = c0 + 4 * tb;
+      double acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) acc[u][w] = 0.0;
+#pragma unroll 4
+      for (int i = 0; i < 16; ++i) {
+        const double* pr = M + (j0 + i) * ldm;
+        double px[4], py[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          px[u] = pr[x0 + u];
+          py[u] = pr[y0 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) acc[u][w] = fma(px[u], py[w], acc[u][w]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const int x = x0 + u, y = y0 + w;
+          if (y < x) continue;
+          M[x * ldm + y] -= acc[u][w];
+          if (y != x) M[y * ldm + x] -= acc[u][w];
+        }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+}
+
+// After wg_chol_blocked_ip: Z = T^-1 (upper) by block columns,
+//   Z[bi][cb] = -(sum_{bi <= l < cb} Z[bi][l] T[l][cb]) TI_cb,  Z[cb][cb] = TI_cb,
+// with the off-diagonal blocks Z[bi][cb] (bi < cb) stored transposed in the
+// lower block triangle of M (block (cb, bi)); T stays in the upper blocks.
+template <int NT>
+__device__ void wg_tinv_blocked(double* M, int ldm, int NB, const double* TI) {
+  const int tid = threadIdx.x;
+  auto zget = [&](int bi, int l, int r, int p) -> double {  // Z[16 bi + r][16 l + p], bi <= l
+    return bi == l ? TI[l * 272 + r * 17 + p] : M[(16 * l + p) * ldm + 16 * bi + r];
+  };
+  for (int cb = 1; cb < NB; ++cb) {
+    // R = sum_l Z[bi][l] T[l][cb] into block (cb, bi), transposed; items (bi, r, 4 columns)
+    for (int e = tid; e < cb * 64; e += NT) {
+      const int bi = e >> 6, r = (e >> 2) & 15, cq = 4 * (e & 3);
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int l = bi; l < cb; ++l) {
+#pragma unroll 4
+        for (int p = 0; p < 16; ++p) {
+          const double z = zget(bi, l, r, p);
+          const double* t = M + (16 * l + p) * ldm + 16 * cb + cq;   // T[16 l + p][16 cb + cq ..]
+          s0 = fma(z, t[0], s0);
+          s1 = fma(z, t[1], s1);
+          s2 = fma(z, t[2], s2);
+          s3 = fma(z, t[3], s3);
+        }
+      }
+      M[(16 * cb + cq + 0) * ldm + 16 * bi + r] = s0;
+      M[(16 * cb + cq + 1) * ldm + 16 * bi + r] = s1;
+      M[(16 * cb + cq + 2) * ldm + 16 * bi + r] = s2;
+      M[(16 * cb + cq + 3) * ldm + 16 * bi + r] = s3;
+    }
+    __syncthreads();
+    // Z[bi][cb] = -R TI_cb, one row per item (in place)
+    const double* tic = TI + cb * 272;
+    for (int e = tid; e < cb * 16; e += NT) {
+      const int bi = e >> 4, r = e & 15;
+      double rv[16];
+#pragma unroll
+      for (int p = 0; p < 16; ++p) rv[p] = M[(16 * cb + p) * ldm + 16 * bi + r];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int p = 0; p <= c; ++p) acc = fma(rv[p], tic[p * 17 + c], acc);
+        M[(16 * cb + c) * ldm + 16 * bi + r] = -acc;
+      }
+    }
+    __syncthreads();
   }
 }
 
