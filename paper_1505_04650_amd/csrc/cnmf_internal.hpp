@@ -46,13 +46,13 @@ hipError_t launch_convert_lowp(const float* A, int64_t lda, int m, int n, __hip_
 hipError_t launch_gemm_lowp(int es, const void* M, int64_t ldm, int rows, int cols, const void* Xt, int64_t ldx,
                             int kk, float* P, int splits, const float* scale, int scale_ld, int scale_t,
                             hipStream_t st);
-int choose_splits_lowp(int rows, int cols, int kk);
+int choose_splits_lowp(int rows, int cols, int kk, int es);
 // Columns [c0, c0 + k) of Q (rows x ldq, FP64) -> rows [dr0, dr0 + k) of the
 // transposed operand Xt (ld ldx) in BF16 (es 2) or FP8 (es 1); FP8 columns
 // are scaled by a power of two (colscale[scol0 + c]) chosen from the column
-// maximum so that they use the E4M3 range.
+// maximum so that they use the E4M3 range (cmax: k words of scratch).
 hipError_t launch_store_lowp(int es, const double* Q, int rows, int ldq, int c0, int k, void* Xt, int64_t ldx,
-                             int dr0, float* colscale, int scol0, hipStream_t st);
+                             int dr0, float* colscale, int scol0, unsigned long long* cmax, hipStream_t st);
 // Y[:, c] /= colscale[c], c < k (FP32, rows x ld).
 hipError_t launch_unscale_cols(float* Y, int rows, int ld, int k, const float* colscale, hipStream_t st);
 

@@ -103,12 +103,20 @@ hipError_t launch_convert_lowp(const float* A, int64_t lda, int m, int n, __hip_
 }
 
 // ---------------------------------------------------------------------------
-// Y (partials [split][rows][kk], FP32) = M (rows x cols, TA, ld ldm) times
-// the operand given transposed as Xt (kk x cols, TA, ld ldx), kk <= 256.
-// Workgroup: 4 waves x RB row blocks of 16; chunks of KC columns (128, or
-// 64 for kk > 128 to bound LDS); lane group g takes columns
-// [g KC/4, (g + 1) KC/4) of the chunk, 8 per MFMA step.
-// FP8: each chunk lies in one 128-column scale tile and each wave's rows in
+// Y (partials [split][rows][kk], FP32) = M (rows x cols, element size ES,
+// ld ldm) times the operand given transposed as Xt (kk x cols, ld ldx),
+// kk <= 256.
+// Workgroup: 16 RB rows of M (RB row blocks of 16: 128 rows for BF16, 64
+// for FP8, whose per-chunk accumulators double the registers) and all kk
+// output columns;
+// wave w owns output column blocks [w KBW, (w + 1) KBW).  Per chunk of KC
+// columns of M (128 bytes per row): the 64 x KC tile of M is staged in LDS
+// (double buffered) and read by all four waves; each wave loads its own
+// operand rows for the chunk straight into registers (prefetched one chunk
+// ahead).  Operand traffic from L2 per byte of M is kk / (16 RB), LDS reads
+// per byte of M staged are 4.  Lane group g covers K [g KC/4, (g + 1) KC/4) of the chunk, eight
+// K values per MFMA step, the same mapping on both operands.
+// FP8: a chunk is one 128-column scale tile and the workgroup's rows lie in
 // one 128-row tile; the chunk's product is accumulated separately and added
 // to the FP32 accumulator times the tile scale.
 // ---------------------------------------------------------------------------
@@ -116,52 +124,68 @@ template <int ES>
 struct Lowp;
 template <>
 struct Lowp<2> {  // BF16
-  typedef __hip_bfloat16 T;
   typedef bf16x8 opnd;
   static __device__ __forceinline__ void mma(const opnd& a, const opnd& b, floatx4& c) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
-  // eight K-consecutive elements s of a lane's column run (16 bytes each)
-  template <int NV>
-  static __device__ __forceinline__ opnd part(const uint4 (&v)[NV], int s) {
-    return __builtin_bit_cast(opnd, v[s]);
-  }
+  // eight K-consecutive elements s of a lane's 32-byte run
+  static __device__ __forceinline__ opnd part(const uint4 (&v)[2], int s) { return __builtin_bit_cast(opnd, v[s]); }
 };
 template <>
 struct Lowp<1> {  // FP8 E4M3
-  typedef uint8_t T;
   typedef long opnd;
   static __device__ __forceinline__ void mma(const opnd& a, const opnd& b, floatx4& c) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
   }
-  template <int NV>
-  static __device__ __forceinline__ opnd part(const uint4 (&v)[NV], int s) {
+  static __device__ __forceinline__ opnd part(const uint4 (&v)[2], int s) {
     const uint4 q = v[s >> 1];
     const uint2 h = (s & 1) ? uint2{q.z, q.w} : uint2{q.x, q.y};
     return __builtin_bit_cast(opnd, h);
   }
 };
 
-template <int ES, int KB, int RB, int KC>
+typedef uint4 v16;
+
+// 32 bytes at p (16-byte aligned when vec), bytes at or beyond `lim` (a
+// byte count from p) read as zero.
+__device__ __forceinline__ void load32(const uint8_t* p, int lim, bool vec, v16 (&d)[2]) {
+  if (vec && lim >= 32) {
+    d[0] = *reinterpret_cast<const v16*>(p);
+    d[1] = *reinterpret_cast<const v16*>(p + 16);
+    return;
+  }
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    uint32_t wd[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t val = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int byte = 16 * v + 4 * q + b;
+        if (byte < lim) val |= (uint32_t)p[byte] << (8 * b);
+      }
+      wd[q] = val;
+    }
+    d[v] = v16{wd[0], wd[1], wd[2], wd[3]};
+  }
+}
+
+template <int ES, int KB, int RB>
 __global__ __launch_bounds__(256, 2) void gemm_lowp_kernel(const void* __restrict__ Mv, int64_t ldm, int rows,
                                                            int cols, const void* __restrict__ Xv, int64_t ldx,
                                                            float* __restrict__ P, int cols_per_split,
                                                            const float* __restrict__ scale, int scale_ld,
                                                            int scale_transposed) {
   typedef typename Lowp<ES>::opnd opnd;
-  typedef uint4 v16;
   constexpr bool SCALED = ES == 1;
+  constexpr int KC = 128 / ES;      // chunk columns (128 bytes per row)
+  constexpr int STEPS = KC / 32;    // MFMA steps per chunk
   constexpr int KK = 16 * KB;
-  constexpr int CPG = KC / 4;           // columns per lane group and chunk
-  constexpr int STEPS = CPG / 8;        // MFMA steps per chunk
-  constexpr int LDX = KC * ES + 16;     // bytes per operand row in LDS (padded)
-  constexpr int NV = CPG * ES / 16;     // 16-byte A vectors per lane and row block
-  constexpr int VPR = KC * ES / 16;     // 16-byte vectors per operand row of a chunk
-  constexpr int TOTV = KK * VPR;        // operand vectors per chunk
-  constexpr int XV = (TOTV + 255) / 256;
-  static_assert(16 * RB <= kFp8Tile && kFp8Tile % (16 * RB) == 0, "wave rows must stay in one scale tile");
-  static_assert(kFp8Tile % KC == 0 && NV >= 1, "chunks must stay in one scale tile");
-  __shared__ __attribute__((aligned(16))) uint8_t Xs[2][KK * LDX];
+  constexpr int KBW = (KB + 3) / 4;  // column blocks per wave
+  constexpr int LDA = 128 + 16;      // LDS bytes per staged row
+  static_assert(kFp8Tile % KC == 0 && kFp8Tile % (16 * RB) == 0, "chunks and rows must stay in one scale tile");
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][16 * RB * LDA];
   const uint8_t* __restrict__ M = (const uint8_t*)Mv;
   const uint8_t* __restrict__ X = (const uint8_t*)Xv;
 
@@ -172,184 +196,153 @@ __global__ __launch_bounds__(256, 2) void gemm_lowp_kernel(const void* __restric
   const int kbeg = split * cols_per_split;
   const int kend = min(cols, kbeg + cols_per_split);
   const int nchunk = kend > kbeg ? (kend - kbeg + KC - 1) / KC : 0;
-  const int row_base = blockIdx.x * (64 * RB) + w * 16 * RB;
+  const int row_blk = blockIdx.x * (16 * RB);
+  const int jb0 = w * KBW;
   const bool vec_a = ((uintptr_t)M % 16 == 0) && ((ldm * ES) % 16 == 0);
   const bool vec_x = ((uintptr_t)X % 16 == 0) && ((ldx * ES) % 16 == 0);
 
-  floatx4 acc[RB][KB];
-  floatx4 cacc[SCALED ? RB : 1][SCALED ? KB : 1];
+  floatx4 acc[RB][KBW];
+  floatx4 cacc[SCALED ? RB : 1][SCALED ? KBW : 1];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int jb = 0; jb < KB; ++jb) acc[rb][jb] = floatx4{0, 0, 0, 0};
+    for (int jj = 0; jj < KBW; ++jj) acc[rb][jj] = floatx4{0, 0, 0, 0};
 
-  v16 a_cur[RB][NV], a_nxt[RB][NV];
-  v16 xr[XV];
-
-  auto load_a = [&](int chunk, v16(&dst)[RB][NV]) {
-    const int c0 = kbeg + chunk * KC + CPG * g;
+  // staging of the M tile: thread t moves 32 bytes of rows t / 4 + 64 q
+  constexpr int SR = RB / 4;
+  const int srow = tid >> 2, sseg = tid & 3;
+  v16 ast[SR][2];
+  auto load_a = [&](int chunk) {
+    const int c0 = kbeg + chunk * KC + sseg * (KC / 4);
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const int row = row_base + rb * 16 + lr;
-      const bool rok = row < rows;
-      const uint8_t* p = M + ((int64_t)(rok ? row : 0) * ldm + c0) * ES;
-      if (vec_a && rok && c0 + CPG <= kend) {
+    for (int q = 0; q < SR; ++q) {
+      const int rr = row_blk + srow + 64 * q;
+      const bool ok = rr < rows;
+      const int lim = ok ? (kend - c0) * ES : 0;
+      load32(M + ((int64_t)(ok ? rr : 0) * ldm + c0) * ES, lim, vec_a, ast[q]);
+    }
+  };
+  auto store_a = [&](int buf) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) dst[rb][v] = *reinterpret_cast<const v16*>(p + 16 * v);
+    for (int q = 0; q < SR; ++q) {
+      uint8_t* p = &As[buf][(srow + 64 * q) * LDA + sseg * 32];
+      *reinterpret_cast<v16*>(p) = ast[q][0];
+      *reinterpret_cast<v16*>(p + 16) = ast[q][1];
+    }
+  };
+  // this wave's operand fragments: lane (lr, g) of column block jj holds
+  // Xt[(jb0 + jj) 16 + lr][chunk cols g KC/4 .. + KC/4)
+  v16 bcur[KBW][2], bnxt[KBW][2];
+  auto load_b = [&](int chunk, v16 (&d)[KBW][2]) {
+    const int c0 = kbeg + chunk * KC + g * (KC / 4);
+    const int lim = (kend - c0) * ES;
+#pragma unroll
+    for (int jj = 0; jj < KBW; ++jj) {
+      if (jb0 + jj < KB) {
+        const uint8_t* p = X + ((int64_t)((jb0 + jj) * 16 + lr) * ldx + c0) * ES;
+        load32(p, lim, vec_x, d[jj]);
       } else {
-        // ragged tail: assemble the bytes in range into dwords, zeros beyond
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          uint32_t wd[4];
-#pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            uint32_t val = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              const int byte = 16 * v + 4 * d + b;
-              if (rok && c0 + byte / ES < kend) val |= (uint32_t)p[byte] << (8 * b);
-            }
-            wd[d] = val;
-          }
-          dst[rb][v] = v16{wd[0], wd[1], wd[2], wd[3]};
-        }
-      }
-    }
-  };
-  // operand chunk: the KK rows of Xt over columns [k0, k0 + KC)
-  auto load_x = [&](int chunk) {
-    const int k0 = kbeg + chunk * KC;
-#pragma unroll
-    for (int e = 0; e < XV; ++e) {
-      const int idx = e * 256 + tid;
-      if (TOTV % 256 == 0 || idx < TOTV) {
-        const int c = idx / VPR, v = idx - c * VPR;
-        const int col = k0 + v * (16 / ES);
-        const uint8_t* p = X + ((int64_t)c * ldx + col) * ES;
-        if (vec_x && col + 16 / ES <= kend) {
-          xr[e] = *reinterpret_cast<const v16*>(p);
-        } else {
-          uint32_t wd[4];
-#pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            uint32_t val = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-              if (col + (4 * d + b) / ES < kend) val |= (uint32_t)p[4 * d + b] << (8 * b);
-            wd[d] = val;
-          }
-          xr[e] = v16{wd[0], wd[1], wd[2], wd[3]};
-        }
-      }
-    }
-  };
-  auto store_x = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < XV; ++e) {
-      const int idx = e * 256 + tid;
-      if (TOTV % 256 == 0 || idx < TOTV) {
-        const int c = idx / VPR, v = idx - c * VPR;
-        *reinterpret_cast<v16*>(&Xs[buf][c * LDX + 16 * v]) = xr[e];
+        d[jj][0] = v16{0, 0, 0, 0};
+        d[jj][1] = v16{0, 0, 0, 0};
       }
     }
   };
 
   if (nchunk > 0) {
-    load_a(0, a_cur);
-    load_x(0);
-    store_x(0);
+    load_a(0);
+    load_b(0, bcur);
+    store_a(0);
   }
   __syncthreads();
   for (int ch = 0; ch < nchunk; ++ch) {
     const int buf = ch & 1;
     const bool more = ch + 1 < nchunk;
     if (more) {
-      load_a(ch + 1, a_nxt);
-      load_x(ch + 1);
+      load_a(ch + 1);
+      load_b(ch + 1, bnxt);
     }
     if (SCALED) {
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int jb = 0; jb < KB; ++jb) cacc[SCALED ? rb : 0][SCALED ? jb : 0] = floatx4{0, 0, 0, 0};
+        for (int jj = 0; jj < KBW; ++jj) cacc[SCALED ? rb : 0][SCALED ? jj : 0] = floatx4{0, 0, 0, 0};
     }
 #pragma unroll
-    for (int s = 0; s < STEPS; ++s) {
+    for (int rb = 0; rb < RB; ++rb) {
+      v16 af[2];
+      const uint8_t* ap = &As[buf][(rb * 16 + lr) * LDA + g * 32];
+      af[0] = *reinterpret_cast<const v16*>(ap);
+      af[1] = *reinterpret_cast<const v16*>(ap + 16);
 #pragma unroll
-      for (int jb = 0; jb < KB; ++jb) {
-        const opnd b = *reinterpret_cast<const opnd*>(&Xs[buf][(jb * 16 + lr) * LDX + (CPG * g + 8 * s) * ES]);
+      for (int s = 0; s < STEPS; ++s) {
+        const opnd a = Lowp<ES>::part(af, s);
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const opnd a = Lowp<ES>::template part<NV>(a_cur[rb], s);
-          if (SCALED)
-            Lowp<ES>::mma(a, b, cacc[SCALED ? rb : 0][SCALED ? jb : 0]);
-          else
-            Lowp<ES>::mma(a, b, acc[rb][jb]);
+        for (int jj = 0; jj < KBW; ++jj) {
+          if (jb0 + jj < KB) {
+            const opnd b = Lowp<ES>::part(bcur[jj], s);
+            if (SCALED)
+              Lowp<ES>::mma(a, b, cacc[SCALED ? rb : 0][SCALED ? jj : 0]);
+            else
+              Lowp<ES>::mma(a, b, acc[rb][jj]);
+          }
         }
       }
     }
     if (SCALED) {
-      const int tr = row_base / kFp8Tile, tc = (kbeg + ch * KC) / kFp8Tile;
+      const int tr = row_blk / kFp8Tile, tc = (kbeg + ch * KC) / kFp8Tile;
       const float sc = scale_transposed ? scale[(int64_t)tc * scale_ld + tr] : scale[(int64_t)tr * scale_ld + tc];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int jb = 0; jb < KB; ++jb)
+        for (int jj = 0; jj < KBW; ++jj)
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            acc[rb][jb][i] = fmaf(sc, cacc[SCALED ? rb : 0][SCALED ? jb : 0][i], acc[rb][jb][i]);
+            acc[rb][jj][i] = fmaf(sc, cacc[SCALED ? rb : 0][SCALED ? jj : 0][i], acc[rb][jj][i]);
     }
-    if (more) store_x(buf ^ 1);
-    __syncthreads();
     if (more) {
+      store_a(buf ^ 1);
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) a_cur[rb][v] = a_nxt[rb][v];
+      for (int jj = 0; jj < KBW; ++jj) {
+        bcur[jj][0] = bnxt[jj][0];
+        bcur[jj][1] = bnxt[jj][1];
+      }
     }
+    __syncthreads();
   }
   float* out = P + (int64_t)split * rows * KK;
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = row_base + rb * 16 + 4 * g + i;
+      const int row = row_blk + rb * 16 + 4 * g + i;
       if (row < rows) {
 #pragma unroll
-        for (int jb = 0; jb < KB; ++jb) out[(int64_t)row * KK + jb * 16 + lr] = acc[rb][jb][i];
+        for (int jj = 0; jj < KBW; ++jj)
+          if (jb0 + jj < KB) out[(int64_t)row * KK + (jb0 + jj) * 16 + lr] = acc[rb][jj][i];
       }
     }
 }
 
-int choose_splits_lowp(int rows, int cols, int kk) {
-  // tiles of 128 rows; same occupancy heuristic as the FP32 passes
-  int tiles = (rows + 127) / 128;
-  int slots = 512;
-  int best = 1;
-  double best_eff = -1.0;
-  int max_s = std::max(1, std::min(64, cols / 1024));
-  for (int s = 1; s <= max_s; ++s) {
-    long long wgs = (long long)tiles * s;
-    long long rounds = (wgs + slots - 1) / slots;
-    double eff = (double)wgs / (double)(rounds * slots) - 0.004 * s;
-    if (eff > best_eff + 1e-9) {
-      best_eff = eff;
-      best = s;
-    }
-    if (wgs >= 4LL * slots) break;
-  }
-  return best;
+int choose_splits_lowp(int rows, int cols, int kk, int es) {
+  // about 3000 workgroups (six rounds of two per CU) for latency hiding, while
+  // the FP32 partials stay below a tenth of the bytes of M read
+  const int tile_rows = es == 2 ? 128 : 64;
+  const int tiles = (rows + tile_rows - 1) / tile_rows;
+  int s = (3072 + tiles - 1) / tiles;
+  const int cap_bytes = (int)std::max<int64_t>(1, (int64_t)cols * es / (10LL * kk * 4));
+  s = std::min(s, cap_bytes);
+  s = std::min(s, std::max(1, cols / 256));
+  return std::max(1, std::min(s, 64));
 }
 
 template <int ES, int KB>
 static hipError_t gemm_lowp_kb(const void* M, int64_t ldm, int rows, int cols, const void* Xt, int64_t ldx,
                                float* P, int splits, const float* scale, int scale_ld, int scale_t, hipStream_t st) {
-  constexpr int RB = KB > 8 ? 1 : 2;
-  constexpr int KC = KB > 8 ? 64 : 128;
+  constexpr int RB = ES == 2 ? 8 : 4;
   int per = (cols + splits - 1) / splits;
   per = (per + 127) / 128 * 128;
-  dim3 grid((rows + 64 * RB - 1) / (64 * RB), splits);
-  hipLaunchKernelGGL((gemm_lowp_kernel<ES, KB, RB, KC>), grid, dim3(256), 0, st, M, ldm, rows, cols, Xt, ldx, P, per,
+  dim3 grid((rows + 16 * RB - 1) / (16 * RB), splits);
+  hipLaunchKernelGGL((gemm_lowp_kernel<ES, KB, RB>), grid, dim3(256), 0, st, M, ldm, rows, cols, Xt, ldx, P, per,
                      scale, scale_ld, scale_t);
   CNMF_LAUNCH_CHECK();
 }
@@ -396,30 +389,40 @@ hipError_t launch_gemm_lowp(int es, const void* M, int64_t ldm, int rows, int co
 // from the column's max magnitude) before rounding; scaling a column of the
 // range-finder operand does not change the orthonormalised result.
 // ---------------------------------------------------------------------------
-__global__ void colmax_kernel(const double* __restrict__ Q, int rows, int ldq, int c0, int k,
-                              float* __restrict__ colscale, int scol0) {
+// Column maxima of |Q[:, c0 + c]| for c < k <= 128, rows in blocks of 256:
+// thread (c, rs) scans every other row of its block, then one exact atomic
+// max per column and block on the bit patterns (nonnegative doubles order
+// like their bits, so the result does not depend on the order).
+__global__ __launch_bounds__(256) void colmax_kernel(const double* __restrict__ Q, int rows, int ldq, int c0, int k,
+                                                     unsigned long long* __restrict__ cmax) {
   __shared__ double red[256];
-  const int c = blockIdx.x;
+  const int c = threadIdx.x & 127, rs = threadIdx.x >> 7;
+  const int i0 = blockIdx.x * 256, i1 = min(rows, i0 + 256);
   double mx = 0.0;
-  for (int i = threadIdx.x; i < rows; i += 256) mx = fmax(mx, fabs(Q[(int64_t)i * ldq + c0 + c]));
+  if (c < k)
+    for (int i = i0 + rs; i < i1; i += 2) mx = fmax(mx, fabs(Q[(int64_t)i * ldq + c0 + c]));
   red[threadIdx.x] = mx;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
+  if (rs == 0 && c < k) {
+    mx = fmax(red[threadIdx.x], red[threadIdx.x + 128]);
+    atomicMax(&cmax[c], (unsigned long long)__double_as_longlong(mx));
   }
-  if (threadIdx.x == 0) {
-    // largest power of two s with max * s <= 256 (headroom below 448):
-    // 256 / max = f 2^e with f in [0.5, 1) gives s = 2^(e - 1)
-    const double mxv = red[0];
-    float s = 1.0f;
-    if (mxv > 0.0) {
-      int e = 0;
-      frexp(256.0 / mxv, &e);
-      s = (float)ldexp(1.0, e - 1);
-    }
-    colscale[scol0 + c] = s;
+}
+
+// colscale[scol0 + c]: the largest power of two s with max * s <= 256
+// (headroom below 448); 256 / max = f 2^e with f in [0.5, 1) gives 2^(e - 1).
+__global__ void colscale_kernel(const unsigned long long* __restrict__ cmax, int k, float* __restrict__ colscale,
+                                int scol0) {
+  const int c = threadIdx.x;
+  if (c >= k) return;
+  const double mxv = __longlong_as_double((long long)cmax[c]);
+  float s = 1.0f;
+  if (mxv > 0.0) {
+    int e = 0;
+    frexp(256.0 / mxv, &e);
+    s = (float)ldexp(1.0, e - 1);
   }
+  colscale[scol0 + c] = s;
 }
 
 template <int ES>
@@ -449,10 +452,16 @@ __global__ void store_lowp_kernel(const double* __restrict__ Q, int rows, int ld
 }
 
 hipError_t launch_store_lowp(int es, const double* Q, int rows, int ldq, int c0, int k, void* Xt, int64_t ldx, int dr0,
-                             float* colscale, int scol0, hipStream_t st) {
+                             float* colscale, int scol0, unsigned long long* cmax, hipStream_t st) {
+  if (k > 128) return hipErrorInvalidValue;
   if (es == 1) {
-    hipLaunchKernelGGL(colmax_kernel, dim3(k), dim3(256), 0, st, Q, rows, ldq, c0, k, colscale, scol0);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_fill(cmax, (size_t)k * sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colmax_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, Q, rows, ldq, c0, k, cmax);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colscale_kernel, dim3(1), dim3(128), 0, st, cmax, k, colscale, scol0);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   dim3 grid((rows + 31) / 32, (k + 31) / 32);

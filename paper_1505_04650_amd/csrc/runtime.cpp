@@ -263,6 +263,7 @@ struct SketchWs {
   uint8_t* XtN = nullptr;
   uint8_t* XtT = nullptr;
   float* cscale = nullptr;
+  unsigned long long* cmax = nullptr;
   // FP32 / FP64 passes wider than 128 columns run one launch per chain
   // block through these tight buffers (max(m, n) x 128)
   T* Xg = nullptr;
@@ -283,7 +284,7 @@ void layout_sketch(Arena& a, SketchWs<T>& w, int64_t m, int64_t n, int k, const 
     int s;
     int kl = p.kk;
     if (is_lowp(p.prec)) {
-      s = choose_splits_lowp((int)rows, (int)cols, p.kk);
+      s = choose_splits_lowp((int)rows, (int)cols, p.kk, lowp_es(p.prec));
       (p.prec == CNMF_BF16 ? need16 : need8) = true;
     } else {
       if (p.kk > 128) {
@@ -329,6 +330,7 @@ void layout_sketch(Arena& a, SketchWs<T>& w, int64_t m, int64_t n, int k, const 
     w.XtN = a.take<uint8_t>((size_t)kkmax * w.ldo * 2);
     w.XtT = a.take<uint8_t>((size_t)kkmax * w.ldt * 2);
     w.cscale = a.take<float>(512);
+    w.cmax = a.take<unsigned long long>(128);
   }
   if (wide) {
     w.Xg = a.take<T>((size_t)mx * 128);
@@ -500,7 +502,7 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
   auto store_operand = [&](const Pass& p, const double* Q, int rows, int ldq, int c0, int col) -> cnmf_status {
     if (is_lowp(p.prec))
       HIPCHK(h, launch_store_lowp(lowp_es(p.prec), Q + 0, rows, ldq, c0, k, xt_for(p), xt_ld(p), col, w.cscale,
-                                  scol_for(p) + col, st));
+                                  scol_for(p) + col, w.cmax, st));
     else
       HIPCHK(h, (launch_copy2d<double, T>(Q + c0, ldq, operand_for(p) + col, p.kk, rows, k, 1.0, st)));
     return CNMF_OK;
@@ -542,7 +544,7 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
     T* op = operand_for(p);
     const bool lp = is_lowp(p.prec);
     const bool wide = !lp && p.kk > 128;
-    int splits = lp ? choose_splits_lowp(rows, p.dirN ? n : m, p.kk)
+    int splits = lp ? choose_splits_lowp(rows, p.dirN ? n : m, p.kk, lowp_es(p.prec))
                     : (p.dirN ? choose_splits_n(m, n, p.kk, sizeof(T)) : choose_splits_t(m, n, p.kk, sizeof(T)));
     if (wide) splits = 1;  // reduced per block below
     T* dst = splits > 1 ? w.Ppart : w.Y;
@@ -1330,23 +1332,26 @@ cnmf_status cnmf_range_product_lowp(cnmf_handle* h, const cnmf_input* A, int tra
   const int64_t ldo = (n + 63) / 64 * 64, ldt = (m + 63) / 64 * 64;
   const int64_t ldm = trans ? ldt : ldo;
   const int ntj = (n + kFp8Tile - 1) / kFp8Tile, nti = (m + kFp8Tile - 1) / kFp8Tile;
-  const int splits = choose_splits_lowp(rows_out, cols, kk);
-  auto layout = [&](Arena& a, uint8_t** Mc, float** tsc, uint8_t** Xt, float** cs, float** Yp, float** Pp) {
+  const int splits = choose_splits_lowp(rows_out, cols, kk, es);
+  auto layout = [&](Arena& a, uint8_t** Mc, float** tsc, uint8_t** Xt, float** cs, float** Yp, float** Pp,
+                    unsigned long long** cm) {
     *Mc = a.take<uint8_t>((size_t)es * (trans ? n : m) * ldm);
     *tsc = a.take<float>((size_t)ntj * nti);
     *Xt = a.take<uint8_t>((size_t)es * kk * ldm);
     *cs = a.take<float>(128);
     *Yp = a.take<float>((size_t)rows_out * kk);
     *Pp = a.take<float>((size_t)std::max(splits, 1) * rows_out * kk);
+    *cm = a.take<unsigned long long>(128);
   };
   uint8_t *Mc, *Xt;
   float *tsc, *cs, *Yp, *Pp;
+  unsigned long long* cm;
   Arena dry(nullptr);
-  layout(dry, &Mc, &tsc, &Xt, &cs, &Yp, &Pp);
+  layout(dry, &Mc, &tsc, &Xt, &cs, &Yp, &Pp, &cm);
   s = ensure_ws(h, dry.off);
   if (s != CNMF_OK) return s;
   Arena a(h->ws);
-  layout(a, &Mc, &tsc, &Xt, &cs, &Yp, &Pp);
+  layout(a, &Mc, &tsc, &Xt, &cs, &Yp, &Pp, &cm);
   hipStream_t st = h->stream;
   const float* Ap = (const float*)A->data_dev;
   // only the copy this direction reads is written
@@ -1355,7 +1360,7 @@ cnmf_status cnmf_range_product_lowp(cnmf_handle* h, const cnmf_input* A, int tra
   HIPCHK(h, launch_convert_lowp(Ap, A->lda, m, n, trans ? nullptr : c16, trans ? c16 : nullptr, trans ? nullptr : c8,
                                 trans ? c8 : nullptr, ldo, ldt, tsc, st));
   HIPCHK(h, launch_fill(Xt, (size_t)es * kk * ldm, st));
-  HIPCHK(h, launch_store_lowp(es, X_dev, cols, kx, 0, kx, Xt, ldm, 0, cs, 0, st));
+  HIPCHK(h, launch_store_lowp(es, X_dev, cols, kx, 0, kx, Xt, ldm, 0, cs, 0, cm, st));
   float* dst = splits > 1 ? Pp : Yp;
   HIPCHK(h, launch_gemm_lowp(es, Mc, ldm, rows_out, cols, Xt, ldm, kk, dst, splits, tsc, ntj, trans, st));
   if (splits > 1) HIPCHK(h, launch_reduce_splits<float>(Pp, splits, rows_out, kk, Yp, st));

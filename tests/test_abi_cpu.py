@@ -133,9 +133,10 @@ def test_precision_combinations(lib):
         assert lib.cnmf_workspace_bytes(20000, 5000, C.byref(d), C.byref(o)) == L.CNMF_OK
         sizes[name] = o.value
     mn = 20000 * 5000
-    assert sizes["bf16"] - sizes["f32"] >= 4 * mn          # BF16 A and A^T copies
-    assert sizes["fp8"] - sizes["f32"] >= 6 * mn           # FP8 copies + the BF16 ones for the final passes
-    assert sizes["fp8f32"] - sizes["f32"] >= 2 * mn
+    assert sizes["bf16"] >= 4 * mn                         # BF16 A and A^T copies
+    assert sizes["fp8"] >= 6 * mn                          # FP8 copies + the BF16 ones for the final passes
+    assert sizes["fp8f32"] >= 2 * mn
+    assert sizes["fp8"] > sizes["bf16"] > sizes["f32"]
 
 
 def test_lowp_range_product_argument_checks(lib):
