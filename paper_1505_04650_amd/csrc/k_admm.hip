@@ -375,6 +375,249 @@ __device__ __forceinline__ void admm_solve_body(const double* __restrict__ Pred,
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same two solves with an explicit inverse kept from one iteration to the
+// next (k <= 80, r <= 64).  For each side the system matrix M = S^T S + pen I
+// (padded to N = 16 ceil(r / 16) with an identity block) is inverted by
+// Newton-Schulz steps Z <- Z + Z (I - M Z), warm-started from the previous
+// iteration's inverse, until ||I - M Z||_F <= 8 N eps or it stops shrinking
+// by half; the first iteration, a warm start with ||I - M Z||_F > 1/2 and a
+// non-converging start use the blocked Cholesky and solve for Z = M^-1
+// instead.  Then X = RHS Z.  Every product is a 16x16x4 FP64 MFMA tile
+// product in LDS; Z is stored for the next iteration.
+// ---------------------------------------------------------------------------
+constexpr int kNsMaxK = 80;
+
+struct NsLayout {
+  int NB, N, ld, kp, KB16;
+  size_t s_off, m_off, z_off, e_off, red_off, total;  // in doubles
+};
+__host__ __device__ inline NsLayout ns_layout(int k, int r) {
+  NsLayout L;
+  L.NB = (r + 15) / 16;
+  L.N = 16 * L.NB;
+  L.ld = L.N + 2;
+  L.KB16 = (k + 15) / 16;
+  L.kp = 16 * L.KB16;
+  const size_t rowsE = (size_t)(L.kp > L.N ? L.kp : L.N);
+  size_t eb = rowsE * L.ld;
+  const size_t fb = (size_t)L.NB * 272 + 16 * (size_t)L.ld + (size_t)L.N * 17;  // fallback scratch
+  if (fb > eb) eb = fb;
+  L.s_off = 0;
+  L.m_off = L.s_off + (size_t)L.kp * L.ld;
+  L.z_off = L.m_off + (size_t)L.N * L.ld;
+  L.e_off = L.z_off + (size_t)L.N * L.ld;
+  L.red_off = L.e_off + eb;
+  L.total = L.red_off + 8;
+  return L;
+}
+
+// acc[cb] = rows 16 rb + g + 4 i, cols 16 cb + c of A B for cb < ncb, where
+// lane (c, g) supplies A(16 rb + c, kk) and B(kk, 16 cb + c) for kk = 4 s + g.
+template <int NCB, typename FA, typename FB>
+__device__ __forceinline__ void ns_tile_rows(FA fa, FB fb, int K, int rb, int c, int g, doublex4 (&acc)[4]) {
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = doublex4{0.0, 0.0, 0.0, 0.0};
+  const int nsteps = K / 4;
+#pragma unroll 4
+  for (int s = 0; s < nsteps; ++s) {
+    const int kk = 4 * s + g;
+    const double a = fa(16 * rb + c, kk);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, fb(kk, 16 * cb + c), acc[cb], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Z = M^-1 by the blocked Cholesky of M (in place) and a solve of Z M = I;
+// kept out of line so that the register budget of the Newton-Schulz path is
+// not set by it.
+__device__ __attribute__((noinline)) void ns_chol_inverse(double* Mb, double* Zb, double* Eb, int ld, int NB, int N,
+                                                          int r, int* flags) {
+  constexpr int NT = kSolveNT;
+  const int tid = threadIdx.x;
+  double* TI = Eb;
+  double* PN = TI + NB * 272;
+  double* Rs = PN + 16 * ld;
+  double mx = 0.0;
+  for (int i = 0; i < r; ++i) mx = fmax(mx, Mb[i * ld + i]);
+  wg_chol_blocked<NT>(Mb, ld, NB, TI, PN, 1e-300 * mx, flags);
+  for (int e = tid; e < N * N; e += NT) {
+    const int i = e / N, j = e - i * N;
+    Zb[i * ld + j] = i == j ? 1.0 : 0.0;
+  }
+  wg_right_solve_blocked<NT>(Zb, N, ld, NB, Mb, ld, TI, Rs);
+  __syncthreads();
+}
+
+template <int NB>
+__device__ __forceinline__ void admm_solve_ns_nb(const double* __restrict__ Pred, const double* __restrict__ At, int k,
+                                                 int r, double lam, double phi, int first, double* __restrict__ XY,
+                                                 double* __restrict__ Zg, int* flags, double* sm) {
+  constexpr int NT = kSolveNT;
+  constexpr int N = 16 * NB;
+  const NsLayout Ly = ns_layout(k, r);
+  const int ld = Ly.ld, kp = Ly.kp, KB16 = Ly.KB16;
+  double* S = sm + Ly.s_off;
+  double* Mb = sm + Ly.m_off;
+  double* Zb = sm + Ly.z_off;
+  double* Eb = sm + Ly.e_off;
+  double* red = sm + Ly.red_off;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int64_t kr = (int64_t)k * r;
+  const double tol = 8.0 * N * 2.220446049250313e-16;
+  // S = Yt^T (k x r, zero padded to kp x N)
+  for (int e = tid; e < kp * N; e += NT) {
+    const int i = e / N, j = e - i * N;
+    S[i * ld + j] = (i < k && j < r) ? (first ? Pred[kr + i * r + j] / phi : XY[kr + i * r + j]) : 0.0;
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    const double pen = pass ? phi : lam;
+    const double* P = Pred + (pass ? kr : 0);
+    double* Zh = Zg + (size_t)pass * 64 * 64;
+    doublex4 acc[4];
+    // (a) M = S^T S + pen I_r, identity on the padding
+    if (w < NB) {
+      ns_tile_rows<NB>([&](int i, int kk) { return S[kk * ld + i]; }, [&](int kk, int j) { return S[kk * ld + j]; }, kp,
+                   w, c, g, acc);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (cb >= NB) continue;
+          const int row = 16 * w + g + 4 * i, col = 16 * cb + c;
+          Mb[row * ld + col] = acc[cb][i] + (row == col ? (row < r ? pen : 1.0) : 0.0);
+        }
+    }
+    // warm start
+    if (!first)
+      for (int e = tid; e < N * N; e += NT) Zb[(e / N) * ld + (e % N)] = Zh[e];
+    __syncthreads();
+    bool need_chol = first != 0;
+    if (!need_chol) {
+      double e_prev = 0.0;
+      int it = 0;
+      const int kMaxIt = 8;
+      for (;; ++it) {
+        // E = I - M Z
+        double ss = 0.0;
+        if (w < NB) {
+          ns_tile_rows<NB>([&](int i, int kk) { return Mb[i * ld + kk]; }, [&](int kk, int j) { return Zb[kk * ld + j]; },
+                       N, w, c, g, acc);
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (cb >= NB) continue;
+              const int row = 16 * w + g + 4 * i, col = 16 * cb + c;
+              const double ev = (row == col ? 1.0 : 0.0) - acc[cb][i];
+              Eb[row * ld + col] = ev;
+              ss = fma(ev, ev, ss);
+            }
+        }
+        ss = wave_sum_d(ss);
+        if (lane == 0) red[w] = ss;
+        __syncthreads();
+        const double en = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+        if (!isfinite(en) || (it == 0 && en > 0.5)) {
+          need_chol = true;
+          break;
+        }
+        if (en <= tol || (it > 0 && en > 0.5 * e_prev)) break;
+        if (it == kMaxIt) {
+          need_chol = true;
+          break;
+        }
+        // Z <- Z + Z E
+        if (w < NB) {
+          ns_tile_rows<NB>([&](int i, int kk) { return Zb[i * ld + kk]; }, [&](int kk, int j) { return Eb[kk * ld + j]; },
+                       N, w, c, g, acc);
+        }
+        __syncthreads();
+        if (w < NB) {
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (cb >= NB) continue;
+              const int row = 16 * w + g + 4 * i, col = 16 * cb + c;
+              Zb[row * ld + col] += acc[cb][i];
+            }
+        }
+        __syncthreads();
+        e_prev = en;
+      }
+    }
+    if (need_chol) ns_chol_inverse(Mb, Zb, Eb, ld, NB, N, r, flags);
+    // (d) RHS = At S + P (pass 0) or At^T S + P (pass 1) into Eb (kp x N)
+    for (int rb = w; rb < KB16; rb += 4) {
+      if (pass == 0)
+        ns_tile_rows<NB>([&](int i, int kk) { return (i < k && kk < k) ? At[i * k + kk] : 0.0; },
+                     [&](int kk, int j) { return S[kk * ld + j]; }, kp, rb, c, g, acc);
+      else
+        ns_tile_rows<NB>([&](int i, int kk) { return (i < k && kk < k) ? At[kk * k + i] : 0.0; },
+                     [&](int kk, int j) { return S[kk * ld + j]; }, kp, rb, c, g, acc);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (cb >= NB) continue;
+          const int row = 16 * rb + g + 4 * i, col = 16 * cb + c;
+          Eb[row * ld + col] = (row < k && col < r) ? acc[cb][i] + P[row * r + col] : 0.0;
+        }
+    }
+    __syncthreads();
+    // (e) X = RHS Z, written to XY and, for pass 0, into S for the other side
+    double* out = XY + (pass ? kr : 0);
+    for (int rb = w; rb < KB16; rb += 4) {
+      ns_tile_rows<NB>([&](int i, int kk) { return Eb[i * ld + kk]; }, [&](int kk, int j) { return Zb[kk * ld + j]; }, N,
+                   rb, c, g, acc);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (cb >= NB) continue;
+          const int row = 16 * rb + g + 4 * i, col = 16 * cb + c;
+          const double v = (row < k && col < r) ? acc[cb][i] : 0.0;
+          if (row < k && col < r) out[row * r + col] = v;
+          if (pass == 0) S[row * ld + col] = v;
+        }
+    }
+    // (f) keep Z for the next iteration
+    for (int e = tid; e < N * N; e += NT) Zh[e] = Zb[(e / N) * ld + (e % N)];
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void admm_solve_ns_body(const double* __restrict__ Pred, const double* __restrict__ At,
+                                                   int k, int r, double lam, double phi, int first,
+                                                   double* __restrict__ XY, double* __restrict__ Zg, int* flags,
+                                                   double* sm) {
+  switch ((r + 15) / 16) {
+    case 1: admm_solve_ns_nb<1>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, sm); break;
+    case 2: admm_solve_ns_nb<2>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, sm); break;
+    case 3: admm_solve_ns_nb<3>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, sm); break;
+    default: admm_solve_ns_nb<4>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, sm); break;
+  }
+}
+
+__global__ __launch_bounds__(kSolveNT) void admm_solve_ns_kernel(const double* __restrict__ Pred,
+                                                                 const double* __restrict__ At, int k, int r,
+                                                                 double lam, double phi, int first,
+                                                                 double* __restrict__ XY, double* __restrict__ Z,
+                                                                 int* flags) {
+  extern __shared__ double sm[];
+  admm_solve_ns_body(Pred, At, k, r, lam, phi, first, XY, Z, flags, sm);
+}
+
 __global__ __launch_bounds__(kSolveNT) void admm_solve_kernel(const double* __restrict__ Pred,
                                                               const double* __restrict__ At, int k, int r,
                                                               double lam, double phi, int first,
@@ -387,7 +630,10 @@ __global__ __launch_bounds__(kSolveNT) void admm_solve_kernel(const double* __re
 __global__ __launch_bounds__(kSolveNT) void admm_solve_batch_kernel(const AdmmJob* __restrict__ jobs) {
   extern __shared__ double sm[];
   const AdmmJob& J = jobs[blockIdx.x];
-  admm_solve_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.flags, J.at_in_lds, sm);
+  if (J.Z && J.k <= kNsMaxK)
+    admm_solve_ns_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.Z, J.flags, sm);
+  else
+    admm_solve_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.flags, J.at_in_lds, sm);
 }
 
 static size_t admm_solve_lds(int k, int r, bool with_at) {
@@ -399,10 +645,22 @@ static size_t admm_solve_lds(int k, int r, bool with_at) {
 
 template <typename T>
 hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const double* At, int k, int r,
-                             double lam, double phi, int first, double* XY, double* Pred, unsigned* /*counter*/,
+                             double lam, double phi, int first, double* XY, double* Pred, double* Z,
                              int* flags, hipStream_t st) {
   if (r > 64 || k > 128) return hipErrorInvalidValue;
   const size_t cap = 160 * 1024;
+  if (Z && k <= kNsMaxK) {
+    int64_t kr = (int64_t)k * r;
+    int nbh = (int)((kr + kRedEPB - 1) / kRedEPB);
+    hipLaunchKernelGGL(admm_reduce_kernel, dim3(2 * nbh), dim3(kRedNT), 0, st, Pp, parts0, parts1, kr, Pred);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t sm = ns_layout(k, r).total * sizeof(double);
+    hipFuncSetAttribute((const void*)admm_solve_ns_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    hipLaunchKernelGGL(admm_solve_ns_kernel, dim3(1), dim3(kSolveNT), sm, st, Pred, At, k, r, lam, phi, first, XY, Z,
+                       flags);
+    CNMF_LAUNCH_CHECK();
+  }
   int at_in_lds = admm_solve_lds(k, r, true) <= cap;
   size_t sm = admm_solve_lds(k, r, at_in_lds);
   if (sm > cap) return hipErrorInvalidValue;
@@ -416,8 +674,8 @@ hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const dou
                      at_in_lds);
   CNMF_LAUNCH_CHECK();
 }
-template hipError_t launch_admm_solve<float>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, unsigned*, int*, hipStream_t);
-template hipError_t launch_admm_solve<double>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, unsigned*, int*, hipStream_t);
+template hipError_t launch_admm_solve<float>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, double*, int*, hipStream_t);
+template hipError_t launch_admm_solve<double>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, double*, int*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Batched ADMM step (serving): for every job, the fixed-order partial sums,
@@ -457,6 +715,9 @@ hipError_t launch_admm_step_batch(const AdmmJob* jobs_dev, const int* uv_first_d
   CNMF_LAUNCH_CHECK();
 }
 
-size_t admm_job_solve_lds(const AdmmJob& J) { return admm_solve_lds(J.k, J.r, J.at_in_lds != 0); }
+size_t admm_job_solve_lds(const AdmmJob& J) {
+  if (J.Z && J.k <= kNsMaxK) return ns_layout(J.k, J.r).total * sizeof(double);
+  return admm_solve_lds(J.k, J.r, J.at_in_lds != 0);
+}
 
 }  // namespace cnmf
