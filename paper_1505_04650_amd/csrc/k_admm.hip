@@ -380,8 +380,9 @@ __device__ __forceinline__ void admm_solve_body(const double* __restrict__ Pred,
 // next (k <= 80, r <= 64).  For each side the system matrix M = S^T S + pen I
 // (padded to N = 16 ceil(r / 16) with an identity block) is inverted by
 // Newton-Schulz steps Z <- Z + Z (I - M Z), warm-started from the previous
-// iteration's inverse, until ||I - M Z||_F <= 8 N eps or it stops shrinking
-// by half; the first iteration, a warm start with ||I - M Z||_F > 1/2 and a
+// iteration's inverse, until ||I - M Z||_F <= tol (8 N eps for FP64
+// factors; 1e-10 for FP32 factors, far below their rounding) or it stops
+// shrinking by half; the first iteration, a warm start with ||I - M Z||_F > 1/2 and a
 // non-converging start use the blocked Cholesky and solve for Z = M^-1
 // instead.  Then X = RHS Z.  Every product is a 16x16x4 FP64 MFMA tile
 // product in LDS; Z is stored for the next iteration.
@@ -459,7 +460,7 @@ __device__ __attribute__((noinline)) void ns_chol_inverse(double* Mb, double* Zb
 template <int NB>
 __device__ __forceinline__ void admm_solve_ns_nb(const double* __restrict__ Pred, const double* __restrict__ At, int k,
                                                  int r, double lam, double phi, int first, double* __restrict__ XY,
-                                                 double* __restrict__ Zg, int* flags, double* sm) {
+                                                 double* __restrict__ Zg, int* flags, double tol_in, double* sm) {
   constexpr int NT = kSolveNT;
   constexpr int N = 16 * NB;
   const NsLayout Ly = ns_layout(k, r);
@@ -472,7 +473,7 @@ __device__ __forceinline__ void admm_solve_ns_nb(const double* __restrict__ Pred
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int64_t kr = (int64_t)k * r;
-  const double tol = 8.0 * N * 2.220446049250313e-16;
+  const double tol = tol_in > 0.0 ? tol_in : 8.0 * N * 2.220446049250313e-16;
   // S = Yt^T (k x r, zero padded to kp x N)
   for (int e = tid; e < kp * N; e += NT) {
     const int i = e / N, j = e - i * N;
@@ -557,21 +558,37 @@ __device__ __forceinline__ void admm_solve_ns_nb(const double* __restrict__ Pred
       }
     }
     if (need_chol) ns_chol_inverse(Mb, Zb, Eb, ld, NB, N, r, flags);
-    // (d) RHS = At S + P (pass 0) or At^T S + P (pass 1) into Eb (kp x N)
+    // (d) RHS = At S + P (pass 0) or At^T S + P (pass 1) into Eb (kp x N).
+    // The lane's At values for all K steps are loaded from global memory up
+    // front, so their latency is paid once.
     for (int rb = w; rb < KB16; rb += 4) {
-      if (pass == 0)
-        ns_tile_rows<NB>([&](int i, int kk) { return (i < k && kk < k) ? At[i * k + kk] : 0.0; },
-                     [&](int kk, int j) { return S[kk * ld + j]; }, kp, rb, c, g, acc);
-      else
-        ns_tile_rows<NB>([&](int i, int kk) { return (i < k && kk < k) ? At[kk * k + i] : 0.0; },
-                     [&](int kk, int j) { return S[kk * ld + j]; }, kp, rb, c, g, acc);
+      const int i = 16 * rb + c;
+      double av[kNsMaxK / 4];
+#pragma unroll
+      for (int s = 0; s < kNsMaxK / 4; ++s) {
+        const int kk = 4 * s + g;
+        double v = 0.0;
+        if (i < k && kk < k) v = pass == 0 ? At[i * k + kk] : At[kk * k + i];
+        av[s] = v;
+      }
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < kNsMaxK / 4; ++s) {
+        if (4 * s < kp) {
+          const int kk = 4 * s + g;
+#pragma unroll
+          for (int cb = 0; cb < NB; ++cb)
+            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], S[kk * ld + 16 * cb + c], acc[cb], 0, 0, 0);
+        }
+      }
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int ii = 0; ii < 4; ++ii) {
           if (cb >= NB) continue;
-          const int row = 16 * rb + g + 4 * i, col = 16 * cb + c;
-          Eb[row * ld + col] = (row < k && col < r) ? acc[cb][i] + P[row * r + col] : 0.0;
+          const int row = 16 * rb + g + 4 * ii, col = 16 * cb + c;
+          Eb[row * ld + col] = (row < k && col < r) ? acc[cb][ii] + P[row * r + col] : 0.0;
         }
     }
     __syncthreads();
@@ -600,12 +617,12 @@ __device__ __forceinline__ void admm_solve_ns_nb(const double* __restrict__ Pred
 __device__ __forceinline__ void admm_solve_ns_body(const double* __restrict__ Pred, const double* __restrict__ At,
                                                    int k, int r, double lam, double phi, int first,
                                                    double* __restrict__ XY, double* __restrict__ Zg, int* flags,
-                                                   double* sm) {
+                                                   double tol, double* sm) {
   switch ((r + 15) / 16) {
-    case 1: admm_solve_ns_nb<1>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, sm); break;
-    case 2: admm_solve_ns_nb<2>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, sm); break;
-    case 3: admm_solve_ns_nb<3>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, sm); break;
-    default: admm_solve_ns_nb<4>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, sm); break;
+    case 1: admm_solve_ns_nb<1>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, tol, sm); break;
+    case 2: admm_solve_ns_nb<2>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, tol, sm); break;
+    case 3: admm_solve_ns_nb<3>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, tol, sm); break;
+    default: admm_solve_ns_nb<4>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, tol, sm); break;
   }
 }
 
@@ -613,9 +630,9 @@ __global__ __launch_bounds__(kSolveNT) void admm_solve_ns_kernel(const double* _
                                                                  const double* __restrict__ At, int k, int r,
                                                                  double lam, double phi, int first,
                                                                  double* __restrict__ XY, double* __restrict__ Z,
-                                                                 int* flags) {
+                                                                 int* flags, double tol) {
   extern __shared__ double sm[];
-  admm_solve_ns_body(Pred, At, k, r, lam, phi, first, XY, Z, flags, sm);
+  admm_solve_ns_body(Pred, At, k, r, lam, phi, first, XY, Z, flags, tol, sm);
 }
 
 __global__ __launch_bounds__(kSolveNT) void admm_solve_kernel(const double* __restrict__ Pred,
@@ -631,7 +648,7 @@ __global__ __launch_bounds__(kSolveNT) void admm_solve_batch_kernel(const AdmmJo
   extern __shared__ double sm[];
   const AdmmJob& J = jobs[blockIdx.x];
   if (J.Z && J.k <= kNsMaxK)
-    admm_solve_ns_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.Z, J.flags, sm);
+    admm_solve_ns_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.Z, J.flags, 1e-10, sm);
   else
     admm_solve_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.flags, J.at_in_lds, sm);
 }
@@ -657,8 +674,9 @@ hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const dou
     if (e != hipSuccess) return e;
     const size_t sm = ns_layout(k, r).total * sizeof(double);
     hipFuncSetAttribute((const void*)admm_solve_ns_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    const double tol = sizeof(T) == 4 ? 1e-10 : 0.0;   // 0: 8 N eps
     hipLaunchKernelGGL(admm_solve_ns_kernel, dim3(1), dim3(kSolveNT), sm, st, Pred, At, k, r, lam, phi, first, XY, Z,
-                       flags);
+                       flags, tol);
     CNMF_LAUNCH_CHECK();
   }
   int at_in_lds = admm_solve_lds(k, r, true) <= cap;
