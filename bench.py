@@ -41,6 +41,24 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def pass_traffic(w):
+    """HBM bytes per range-pass launch from the committed counter profile
+    (FETCH_SIZE / WRITE_SIZE scaled by a copy of known size), or None when
+    the profile is for another workload or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_range_passes_{w.name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        prof = json.load(f)
+    with open(os.path.join(ROOT, prof["kernel_source"]), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if sha != prof["kernel_source_sha256"]:
+        return None
+    return prof["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(inp, w, lam, budget_s=15.0):
     """The FP64 oracle, as it stands, on the host: full solves of the same
     workload (sketch + 200 ADMM iterations + residual) until ~budget_s."""
@@ -247,6 +265,9 @@ def main():
     ap.add_argument("--precision-only", action="store_true",
                     help="only the precision sketches (for kernel profiles); prints that object")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy a 1 GiB FP32 tensor three times (a plain copy kernel of known size, so that "
+                         "hardware byte counters can be scaled)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving run; prints that object")
     ap.add_argument("--serving-requests", type=int, default=WL.SERVING["count"])
     ap.add_argument("--serving-qps", type=float, default=400.0, help="Poisson arrival rate (0: all at once)")
@@ -263,6 +284,14 @@ def main():
     w = WL.WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 1 GiB (read 1 GiB, write 1 GiB each)")
+        del src, dst
     if args.precision_only:
         print(json.dumps({"precision": precision_section(api.default_handle(), max(1, args.steps), args.warmup)}),
               flush=True)
@@ -338,7 +367,7 @@ def main():
     pass_n = pn[2] + pt[2]
     achieved = pass_fl / (pass_ms * 1e-3) / 1e12 if pass_ms > 0 else None
     roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": (achieved / FP32_PEAK_TFLOPS) if achieved else None, "traffic": None,
+                "frac": (achieved / FP32_PEAK_TFLOPS) if achieved else None, "traffic": pass_traffic(w),
                 "kernel": "gemm_n_kernel + gemm_t_kernel (range-finder passes, FP32 16x16x4 MFMA)",
                 "avg_launch_ms": pass_ms / pass_n if pass_n else None,
                 "gflop_per_launch": pass_fl / pass_n / 1e9 if pass_n else None}
