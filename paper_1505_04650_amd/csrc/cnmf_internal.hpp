@@ -100,12 +100,11 @@ struct AdmmSide {
 template <typename T>
 hipError_t launch_admm_uv(AdmmSide s0, AdmmSide s1, int nsides, const double* XY, int k, int r,
                           double xi, int mode, double* Pp, int parts0, int parts1, hipStream_t st);
-// Z: 2 x 64 x 64 FP64 inverses kept between iterations (NULL: Cholesky
-// every iteration).  first != 0 for the first iteration of a run.
+// first != 0 for the first iteration of a run.
 template <typename T>
 hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const double* At, int k, int r,
-                             double lam, double phi, int first, double* XY, double* Pred,
-                             double* Z, int* flags, hipStream_t st);
+                             double lam, double phi, int first, double* XY, double* Pred, int* flags,
+                             hipStream_t st);
 
 // One request of a batched ADMM step (FP32 factors): its two sides, the
 // FP64 solve state and its partial buffers, all in its own workspace.
@@ -115,7 +114,6 @@ struct AdmmJob {
   double* XY;             // Xt, Yt^T (k x r each)
   double* Pp;             // (parts0 + parts1) k x r partials
   double* Pred;           // 2 k x r reduced partials
-  double* Z;              // 2 x 64 x 64 inverses kept between iterations
   int* flags;             // breakdown flag word
   double lam, phi, xi;
   int k, r, parts0, parts1;

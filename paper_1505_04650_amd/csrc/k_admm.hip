@@ -376,263 +376,256 @@ __device__ __forceinline__ void admm_solve_body(const double* __restrict__ Pred,
 }
 
 // ---------------------------------------------------------------------------
-// The same two solves with an explicit inverse kept from one iteration to the
-// next (k <= 80, r <= 64).  For each side the system matrix M = S^T S + pen I
-// (padded to N = 16 ceil(r / 16) with an identity block) is inverted by
-// Newton-Schulz steps Z <- Z + Z (I - M Z), warm-started from the previous
-// iteration's inverse, until ||I - M Z||_F <= tol (8 N eps for FP64
-// factors; 1e-10 for FP32 factors, far below their rounding) or it stops
-// shrinking by half; the first iteration, a warm start with ||I - M Z||_F > 1/2 and a
-// non-converging start use the blocked Cholesky and solve for Z = M^-1
-// instead.  Then X = RHS Z.  Every product is a 16x16x4 FP64 MFMA tile
-// product in LDS; Z is stored for the next iteration.
+// The same two solves by a direct Cholesky factorisation, every product on
+// the FP64 MFMA (r <= 64, k <= 128).  Per side, with the system padded to
+// N = 16 ceil(r / 16) by an identity block, X M = RHS is solved as
+// M X^T = RHS^T:
+//   (a) all waves: M = S^T S + pen I (wave w: block row w), and each wave's
+//       16-column strips of RHS^T = S^T At^T + P^T (pass 0) or
+//       S^T At + P^T (pass 1), kept in registers;
+//   (b) wave 0: M = L L^T (wave_chol_lower: 16-column panels in registers,
+//       MFMA trailing updates, inverses V_b of the diagonal blocks);
+//   (c) each wave on its strips, still in registers:
+//         W_b = V_b (RHS^T_b - sum_{a<b} L[b][a] W_a),        b ascending,
+//         X^T_b = V_b^T (W_b - sum_{a>b} L[a][b]^T X^T_a),    b descending.
+// A 16x16x4 FP64 MFMA leaves item i of lane (c, g) at row g + 4 i, column c
+// of its tile, which is where the next product takes its right operand for
+// K step i, so the strips never leave the registers; L and V come from LDS.
 // ---------------------------------------------------------------------------
-constexpr int kNsMaxK = 80;
+constexpr int kCholMaxK = 128;
 
-struct NsLayout {
-  int NB, N, ld, kp, KB16;
-  size_t s_off, m_off, z_off, e_off, red_off, total;  // in doubles
+struct CholLayout {
+  int NB, N, ld, kp, KB16, lda;
+  size_t s_off, m_off, v_off, w_off, a_off, total;  // in doubles
 };
-__host__ __device__ inline NsLayout ns_layout(int k, int r) {
-  NsLayout L;
+__host__ __device__ inline CholLayout chol_layout(int k, int r) {
+  CholLayout L;
   L.NB = (r + 15) / 16;
   L.N = 16 * L.NB;
   L.ld = L.N + 2;
   L.KB16 = (k + 15) / 16;
   L.kp = 16 * L.KB16;
-  const size_t rowsE = (size_t)(L.kp > L.N ? L.kp : L.N);
-  size_t eb = rowsE * L.ld;
-  const size_t fb = (size_t)L.NB * 272 + 16 * (size_t)L.ld + (size_t)L.N * 17;  // fallback scratch
-  if (fb > eb) eb = fb;
+  L.lda = L.kp + 1;
   L.s_off = 0;
   L.m_off = L.s_off + (size_t)L.kp * L.ld;
-  L.z_off = L.m_off + (size_t)L.N * L.ld;
-  L.e_off = L.z_off + (size_t)L.N * L.ld;
-  L.red_off = L.e_off + eb;
-  L.total = L.red_off + 8;
+  L.v_off = L.m_off + (size_t)L.N * L.ld;
+  L.w_off = L.v_off + (size_t)L.NB * 272;
+  L.a_off = L.w_off + 128;
+  L.total = L.a_off + (size_t)L.kp * L.lda;
   return L;
 }
-
-// acc[cb] = rows 16 rb + g + 4 i, cols 16 cb + c of A B for cb < ncb, where
-// lane (c, g) supplies A(16 rb + c, kk) and B(kk, 16 cb + c) for kk = 4 s + g.
-template <int NCB, typename FA, typename FB>
-__device__ __forceinline__ void ns_tile_rows(FA fa, FB fb, int K, int rb, int c, int g, doublex4 (&acc)[4]) {
-#pragma unroll
-  for (int cb = 0; cb < 4; ++cb) acc[cb] = doublex4{0.0, 0.0, 0.0, 0.0};
-  const int nsteps = K / 4;
-#pragma unroll 4
-  for (int s = 0; s < nsteps; ++s) {
-    const int kk = 4 * s + g;
-    const double a = fa(16 * rb + c, kk);
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, fb(kk, 16 * cb + c), acc[cb], 0, 0, 0);
-  }
+static bool chol_fits(int k, int r) {
+  return k <= kCholMaxK && r <= 64 && chol_layout(k, r).total * sizeof(double) <= 160 * 1024;
 }
 
-__device__ __forceinline__ double wave_sum_d(double x) {
+// K loop over the kp rows of S (LDS, row stride ld) in chunks of 16 rows;
+// the next chunk's operands are loaded (row clamped into S) before this
+// chunk's products, so their LDS latency overlaps the MFMA work.  For K step
+// s (rows 4 s + g of lane (c, g)) f(s, sv, sx) gets sv[b] = S[4 s + g][16 b + c]
+// (b < NB) and sx = fx(4 s + g).
+template <int NB, typename FX, typename F>
+__device__ __forceinline__ void s_chunks(const double* S, int ld, int kp, int c, int g, FX fx, F f) {
+  constexpr int KS = kCholMaxK / 4;
+  double cur[4][NB + 1], nxt[4][NB + 1];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
-}
-
-// Z = M^-1 by the blocked Cholesky of M (in place) and a solve of Z M = I;
-// kept out of line so that the register budget of the Newton-Schulz path is
-// not set by it.
-__device__ __attribute__((noinline)) void ns_chol_inverse(double* Mb, double* Zb, double* Eb, int ld, int NB, int N,
-                                                          int r, int* flags) {
-  constexpr int NT = kSolveNT;
-  const int tid = threadIdx.x;
-  double* TI = Eb;
-  double* PN = TI + NB * 272;
-  double* Rs = PN + 16 * ld;
-  double mx = 0.0;
-  for (int i = 0; i < r; ++i) mx = fmax(mx, Mb[i * ld + i]);
-  wg_chol_blocked<NT>(Mb, ld, NB, TI, PN, 1e-300 * mx, flags);
-  for (int e = tid; e < N * N; e += NT) {
-    const int i = e / N, j = e - i * N;
-    Zb[i * ld + j] = i == j ? 1.0 : 0.0;
+  for (int s4 = 0; s4 < 4; ++s4) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) cur[s4][b] = S[(4 * s4 + g) * ld + 16 * b + c];
+    cur[s4][NB] = fx(4 * s4 + g);
   }
-  wg_right_solve_blocked<NT>(Zb, N, ld, NB, Mb, ld, TI, Rs);
-  __syncthreads();
+#pragma unroll
+  for (int ch = 0; ch < KS / 4; ++ch) {
+    if (16 * ch < kp) {
+      if (ch + 1 < KS / 4) {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int row = min(16 * (ch + 1) + 4 * s4 + g, kp - 1);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) nxt[s4][b] = S[row * ld + 16 * b + c];
+          nxt[s4][NB] = fx(row);
+        }
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) f(4 * ch + s4, cur[s4], cur[s4][NB]);
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int b = 0; b <= NB; ++b) cur[s4][b] = nxt[s4][b];
+    }
+  }
 }
 
 template <int NB>
-__device__ __forceinline__ void admm_solve_ns_nb(const double* __restrict__ Pred, const double* __restrict__ At, int k,
-                                                 int r, double lam, double phi, int first, double* __restrict__ XY,
-                                                 double* __restrict__ Zg, int* flags, double tol_in, double* sm) {
+__device__ __forceinline__ void admm_solve_chol_nb(const double* __restrict__ Pred, const double* __restrict__ At,
+                                                   int k, int r, double lam, double phi, int first,
+                                                   double* __restrict__ XY, int* flags, double* sm) {
   constexpr int NT = kSolveNT;
   constexpr int N = 16 * NB;
-  const NsLayout Ly = ns_layout(k, r);
-  const int ld = Ly.ld, kp = Ly.kp, KB16 = Ly.KB16;
+  const CholLayout Ly = chol_layout(k, r);
+  const int ld = Ly.ld, kp = Ly.kp, KB16 = Ly.KB16, lda = Ly.lda;
   double* S = sm + Ly.s_off;
   double* Mb = sm + Ly.m_off;
-  double* Zb = sm + Ly.z_off;
-  double* Eb = sm + Ly.e_off;
-  double* red = sm + Ly.red_off;
+  double* V = sm + Ly.v_off;
+  double* W = sm + Ly.w_off;
+  double* Al = sm + Ly.a_off;   // At, kp x lda, zero padded
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int64_t kr = (int64_t)k * r;
-  const double tol = tol_in > 0.0 ? tol_in : 8.0 * N * 2.220446049250313e-16;
-  // S = Yt^T (k x r, zero padded to kp x N)
+  // S = Yt^T (k x r, zero padded to kp x N); At into LDS
   for (int e = tid; e < kp * N; e += NT) {
     const int i = e / N, j = e - i * N;
     S[i * ld + j] = (i < k && j < r) ? (first ? Pred[kr + i * r + j] / phi : XY[kr + i * r + j]) : 0.0;
   }
+  for (int e = tid; e < kp * kp; e += NT) {
+    const int i = e / kp, j = e - i * kp;
+    Al[i * lda + j] = (i < k && j < k) ? At[i * k + j] : 0.0;
+  }
   __syncthreads();
+  // strips of X^T (16 columns = 16 rows of X): strip rb belongs to wave
+  // 3 - (rb % 4), so wave 0, which factors M, has at most one for k <= 112
+  const int rb0 = 3 - w, rb1 = 7 - w;
   for (int pass = 0; pass < 2; ++pass) {
     const double pen = pass ? phi : lam;
     const double* P = Pred + (pass ? kr : 0);
-    double* Zh = Zg + (size_t)pass * 64 * 64;
-    doublex4 acc[4];
-    // (a) M = S^T S + pen I_r, identity on the padding
-    if (w < NB) {
-      ns_tile_rows<NB>([&](int i, int kk) { return S[kk * ld + i]; }, [&](int kk, int j) { return S[kk * ld + j]; }, kp,
-                   w, c, g, acc);
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if (cb >= NB) continue;
-          const int row = 16 * w + g + 4 * i, col = 16 * cb + c;
-          Mb[row * ld + col] = acc[cb][i] + (row == col ? (row < r ? pen : 1.0) : 0.0);
-        }
-    }
-    // warm start
-    if (!first)
-      for (int e = tid; e < N * N; e += NT) Zb[(e / N) * ld + (e % N)] = Zh[e];
-    __syncthreads();
-    bool need_chol = first != 0;
-    if (!need_chol) {
-      double e_prev = 0.0;
-      int it = 0;
-      const int kMaxIt = 8;
-      for (;; ++it) {
-        // E = I - M Z
-        double ss = 0.0;
-        if (w < NB) {
-          ns_tile_rows<NB>([&](int i, int kk) { return Mb[i * ld + kk]; }, [&](int kk, int j) { return Zb[kk * ld + j]; },
-                       N, w, c, g, acc);
-#pragma unroll
-          for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (cb >= NB) continue;
-              const int row = 16 * w + g + 4 * i, col = 16 * cb + c;
-              const double ev = (row == col ? 1.0 : 0.0) - acc[cb][i];
-              Eb[row * ld + col] = ev;
-              ss = fma(ev, ev, ss);
-            }
-        }
-        ss = wave_sum_d(ss);
-        if (lane == 0) red[w] = ss;
-        __syncthreads();
-        const double en = sqrt((red[0] + red[1]) + (red[2] + red[3]));
-        if (!isfinite(en) || (it == 0 && en > 0.5)) {
-          need_chol = true;
-          break;
-        }
-        if (en <= tol || (it > 0 && en > 0.5 * e_prev)) break;
-        if (it == kMaxIt) {
-          need_chol = true;
-          break;
-        }
-        // Z <- Z + Z E
-        if (w < NB) {
-          ns_tile_rows<NB>([&](int i, int kk) { return Zb[i * ld + kk]; }, [&](int kk, int j) { return Eb[kk * ld + j]; },
-                       N, w, c, g, acc);
-        }
-        __syncthreads();
-        if (w < NB) {
-#pragma unroll
-          for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (cb >= NB) continue;
-              const int row = 16 * w + g + 4 * i, col = 16 * cb + c;
-              Zb[row * ld + col] += acc[cb][i];
-            }
-        }
-        __syncthreads();
-        e_prev = en;
-      }
-    }
-    if (need_chol) ns_chol_inverse(Mb, Zb, Eb, ld, NB, N, r, flags);
-    // (d) RHS = At S + P (pass 0) or At^T S + P (pass 1) into Eb (kp x N).
-    // The lane's At values for all K steps are loaded from global memory up
-    // front, so their latency is paid once.
-    for (int rb = w; rb < KB16; rb += 4) {
-      const int i = 16 * rb + c;
-      double av[kNsMaxK / 4];
-#pragma unroll
-      for (int s = 0; s < kNsMaxK / 4; ++s) {
-        const int kk = 4 * s + g;
-        double v = 0.0;
-        if (i < k && kk < k) v = pass == 0 ? At[i * k + kk] : At[kk * k + i];
-        av[s] = v;
-      }
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb) acc[cb] = doublex4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < kNsMaxK / 4; ++s) {
-        if (4 * s < kp) {
-          const int kk = 4 * s + g;
-#pragma unroll
-          for (int cb = 0; cb < NB; ++cb)
-            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], S[kk * ld + 16 * cb + c], acc[cb], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-        for (int ii = 0; ii < 4; ++ii) {
-          if (cb >= NB) continue;
-          const int row = 16 * rb + g + 4 * ii, col = 16 * cb + c;
-          Eb[row * ld + col] = (row < k && col < r) ? acc[cb][ii] + P[row * r + col] : 0.0;
-        }
-    }
-    __syncthreads();
-    // (e) X = RHS Z, written to XY and, for pass 0, into S for the other side
     double* out = XY + (pass ? kr : 0);
-    for (int rb = w; rb < KB16; rb += 4) {
-      ns_tile_rows<NB>([&](int i, int kk) { return Eb[i * ld + kk]; }, [&](int kk, int j) { return Zb[kk * ld + j]; }, N,
-                   rb, c, g, acc);
+    // RHS^T strip rb = S^T At^T + P^T (pass 0) or S^T At + P^T (pass 1)
+    auto rhs_strip = [&](int rb, doublex4 (&z)[NB]) {
+      const int xr = 16 * rb + c;
+      double pv[NB][4];
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
+      for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          if (cb >= NB) continue;
-          const int row = 16 * rb + g + 4 * i, col = 16 * cb + c;
-          const double v = (row < k && col < r) ? acc[cb][i] : 0.0;
-          if (row < k && col < r) out[row * r + col] = v;
-          if (pass == 0) S[row * ld + col] = v;
+          const int pr = 16 * b + g + 4 * i;
+          pv[b][i] = (xr < k && pr < r) ? P[xr * r + pr] : 0.0;
+        }
+      doublex4 acc[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[b] = doublex4{0.0, 0.0, 0.0, 0.0};
+      s_chunks<NB>(S, ld, kp, c, g, [&](int kk) { return pass == 0 ? Al[xr * lda + kk] : Al[kk * lda + xr]; },
+                   [&](int, const double* sv, double sx) {
+#pragma unroll
+                     for (int b = 0; b < NB; ++b)
+                       acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sv[b], sx, acc[b], 0, 0, 0);
+                   });
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) z[b][i] = acc[b][i] + pv[b][i];
+    };
+    // block substitutions on one strip, in registers; X rows to XY
+    auto solve_strip = [&](int rb, doublex4 (&z)[NB]) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        doublex4 t = z[b];
+#pragma unroll
+        for (int a = 0; a < b; ++a)
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            t = __builtin_amdgcn_mfma_f64_16x16x4f64(-Mb[(16 * b + c) * ld + 16 * a + 4 * s + g], z[a][s], t, 0, 0, 0);
+        doublex4 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          y = __builtin_amdgcn_mfma_f64_16x16x4f64(V[b * 272 + c * 17 + 4 * s + g], t[s], y, 0, 0, 0);
+        z[b] = y;
+      }
+#pragma unroll
+      for (int b = NB - 1; b >= 0; --b) {
+        doublex4 t = z[b];
+#pragma unroll
+        for (int a = b + 1; a < NB; ++a)
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            t = __builtin_amdgcn_mfma_f64_16x16x4f64(-Mb[(16 * a + 4 * s + g) * ld + 16 * b + c], z[a][s], t, 0, 0, 0);
+        doublex4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          x = __builtin_amdgcn_mfma_f64_16x16x4f64(V[b * 272 + (4 * s + g) * 17 + c], t[s], x, 0, 0, 0);
+        z[b] = x;
+      }
+      const int xr = 16 * rb + c;
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int col = 16 * b + g + 4 * i;
+          if (xr < k && col < r) out[xr * r + col] = z[b][i];
+        }
+    };
+    auto strip_to_s = [&](int rb, const doublex4 (&z)[NB]) {
+      const int xr = 16 * rb + c;
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) S[xr * ld + 16 * b + g + 4 * i] = z[b][i];
+    };
+    // (a) block row w of M and the first strip of RHS^T
+    if (w < NB) {
+      doublex4 am[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) am[b] = doublex4{0.0, 0.0, 0.0, 0.0};
+      s_chunks<NB>(S, ld, kp, c, g, [&](int kk) { return S[kk * ld + 16 * w + c]; },
+                   [&](int, const double* sv, double sx) {
+#pragma unroll
+                     for (int b = 0; b < NB; ++b)
+                       am[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sx, sv[b], am[b], 0, 0, 0);
+                   });
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * w + g + 4 * i, col = 16 * b + c;
+          Mb[row * ld + col] = am[b][i] + (row == col ? (row < r ? pen : 1.0) : 0.0);
         }
     }
-    // (f) keep Z for the next iteration
-    for (int e = tid; e < N * N; e += NT) Zh[e] = Zb[(e / N) * ld + (e % N)];
+    doublex4 z0[NB];
+    if (rb0 < KB16) rhs_strip(rb0, z0);
+    __syncthreads();
+    // (b) the factor; pivots below 1e-300 max diag(M) are floored
+    if (w == 0) {
+      double dg = lane < r ? Mb[lane * ld + lane] : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o));
+      wave_chol_lower<NB>(Mb, ld, r, V, W, 1e-300 * dg, flags);
+    }
+    __syncthreads();
+    // (c) substitutions; a second strip (k > 64) is formed and solved after
+    // the first, S being overwritten (pass 0) only once every strip is formed
+    if (rb0 < KB16) solve_strip(rb0, z0);
+    if (rb1 < KB16) {
+      doublex4 z1[NB];
+      rhs_strip(rb1, z1);
+      solve_strip(rb1, z1);
+      if (pass == 0) {
+        __syncthreads();
+        if (rb0 < KB16) strip_to_s(rb0, z0);
+        strip_to_s(rb1, z1);
+      }
+    } else if (pass == 0) {
+      if (KB16 > 4) __syncthreads();
+      if (rb0 < KB16) strip_to_s(rb0, z0);
+    }
     __syncthreads();
   }
 }
 
-__device__ __forceinline__ void admm_solve_ns_body(const double* __restrict__ Pred, const double* __restrict__ At,
-                                                   int k, int r, double lam, double phi, int first,
-                                                   double* __restrict__ XY, double* __restrict__ Zg, int* flags,
-                                                   double tol, double* sm) {
+__device__ __forceinline__ void admm_solve_chol_body(const double* __restrict__ Pred, const double* __restrict__ At,
+                                                     int k, int r, double lam, double phi, int first,
+                                                     double* __restrict__ XY, int* flags, double* sm) {
   switch ((r + 15) / 16) {
-    case 1: admm_solve_ns_nb<1>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, tol, sm); break;
-    case 2: admm_solve_ns_nb<2>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, tol, sm); break;
-    case 3: admm_solve_ns_nb<3>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, tol, sm); break;
-    default: admm_solve_ns_nb<4>(Pred, At, k, r, lam, phi, first, XY, Zg, flags, tol, sm); break;
+    case 1: admm_solve_chol_nb<1>(Pred, At, k, r, lam, phi, first, XY, flags, sm); break;
+    case 2: admm_solve_chol_nb<2>(Pred, At, k, r, lam, phi, first, XY, flags, sm); break;
+    case 3: admm_solve_chol_nb<3>(Pred, At, k, r, lam, phi, first, XY, flags, sm); break;
+    default: admm_solve_chol_nb<4>(Pred, At, k, r, lam, phi, first, XY, flags, sm); break;
   }
 }
 
-__global__ __launch_bounds__(kSolveNT) void admm_solve_ns_kernel(const double* __restrict__ Pred,
-                                                                 const double* __restrict__ At, int k, int r,
-                                                                 double lam, double phi, int first,
-                                                                 double* __restrict__ XY, double* __restrict__ Z,
-                                                                 int* flags, double tol) {
+__global__ __launch_bounds__(kSolveNT) void admm_solve_chol_kernel(const double* __restrict__ Pred,
+                                                                   const double* __restrict__ At, int k, int r,
+                                                                   double lam, double phi, int first,
+                                                                   double* __restrict__ XY, int* flags) {
   extern __shared__ double sm[];
-  admm_solve_ns_body(Pred, At, k, r, lam, phi, first, XY, Z, flags, tol, sm);
+  admm_solve_chol_body(Pred, At, k, r, lam, phi, first, XY, flags, sm);
 }
 
 __global__ __launch_bounds__(kSolveNT) void admm_solve_kernel(const double* __restrict__ Pred,
@@ -647,8 +640,8 @@ __global__ __launch_bounds__(kSolveNT) void admm_solve_kernel(const double* __re
 __global__ __launch_bounds__(kSolveNT) void admm_solve_batch_kernel(const AdmmJob* __restrict__ jobs) {
   extern __shared__ double sm[];
   const AdmmJob& J = jobs[blockIdx.x];
-  if (J.Z && J.k <= kNsMaxK)
-    admm_solve_ns_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.Z, J.flags, 1e-10, sm);
+  if (J.k <= kCholMaxK && chol_layout(J.k, J.r).total * sizeof(double) <= 160 * 1024)
+    admm_solve_chol_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.flags, sm);
   else
     admm_solve_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.flags, J.at_in_lds, sm);
 }
@@ -662,38 +655,32 @@ static size_t admm_solve_lds(int k, int r, bool with_at) {
 
 template <typename T>
 hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const double* At, int k, int r,
-                             double lam, double phi, int first, double* XY, double* Pred, double* Z,
-                             int* flags, hipStream_t st) {
+                             double lam, double phi, int first, double* XY, double* Pred, int* flags,
+                             hipStream_t st) {
   if (r > 64 || k > 128) return hipErrorInvalidValue;
   const size_t cap = 160 * 1024;
-  if (Z && k <= kNsMaxK) {
-    int64_t kr = (int64_t)k * r;
-    int nbh = (int)((kr + kRedEPB - 1) / kRedEPB);
-    hipLaunchKernelGGL(admm_reduce_kernel, dim3(2 * nbh), dim3(kRedNT), 0, st, Pp, parts0, parts1, kr, Pred);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t sm = ns_layout(k, r).total * sizeof(double);
-    hipFuncSetAttribute((const void*)admm_solve_ns_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    const double tol = sizeof(T) == 4 ? 1e-10 : 0.0;   // 0: 8 N eps
-    hipLaunchKernelGGL(admm_solve_ns_kernel, dim3(1), dim3(kSolveNT), sm, st, Pred, At, k, r, lam, phi, first, XY, Z,
-                       flags, tol);
-    CNMF_LAUNCH_CHECK();
-  }
-  int at_in_lds = admm_solve_lds(k, r, true) <= cap;
-  size_t sm = admm_solve_lds(k, r, at_in_lds);
-  if (sm > cap) return hipErrorInvalidValue;
   int64_t kr = (int64_t)k * r;
   int nbh = (int)((kr + kRedEPB - 1) / kRedEPB);
   hipLaunchKernelGGL(admm_reduce_kernel, dim3(2 * nbh), dim3(kRedNT), 0, st, Pp, parts0, parts1, kr, Pred);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (chol_fits(k, r)) {
+    const size_t sm = chol_layout(k, r).total * sizeof(double);
+    hipFuncSetAttribute((const void*)admm_solve_chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    hipLaunchKernelGGL(admm_solve_chol_kernel, dim3(1), dim3(kSolveNT), sm, st, Pred, At, k, r, lam, phi, first, XY,
+                       flags);
+    CNMF_LAUNCH_CHECK();
+  }
+  int at_in_lds = admm_solve_lds(k, r, true) <= cap;
+  size_t sm = admm_solve_lds(k, r, at_in_lds);
+  if (sm > cap) return hipErrorInvalidValue;
   hipFuncSetAttribute((const void*)admm_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   hipLaunchKernelGGL(admm_solve_kernel, dim3(1), dim3(kSolveNT), sm, st, Pred, At, k, r, lam, phi, first, XY, flags,
                      at_in_lds);
   CNMF_LAUNCH_CHECK();
 }
-template hipError_t launch_admm_solve<float>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, double*, int*, hipStream_t);
-template hipError_t launch_admm_solve<double>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, double*, int*, hipStream_t);
+template hipError_t launch_admm_solve<float>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, int*, hipStream_t);
+template hipError_t launch_admm_solve<double>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, int*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Batched ADMM step (serving): for every job, the fixed-order partial sums,
@@ -734,7 +721,7 @@ hipError_t launch_admm_step_batch(const AdmmJob* jobs_dev, const int* uv_first_d
 }
 
 size_t admm_job_solve_lds(const AdmmJob& J) {
-  if (J.Z && J.k <= kNsMaxK) return ns_layout(J.k, J.r).total * sizeof(double);
+  if (chol_fits(J.k, J.r)) return chol_layout(J.k, J.r).total * sizeof(double);
   return admm_solve_lds(J.k, J.r, J.at_in_lds != 0);
 }
 

@@ -347,7 +347,6 @@ struct AdmmWs {
   double* XY = nullptr;
   double* Pp = nullptr;
   double* Pred = nullptr;
-  double* Z = nullptr;
   unsigned* counter = nullptr;
   int parts0 = 0, parts1 = 0;
   double* rpart = nullptr;
@@ -367,7 +366,6 @@ void layout_admm(Arena& a, AdmmWs<T>& w, int64_t m, int64_t n, int k, int r) {
   w.parts1 = uv_parts(n);
   w.Pp = a.take<double>((size_t)(w.parts0 + w.parts1) * k * r);
   w.Pred = a.take<double>(2 * (size_t)k * r);
-  w.Z = a.take<double>(2 * 64 * 64);
   w.counter = a.take<unsigned>(4);
   w.rparts = (int)((m + 15) / 16);
   w.rpart = a.take<double>(2 * (size_t)w.rparts);
@@ -795,7 +793,6 @@ AdmmJob admm_job_of(FactState<T>& f, const cnmf_input* A, const cnmf_factorize_d
   J.XY = f.aw.XY;
   J.Pp = f.aw.Pp;
   J.Pred = f.aw.Pred;
-  J.Z = f.aw.Z;
   J.flags = f.w.flags + 2;
   J.lam = d->lambda;
   J.phi = d->phi;
@@ -881,7 +878,7 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
     AdmmJob J = admm_job_of(f, A, d);
     for (int it = 0; it < d->iters; ++it) {
       HIPCHK(h, launch_admm_solve<T>(aw.Pp, aw.parts0, aw.parts1, w.At, k, r, d->lambda, d->phi, it == 0, aw.XY,
-                                     aw.Pred, aw.Z, w.flags + 2, st));
+                                     aw.Pred, w.flags + 2, st));
       HIPCHK(h, launch_admm_uv<T>(J.s0, J.s1, 2, aw.XY, k, r, d->xi, 1, aw.Pp, aw.parts0, aw.parts1, st));
     }
   } else if (d->method == CNMF_MU) {

@@ -612,4 +612,163 @@ __device__ void wg_right_solve_blocked(double* X, int rows, int ldx, int NB, con
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// One wave, no barriers: M (N x N, N = 16 NB <= 64, LDS, row stride ld) =
+// L L^T with L lower triangular and a positive diagonal.  Read: the lower
+// triangle and diagonal of M (the strict upper triangle of the diagonal
+// 16 x 16 blocks may hold anything).  On return L is in M's lower triangle
+// (the strict upper triangle is left undefined) and V[b] (16 x 17 each)
+// holds the inverse of the diagonal block L[b][b] (lower, zeros above).
+// Rows and columns from n on must be those of the identity (no coupling),
+// so their steps are skipped and L is the identity there too.  A pivot
+// <= floor (or not finite) is replaced by floor; the number of such pivots
+// is added to *flag.  W: 128 doubles of LDS scratch.
+//
+// Right-looking by 16-column panels: lane j keeps row j of the panel in
+// registers.  Step s takes the pivot of lane c0 + s by readlane; the entry
+// of the next pivot row comes by readlane too, so the dependent chain of a
+// step is short, and the rest of the column is broadcast through LDS.  The
+// trailing lower block triangle is updated with 16x16x4 FP64 MFMA tile
+// products.  At the end the lanes 16 q + v (v < 16) invert block q, column
+// v, by forward substitution.  A wave's LDS operations complete in order,
+// so no barrier is needed between them.
+// ---------------------------------------------------------------------------
+// Steps of one 16-column panel (see wave_chol_lower).  FULL: all 16 steps,
+// no branches, so the scheduler can overlap consecutive steps; otherwise
+// only the first `steps` (uniform) are taken.
+template <bool FULL>
+__device__ __forceinline__ void wave_panel_steps(double (&a)[16], int c0, int steps, double* colbuf,
+                                                 double floor_piv, double& myinv, int& nbad) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    if (FULL || s < steps) {
+      double d = readlane_d(a[s], c0 + s);
+      const bool bad = !(d > floor_piv) || !isfinite(d);
+      nbad += bad ? 1 : 0;
+      d = bad ? (floor_piv > 0.0 ? floor_piv : 1.0) : d;
+      const double y = rsqrt_refined(d);
+      const bool piv = lane == c0 + s;
+      const double l = piv ? d * y : a[s] * y;   // L[lane][c0 + s]
+      a[s] = l;
+      myinv = piv ? y : myinv;
+      if (s + 1 < 16) {
+        a[s + 1] = fma(-l, readlane_d(l, c0 + s + 1), a[s + 1]);
+        if (s + 2 < 16) {
+          colbuf[lane] = l;
+#pragma unroll
+          for (int t = s + 2; t < 16; ++t) a[t] = fma(-l, colbuf[c0 + t], a[t]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One wave, no barriers: M (N x N, N = 16 NB <= 64, LDS, row stride ld) =
+// L L^T with L lower triangular and a positive diagonal.  Read: the lower
+// triangle and diagonal of M (the strict upper triangle of the diagonal
+// 16 x 16 blocks may hold anything).  On return L is in M's lower triangle
+// (the strict upper triangle is left undefined) and V[b] (16 x 17 each)
+// holds the inverse of the diagonal block L[b][b] (lower, zeros above).
+// Rows and columns from n on must be those of the identity (no coupling),
+// so their steps are skipped and L is the identity there too.  A pivot
+// <= floor (or not finite) is replaced by floor; the number of such pivots
+// is added to *flag.  W: 128 doubles of LDS scratch.
+//
+// Right-looking by 16-column panels: lane j keeps row j of the panel in
+// registers.  Step s takes the pivot of lane c0 + s by readlane; the entry
+// of the next pivot row comes by readlane too, so the dependent chain of a
+// step is short, and the rest of the column is broadcast through LDS.  The
+// trailing lower block triangle is updated with 16x16x4 FP64 MFMA tile
+// products, all operands loaded before the first product.  At the end the
+// lanes 16 q + v (v < 16) invert block q, column v, by forward
+// substitution.  A wave's LDS operations complete in order, so no barrier
+// is needed between them.
+// ---------------------------------------------------------------------------
+template <int NB>
+__device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double* V, double* W, double floor_piv,
+                                                int* flag) {
+  constexpr int N = 16 * NB;
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 15, g = lane >> 4;
+  double* colbuf = W;       // the current column of L
+  double* dinv = W + 64;    // 1 / L[i][i]
+  int nbad = 0;
+#pragma unroll
+  for (int P = 0; P < NB; ++P) {
+    const int c0 = 16 * P;
+    const bool act = lane >= c0 && lane < N;
+    double a[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) a[t] = act ? M[lane * ld + c0 + t] : 0.0;
+    double myinv = 1.0;
+    const int steps = n - c0;   // uniform
+    if (steps >= 16)
+      wave_panel_steps<true>(a, c0, steps, colbuf, floor_piv, myinv, nbad);
+    else
+      wave_panel_steps<false>(a, c0, steps, colbuf, floor_piv, myinv, nbad);
+    if (act) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) M[lane * ld + c0 + t] = a[t];
+    }
+    if (lane >= c0 && lane < c0 + 16) dinv[lane] = myinv;
+    // trailing update of the lower block triangle: M[ti][tj] -= L[ti][P] L[tj][P]^T
+    if (P + 1 < NB) {
+      constexpr int kMaxT = NB - 1;
+      double lv[kMaxT > 0 ? kMaxT : 1][4];   // L[16 ti + c][c0 + 4 s + g], ti = P + 1 + u
+      doublex4 acc[kMaxT > 0 ? kMaxT * (kMaxT + 1) / 2 : 1];
+#pragma unroll
+      for (int u = 0; u < kMaxT; ++u) {
+        if (P + 1 + u < NB) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) lv[u][s] = M[(16 * (P + 1 + u) + c) * ld + c0 + 4 * s + g];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kMaxT; ++u)
+#pragma unroll
+        for (int v = 0; v <= u; ++v) {
+          if (P + 1 + u < NB) {
+            const int ti = P + 1 + u, tj = P + 1 + v;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[u * (u + 1) / 2 + v][i] = M[(16 * ti + g + 4 * i) * ld + 16 * tj + c];
+          }
+        }
+#pragma unroll
+      for (int u = 0; u < kMaxT; ++u)
+#pragma unroll
+        for (int v = 0; v <= u; ++v) {
+          if (P + 1 + u < NB) {
+            const int ti = P + 1 + u, tj = P + 1 + v;
+            doublex4 t = acc[u * (u + 1) / 2 + v];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) t = __builtin_amdgcn_mfma_f64_16x16x4f64(-lv[u][s], lv[v][s], t, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) M[(16 * ti + g + 4 * i) * ld + 16 * tj + c] = t[i];
+          }
+        }
+    }
+  }
+  // V_q = L[q][q]^-1, lanes 16 q + v: column v, x = e_v, then for each i
+  // x_i /= L[i][i] and x_t -= L[t][i] x_i (t > i)
+  if (g < NB) {
+    const int q0 = 16 * g;
+    double x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = i == c ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      x[i] *= dinv[q0 + i];
+#pragma unroll
+      for (int t = i + 1; t < 16; ++t) x[t] = fma(-M[(q0 + t) * ld + q0 + i], x[i], x[t]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) V[g * 272 + i * 17 + c] = x[i];
+  }
+  if (nbad && lane == 0 && flag) atomicAdd(flag, nbad);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+}
 }  // namespace cnmf
