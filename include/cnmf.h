@@ -150,7 +150,10 @@ cnmf_status cnmf_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_d
  * (no early stop).  lambda, phi > 0: ADMM penalties; xi > 0: ADMM step
  * (1 in the paper).  mu_eps >= 0: added to every MU denominator.
  * U0_dev (m x r) and V0_dev (r x n): FP64 initial factors (Alg. 2 / Alg. 3
- * "Initialize"), row-major, required. */
+ * "Initialize"), row-major, required.  Limits: r <= 64 (CNMF_ENOTSUP
+ * otherwise); CNMF_ADMM solves its two r x r systems per iteration in one
+ * workgroup whose LDS must hold three k x r FP64 blocks and the r x r
+ * system, so it also needs k <= 112 when r > 48 (CNMF_ENOTSUP). */
 typedef struct {
   cnmf_sketch_desc sk;
   int32_t method;

@@ -100,7 +100,9 @@ struct AdmmSide {
 template <typename T>
 hipError_t launch_admm_uv(AdmmSide s0, AdmmSide s1, int nsides, const double* XY, int k, int r,
                           double xi, int mode, double* Pp, int parts0, int parts1, hipStream_t st);
-// first != 0 for the first iteration of a run.
+// first != 0 for the first iteration of a run.  The solve runs in one
+// workgroup whose LDS holds admm_solve_lds_bytes(k, r) (<= 160 KiB required).
+size_t admm_solve_lds_bytes(int k, int r);
 template <typename T>
 hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const double* At, int k, int r,
                              double lam, double phi, int first, double* XY, double* Pred, int* flags,
@@ -119,7 +121,6 @@ struct AdmmJob {
   int k, r, parts0, parts1;
   int rpb0, rpb1;         // rows per uv block (filled by admm_job_prepare)
   int first;              // 1 for the request's first iteration
-  int at_in_lds;          // filled by admm_job_prepare
 };
 void admm_job_prepare(AdmmJob& J);
 int admm_job_uv_blocks(const AdmmJob& J);

@@ -9,8 +9,9 @@
 // R^T) are the same operation on two "sides" and run in one launch
 // (admm_uv_kernel).  That launch also forms the partial sums of
 // basis^T (pen * F - M) for the next iteration's P_U / P_V, so the big
-// matrices are read once per iteration.  admm_solve_kernel reduces those
-// partials in a fixed order and does the r x r solves by Cholesky in FP64.
+// matrices are read once per iteration.  admm_reduce_kernel reduces those
+// partials in a fixed order; admm_solve_chol_kernel does the r x r solves by
+// Cholesky in FP64.
 #include "cnmf_internal.hpp"
 #include "small_dense.hpp"
 
@@ -258,145 +259,36 @@ __global__ __launch_bounds__(kRedNT) void admm_reduce_batch_kernel(const AdmmJob
   admm_reduce_body(J.Pp, J.parts0, J.parts1, kr, J.Pred, nbh, (int)blockIdx.x - red_first[j], red);
 }
 
-// The two r x r solves of one iteration in one workgroup.  XY: [0] Xt
+// The two r x r solves of one iteration run in one workgroup.  XY: [0] Xt
 // (k x r), [1] Yt^T (k x r), FP64.  first != 0: Yt^T = P_V / phi before the
 // Xt solve (Alg. 3 initialisation Yt = V R^T, the partial having been
-// formed as R (phi V^T)).  The systems are padded to N = 16 ceil(r / 16)
-// with an identity block and solved by the blocked Cholesky in LDS.
+// formed as R (phi V^T)).
 constexpr int kSolveNT = 256;
 
-__device__ __forceinline__ void admm_solve_body(const double* __restrict__ Pred, const double* __restrict__ At,
-                                                int k, int r, double lam, double phi, int first,
-                                                double* __restrict__ XY, int* flags, int at_in_lds, double* sm) {
-  constexpr int NT = kSolveNT;
-  const int tid = threadIdx.x;
-  const int64_t kr = (int64_t)k * r;
-  const int NB = (r + 15) / 16, N = 16 * NB, ld = N + 1;
-  double* Y = sm;                  // Yt^T, k x ld
-  double* X = Y + k * ld;          // Xt / RHS, k x ld
-  double* Mm = X + k * ld;         // N x ld: system matrix, then its factor
-  double* TI = Mm + N * ld;        // NB x 16 x 17
-  double* PN = TI + NB * 272;      // 16 x ld
-  double* Rs = PN + 16 * ld;       // k x 17
-  double* Ats = Rs + k * 17;       // k x k when at_in_lds
-  const double* Aa = at_in_lds ? Ats : At;
-  const double* PU = Pred;
-  const double* PV = Pred + kr;
-  for (int e = tid; e < k * N; e += NT) {
-    int i = e / N, c = e - i * N;
-    Y[i * ld + c] = c < r ? (first ? PV[i * r + c] / phi : XY[kr + i * r + c]) : 0.0;
-  }
-  if (at_in_lds)
-    for (int e = tid; e < k * k; e += NT) Ats[e] = At[e];
-  __syncthreads();
-  // pass 0: Xt from (At, Yt, P_U, lam); pass 1: Yt^T from (At^T, Xt, P_V, phi)
-  for (int pass = 0; pass < 2; ++pass) {
-    const double* S = pass ? X : Y;     // k x ld (the other factor)
-    double* D = pass ? Y : X;           // RHS, then the solution
-    const double* P = pass ? PV : PU;
-    const double pen = pass ? phi : lam;
-    // system matrix S^T S + pen I (padded with I), 4 x 4 tiles of the upper
-    // block triangle
-    const int NQ = N / 4;
-    for (int e = tid; e < NQ * NQ; e += NT) {
-      const int ta = e / NQ, tb = e - ta * NQ;
-      if (tb < ta) continue;
-      double acc[4][4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-#pragma unroll 4
-      for (int l = 0; l < k; ++l) {
-        const double* sl = S + l * ld;
-        double x[4], y[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          x[u] = sl[4 * ta + u];
-          y[u] = sl[4 * tb + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] = fma(x[u], y[v], acc[u][v]);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = 4 * ta + u, b = 4 * tb + v;
-          if (b < a) continue;
-          const double val = acc[u][v] + (a == b ? (a < r ? pen : 1.0) : 0.0);
-          Mm[a * ld + b] = val;
-          Mm[b * ld + a] = val;
-        }
-    }
-    // RHS = At S + P (pass 0) or At^T S + P (pass 1), zero padding; 4 x 4 tiles
-    const int KQ = (k + 3) / 4;
-    for (int e = tid; e < KQ * NQ; e += NT) {
-      const int ta = e / NQ, tc = e - ta * NQ;
-      double acc[4][4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-#pragma unroll 4
-      for (int l = 0; l < k; ++l) {
-        double x[4], y[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int a = min(4 * ta + u, k - 1);
-          x[u] = pass == 0 ? Aa[a * k + l] : Aa[l * k + a];
-          y[u] = S[l * ld + 4 * tc + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] = fma(x[u], y[v], acc[u][v]);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = 4 * ta + u, c = 4 * tc + v;
-          if (a < k) D[a * ld + c] = c < r ? acc[u][v] + P[a * r + c] : 0.0;
-        }
-    }
-    __syncthreads();
-    double mx = 0.0;
-    for (int i = 0; i < r; ++i) mx = fmax(mx, Mm[i * ld + i]);
-    wg_chol_blocked<NT>(Mm, ld, NB, TI, PN, 1e-300 * mx, flags);
-    wg_right_solve_blocked<NT>(D, k, ld, NB, Mm, ld, TI, Rs);
-    double* out = XY + (pass ? kr : 0);
-    for (int e = tid; e < kr; e += NT) {
-      int i = e / r, c = e - i * r;
-      out[e] = D[i * ld + c];
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// The same two solves by a direct Cholesky factorisation, every product on
-// the FP64 MFMA (r <= 64, k <= 128).  Per side, with the system padded to
-// N = 16 ceil(r / 16) by an identity block, X M = RHS is solved as
+// The solves by a direct Cholesky factorisation, every product on the FP64
+// MFMA (r <= 64, k <= 128 within the LDS budget).  Per side, with the system
+// padded to N = 16 ceil(r / 16) by an identity block, X M = RHS is solved as
 // M X^T = RHS^T:
-//   (a) all waves: M = S^T S + pen I (wave w: block row w), and each wave's
-//       16-column strips of RHS^T = S^T At^T + P^T (pass 0) or
-//       S^T At + P^T (pass 1), kept in registers;
+//   (a) all waves: M = S^T S + pen I (wave w: block row w);
 //   (b) wave 0: M = L L^T (wave_chol_lower: 16-column panels in registers,
-//       MFMA trailing updates, inverses V_b of the diagonal blocks);
-//   (c) each wave on its strips, still in registers:
+//       MFMA trailing updates, inverses V_b of the diagonal blocks); waves
+//       1-3 meanwhile form the 16-row strips of RHS = At S + P (pass 0) or
+//       At^T S + P (pass 1) into E;
+//   (c) each wave, on its strips (one 16-row block of X, as X^T tiles in
+//       registers):
 //         W_b = V_b (RHS^T_b - sum_{a<b} L[b][a] W_a),        b ascending,
 //         X^T_b = V_b^T (W_b - sum_{a>b} L[a][b]^T X^T_a),    b descending.
 // A 16x16x4 FP64 MFMA leaves item i of lane (c, g) at row g + 4 i, column c
 // of its tile, which is where the next product takes its right operand for
-// K step i, so the strips never leave the registers; L and V come from LDS.
+// K step i, so a strip stays in registers through both substitutions; L and
+// V come from LDS.
 // ---------------------------------------------------------------------------
 constexpr int kCholMaxK = 128;
 
 struct CholLayout {
-  int NB, N, ld, kp, KB16, lda;
-  size_t s_off, m_off, v_off, w_off, a_off, total;  // in doubles
+  int NB, N, ld, kp, KB16;
+  size_t s_off, e_off, m_off, v_off, w_off, total;  // in doubles
 };
 __host__ __device__ inline CholLayout chol_layout(int k, int r) {
   CholLayout L;
@@ -405,18 +297,16 @@ __host__ __device__ inline CholLayout chol_layout(int k, int r) {
   L.ld = L.N + 2;
   L.KB16 = (k + 15) / 16;
   L.kp = 16 * L.KB16;
-  L.lda = L.kp + 1;
   L.s_off = 0;
-  L.m_off = L.s_off + (size_t)L.kp * L.ld;
+  L.e_off = L.s_off + (size_t)L.kp * L.ld;
+  L.m_off = L.e_off + (size_t)L.kp * L.ld;
   L.v_off = L.m_off + (size_t)L.N * L.ld;
   L.w_off = L.v_off + (size_t)L.NB * 272;
-  L.a_off = L.w_off + 128;
-  L.total = L.a_off + (size_t)L.kp * L.lda;
+  L.total = L.w_off + 128;
   return L;
 }
-static bool chol_fits(int k, int r) {
-  return k <= kCholMaxK && r <= 64 && chol_layout(k, r).total * sizeof(double) <= 160 * 1024;
-}
+
+size_t admm_solve_lds_bytes(int k, int r) { return chol_layout(k, r).total * sizeof(double); }
 
 // K loop over the kp rows of S (LDS, row stride ld) in chunks of 16 rows;
 // the next chunk's operands are loaded (row clamped into S) before this
@@ -455,42 +345,57 @@ __device__ __forceinline__ void s_chunks(const double* S, int ld, int kp, int c,
   }
 }
 
-template <int NB>
-__device__ __forceinline__ void admm_solve_chol_nb(const double* __restrict__ Pred, const double* __restrict__ At,
-                                                   int k, int r, double lam, double phi, int first,
-                                                   double* __restrict__ XY, int* flags, double* sm) {
-  constexpr int NT = kSolveNT;
-  constexpr int N = 16 * NB;
-  const CholLayout Ly = chol_layout(k, r);
-  const int ld = Ly.ld, kp = Ly.kp, KB16 = Ly.KB16, lda = Ly.lda;
+// One side of the iteration: PASS 0 solves for Xt (S = Yt^T, At), PASS 1
+// for Yt^T (S = Xt, At^T).  Starts after a barrier, ends with one.
+template <int NB, int PASS>
+__device__ __forceinline__ void chol_side(const double* __restrict__ At, const double* __restrict__ P, int k, int r,
+                                          double pen, double* __restrict__ out, int* flags, const CholLayout& Ly,
+                                          double* sm) {
+  constexpr int KS = kCholMaxK / 4;
+  const int ld = Ly.ld, kp = Ly.kp, KB16 = Ly.KB16;
   double* S = sm + Ly.s_off;
+  double* E = sm + Ly.e_off;
   double* Mb = sm + Ly.m_off;
   double* V = sm + Ly.v_off;
   double* W = sm + Ly.w_off;
-  double* Al = sm + Ly.a_off;   // At, kp x lda, zero padded
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = lane & 15, g = lane >> 4;
-  const int64_t kr = (int64_t)k * r;
-  // S = Yt^T (k x r, zero padded to kp x N); At into LDS
-  for (int e = tid; e < kp * N; e += NT) {
-    const int i = e / N, j = e - i * N;
-    S[i * ld + j] = (i < k && j < r) ? (first ? Pred[kr + i * r + j] / phi : XY[kr + i * r + j]) : 0.0;
-  }
-  for (int e = tid; e < kp * kp; e += NT) {
-    const int i = e / kp, j = e - i * kp;
-    Al[i * lda + j] = (i < k && j < k) ? At[i * k + j] : 0.0;
+  // (a) block row w of M = S^T S + pen I_r (identity on the padding)
+  if (w < NB) {
+    doublex4 am[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) am[b] = doublex4{0.0, 0.0, 0.0, 0.0};
+    s_chunks<NB>(S, ld, kp, c, g, [&](int kk) { return S[kk * ld + 16 * w + c]; },
+                 [&](int, const double* sv, double sx) {
+#pragma unroll
+                   for (int b = 0; b < NB; ++b) am[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sx, sv[b], am[b], 0, 0, 0);
+                 });
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * w + g + 4 * i, col = 16 * b + c;
+        Mb[row * ld + col] = am[b][i] + (row == col ? (row < r ? pen : 1.0) : 0.0);
+      }
   }
   __syncthreads();
-  // strips of X^T (16 columns = 16 rows of X): strip rb belongs to wave
-  // 3 - (rb % 4), so wave 0, which factors M, has at most one for k <= 112
-  const int rb0 = 3 - w, rb1 = 7 - w;
-  for (int pass = 0; pass < 2; ++pass) {
-    const double pen = pass ? phi : lam;
-    const double* P = Pred + (pass ? kr : 0);
-    double* out = XY + (pass ? kr : 0);
-    // RHS^T strip rb = S^T At^T + P^T (pass 0) or S^T At + P^T (pass 1)
-    auto rhs_strip = [&](int rb, doublex4 (&z)[NB]) {
+  if (w == 0) {
+    // (b) the factor; pivots below 1e-300 max diag(M) are floored
+    double dg = lane < r ? Mb[lane * ld + lane] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o));
+    wave_chol_lower<NB>(Mb, ld, r, V, W, 1e-300 * dg, flags);
+  } else {
+    // (b) strips of RHS into E (kp x ld, row xr = 16 rb + c): the lane's At
+    // and P values are loaded up front, then RHS^T tiles = S^T At^T (+ P^T)
+    for (int rb = w - 1; rb < KB16; rb += 3) {
       const int xr = 16 * rb + c;
+      double at[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int kk = 4 * s + g;
+        at[s] = (xr < k && kk < k) ? (PASS == 0 ? At[xr * k + kk] : At[kk * k + xr]) : 0.0;
+      }
       double pv[NB][4];
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -502,19 +407,28 @@ __device__ __forceinline__ void admm_solve_chol_nb(const double* __restrict__ Pr
       doublex4 acc[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) acc[b] = doublex4{0.0, 0.0, 0.0, 0.0};
-      s_chunks<NB>(S, ld, kp, c, g, [&](int kk) { return pass == 0 ? Al[xr * lda + kk] : Al[kk * lda + xr]; },
-                   [&](int, const double* sv, double sx) {
+      s_chunks<NB>(S, ld, kp, c, g, [](int) { return 0.0; }, [&](int s, const double* sv, double) {
 #pragma unroll
-                     for (int b = 0; b < NB; ++b)
-                       acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sv[b], sx, acc[b], 0, 0, 0);
-                   });
+        for (int b = 0; b < NB; ++b) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sv[b], at[s], acc[b], 0, 0, 0);
+      });
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) z[b][i] = acc[b][i] + pv[b][i];
-    };
-    // block substitutions on one strip, in registers; X rows to XY
-    auto solve_strip = [&](int rb, doublex4 (&z)[NB]) {
+        for (int i = 0; i < 4; ++i) E[xr * ld + 16 * b + g + 4 * i] = acc[b][i] + pv[b][i];
+    }
+  }
+  __syncthreads();
+  // (c) substitutions; strip rb belongs to wave 3 - (rb % 4)
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int rb = 4 * q + 3 - w;
+    if (rb < KB16) {
+      const int xr = 16 * rb + c;
+      doublex4 z[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) z[b][i] = E[xr * ld + 16 * b + g + 4 * i];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         doublex4 t = z[b];
@@ -543,70 +457,38 @@ __device__ __forceinline__ void admm_solve_chol_nb(const double* __restrict__ Pr
           x = __builtin_amdgcn_mfma_f64_16x16x4f64(V[b * 272 + (4 * s + g) * 17 + c], t[s], x, 0, 0, 0);
         z[b] = x;
       }
-      const int xr = 16 * rb + c;
+      // X[xr][16 b + g + 4 i] = item i of tile b: to XY and, for pass 0,
+      // into S for the other side (no wave reads S in this phase)
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int col = 16 * b + g + 4 * i;
           if (xr < k && col < r) out[xr * r + col] = z[b][i];
-        }
-    };
-    auto strip_to_s = [&](int rb, const doublex4 (&z)[NB]) {
-      const int xr = 16 * rb + c;
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) S[xr * ld + 16 * b + g + 4 * i] = z[b][i];
-    };
-    // (a) block row w of M and the first strip of RHS^T
-    if (w < NB) {
-      doublex4 am[NB];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) am[b] = doublex4{0.0, 0.0, 0.0, 0.0};
-      s_chunks<NB>(S, ld, kp, c, g, [&](int kk) { return S[kk * ld + 16 * w + c]; },
-                   [&](int, const double* sv, double sx) {
-#pragma unroll
-                     for (int b = 0; b < NB; ++b)
-                       am[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sx, sv[b], am[b], 0, 0, 0);
-                   });
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = 16 * w + g + 4 * i, col = 16 * b + c;
-          Mb[row * ld + col] = am[b][i] + (row == col ? (row < r ? pen : 1.0) : 0.0);
+          if (PASS == 0) S[xr * ld + col] = z[b][i];
         }
     }
-    doublex4 z0[NB];
-    if (rb0 < KB16) rhs_strip(rb0, z0);
-    __syncthreads();
-    // (b) the factor; pivots below 1e-300 max diag(M) are floored
-    if (w == 0) {
-      double dg = lane < r ? Mb[lane * ld + lane] : 0.0;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o));
-      wave_chol_lower<NB>(Mb, ld, r, V, W, 1e-300 * dg, flags);
-    }
-    __syncthreads();
-    // (c) substitutions; a second strip (k > 64) is formed and solved after
-    // the first, S being overwritten (pass 0) only once every strip is formed
-    if (rb0 < KB16) solve_strip(rb0, z0);
-    if (rb1 < KB16) {
-      doublex4 z1[NB];
-      rhs_strip(rb1, z1);
-      solve_strip(rb1, z1);
-      if (pass == 0) {
-        __syncthreads();
-        if (rb0 < KB16) strip_to_s(rb0, z0);
-        strip_to_s(rb1, z1);
-      }
-    } else if (pass == 0) {
-      if (KB16 > 4) __syncthreads();
-      if (rb0 < KB16) strip_to_s(rb0, z0);
-    }
-    __syncthreads();
   }
+  __syncthreads();
+}
+
+template <int NB>
+__device__ __forceinline__ void admm_solve_chol_nb(const double* __restrict__ Pred, const double* __restrict__ At,
+                                                   int k, int r, double lam, double phi, int first,
+                                                   double* __restrict__ XY, int* flags, double* sm) {
+  constexpr int NT = kSolveNT;
+  constexpr int N = 16 * NB;
+  const CholLayout Ly = chol_layout(k, r);
+  double* S = sm + Ly.s_off;
+  const int64_t kr = (int64_t)k * r;
+  // S = Yt^T (k x r, zero padded to kp x N)
+  for (int e = threadIdx.x; e < Ly.kp * N; e += NT) {
+    const int i = e / N, j = e - i * N;
+    S[i * Ly.ld + j] = (i < k && j < r) ? (first ? Pred[kr + i * r + j] / phi : XY[kr + i * r + j]) : 0.0;
+  }
+  __syncthreads();
+  chol_side<NB, 0>(At, Pred, k, r, lam, XY, flags, Ly, sm);
+  chol_side<NB, 1>(At, Pred + kr, k, r, phi, XY + kr, flags, Ly, sm);
 }
 
 __device__ __forceinline__ void admm_solve_chol_body(const double* __restrict__ Pred, const double* __restrict__ At,
@@ -628,55 +510,27 @@ __global__ __launch_bounds__(kSolveNT) void admm_solve_chol_kernel(const double*
   admm_solve_chol_body(Pred, At, k, r, lam, phi, first, XY, flags, sm);
 }
 
-__global__ __launch_bounds__(kSolveNT) void admm_solve_kernel(const double* __restrict__ Pred,
-                                                              const double* __restrict__ At, int k, int r,
-                                                              double lam, double phi, int first,
-                                                              double* __restrict__ XY, int* flags, int at_in_lds) {
-  extern __shared__ double sm[];
-  admm_solve_body(Pred, At, k, r, lam, phi, first, XY, flags, at_in_lds, sm);
-}
-
 // One workgroup per job.
 __global__ __launch_bounds__(kSolveNT) void admm_solve_batch_kernel(const AdmmJob* __restrict__ jobs) {
   extern __shared__ double sm[];
   const AdmmJob& J = jobs[blockIdx.x];
-  if (J.k <= kCholMaxK && chol_layout(J.k, J.r).total * sizeof(double) <= 160 * 1024)
-    admm_solve_chol_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.flags, sm);
-  else
-    admm_solve_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.flags, J.at_in_lds, sm);
-}
-
-static size_t admm_solve_lds(int k, int r, bool with_at) {
-  const int NB = (r + 15) / 16, N = 16 * NB, ld = N + 1;
-  size_t d = 2 * (size_t)k * ld + (size_t)N * ld + (size_t)NB * 272 + 16 * (size_t)ld + (size_t)k * 17;
-  if (with_at) d += (size_t)k * k;
-  return d * sizeof(double);
+  admm_solve_chol_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.flags, sm);
 }
 
 template <typename T>
 hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const double* At, int k, int r,
                              double lam, double phi, int first, double* XY, double* Pred, int* flags,
                              hipStream_t st) {
-  if (r > 64 || k > 128) return hipErrorInvalidValue;
-  const size_t cap = 160 * 1024;
+  if (r > 64 || k > kCholMaxK || admm_solve_lds_bytes(k, r) > 160 * 1024) return hipErrorInvalidValue;
   int64_t kr = (int64_t)k * r;
   int nbh = (int)((kr + kRedEPB - 1) / kRedEPB);
   hipLaunchKernelGGL(admm_reduce_kernel, dim3(2 * nbh), dim3(kRedNT), 0, st, Pp, parts0, parts1, kr, Pred);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (chol_fits(k, r)) {
-    const size_t sm = chol_layout(k, r).total * sizeof(double);
-    hipFuncSetAttribute((const void*)admm_solve_chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    hipLaunchKernelGGL(admm_solve_chol_kernel, dim3(1), dim3(kSolveNT), sm, st, Pred, At, k, r, lam, phi, first, XY,
-                       flags);
-    CNMF_LAUNCH_CHECK();
-  }
-  int at_in_lds = admm_solve_lds(k, r, true) <= cap;
-  size_t sm = admm_solve_lds(k, r, at_in_lds);
-  if (sm > cap) return hipErrorInvalidValue;
-  hipFuncSetAttribute((const void*)admm_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  hipLaunchKernelGGL(admm_solve_kernel, dim3(1), dim3(kSolveNT), sm, st, Pred, At, k, r, lam, phi, first, XY, flags,
-                     at_in_lds);
+  const size_t sm = chol_layout(k, r).total * sizeof(double);
+  hipFuncSetAttribute((const void*)admm_solve_chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  hipLaunchKernelGGL(admm_solve_chol_kernel, dim3(1), dim3(kSolveNT), sm, st, Pred, At, k, r, lam, phi, first, XY,
+                     flags);
   CNMF_LAUNCH_CHECK();
 }
 template hipError_t launch_admm_solve<float>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, int*, hipStream_t);
@@ -691,7 +545,6 @@ template hipError_t launch_admm_solve<double>(const double*, int, int, const dou
 void admm_job_prepare(AdmmJob& J) {
   J.rpb0 = (J.s0.rows + J.parts0 - 1) / J.parts0;
   J.rpb1 = (J.s1.rows + J.parts1 - 1) / J.parts1;
-  J.at_in_lds = admm_solve_lds(J.k, J.r, true) <= 160 * 1024;
 }
 
 int admm_job_uv_blocks(const AdmmJob& J) { return J.parts0 + J.parts1; }
@@ -721,8 +574,7 @@ hipError_t launch_admm_step_batch(const AdmmJob* jobs_dev, const int* uv_first_d
 }
 
 size_t admm_job_solve_lds(const AdmmJob& J) {
-  if (chol_fits(J.k, J.r)) return chol_layout(J.k, J.r).total * sizeof(double);
-  return admm_solve_lds(J.k, J.r, J.at_in_lds != 0);
+  return chol_layout(J.k, J.r).total * sizeof(double);
 }
 
 }  // namespace cnmf

@@ -1192,6 +1192,9 @@ static cnmf_status check_factorize(cnmf_handle* h, const cnmf_input* A, const cn
   if (!(d->mu_eps >= 0)) return fail(h, CNMF_EINVAL, "mu_eps must be >= 0");
   if (!d->U0_dev || !d->V0_dev) return fail(h, CNMF_EINVAL, "U0_dev and V0_dev are required");
   if (d->sk.r > 64) return fail(h, CNMF_ENOTSUP, "r=%d > 64 is not supported by the NMF iterations", d->sk.r);
+  if (d->method == CNMF_ADMM && admm_solve_lds_bytes(d->sk.k, d->sk.r) > 160 * 1024)
+    return fail(h, CNMF_ENOTSUP, "compressed ADMM at r=%d, k=%d needs more than 160 KiB of LDS (k <= 112 for r > 48)",
+                d->sk.r, d->sk.k);
   return CNMF_OK;
 }
 

@@ -1,6 +1,7 @@
-// Workgroup-level FP64 building blocks for the small (<= 128 x 128) dense
-// steps: fixed-order reduction of per-block partial sums, and an in-LDS
-// Cholesky factorisation with the inverse of its triangular factor.
+// FP64 building blocks for the small (<= 128 x 128) dense steps: fixed-order
+// reduction of per-block partial sums, blocked in-LDS Cholesky factorisations
+// with the inverses of their triangular factors, and a single-wave Cholesky
+// whose products run on the FP64 MFMA.
 #pragma once
 
 #include "cnmf_internal.hpp"
@@ -39,142 +40,6 @@ __device__ __forceinline__ void block_sum_parts(const double* __restrict__ in, i
     __syncthreads();
   }
   if (pg == 0 && e < count) out[e] = red[el];
-  __syncthreads();
-}
-
-// In-LDS Cholesky of the symmetric positive definite n x n matrix M (row
-// stride ld, upper triangle read): M = T^T T with T upper triangular and a
-// positive diagonal.  On return
-//   Td[i]            = T[i][i]
-//   M[l][i] (l > i)  = T[i][l]           (strict lower triangle, transposed)
-//   M[i][j] (j >= i) = Tinv[i][j]        (upper triangle: inverse of T)
-// A pivot <= floor (or not finite) is replaced by floor and counted in *flag.
-// One barrier per elimination step.
-template <int NT>
-__device__ void wg_cholesky_inverse(double* M, int n, int ld, double* Td, double floor_piv, int* flag) {
-  const int tid = threadIdx.x;
-  constexpr int TW = 32;
-  constexpr int TH = NT / TW;
-  const int tx = tid % TW, ty = tid / TW;
-  for (int j = 0; j < n; ++j) {
-    __syncthreads();
-    double d = M[j * ld + j];
-    if (!(d > floor_piv) || !isfinite(d)) {
-      if (tid == 0 && flag) atomicAdd(flag, 1);
-      d = floor_piv > 0.0 ? floor_piv : 1.0;
-    }
-    const double t = sqrt(d);
-    const double inv_d = 1.0 / d;
-    if (tid == 0) Td[j] = t;
-    for (int b = j + 1 + tid; b < n; b += NT) M[b * ld + j] = M[j * ld + b] / t;
-    for (int a = j + 1 + ty; a < n; a += TH) {
-      const double mja = M[j * ld + a] * inv_d;
-      for (int b = j + 1 + tx; b < n; b += TW)
-        if (b >= a) M[a * ld + b] -= mja * M[j * ld + b];
-    }
-  }
-  __syncthreads();
-  // Tinv rows from the bottom: Ti[i][i] = 1/T_ii,
-  // Ti[i][j] = -(sum_{l = i+1..j} T[i][l] Ti[l][j]) / T_ii   (j > i).
-  // Eight threads per column j, combined by a fixed butterfly.
-  constexpr int GS = 8;
-  const int gl = tid % GS, col = tid / GS;
-  for (int i = n - 1; i >= 0; --i) {
-    const double inv_t = 1.0 / Td[i];
-    for (int j0 = i; j0 < n; j0 += NT / GS) {
-      const int j = j0 + col;
-      double s = 0.0;
-      if (j < n && j > i)
-        for (int l = i + 1 + gl; l <= j; l += GS) s = fma(M[l * ld + i], M[l * ld + j], s);
-      s += __shfl_xor(s, 1, GS);
-      s += __shfl_xor(s, 2, GS);
-      s += __shfl_xor(s, 4, GS);
-      if (gl == 0 && j < n) M[i * ld + j] = (j == i) ? inv_t : -s * inv_t;
-    }
-    __syncthreads();
-  }
-}
-
-}  // namespace cnmf
-
-namespace cnmf {
-
-// Single-wave Cholesky (no inverse): M = T^T T, T upper, positive diagonal.
-// Called by the 64 lanes of ONE wave.  On return Td[i] = T[i][i] and
-// M[l][i] = T[i][l] for l > i (strict lower triangle, transposed).  The
-// trailing update of each step is spread over all lanes (lane = (ty, tx),
-// 8 x 8); a wave runs in lockstep and its LDS operations complete in order,
-// so steps need no barrier.
-__device__ void wave_cholesky(double* M, int n, int ld, double* Td, double floor_piv, int* flag) {
-  const int lane = threadIdx.x & 63;
-  const int tx = lane & 7, ty = lane >> 3;
-  for (int j = 0; j < n; ++j) {
-    double d = M[j * ld + j];
-    if (!(d > floor_piv) || !isfinite(d)) {
-      if (lane == 0 && flag) atomicAdd(flag, 1);
-      d = floor_piv > 0.0 ? floor_piv : 1.0;
-    }
-    const double t = sqrt(d);
-    const double inv_d = 1.0 / d;
-    if (lane == 0) Td[j] = t;
-    for (int b = j + 1 + lane; b < n; b += 64) M[b * ld + j] = M[j * ld + b] / t;
-    for (int a = j + 1 + ty; a < n; a += 8) {
-      const double mja = M[j * ld + a] * inv_d;
-      for (int b = a + tx; b < n; b += 8) M[a * ld + b] = fma(-mja, M[j * ld + b], M[a * ld + b]);
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
-// 32-bit DPP move on the two halves of a double.
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double x) {
-  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
-  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-// Sum over aligned groups of 8 lanes (swap-1, swap-2 within quads, then the
-// mirror within each half-row of 8).  Every lane gets its group's sum.
-__device__ __forceinline__ double group8_sum(double x) {
-  x += dpp_d<0xB1>(x);   // quad_perm [1,0,3,2]
-  x += dpp_d<0x4E>(x);   // quad_perm [2,3,0,1]
-  x += dpp_d<0x141>(x);  // row_half_mirror
-  return x;
-}
-
-// X (rows x r, LDS, row stride r) <- X (T^T T)^-1 for the factor left by
-// wave_cholesky: forward substitution Z T = X, then backward W T^T = Z, in
-// place.  Eight lanes per row (DPP sums); the groups of a wave are
-// independent rows, so no block barrier is needed inside.  Requires
-// rows <= blockDim / 8; ends with a block barrier.
-template <int NT>
-__device__ void wg_right_solve_chol(double* X, int rows, int r, const double* M, int ld, const double* Td) {
-  constexpr int GS = 8;
-  const int tid = threadIdx.x;
-  const int gl = tid % GS, row = tid / GS;
-  const bool act = row < rows;
-  double* x = X + (act ? row : 0) * r;
-  // forward: z[c] = (x[c] - sum_{l<c} z[l] T[l][c]) / T[c][c],  T[l][c] = M[c][l]
-  for (int c = 0; c < r; ++c) {
-    double s = 0.0;
-    if (act)
-      for (int l = gl; l < c; l += GS) s = fma(x[l], M[c * ld + l], s);
-    s = group8_sum(s);
-    if (act && gl == 0) x[c] = (x[c] - s) / Td[c];
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-  }
-  // backward: w[c] = (z[c] - sum_{l>c} w[l] T[c][l]) / T[c][c],  T[c][l] = M[l][c]
-  for (int c = r - 1; c >= 0; --c) {
-    double s = 0.0;
-    if (act)
-      for (int l = c + 1 + gl; l < r; l += GS) s = fma(x[l], M[l * ld + c], s);
-    s = group8_sum(s);
-    if (act && gl == 0) x[c] = (x[c] - s) / Td[c];
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-  }
   __syncthreads();
 }
 
@@ -254,99 +119,6 @@ __device__ __forceinline__ double rsqrt_refined(double d) {
   y = y * fma(-h * y, y, 1.5);
   y = y * fma(-h * y, y, 1.5);
   return y;
-}
-
-// x from lane `src` (any lane; every lane may name a different source).
-__device__ __forceinline__ double bperm_d(double x, int src) {
-  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(x));
-  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(x));
-  return __hiloint2double(hi, lo);
-}
-
-// The same contract as wave_diag16 with a quad layout: lane 4 i + q holds
-// D[i][4q .. 4q + 3].  Step j: the pivot comes by readlane, 1/sqrt by a
-// refined reciprocal square root, column j within each quad by DPP and row
-// j by bpermute, so each step is a short dependent chain.  T^-1 follows
-// column by column, S[:, j] = (e_j - S[:, <j] T[<j, j]) / T[j][j], with the
-// row sums reduced inside the quads.
-template <int J>
-__device__ __forceinline__ double quad_bcast_d(double x) {
-  constexpr int ctrl = J | (J << 2) | (J << 4) | (J << 6);
-  return dpp_d<ctrl>(x);
-}
-
-__device__ void wave_diag16_quad(double* D, int ldd, double* TI, double floor_piv, int* flag) {
-  const int lane = threadIdx.x & 63;
-  const int i = lane >> 2, q = lane & 3;
-  double a[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) a[e] = D[i * ldd + 4 * q + e];
-  double ys[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int jq = j >> 2, je = j & 3;
-    double d = readlane_d(a[je], 4 * j + jq);
-    if (!(d > floor_piv) || !isfinite(d)) {
-      if (lane == 0 && flag) atomicAdd(flag, 1);
-      d = floor_piv > 0.0 ? floor_piv : 1.0;
-    }
-    const double y = rsqrt_refined(d);
-    ys[j] = y;
-    double mij;
-    switch (jq) {
-      case 0: mij = quad_bcast_d<0>(a[je]); break;
-      case 1: mij = quad_bcast_d<1>(a[je]); break;
-      case 2: mij = quad_bcast_d<2>(a[je]); break;
-      default: mij = quad_bcast_d<3>(a[je]); break;
-    }
-    double rj[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) rj[e] = bperm_d(a[e], 4 * j + q);
-    const double f = mij * (y * y);
-    if (i > j) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (4 * q + e > j) a[e] = fma(-f, rj[e], a[e]);
-    } else if (i == j) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int c = 4 * q + e;
-        if (c > j) a[e] *= y;
-        else if (c == j) a[e] = d * y;
-      }
-    }
-  }
-  // T (upper, zeros below) back to D
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int c = 4 * q + e;
-    D[i * ldd + c] = c >= i ? a[e] : 0.0;
-  }
-  // S = T^-1, column by column
-  double sv[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int jq = j >> 2, je = j & 3;
-    double p = 0.0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int l = 4 * q + e;
-      const double tlj = bperm_d(a[je], 4 * l + jq);   // T[l][j], held by lane (l, jq)
-      if (l < j) p = fma(sv[e], tlj, p);
-    }
-    p += dpp_d<0xB1>(p);
-    p += dpp_d<0x4E>(p);
-    const double sij = i <= j ? ((i == j ? 1.0 : 0.0) - p) * ys[j] : 0.0;
-    if (q == jq) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (e == je) sv[e] = sij;
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) TI[i * 17 + 4 * q + e] = sv[e];
-  __builtin_amdgcn_s_waitcnt(0);
-  __builtin_amdgcn_wave_barrier();
 }
 
 // M (N x N, LDS, row stride ldm, full symmetric) = T^T T.  On return the
@@ -696,7 +468,7 @@ __device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double
   double* colbuf = W;       // the current column of L
   double* dinv = W + 64;    // 1 / L[i][i]
   int nbad = 0;
-#pragma unroll
+#pragma unroll 1
   for (int P = 0; P < NB; ++P) {
     const int c0 = 16 * P;
     const bool act = lane >= c0 && lane < N;

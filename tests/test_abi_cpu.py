@@ -99,6 +99,21 @@ def test_factorize_parameter_checks(lib):
     assert lib.cnmf_factorize(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
 
 
+@pytest.mark.parametrize("r,k,ok", [(64, 112, True), (48, 128, True), (64, 113, False), (64, 128, False)])
+def test_admm_solve_lds_limit(lib, r, k, ok):
+    # the r x r solves of one iteration run in one workgroup's LDS
+    A = L.cnmf_input(C.c_void_p(16), L.CNMF_F32, 2000, 1000, 1000)
+    d = _desc(r=r, k=k)
+    out = L.cnmf_factorize_out()
+    st = lib.cnmf_factorize(None, C.byref(A), C.byref(d), C.byref(out))
+    if ok:
+        assert st == L.CNMF_EINVAL and b"handle" in lib.cnmf_last_error(None)
+    else:
+        assert st == L.CNMF_ENOTSUP and b"LDS" in lib.cnmf_last_error(None)
+    d.method = L.CNMF_MU
+    assert lib.cnmf_factorize(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
+
+
 def test_python_binding_fails_loudly_without_library(tmp_path):
     with pytest.raises(FileNotFoundError):
         L._lib_backup = L._lib

@@ -110,6 +110,26 @@ def test_factorize_admm_fp64_parity(c1):
     assert abs(float(host(f.rel_residual)[0]) - res) <= 1e-10 * res
 
 
+# The r x r solves across block counts (r up to 64) and sketch widths (k up to
+# 128): one and two 16-row strips of X per wave, up to the largest shapes the
+# single-workgroup solve holds in LDS.
+@pytest.mark.parametrize("m,n,r,k", [(420, 300, 5, 9), (500, 400, 37, 47), (500, 400, 48, 80), (500, 400, 64, 74),
+                                     (500, 400, 20, 100), (500, 400, 64, 112), (500, 400, 48, 128)])
+def test_factorize_admm_fp64_solve_shapes(m, n, r, k):
+    A = WL.nmf_matrix(m, n, r, 0.05, seed=31 + r, dtype=np.float64)
+    g = np.random.default_rng(41 + k)
+    oml, omr = g.standard_normal((n, k)), g.standard_normal((m, k))
+    U1, V1 = WL.init_factors(float(A.mean()), m, n, r, 51 + r)
+    q, iters = 1, 15
+    sk = O.sketch(A, oml, omr, q)
+    lam = float(np.linalg.svd(sk["At"], compute_uv=False)[r - 1])
+    ref = O.admm(sk["At"], sk["L"], sk["R"], U1, V1, lam, 0.7 * lam, 1.0, iters)
+    f = api.factorize(dev(A), r, k, q, dev(U1), dev(V1), dev(oml), dev(omr), method="admm", iters=iters, lam=lam,
+                      phi=0.7 * lam)
+    assert rel(host(f.U), ref["U"]) < 1e-10
+    assert rel(host(f.V), ref["V"]) < 1e-10
+
+
 @pytest.mark.parametrize("sides", ["left", "right"])
 @pytest.mark.parametrize("q", [0, 1, 3])
 def test_sketch_one_sided_ragged_fp64(sides, q):
