@@ -111,16 +111,6 @@ __device__ void wave_diag16(double* D, int ldd, double* TI, double floor_piv, in
   __builtin_amdgcn_wave_barrier();
 }
 
-// 1 / sqrt(d) for d > 0: the hardware estimate refined by two Newton steps
-// y <- y (3/2 - d y^2 / 2) (each step squares the relative error).
-__device__ __forceinline__ double rsqrt_refined(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-  const double h = 0.5 * d;
-  y = y * fma(-h * y, y, 1.5);
-  y = y * fma(-h * y, y, 1.5);
-  return y;
-}
-
 // M (N x N, LDS, row stride ldm, full symmetric) = T^T T.  On return the
 // upper block triangle of M holds T (diagonal blocks upper triangular),
 // TI[jb] (16 x 17 each) the inverses of the diagonal blocks.  PN: 16 x ldm
@@ -385,30 +375,21 @@ __device__ void wg_right_solve_blocked(double* X, int rows, int ldx, int NB, con
 }
 
 
-// ---------------------------------------------------------------------------
-// One wave, no barriers: M (N x N, N = 16 NB <= 64, LDS, row stride ld) =
-// L L^T with L lower triangular and a positive diagonal.  Read: the lower
-// triangle and diagonal of M (the strict upper triangle of the diagonal
-// 16 x 16 blocks may hold anything).  On return L is in M's lower triangle
-// (the strict upper triangle is left undefined) and V[b] (16 x 17 each)
-// holds the inverse of the diagonal block L[b][b] (lower, zeros above).
-// Rows and columns from n on must be those of the identity (no coupling),
-// so their steps are skipped and L is the identity there too.  A pivot
-// <= floor (or not finite) is replaced by floor; the number of such pivots
-// is added to *flag.  W: 128 doubles of LDS scratch.
-//
-// Right-looking by 16-column panels: lane j keeps row j of the panel in
-// registers.  Step s takes the pivot of lane c0 + s by readlane; the entry
-// of the next pivot row comes by readlane too, so the dependent chain of a
-// step is short, and the rest of the column is broadcast through LDS.  The
-// trailing lower block triangle is updated with 16x16x4 FP64 MFMA tile
-// products.  At the end the lanes 16 q + v (v < 16) invert block q, column
-// v, by forward substitution.  A wave's LDS operations complete in order,
-// so no barrier is needed between them.
-// ---------------------------------------------------------------------------
+// 1 / sqrt(d) for d > 0 in four dependent operations: the hardware estimate
+// y0 (relative error below 2^-24) and one second-order correction
+// y = y0 (1 + e / 2 + 3 e^2 / 8), e = 1 - d y0^2, whose truncation error is
+// of order e^3 (below 1e-21), so y is within rounding of 1 / sqrt(d).
+__device__ __forceinline__ double rsqrt_fast(double d) {
+  const double y0 = __builtin_amdgcn_rsq(d);
+  const double e = fma(-d * y0, y0, 1.0);
+  return fma(y0 * e, fma(e, 0.375, 0.5), y0);
+}
+
 // Steps of one 16-column panel (see wave_chol_lower).  FULL: all 16 steps,
 // no branches, so the scheduler can overlap consecutive steps; otherwise
-// only the first `steps` (uniform) are taken.
+// only the first `steps` (uniform) are taken.  The dependent chain of a step
+// is: pivot by readlane, floor, 1 / sqrt, the column entry, its readlane by
+// the next pivot row and that row's update.
 template <bool FULL>
 __device__ __forceinline__ void wave_panel_steps(double (&a)[16], int c0, int steps, double* colbuf,
                                                  double floor_piv, double& myinv, int& nbad) {
@@ -416,13 +397,13 @@ __device__ __forceinline__ void wave_panel_steps(double (&a)[16], int c0, int st
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     if (FULL || s < steps) {
-      double d = readlane_d(a[s], c0 + s);
-      const bool bad = !(d > floor_piv) || !isfinite(d);
-      nbad += bad ? 1 : 0;
-      d = bad ? (floor_piv > 0.0 ? floor_piv : 1.0) : d;
-      const double y = rsqrt_refined(d);
+      const double d0 = readlane_d(a[s], c0 + s);
+      nbad += (d0 > floor_piv) ? 0 : 1;   // also counts NaN
+      const double d = fmax(d0, floor_piv);
       const bool piv = lane == c0 + s;
-      const double l = piv ? d * y : a[s] * y;   // L[lane][c0 + s]
+      const double as = piv ? d : a[s];
+      const double y = rsqrt_fast(d);
+      const double l = as * y;   // L[lane][c0 + s]; sqrt(d) on the pivot lane
       a[s] = l;
       myinv = piv ? y : myinv;
       if (s + 1 < 16) {
@@ -446,8 +427,8 @@ __device__ __forceinline__ void wave_panel_steps(double (&a)[16], int c0, int st
 // holds the inverse of the diagonal block L[b][b] (lower, zeros above).
 // Rows and columns from n on must be those of the identity (no coupling),
 // so their steps are skipped and L is the identity there too.  A pivot
-// <= floor (or not finite) is replaced by floor; the number of such pivots
-// is added to *flag.  W: 128 doubles of LDS scratch.
+// <= floor (or NaN) is replaced by floor (floor > 0); the number of such
+// pivots is added to *flag.  W: 128 doubles of LDS scratch.
 //
 // Right-looking by 16-column panels: lane j keeps row j of the panel in
 // registers.  Step s takes the pivot of lane c0 + s by readlane; the entry
