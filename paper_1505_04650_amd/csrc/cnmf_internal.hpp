@@ -113,7 +113,7 @@ hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const dou
 struct AdmmJob {
   AdmmSide s0, s1;        // U / Lam with L, and V^T / Phi^T with R^T
   const double* At;       // k x k
-  double* XY;             // Xt, Yt^T (k x r each)
+  double* XY;             // Xt, Yt^T (k x r each), then FP32 copies (KP x RP each)
   double* Pp;             // (parts0 + parts1) k x r partials
   double* Pred;           // 2 k x r reduced partials
   int* flags;             // breakdown flag word
@@ -121,6 +121,7 @@ struct AdmmJob {
   int k, r, parts0, parts1;
   int rpb0, rpb1;         // rows per uv block (filled by admm_job_prepare)
   int first;              // 1 for the request's first iteration
+  int last;               // 1 for its last iteration (U, V^T are stored)
 };
 void admm_job_prepare(AdmmJob& J);
 int admm_job_uv_blocks(const AdmmJob& J);

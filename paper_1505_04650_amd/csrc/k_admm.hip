@@ -38,7 +38,10 @@ struct Mf<double> {
 };
 
 // mode 0: only partials of basis^T (pen F - M)  (initialisation)
-// mode 1: update F, M, then partials
+// mode 1: update M, then partials; F (U or V^T) is not read: Alg. 3 sets it
+//         from L Xt and the previous multipliers only, so within the
+//         iterations it is needed only in registers
+// mode 2: mode 1 and F stored (the last iteration)
 // Per sweep of CH rows: the basis rows go to LDS; LX = basis * C on the
 // MFMA (wave w owns rows 16w..16w+15); the row update is applied in the
 // MFMA's result layout; then the k x r partial basis^T (pen F - M) is
@@ -72,10 +75,53 @@ __device__ __forceinline__ void admm_uv_body(const AdmmSide& s0, const AdmmSide&
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, g = lane >> 4;
-  for (int e = tid; e < KP * RP; e += 256) {
-    int a = e / RP, c = e - a * RP;
-    cs[a * ldc + c] = (a < k && c < r) ? (T)C[a * r + c] : T(0);
+  // C of this side into LDS.  T = float: from the zero-padded FP32 copy
+  // (KP x RP) the solve leaves after XY, 16-byte loads; T = double: from XY.
+  // The loads are issued here and stored with the first sweep's, so the
+  // block pays one memory latency for both.
+  constexpr int NCV = std::is_same<T, float>::value ? 8 : 32;
+  T cv[NCV][std::is_same<T, float>::value ? 4 : 1];
+  {
+    if constexpr (std::is_same<T, float>::value) {
+      const float* Cf = reinterpret_cast<const float*>(XY + 2 * (int64_t)k * r) + (side1 ? KP * RP : 0);
+#pragma unroll
+      for (int j = 0; j < NCV; ++j) {
+        const int v4 = tid + 256 * j;
+        if (4 * v4 < KP * RP) {
+          const float4 q = *reinterpret_cast<const float4*>(Cf + 4 * v4);
+          cv[j][0] = q.x; cv[j][1] = q.y; cv[j][2] = q.z; cv[j][3] = q.w;
+        }
+      }
+    } else {
+      const int cc = tid & 63, rg0 = tid >> 6;
+#pragma unroll
+      for (int j = 0; j < NCV; ++j) {
+        const int a = rg0 + 4 * j;
+        cv[j][0] = (a < k && cc < r) ? (T)C[a * r + cc] : T(0);
+      }
+    }
   }
+  auto store_c = [&]() {
+    if constexpr (std::is_same<T, float>::value) {
+#pragma unroll
+      for (int j = 0; j < NCV; ++j) {
+        const int v4 = tid + 256 * j;
+        if (4 * v4 < KP * RP) {
+          const int a = (4 * v4) / RP, c = 4 * v4 - a * RP;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) cs[a * ldc + c + u] = cv[j][u];
+        }
+      }
+    } else {
+      const int cc = tid & 63, rg0 = tid >> 6;
+#pragma unroll
+      for (int j = 0; j < NCV; ++j) {
+        const int a = rg0 + 4 * j;
+        if (a < KP && cc < RP) cs[a * ldc + cc] = cv[j][0];
+      }
+    }
+  };
+  for (int e = tid; e < CH * ldb; e += 256) bs[e] = T(0);
   acc_t pacc[2][4];
 #pragma unroll
   for (int u = 0; u < 2; ++u)
@@ -98,14 +144,29 @@ __device__ __forceinline__ void admm_uv_body(const AdmmSide& s0, const AdmmSide&
           const int row = 16 * rg + Mf<T>::out_row(g, i), col = 16 * cb + lr;
           const bool ok = rg < CH / 16 && cb < RP16 && row < nr && col < r;
           const int64_t off = (int64_t)(base + row) * S.ldf + col;
-          fv[q][cb][i] = ok ? F[off] : T(0);
+          fv[q][cb][i] = (ok && mode == 0) ? F[off] : T(0);
           mv[q][cb][i] = ok ? M[off] : T(0);
         }
     }
     __syncthreads();
-    for (int e = tid; e < CH * KP; e += 256) {
-      int rr = e / KP, a = e - rr * KP;
-      bs[rr * ldb + a] = (rr < nr && a < k) ? Bm[(int64_t)(base + rr) * S.ldb + a] : T(0);
+    if (base == i0) store_c();
+    // basis rows of the sweep straight into LDS (global_load_lds: lane l of
+    // a wave writes dword l after the row's LDS base), one row per wave
+    // instruction and 64-dword chunk; lanes past the row's k entries are
+    // masked off, so bs keeps the zeros written at the start there (and in
+    // rows from nr on, which only meet zero rows of ws)
+    {
+      constexpr int DW = sizeof(T) / 4;   // dwords per element
+      const int rowdw = k * DW;
+      for (int rr = w; rr < nr; rr += 4) {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(Bm + (int64_t)(base + rr) * S.ldb);
+        for (int d0 = 0; d0 < rowdw; d0 += 64) {
+          if (d0 + lane < rowdw)
+            __builtin_amdgcn_global_load_lds(src + d0 + lane, reinterpret_cast<uint32_t*>(bs + rr * ldb) + d0, 4, 0,
+                                             0);
+        }
+      }
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
     __syncthreads();
     // ---- LX and the row update (waves own 16-row groups) ----
@@ -117,7 +178,7 @@ __device__ __forceinline__ void admm_uv_body(const AdmmSide& s0, const AdmmSide&
       for (int cb = 0; cb < 4; ++cb) {
         if (cb >= RP16) continue;
         acc_t acc = acc_t{0, 0, 0, 0};
-        if (mode == 1) {
+        if (mode != 0) {
           const T* ap = bs + (16 * rg + lr) * ldb + g;
           const T* bp = cs + g * ldc + 16 * cb + lr;
           for (int ks = 0; ks < KP / 4; ++ks) Mf<T>::mma(ap[4 * ks], bp[4 * ks * ldc], acc);
@@ -127,13 +188,13 @@ __device__ __forceinline__ void admm_uv_body(const AdmmSide& s0, const AdmmSide&
           const int row = 16 * rg + Mf<T>::out_row(g, i), col = 16 * cb + lr;
           const bool ok = row < nr && col < r;
           T f = fv[q][cb][i], mu = mv[q][cb][i];
-          if (ok && mode == 1) {
+          if (ok && mode != 0) {
             const T lx = acc[i];
             const T t = lx + mu * inv_pen;
             f = t > T(0) ? t : T(0);
             mu = mu + xpen * (lx - f);
             const int64_t off = (int64_t)(base + row) * S.ldf + col;
-            F[off] = f;
+            if (mode == 2) F[off] = f;
             M[off] = mu;
           }
           ws[row * ldc + col] = ok ? pen * f - mu : T(0);
@@ -198,8 +259,8 @@ __global__ __launch_bounds__(256) void admm_uv_batch_kernel(const AdmmJob* __res
   extern __shared__ char smraw[];
   const int j = batch_job(uv_first, njobs, blockIdx.x);
   const AdmmJob& J = jobs[j];
-  admm_uv_body<T, CH>(J.s0, J.s1, J.parts0, (int)blockIdx.x - uv_first[j], J.XY, J.k, J.r, J.xi, 1, J.Pp,
-                      J.rpb0, J.rpb1, smraw);
+  admm_uv_body<T, CH>(J.s0, J.s1, J.parts0, (int)blockIdx.x - uv_first[j], J.XY, J.k, J.r, J.xi, J.last ? 2 : 1,
+                      J.Pp, J.rpb0, J.rpb1, smraw);
 }
 
 template <typename T>
@@ -260,7 +321,8 @@ __global__ __launch_bounds__(kRedNT) void admm_reduce_batch_kernel(const AdmmJob
 }
 
 // The two r x r solves of one iteration run in one workgroup.  XY: [0] Xt
-// (k x r), [1] Yt^T (k x r), FP64.  first != 0: Yt^T = P_V / phi before the
+// (k x r), [1] Yt^T (k x r), FP64, followed by both again in FP32, zero
+// padded to KP x RP (k, r rounded up to 16) for the row updates.  first != 0: Yt^T = P_V / phi before the
 // Xt solve (Alg. 3 initialisation Yt = V R^T, the partial having been
 // formed as R (phi V^T)).
 constexpr int kSolveNT = 256;
@@ -349,9 +411,10 @@ __device__ __forceinline__ void s_chunks(const double* S, int ld, int kp, int c,
 // for Yt^T (S = Xt, At^T).  Starts after a barrier, ends with one.
 template <int NB, int PASS>
 __device__ __forceinline__ void chol_side(const double* __restrict__ At, const double* __restrict__ P, int k, int r,
-                                          double pen, double* __restrict__ out, int* flags, const CholLayout& Ly,
-                                          double* sm) {
+                                          double pen, double* __restrict__ out, float* __restrict__ outf,
+                                          int* flags, const CholLayout& Ly, double* sm) {
   constexpr int KS = kCholMaxK / 4;
+  constexpr int N = 16 * NB;
   const int ld = Ly.ld, kp = Ly.kp, KB16 = Ly.KB16;
   double* S = sm + Ly.s_off;
   double* E = sm + Ly.e_off;
@@ -465,6 +528,7 @@ __device__ __forceinline__ void chol_side(const double* __restrict__ At, const d
         for (int i = 0; i < 4; ++i) {
           const int col = 16 * b + g + 4 * i;
           if (xr < k && col < r) out[xr * r + col] = z[b][i];
+          outf[xr * N + col] = (float)z[b][i];
           if (PASS == 0) S[xr * ld + col] = z[b][i];
         }
     }
@@ -487,8 +551,10 @@ __device__ __forceinline__ void admm_solve_chol_nb(const double* __restrict__ Pr
     S[i * Ly.ld + j] = (i < k && j < r) ? (first ? Pred[kr + i * r + j] / phi : XY[kr + i * r + j]) : 0.0;
   }
   __syncthreads();
-  chol_side<NB, 0>(At, Pred, k, r, lam, XY, flags, Ly, sm);
-  chol_side<NB, 1>(At, Pred + kr, k, r, phi, XY + kr, flags, Ly, sm);
+  // the zero-padded FP32 copies (kp x N per side) after XY feed the row updates
+  float* XYf = reinterpret_cast<float*>(XY + 2 * kr);
+  chol_side<NB, 0>(At, Pred, k, r, lam, XY, XYf, flags, Ly, sm);
+  chol_side<NB, 1>(At, Pred + kr, k, r, phi, XY + kr, XYf + Ly.kp * N, flags, Ly, sm);
 }
 
 __device__ __forceinline__ void admm_solve_chol_body(const double* __restrict__ Pred, const double* __restrict__ At,

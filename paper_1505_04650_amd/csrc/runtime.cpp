@@ -361,7 +361,8 @@ void layout_admm(Arena& a, AdmmWs<T>& w, int64_t m, int64_t n, int k, int r) {
   w.Lam = a.take<T>((size_t)m * r);
   w.Vt = a.take<T>((size_t)n * r);
   w.Phit = a.take<T>((size_t)n * r);
-  w.XY = a.take<double>(2 * (size_t)k * r);
+  // Xt, Yt^T in FP64, then their zero-padded FP32 copies (2 x KP x RP floats)
+  w.XY = a.take<double>(2 * (size_t)k * r + (size_t)((k + 15) / 16 * 16) * ((r + 15) / 16 * 16));
   w.parts0 = uv_parts(m);
   w.parts1 = uv_parts(n);
   w.Pp = a.take<double>((size_t)(w.parts0 + w.parts1) * k * r);
@@ -879,7 +880,8 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
     for (int it = 0; it < d->iters; ++it) {
       HIPCHK(h, launch_admm_solve<T>(aw.Pp, aw.parts0, aw.parts1, w.At, k, r, d->lambda, d->phi, it == 0, aw.XY,
                                      aw.Pred, w.flags + 2, st));
-      HIPCHK(h, launch_admm_uv<T>(J.s0, J.s1, 2, aw.XY, k, r, d->xi, 1, aw.Pp, aw.parts0, aw.parts1, st));
+      HIPCHK(h, launch_admm_uv<T>(J.s0, J.s1, 2, aw.XY, k, r, d->xi, it + 1 == d->iters ? 2 : 1, aw.Pp, aw.parts0,
+                                  aw.parts1, st));
     }
   } else if (d->method == CNMF_MU) {
     Span sp(h, ST_ITER, (double)d->iters * (4.0 * (double)(m + n) * k * r + 4.0 * (double)(m + n) * r * r));

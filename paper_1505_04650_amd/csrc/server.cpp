@@ -279,6 +279,7 @@ bool batch_step(cnmf_server* S) {
     Req* r = S->active[j];
     jobs[j] = r->job;
     jobs[j].first = r->it == 0 ? 1 : 0;
+    jobs[j].last = r->it + 1 == r->d.iters ? 1 : 0;
     uvf[j] = uv_total;
     rdf[j] = red_total;
     uv_total += admm_job_uv_blocks(r->job);
