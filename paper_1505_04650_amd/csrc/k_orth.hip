@@ -187,12 +187,101 @@ __global__ __launch_bounds__(kFacNT) void chol_tinv_kernel(const double* __restr
   }
 }
 
+// The same contract for kh <= 64 with the products on the FP64 MFMA: wave 0
+// factors G_h = L L^T (wave_chol_lower: 16-column register panels, MFMA
+// trailing updates, inverses V_b of the diagonal blocks); then wave j forms
+// column strip j of Z = L^-1 by block forward substitution,
+//   Z_jj = V_j,  Z_bj = -V_b sum_{j <= a < b} L[b][a] Z_aj   (b > j),
+// with the strip's tiles in registers (a 16x16x4 FP64 MFMA result is the
+// right operand of the next product as it stands), and writes Tinv_h =
+// T^-1 = Z^T, since T = L^T.
+template <int NB>
+__device__ __forceinline__ void chol_tinv_wave_body(const double* __restrict__ Gh, int kh, double* __restrict__ out,
+                                                    int* flag, double* sm) {
+  constexpr int N = 16 * NB, ld = N + 2;
+  double* M = sm;                 // N x ld
+  double* V = M + N * ld;         // NB x 272
+  double* W = V + NB * 272;       // 128
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  for (int e = tid; e < N * N; e += kFacNT) {
+    const int i = e / N, j = e - i * N;
+    M[i * ld + j] = (i < kh && j < kh) ? 0.5 * (Gh[i * kh + j] + Gh[j * kh + i]) : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (w == 0) {
+    double dg = lane < kh ? M[lane * ld + lane] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o));
+    wave_chol_lower<NB>(M, ld, kh, V, W, dg > 0.0 ? 1e-20 * dg : 1.0, flag);
+  }
+  __syncthreads();
+  if (w < NB) {
+    const int j = w;
+    doublex4 z[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (b < j) {
+        z[b] = doublex4{0.0, 0.0, 0.0, 0.0};
+      } else if (b == j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) z[b][i] = V[b * 272 + (g + 4 * i) * 17 + c];
+      } else {
+        doublex4 t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < b; ++a) {
+          if (a < j) continue;
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            t = __builtin_amdgcn_mfma_f64_16x16x4f64(M[(16 * b + c) * ld + 16 * a + 4 * s + g], z[a][s], t, 0, 0, 0);
+        }
+        doublex4 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          y = __builtin_amdgcn_mfma_f64_16x16x4f64(-V[b * 272 + c * 17 + 4 * s + g], t[s], y, 0, 0, 0);
+        z[b] = y;
+      }
+    }
+    // Tinv[16 j + c][16 b + g + 4 i] = Z[16 b + g + 4 i][16 j + c] = item i of tile b
+    const int trow = 16 * j + c;
+    if (trow < kh) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int tcol = 16 * b + g + 4 * i;
+          if (tcol < kh) out[trow * kh + tcol] = z[b][i];
+        }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kFacNT) void chol_tinv_wave_kernel(const double* __restrict__ G, int kh,
+                                                                double* __restrict__ Tinv, int* flags) {
+  extern __shared__ double sm[];
+  const int h = blockIdx.x;
+  const int64_t cnt = (int64_t)kh * kh;
+  int* flag = flags ? flags + h : nullptr;
+  switch ((kh + 15) / 16) {
+    case 1: chol_tinv_wave_body<1>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
+    case 2: chol_tinv_wave_body<2>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
+    case 3: chol_tinv_wave_body<3>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
+    default: chol_tinv_wave_body<4>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
+  }
+}
+
 hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double* G, double* Tinv, int* flags,
                             unsigned* /*counters*/, hipStream_t st) {
   if (kh > 128) return hipErrorInvalidValue;
   hipError_t e = launch_sum_parts(Gp, parts, (int64_t)nh * kh * kh, G, st);
   if (e != hipSuccess) return e;
   const int NB = (kh + 15) / 16, N = 16 * NB, ld = N + 1;
+  if (kh <= 64) {
+    const size_t smw = ((size_t)N * (N + 2) + (size_t)NB * 272 + 128) * sizeof(double);
+    hipFuncSetAttribute((const void*)chol_tinv_wave_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smw);
+    hipLaunchKernelGGL(chol_tinv_wave_kernel, dim3(nh), dim3(kFacNT), smw, st, G, kh, Tinv, flags);
+    CNMF_LAUNCH_CHECK();
+  }
   size_t sm = ((size_t)N * ld + (size_t)NB * 272) * sizeof(double);
   hipFuncSetAttribute((const void*)chol_tinv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   hipLaunchKernelGGL(chol_tinv_kernel, dim3(nh), dim3(kFacNT), sm, st, G, kh, Tinv, flags);
