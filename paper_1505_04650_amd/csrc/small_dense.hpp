@@ -449,7 +449,7 @@ __device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double
   double* colbuf = W;       // the current column of L
   double* dinv = W + 64;    // 1 / L[i][i]
   int nbad = 0;
-#pragma unroll 1
+#pragma unroll
   for (int P = 0; P < NB; ++P) {
     const int c0 = 16 * P;
     const bool act = lane >= c0 && lane < N;
