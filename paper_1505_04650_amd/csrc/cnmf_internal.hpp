@@ -176,6 +176,8 @@ template <typename T>
 hipError_t launch_residual(const T* A, int64_t lda, int m, int n, const T* U, int ldu, const T* Vt,
                            int ldv, int r, double* partial, int parts, hipStream_t st);
 hipError_t launch_residual_finish(const double* partial, int parts, double* out, hipStream_t st);
+// Partial count of the residual launch for an m x n A.
+int residual_blocks(int m, int n);
 hipError_t launch_flags_to_stats(const int* flags, int nflags, double* out, hipStream_t st);
 hipError_t launch_spa_step(double* Bt, int n, int k, int ldb, int t, int64_t* K, double* score,
                            double* u, double* wg_best, int64_t* wg_idx, unsigned* counter,

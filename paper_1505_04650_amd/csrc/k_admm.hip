@@ -58,7 +58,7 @@ __device__ __forceinline__ void admm_uv_body(const AdmmSide& s0, const AdmmSide&
   const int blk = side1 ? bid - nblk0 : bid;
   const int rpb = side1 ? rows_per_blk1 : rows_per_blk0;
   const double* C = XY + (side1 ? (int64_t)k * r : 0);
-  double* out = Pp + (int64_t)bid * k * r;   // partial slot = block index within the request
+  T* out = reinterpret_cast<T*>(Pp) + (int64_t)bid * k * r;   // partial slot = block index within the request
   const T* __restrict__ Bm = (const T*)S.Bm;
   T* __restrict__ F = (T*)S.F;
   T* __restrict__ M = (T*)S.M;
@@ -225,7 +225,7 @@ __device__ __forceinline__ void admm_uv_body(const AdmmSide& s0, const AdmmSide&
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int a = 16 * mb + Mf<T>::out_row(g, i), c = 16 * v + lr;
-          if (v < RP16 && a < k && c < r) out[a * r + c] = (double)pacc[u][v][i];
+          if (v < RP16 && a < k && c < r) out[a * r + c] = (T)pacc[u][v][i];
         }
     }
   }
@@ -292,20 +292,25 @@ template hipError_t launch_admm_uv<double>(AdmmSide, AdmmSide, int, const double
 constexpr int kRedNT = 256;
 constexpr int kRedEPB = 32;
 
+// The partials are stored in the factors' precision T (the row updates
+// accumulate them in T on the MFMA) and summed in FP64.
+template <typename T>
 __device__ __forceinline__ void admm_reduce_body(const double* __restrict__ Pp, int parts0, int parts1, int64_t kr,
                                                  double* __restrict__ Pred, int nbh, int bid, double* red) {
   const bool vside = bid >= nbh;
   const int64_t e0 = (int64_t)(vside ? bid - nbh : bid) * kRedEPB;
+  const T* P = reinterpret_cast<const T*>(Pp);
   if (!vside)
-    block_sum_parts<kRedNT, kRedEPB>(Pp, parts0, kr, kr, e0, Pred, red);
+    block_sum_parts<kRedNT, kRedEPB, T>(P, parts0, kr, kr, e0, Pred, red);
   else
-    block_sum_parts<kRedNT, kRedEPB>(Pp + (int64_t)parts0 * kr, parts1, kr, kr, e0, Pred + kr, red);
+    block_sum_parts<kRedNT, kRedEPB, T>(P + (int64_t)parts0 * kr, parts1, kr, kr, e0, Pred + kr, red);
 }
 
+template <typename T>
 __global__ __launch_bounds__(kRedNT) void admm_reduce_kernel(const double* __restrict__ Pp, int parts0,
                                                              int parts1, int64_t kr, double* __restrict__ Pred) {
   __shared__ double red[kRedNT];
-  admm_reduce_body(Pp, parts0, parts1, kr, Pred, gridDim.x / 2, blockIdx.x, red);
+  admm_reduce_body<T>(Pp, parts0, parts1, kr, Pred, gridDim.x / 2, blockIdx.x, red);
 }
 
 int admm_reduce_blocks(int k, int r) { return 2 * (int)(((int64_t)k * r + kRedEPB - 1) / kRedEPB); }
@@ -317,7 +322,7 @@ __global__ __launch_bounds__(kRedNT) void admm_reduce_batch_kernel(const AdmmJob
   const AdmmJob& J = jobs[j];
   const int64_t kr = (int64_t)J.k * J.r;
   const int nbh = (int)((kr + kRedEPB - 1) / kRedEPB);
-  admm_reduce_body(J.Pp, J.parts0, J.parts1, kr, J.Pred, nbh, (int)blockIdx.x - red_first[j], red);
+  admm_reduce_body<float>(J.Pp, J.parts0, J.parts1, kr, J.Pred, nbh, (int)blockIdx.x - red_first[j], red);
 }
 
 // The two r x r solves of one iteration run in one workgroup.  XY: [0] Xt
@@ -590,7 +595,7 @@ hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const dou
   if (r > 64 || k > kCholMaxK || admm_solve_lds_bytes(k, r) > 160 * 1024) return hipErrorInvalidValue;
   int64_t kr = (int64_t)k * r;
   int nbh = (int)((kr + kRedEPB - 1) / kRedEPB);
-  hipLaunchKernelGGL(admm_reduce_kernel, dim3(2 * nbh), dim3(kRedNT), 0, st, Pp, parts0, parts1, kr, Pred);
+  hipLaunchKernelGGL(admm_reduce_kernel<T>, dim3(2 * nbh), dim3(kRedNT), 0, st, Pp, parts0, parts1, kr, Pred);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t sm = chol_layout(k, r).total * sizeof(double);

@@ -1,4 +1,7 @@
 // Data movement, the reported residual and SPA.
+#include <algorithm>
+#include <type_traits>
+
 #include "cnmf_internal.hpp"
 
 namespace cnmf {
@@ -101,67 +104,152 @@ hipError_t launch_fill(void* p, size_t bytes, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Relative residual ||A - U V||_F / ||A||_F: each block takes 16 rows and
-// sweeps the columns in chunks of 256; U rows and V^T chunk rows in LDS;
-// the product in T, differences and sums of squares in FP64.  partial[blk]
-// = (sum (a - uv)^2, sum a^2).
+// Relative residual ||A - U V||_F / ||A||_F.  A block takes 64 rows (wave w:
+// rows 16 w .. 16 w + 15, whose U rows are the MFMA's left operands, held in
+// registers) and a range of 64-column chunks.  Each chunk's V^T rows are
+// staged in LDS (double buffered; the next chunk's V^T and A values are
+// loaded while the current one is used), the U V tile is formed in T on the
+// 16x16x4 MFMA, and the differences and squares are accumulated in FP64.
+// partial[blk] = (sum (a - uv)^2, sum a^2), blk = y * gridDim.x + x.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void residual_kernel(const T* __restrict__ A, int64_t lda, int m, int n,
                                                        const T* __restrict__ U, int ldu,
-                                                       const T* __restrict__ Vt, int ldv, int r,
+                                                       const T* __restrict__ Vt, int ldv, int r, int chunks_per_split,
                                                        double* __restrict__ partial) {
-  constexpr int RB = 16;
-  __shared__ T us[RB][65];
+  constexpr bool F32 = std::is_same<T, float>::value;
+  typedef typename std::conditional<F32, floatx4, doublex4>::type acc_t;
+  constexpr int LDV = 66;   // V^T chunk row stride in LDS (conflict-free FP32 operand reads)
+  __shared__ T vs[2][64 * LDV];
   __shared__ double red[2][256];
-  const int tid = threadIdx.x;
-  const int row0 = blockIdx.x * RB;
-  for (int e = tid; e < RB * r; e += 256) {
-    int i = e / r, c = e - i * r;
-    us[i][c] = row0 + i < m ? U[(int64_t)(row0 + i) * ldu + c] : T(0);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int row0 = blockIdx.x * 64;
+  const int nch = (n + 63) / 64;
+  const int ch0 = blockIdx.y * chunks_per_split, ch1 = min(nch, ch0 + chunks_per_split);
+  const int KS = (r + 3) / 4;
+  auto out_row = [&](int i) { return F32 ? 4 * g + i : g + 4 * i; };
+  // U rows of the wave as left operands: lane (c, g), K step s -> U[row c][4 s + g]
+  T ua[16];
+  {
+    const int ur = row0 + 16 * w + c;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int kk = 4 * s + g;
+      ua[s] = (ur < m && kk < r) ? U[(int64_t)ur * ldu + kk] : T(0);
+    }
   }
-  __syncthreads();
+  T vreg[16];
+  T areg[16], anext[16];   // raw A values (converted where they are used, so the prefetch does not wait)
+  auto load_v = [&](int ch) {
+    const int j0 = 64 * ch;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q, col = e >> 6, kk = e & 63;
+      vreg[q] = (j0 + col < n && kk < r) ? Vt[(int64_t)(j0 + col) * ldv + kk] : T(0);
+    }
+  };
+  auto store_v = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q, col = e >> 6, kk = e & 63;
+      vs[buf][col * LDV + kk] = vreg[q];
+    }
+  };
+  auto load_a = [&](int ch, T (&dst)[16]) {
+    const int j0 = 64 * ch;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = row0 + 16 * w + out_row(i), col = j0 + 16 * cb + c;
+        dst[4 * cb + i] = (row < m && col < n) ? A[(int64_t)row * lda + col] : T(0);
+      }
+  };
   double num = 0.0, den = 0.0;
-  for (int j0 = 0; j0 < n; j0 += 256) {
-    int j = j0 + tid;
-    if (j < n) {
-      T v[64];
+  if (ch0 < ch1) {
+    load_v(ch0);
+    load_a(ch0, areg);
+    store_v(0);
+  }
+  // every load so far (U operands included) has landed: the loop's MFMAs
+  // then wait only for LDS, not for the next chunk's prefetch
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+  __syncthreads();
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int buf = (ch - ch0) & 1;
+    const bool more = ch + 1 < ch1;
+    if (more) {
+      load_v(ch + 1);
+      load_a(ch + 1, anext);
+    }
+    const T* vb = vs[buf];
+    acc_t acc[4];
 #pragma unroll
-      for (int c = 0; c < 64; ++c) v[c] = c < r ? Vt[(int64_t)j * ldv + c] : T(0);
-      for (int i = 0; i < RB && row0 + i < m; ++i) {
-        T s = 0;
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
 #pragma unroll
-        for (int c = 0; c < 64; ++c) s = fma(us[i][c < r ? c : 0], v[c], s);
-        double a = (double)A[(int64_t)(row0 + i) * lda + j];
-        double d = a - (double)s;
+    for (int s = 0; s < 16; ++s) {
+      if (s < KS) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const T bv = vb[(16 * cb + c) * LDV + 4 * s + g];
+          if constexpr (F32)
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[s], bv, acc[cb], 0, 0, 0);
+          else
+            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[s], bv, acc[cb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double a = (double)areg[4 * cb + i];
+        const double d = a - (double)acc[cb][i];
         num = fma(d, d, num);
         den = fma(a, a, den);
       }
+    if (more) {
+      store_v(buf ^ 1);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) areg[q] = anext[q];
     }
+    __syncthreads();
   }
   red[0][tid] = num;
   red[1][tid] = den;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) {
-      red[0][tid] += red[0][tid + s];
-      red[1][tid] += red[1][tid + s];
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (tid < s2) {
+      red[0][tid] += red[0][tid + s2];
+      red[1][tid] += red[1][tid + s2];
     }
     __syncthreads();
   }
   if (tid == 0) {
-    partial[2 * blockIdx.x] = red[0][0];
-    partial[2 * blockIdx.x + 1] = red[1][0];
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    partial[2 * blk] = red[0][0];
+    partial[2 * blk + 1] = red[1][0];
   }
+}
+
+// Blocks of the residual launch (its partial count): ceil(m / 64) row blocks
+// times up to 4 column splits.
+int residual_blocks(int m, int n) {
+  const int rb = (m + 63) / 64, nch = (n + 63) / 64;
+  const int cs = std::max(1, std::min({4, nch, (1024 + rb - 1) / rb}));
+  return rb * cs;
 }
 
 template <typename T>
 hipError_t launch_residual(const T* A, int64_t lda, int m, int n, const T* U, int ldu, const T* Vt, int ldv,
                            int r, double* partial, int parts, hipStream_t st) {
-  if (r > 64) return hipErrorInvalidValue;
-  int blocks = (m + 15) / 16;
-  if (blocks != parts) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(residual_kernel<T>, dim3(blocks), dim3(256), 0, st, A, lda, m, n, U, ldu, Vt, ldv, r,
+  if (r > 64 || m < 1 || n < 1) return hipErrorInvalidValue;
+  const int rb = (m + 63) / 64, nch = (n + 63) / 64;
+  const int cs = std::max(1, std::min({4, nch, (1024 + rb - 1) / rb}));
+  if (rb * cs != parts) return hipErrorInvalidValue;
+  const int cps = (nch + cs - 1) / cs;
+  hipLaunchKernelGGL(residual_kernel<T>, dim3(rb, cs), dim3(256), 0, st, A, lda, m, n, U, ldu, Vt, ldv, r, cps,
                      partial);
   CNMF_LAUNCH_CHECK();
 }

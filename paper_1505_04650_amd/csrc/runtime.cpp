@@ -368,7 +368,7 @@ void layout_admm(Arena& a, AdmmWs<T>& w, int64_t m, int64_t n, int k, int r) {
   w.Pp = a.take<double>((size_t)(w.parts0 + w.parts1) * k * r);
   w.Pred = a.take<double>(2 * (size_t)k * r);
   w.counter = a.take<unsigned>(4);
-  w.rparts = (int)((m + 15) / 16);
+  w.rparts = residual_blocks((int)m, (int)n);
   w.rpart = a.take<double>(2 * (size_t)w.rparts);
 }
 

@@ -9,12 +9,13 @@
 namespace cnmf {
 
 // Sum parts [0, nparts) of `count` elements laid out as in[p * stride + e]
-// for the elements [e0, e0 + EPB) handled by this block.  NT threads:
+// (TI: FP64 or FP32 parts, summed in FP64) for the elements [e0, e0 + EPB)
+// handled by this block.  NT threads:
 // thread (el = tid % EPB, pg = tid / EPB) sums parts pg, pg + PG, ... with
 // four independent chains, then the PG groups are combined by a fixed tree in
 // LDS.  The order depends only on nparts, so results are reproducible.
-template <int NT, int EPB>
-__device__ __forceinline__ void block_sum_parts(const double* __restrict__ in, int nparts, int64_t stride,
+template <int NT, int EPB, typename TI = double>
+__device__ __forceinline__ void block_sum_parts(const TI* __restrict__ in, int nparts, int64_t stride,
                                                 int64_t count, int64_t e0, double* __restrict__ out,
                                                 double* red /* LDS, NT doubles */) {
   constexpr int PG = NT / EPB;
@@ -25,12 +26,12 @@ __device__ __forceinline__ void block_sum_parts(const double* __restrict__ in, i
   if (e < count) {
     int p = pg;
     for (; p + 3 * PG < nparts; p += 4 * PG) {
-      s0 += in[(int64_t)p * stride + e];
-      s1 += in[(int64_t)(p + PG) * stride + e];
-      s2 += in[(int64_t)(p + 2 * PG) * stride + e];
-      s3 += in[(int64_t)(p + 3 * PG) * stride + e];
+      s0 += (double)in[(int64_t)p * stride + e];
+      s1 += (double)in[(int64_t)(p + PG) * stride + e];
+      s2 += (double)in[(int64_t)(p + 2 * PG) * stride + e];
+      s3 += (double)in[(int64_t)(p + 3 * PG) * stride + e];
     }
-    for (; p < nparts; p += PG) s0 += in[(int64_t)p * stride + e];
+    for (; p < nparts; p += PG) s0 += (double)in[(int64_t)p * stride + e];
   }
   red[tid] = (s0 + s1) + (s2 + s3);
   __syncthreads();
