@@ -317,10 +317,11 @@ static int num_cu() {
 }
 
 // Pick the number of reduction slices so that tiles * splits fills the
-// resident workgroup slots (2 per CU) with a small tail, without cutting a
-// slice below a few chunks.  Depends only on the shape and the CU count.
-static int choose_splits(int tiles, int klen, int min_per_split) {
-  const int slots = 2 * num_cu();
+// resident workgroup slots (wg_per_cu per CU, from the variant's register
+// use) with a small tail, without cutting a slice below a few chunks.
+// Depends only on the shape and the CU count.
+static int choose_splits(int tiles, int klen, int min_per_split, int wg_per_cu = 2) {
+  const int slots = wg_per_cu * num_cu();
   int max_s = std::max(1, klen / min_per_split);
   max_s = std::min(max_s, 64);
   int best = 1;
@@ -350,16 +351,16 @@ int choose_splits_n(int m, int n, int kk, int elem_bytes) {
   return choose_splits(tiles, n, 512);
 }
 
-static int t_cols_per_wg(int kk, int elem_bytes) {
-  int kb = kk / 16;
-  int vw = elem_bytes == 4 ? (kb > 4 ? 2 : 4) : (kb > 4 ? 1 : 2);
-  return 4 * 16 * vw;
-}
+// Columns of A per lane in the A^T Z kernel: one for wide operands (the
+// kernel then needs few registers and four workgroups fit on a CU, which
+// measured faster than two columns at 20000 x 5000 and 100000 x 20000).
+static constexpr int t_vw(int kb, int elem_bytes) { return kb > 4 ? 1 : (elem_bytes == 4 ? 4 : 2); }
 
 int choose_splits_t(int m, int n, int kk, int elem_bytes) {
-  int cw = t_cols_per_wg(kk, elem_bytes);
-  int tiles = (n + cw - 1) / cw;
-  return choose_splits(tiles, m, 512);
+  const int kb = kk / 16;
+  const int cw = 4 * 16 * t_vw(kb, elem_bytes);
+  const int tiles = (n + cw - 1) / cw;
+  return choose_splits(tiles, m, 512, (elem_bytes == 4 && kb > 4) ? 4 : 2);
 }
 
 template <typename T, int KB>
@@ -397,7 +398,7 @@ hipError_t launch_gemm_n(const T* A, int64_t lda, int m, int n, const T* X, int 
 template <typename T, int KB>
 static hipError_t gemm_t_kb(const T* A, int64_t lda, int m, int n, const T* Z, T* P, int splits,
                             hipStream_t st) {
-  constexpr int VW = sizeof(T) == 4 ? (KB > 4 ? 2 : 4) : (KB > 4 ? 1 : 2);
+  constexpr int VW = t_vw(KB, sizeof(T));
   constexpr int KC = 32;
   int per = (m + splits - 1) / splits;
   per = (per + KC - 1) / KC * KC;
