@@ -41,8 +41,11 @@ def make_request(i, m, n, r, q=2, iters=30):
     return req
 
 
+# r up to 60 (k = 70): one to four 16-column blocks in the batched solve and,
+# for k > 64, a second row strip on some of its waves
 SHAPES = [(613, 389, 7), (1500, 700, 23), (300, 1200, 12), (2048, 512, 30), (777, 777, 5), (1000, 260, 18),
-          (2600, 1400, 26), (450, 900, 9), (1300, 1100, 15), (520, 2100, 21), (3000, 333, 11), (900, 600, 29)]
+          (2600, 1400, 26), (450, 900, 9), (1300, 1100, 15), (520, 2100, 21), (3000, 333, 11), (900, 600, 29),
+          (1200, 900, 60), (700, 1600, 45)]
 
 
 @pytest.fixture(scope="module")
