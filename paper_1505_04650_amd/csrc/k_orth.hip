@@ -148,46 +148,14 @@ hipError_t launch_sum_parts(const double* in, int parts, int64_t count, double* 
 // ---------------------------------------------------------------------------
 // G_h = sum of the Gram partials (fixed order; sum_parts kernel), then one
 // workgroup per half: G_h (padded to N = 16 ceil(kh / 16) with an identity
-// block) = T^T T by the blocked Cholesky in LDS (T upper, positive
-// diagonal), then Tinv_h = T^-1 by block columns, written to global memory
-// (kh x kh, zero below the diagonal).  A pivot <= 1e-20 max_i G_ii (or not
-// finite) counts as a breakdown in flags[h] and is replaced by that floor.
+// block) = T^T T (T upper, positive diagonal) and Tinv_h = T^-1 written to
+// global memory (kh x kh, zero below the diagonal).  A pivot <= 1e-20
+// max_i G_ii (or NaN) counts as a breakdown in flags[h] and is replaced by
+// that floor.
 // ---------------------------------------------------------------------------
 constexpr int kFacNT = 256;
-__global__ __launch_bounds__(kFacNT) void chol_tinv_kernel(const double* __restrict__ G, int kh,
-                                                           double* __restrict__ Tinv, int* flags) {
-  const int h = blockIdx.x;
-  const int64_t cnt = (int64_t)kh * kh;
-  const int NB = (kh + 15) / 16, N = 16 * NB, ld = N + 1;
-  extern __shared__ double sm[];
-  double* M = sm;              // N x ld
-  double* TI = M + N * ld;     // NB x 272
-  const double* Gh = G + h * cnt;
-  for (int e = threadIdx.x; e < N * N; e += kFacNT) {
-    int i = e / N, j = e - i * N;
-    double v;
-    if (i < kh && j < kh)
-      v = 0.5 * (Gh[i * kh + j] + Gh[j * kh + i]);
-    else
-      v = (i == j) ? 1.0 : 0.0;
-    M[i * ld + j] = v;
-  }
-  __syncthreads();
-  double mx = 0.0;
-  for (int i = 0; i < kh; ++i) mx = fmax(mx, M[i * ld + i]);
-  wg_chol_blocked_ip<kFacNT>(M, ld, NB, TI, 1e-20 * mx, flags ? flags + h : nullptr);
-  wg_tinv_blocked<kFacNT>(M, ld, NB, TI);
-  double* out = Tinv + h * cnt;
-  for (int e = threadIdx.x; e < kh * kh; e += kFacNT) {
-    const int i = e / kh, j = e - i * kh;
-    const int bi = i >> 4, bj = j >> 4, r = i & 15, c = j & 15;
-    double v = 0.0;
-    if (j >= i) v = bi == bj ? TI[bi * 272 + r * 17 + c] : M[j * ld + 16 * bi + r];
-    out[e] = v;
-  }
-}
 
-// The same contract for kh <= 64 with the products on the FP64 MFMA: wave 0
+// kh <= 64, with the products on the FP64 MFMA: wave 0
 // factors G_h = L L^T (wave_chol_lower: 16-column register panels, MFMA
 // trailing updates, inverses V_b of the diagonal blocks); then wave j forms
 // column strip j of Z = L^-1 by block forward substitution,
@@ -256,6 +224,126 @@ __device__ __forceinline__ void chol_tinv_wave_body(const double* __restrict__ G
   }
 }
 
+// 64 < kh <= 128 (N = 128, identity padding), from the same pieces in 2 x 2
+// blocks of 64:  L11 = chol(G11) (wave 0);  L21 from L21 L11^T = G21, each
+// wave solving its 16 rows by block substitution in registers;
+// S22 = G22 - L21 L21^T on the MFMA (wave w: block row w);  L22 = chol(S22)
+// (wave 0);  then Z = L^-1 over all 8 block rows, two column strips per
+// wave, and Tinv = Z^T.
+__device__ __forceinline__ void chol_tinv_wave128_body(const double* __restrict__ Gh, int kh, double* __restrict__ out,
+                                                       int* flag, double* sm) {
+  constexpr int N = 128, ld = N + 2;
+  double* M = sm;                 // N x ld
+  double* V = M + N * ld;         // 8 x 272: V[b], b < 4 from L11, b >= 4 from L22
+  double* W = V + 8 * 272;        // 128
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  for (int e = tid; e < N * N; e += kFacNT) {
+    const int i = e / N, j = e - i * N;
+    M[i * ld + j] = (i < kh && j < kh) ? 0.5 * (Gh[i * kh + j] + Gh[j * kh + i]) : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  double fl = 1.0;
+  {
+    double dg = 0.0;
+    for (int i = lane; i < kh; i += 64) dg = fmax(dg, M[i * ld + i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o));
+    if (dg > 0.0) fl = 1e-20 * dg;
+  }
+  if (w == 0) wave_chol_lower<4>(M, ld, 64, V, W, fl, flag);
+  __syncthreads();
+  // L21: wave w solves rows 64 + 16 w .. + 15 of X L11^T = G21 as L11 X^T = G21^T
+  {
+    double* R = M + (64 + 16 * w) * ld;   // the wave's rows of G21 (columns 0..63)
+    doublex4 z[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) z[b][i] = R[c * ld + 16 * b + g + 4 * i];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      doublex4 t = z[b];
+#pragma unroll
+      for (int a = 0; a < b; ++a)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          t = __builtin_amdgcn_mfma_f64_16x16x4f64(-M[(16 * b + c) * ld + 16 * a + 4 * s + g], z[a][s], t, 0, 0, 0);
+      doublex4 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        y = __builtin_amdgcn_mfma_f64_16x16x4f64(V[b * 272 + c * 17 + 4 * s + g], t[s], y, 0, 0, 0);
+      z[b] = y;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) R[c * ld + 16 * b + g + 4 * i] = z[b][i];
+  }
+  __syncthreads();
+  // S22 = G22 - L21 L21^T, block row w (all four column tiles)
+  {
+    doublex4 acc[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[jb][i] = M[(64 + 16 * w + g + 4 * i) * ld + 64 + 16 * jb + c];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const double a = -M[(64 + 16 * w + c) * ld + 4 * s + g];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, M[(64 + 16 * jb + c) * ld + 4 * s + g], acc[jb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) M[(64 + 16 * w + g + 4 * i) * ld + 64 + 16 * jb + c] = acc[jb][i];
+  }
+  __syncthreads();
+  if (w == 0) wave_chol_lower<4>(M + 64 * ld + 64, ld, kh - 64, V + 4 * 272, W, fl, flag);
+  __syncthreads();
+  // Z = L^-1, column strips j = w and w + 4
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int j = w + 4 * q;
+    doublex4 z[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (b < j) {
+        z[b] = doublex4{0.0, 0.0, 0.0, 0.0};
+      } else if (b == j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) z[b][i] = V[b * 272 + (g + 4 * i) * 17 + c];
+      } else {
+        doublex4 t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < b; ++a) {
+          if (a < j) continue;
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            t = __builtin_amdgcn_mfma_f64_16x16x4f64(M[(16 * b + c) * ld + 16 * a + 4 * s + g], z[a][s], t, 0, 0, 0);
+        }
+        doublex4 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          y = __builtin_amdgcn_mfma_f64_16x16x4f64(-V[b * 272 + c * 17 + 4 * s + g], t[s], y, 0, 0, 0);
+        z[b] = y;
+      }
+    }
+    const int trow = 16 * j + c;
+    if (trow < kh) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int tcol = 16 * b + g + 4 * i;
+          if (tcol < kh) out[trow * kh + tcol] = z[b][i];
+        }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kFacNT) void chol_tinv_wave_kernel(const double* __restrict__ G, int kh,
                                                                 double* __restrict__ Tinv, int* flags) {
   extern __shared__ double sm[];
@@ -266,7 +354,8 @@ __global__ __launch_bounds__(kFacNT) void chol_tinv_wave_kernel(const double* __
     case 1: chol_tinv_wave_body<1>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
     case 2: chol_tinv_wave_body<2>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
     case 3: chol_tinv_wave_body<3>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
-    default: chol_tinv_wave_body<4>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
+    case 4: chol_tinv_wave_body<4>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
+    default: chol_tinv_wave128_body(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
   }
 }
 
@@ -275,16 +364,12 @@ hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double*
   if (kh > 128) return hipErrorInvalidValue;
   hipError_t e = launch_sum_parts(Gp, parts, (int64_t)nh * kh * kh, G, st);
   if (e != hipSuccess) return e;
-  const int NB = (kh + 15) / 16, N = 16 * NB, ld = N + 1;
-  if (kh <= 64) {
-    const size_t smw = ((size_t)N * (N + 2) + (size_t)NB * 272 + 128) * sizeof(double);
-    hipFuncSetAttribute((const void*)chol_tinv_wave_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smw);
-    hipLaunchKernelGGL(chol_tinv_wave_kernel, dim3(nh), dim3(kFacNT), smw, st, G, kh, Tinv, flags);
-    CNMF_LAUNCH_CHECK();
-  }
-  size_t sm = ((size_t)N * ld + (size_t)NB * 272) * sizeof(double);
-  hipFuncSetAttribute((const void*)chol_tinv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  hipLaunchKernelGGL(chol_tinv_kernel, dim3(nh), dim3(kFacNT), sm, st, G, kh, Tinv, flags);
+  const int NB = (kh + 15) / 16, N = 16 * NB;
+  // kh <= 64: N x (N + 2) + NB x 272 + 128 doubles; kh > 64: 128 x 130 + 8 x 272 + 128
+  const size_t smw = kh <= 64 ? ((size_t)N * (N + 2) + (size_t)NB * 272 + 128) * sizeof(double)
+                              : ((size_t)128 * 130 + 8 * 272 + 128) * sizeof(double);
+  hipFuncSetAttribute((const void*)chol_tinv_wave_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smw);
+  hipLaunchKernelGGL(chol_tinv_wave_kernel, dim3(nh), dim3(kFacNT), smw, st, G, kh, Tinv, flags);
   CNMF_LAUNCH_CHECK();
 }
 

@@ -165,129 +165,6 @@ __device__ void wg_chol_blocked(double* M, int ldm, int NB, double* TI, double* 
   }
 }
 
-// Blocked factorisation for N = 16 NB <= 128 without panel scratch (LDS:
-// M, N x ldm, and TI, NB x 272): M = T^T T as in wg_chol_blocked.  The panel
-// is formed in place one column per thread; the trailing update (both
-// triangles) uses 4 x 4 register tiles.  Starts and ends with a barrier.
-template <int NT>
-__device__ void wg_chol_blocked_ip(double* M, int ldm, int NB, double* TI, double floor_piv, int* flag) {
-  const int tid = threadIdx.x;
-  const int N = 16 * NB;
-  __syncthreads();
-  for (int jb = 0; jb < NB; ++jb) {
-    const int j0 = 16 * jb, c0 = j0 + 16, rem = N - c0;
-    if (tid < 64) wave_diag16(M + j0 * ldm + j0, ldm, TI + jb * 272, floor_piv, flag);
-    __syncthreads();
-    if (rem <= 0) break;
-    const double* ti = TI + jb * 272;
-    // panel T[j0 + i][c] = sum_{l <= i} Tinv[l][i] M[j0 + l][c], in place
-    for (int c = c0 + tid; c < N; c += NT) {
-      double v[16], o[16];
-#pragma unroll
-      for (int l = 0; l < 16; ++l) v[l] = M[(j0 + l) * ldm + c];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        double acc = 0.0;
-#pragma unroll
-        for (int l = 0; l <= i; ++l) acc = fma(ti[l * 17 + i], v[l], acc);
-        o[i] = acc;
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) M[(j0 + i) * ldm + c] = o[i];
-    }
-    __syncthreads();
-    // trailing update M[x][y] -= sum_i P[i][x] P[i][y] over 4 x 4 tiles of the
-    // upper tile triangle, mirrored to the lower one
-    const int RQ = rem / 4;
-    for (int e = tid; e < RQ * RQ; e += NT) {
-      const int ta = e / RQ, tb = e - ta * RQ;
-      if (tb < ta) continue;
-      const int x0 = c0 + 4 * ta, y0 = c0 + 4 * tb;
-      double acc[4][4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int w = 0; w < 4; ++w) acc[u][w] = 0.0;
-#pragma unroll 4
-      for (int i = 0; i < 16; ++i) {
-        const double* pr = M + (j0 + i) * ldm;
-        double px[4], py[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          px[u] = pr[x0 + u];
-          py[u] = pr[y0 + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int w = 0; w < 4; ++w) acc[u][w] = fma(px[u], py[w], acc[u][w]);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          const int x = x0 + u, y = y0 + w;
-          if (y < x) continue;
-          M[x * ldm + y] -= acc[u][w];
-          if (y != x) M[y * ldm + x] -= acc[u][w];
-        }
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-}
-
-// After wg_chol_blocked_ip: Z = T^-1 (upper) by block columns,
-//   Z[bi][cb] = -(sum_{bi <= l < cb} Z[bi][l] T[l][cb]) TI_cb,  Z[cb][cb] = TI_cb,
-// with the off-diagonal blocks Z[bi][cb] (bi < cb) stored transposed in the
-// lower block triangle of M (block (cb, bi)); T stays in the upper blocks.
-template <int NT>
-__device__ void wg_tinv_blocked(double* M, int ldm, int NB, const double* TI) {
-  const int tid = threadIdx.x;
-  auto zget = [&](int bi, int l, int r, int p) -> double {  // Z[16 bi + r][16 l + p], bi <= l
-    return bi == l ? TI[l * 272 + r * 17 + p] : M[(16 * l + p) * ldm + 16 * bi + r];
-  };
-  for (int cb = 1; cb < NB; ++cb) {
-    // R = sum_l Z[bi][l] T[l][cb] into block (cb, bi), transposed; items (bi, r, 4 columns)
-    for (int e = tid; e < cb * 64; e += NT) {
-      const int bi = e >> 6, r = (e >> 2) & 15, cq = 4 * (e & 3);
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      for (int l = bi; l < cb; ++l) {
-#pragma unroll 4
-        for (int p = 0; p < 16; ++p) {
-          const double z = zget(bi, l, r, p);
-          const double* t = M + (16 * l + p) * ldm + 16 * cb + cq;   // T[16 l + p][16 cb + cq ..]
-          s0 = fma(z, t[0], s0);
-          s1 = fma(z, t[1], s1);
-          s2 = fma(z, t[2], s2);
-          s3 = fma(z, t[3], s3);
-        }
-      }
-      M[(16 * cb + cq + 0) * ldm + 16 * bi + r] = s0;
-      M[(16 * cb + cq + 1) * ldm + 16 * bi + r] = s1;
-      M[(16 * cb + cq + 2) * ldm + 16 * bi + r] = s2;
-      M[(16 * cb + cq + 3) * ldm + 16 * bi + r] = s3;
-    }
-    __syncthreads();
-    // Z[bi][cb] = -R TI_cb, one row per item (in place)
-    const double* tic = TI + cb * 272;
-    for (int e = tid; e < cb * 16; e += NT) {
-      const int bi = e >> 4, r = e & 15;
-      double rv[16];
-#pragma unroll
-      for (int p = 0; p < 16; ++p) rv[p] = M[(16 * cb + p) * ldm + 16 * bi + r];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int p = 0; p <= c; ++p) acc = fma(rv[p], tic[p * 17 + c], acc);
-        M[(16 * cb + c) * ldm + 16 * bi + r] = -acc;
-      }
-    }
-    __syncthreads();
-  }
-}
-
 // X (rows x N, LDS, row stride ldx) <- X (T^T T)^-1 with T from
 // wg_chol_blocked (upper blocks of M) and the diagonal-block inverses TI.
 // R: rows x 17 LDS scratch.  Starts and ends with a barrier.
