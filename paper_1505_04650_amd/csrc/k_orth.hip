@@ -44,9 +44,10 @@ template hipError_t launch_reduce_splits<double>(const double*, int, int64_t, in
 // Cross products C_h = X[:, x0 + h*hs : + ka]^T Y[:, y0 + h*hs : + kb] over a
 // slice of rows, FP64 accumulation; partial for (slice p, half h) at
 // Cp[(p * nh + h) * ka * kb].  Thread (ta, tb) owns entries
-// (ta + 16 i, tb + 16 j).
+// (ta + 16 i, tb + 16 j).  SYM (a Gram matrix, X == Y): only the blocks
+// i >= j are formed and the strictly lower ones are mirrored.
 // ---------------------------------------------------------------------------
-template <typename TX, typename TY, int KH16>
+template <typename TX, typename TY, int KH16, bool SYM>
 __global__ __launch_bounds__(256) void cross_kernel(const TX* __restrict__ X, int ldx, int x0,
                                                    const TY* __restrict__ Y, int ldy, int y0, int hs,
                                                    int rows, int ka, int kb, double* __restrict__ Cp,
@@ -86,7 +87,8 @@ __global__ __launch_bounds__(256) void cross_kernel(const TX* __restrict__ X, in
 #pragma unroll
       for (int i = 0; i < KH16; ++i)
 #pragma unroll
-        for (int j = 0; j < KH16; ++j) acc[i][j] = fma(xa[i], yb[j], acc[i][j]);
+        for (int j = 0; j < KH16; ++j)
+          if (!SYM || i >= j) acc[i][j] = fma(xa[i], yb[j], acc[i][j]);
     }
     __syncthreads();
   }
@@ -95,8 +97,12 @@ __global__ __launch_bounds__(256) void cross_kernel(const TX* __restrict__ X, in
   for (int i = 0; i < KH16; ++i)
 #pragma unroll
     for (int j = 0; j < KH16; ++j) {
+      if (SYM && i < j) continue;
       int a = ta + 16 * i, b = tb + 16 * j;
-      if (a < ka && b < kb) out[a * kb + b] = acc[i][j];
+      if (a < ka && b < kb) {
+        out[a * kb + b] = acc[i][j];
+        if (SYM && i > j) out[b * kb + a] = acc[i][j];
+      }
     }
 }
 
@@ -104,8 +110,13 @@ template <typename TX, typename TY, int KH16>
 static hipError_t cross_kh(const TX* X, int ldx, int x0, const TY* Y, int ldy, int y0, int hs, int nh,
                            int rows, int ka, int kb, double* Cp, int parts, hipStream_t st) {
   int rpp = (rows + parts - 1) / parts;
-  hipLaunchKernelGGL((cross_kernel<TX, TY, KH16>), dim3(parts, nh), dim3(256), 0, st, X, ldx, x0, Y, ldy,
-                     y0, hs, rows, ka, kb, Cp, rpp);
+  const bool sym = (const void*)X == (const void*)Y && ldx == ldy && x0 == y0 && ka == kb;
+  if (sym)
+    hipLaunchKernelGGL((cross_kernel<TX, TY, KH16, true>), dim3(parts, nh), dim3(256), 0, st, X, ldx, x0, Y, ldy,
+                       y0, hs, rows, ka, kb, Cp, rpp);
+  else
+    hipLaunchKernelGGL((cross_kernel<TX, TY, KH16, false>), dim3(parts, nh), dim3(256), 0, st, X, ldx, x0, Y, ldy,
+                       y0, hs, rows, ka, kb, Cp, rpp);
   CNMF_LAUNCH_CHECK();
 }
 
