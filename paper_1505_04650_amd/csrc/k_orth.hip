@@ -106,14 +106,97 @@ __global__ __launch_bounds__(256) void cross_kernel(const TX* __restrict__ X, in
     }
 }
 
+// Gram partials on the FP64 MFMA (X == Y, k <= 16 KB16): the rows of a
+// part are staged in LDS as FP64, 32 at a time (the next 32 are loaded into
+// registers while the current ones are used); the lower 16 x 16 tiles
+// (ti >= tj) are dealt round robin to the waves, each tile an FP64 16x16x4
+// MFMA chain over the rows, and the strictly lower ones are mirrored.
+// Same partial layout as cross_kernel.  FP32 inputs give exact products in
+// FP64, as there.
+template <typename TY, int KB16>
+__global__ __launch_bounds__(256) void gram_mfma_kernel(const TY* __restrict__ Y, int ldy, int y0, int hs, int rows,
+                                                        int k, double* __restrict__ Cp, int rows_per_part) {
+  constexpr int CR = 32, KW = 16 * KB16, LDC = KW + 1;
+  constexpr int NT = KB16 * (KB16 + 1) / 2, NQ = (NT + 3) / 4;
+  constexpr int PER = CR * KW / 256;   // staged values per thread and chunk
+  __shared__ double ys[2][CR * LDC];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int p = blockIdx.x, h = blockIdx.y, nh = gridDim.y;
+  const int yc = y0 + h * hs;
+  const int i0 = p * rows_per_part, i1 = min(rows, i0 + rows_per_part);
+  int ti[NQ], tj[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = w + 4 * q;
+    int a = 0;
+    while ((a + 1) * (a + 2) / 2 <= e) ++a;
+    ti[q] = a;
+    tj[q] = e - a * (a + 1) / 2;
+  }
+  doublex4 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = doublex4{0.0, 0.0, 0.0, 0.0};
+  TY v[PER];
+  auto load = [&](int base) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = tid + 256 * e, rr = idx / KW, cc = idx - rr * KW;
+      const int row = base + rr;
+      v[e] = (row < i1 && cc < k) ? Y[(int64_t)row * ldy + yc + cc] : TY(0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = tid + 256 * e, rr = idx / KW, cc = idx - rr * KW;
+      ys[buf][rr * LDC + cc] = (double)v[e];
+    }
+  };
+  const int nch = i1 > i0 ? (i1 - i0 + CR - 1) / CR : 0;
+  if (nch > 0) {
+    load(i0);
+    store(0);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nch;
+    if (more) load(i0 + CR * (ch + 1));
+    const double* yb = ys[buf];
+#pragma unroll
+    for (int s = 0; s < CR / 4; ++s) {
+      const double* yr = yb + (4 * s + g) * LDC + c;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (w + 4 * q < NT) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[16 * ti[q]], yr[16 * tj[q]], acc[q], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+  }
+  double* out = Cp + ((int64_t)p * nh + h) * k * k;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (w + 4 * q >= NT) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int a = 16 * ti[q] + g + 4 * i, b = 16 * tj[q] + c;
+      if (a < k && b < k) {
+        out[a * k + b] = acc[q][i];
+        if (ti[q] > tj[q]) out[b * k + a] = acc[q][i];
+      }
+    }
+  }
+}
+
 template <typename TX, typename TY, int KH16>
 static hipError_t cross_kh(const TX* X, int ldx, int x0, const TY* Y, int ldy, int y0, int hs, int nh,
                            int rows, int ka, int kb, double* Cp, int parts, hipStream_t st) {
   int rpp = (rows + parts - 1) / parts;
   const bool sym = (const void*)X == (const void*)Y && ldx == ldy && x0 == y0 && ka == kb;
   if (sym)
-    hipLaunchKernelGGL((cross_kernel<TX, TY, KH16, true>), dim3(parts, nh), dim3(256), 0, st, X, ldx, x0, Y, ldy,
-                       y0, hs, rows, ka, kb, Cp, rpp);
+    hipLaunchKernelGGL((gram_mfma_kernel<TY, KH16>), dim3(parts, nh), dim3(256), 0, st, Y, ldy, y0, hs, rows, ka, Cp,
+                       rpp);
   else
     hipLaunchKernelGGL((cross_kernel<TX, TY, KH16, false>), dim3(parts, nh), dim3(256), 0, st, X, ldx, x0, Y, ldy,
                        y0, hs, rows, ka, kb, Cp, rpp);
