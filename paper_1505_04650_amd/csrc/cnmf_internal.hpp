@@ -100,13 +100,32 @@ struct AdmmSide {
 template <typename T>
 hipError_t launch_admm_uv(AdmmSide s0, AdmmSide s1, int nsides, const double* XY, int k, int r,
                           double xi, int mode, double* Pp, int parts0, int parts1, hipStream_t st);
-// first != 0 for the first iteration of a run.  The solve runs in one
-// workgroup whose LDS holds admm_solve_lds_bytes(k, r) (<= 160 KiB required).
+// The solves run in one workgroup whose LDS holds admm_solve_lds_bytes(k, r)
+// (<= 160 KiB required).
 size_t admm_solve_lds_bytes(int k, int r);
+// Split schedule of one request (Alg. 3 order kept): with solve != 0, block
+// 0 solves one side (pass 0: Xt, with S = Yt^T, or P_V / phi when first;
+// pass 1: Yt^T, with S = Xt) and the other blocks run the row update of side
+// `side` (0: U / Lam, parts0 blocks; 1: V^T / Phi^T, parts1 blocks) writing
+// its partial slots as launch_admm_uv does, when uv != 0.
+struct AdmmHalf {
+  AdmmSide s0, s1;
+  const double* At;
+  const double* Pred;
+  double* XY;
+  double* Pp;
+  int* flags;
+  double lam, phi, xi;
+  int k, r, parts0, parts1, rpb0, rpb1;
+  int solve, pass, first, uv, side, mode;
+};
 template <typename T>
-hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const double* At, int k, int r,
-                             double lam, double phi, int first, double* XY, double* Pred, int* flags,
-                             hipStream_t st);
+hipError_t launch_admm_half(const AdmmHalf& a, hipStream_t st);
+// Fixed-order FP64 sums of the partials of one side (0: P_U into Pred, 1:
+// P_V into Pred + k r) or of both (2).
+template <typename T>
+hipError_t launch_admm_reduce(const double* Pp, int parts0, int parts1, int k, int r, int side, double* Pred,
+                              hipStream_t st);
 
 // One request of a batched ADMM step (FP32 factors): its two sides, the
 // FP64 solve state and its partial buffers, all in its own workspace.

@@ -6,12 +6,15 @@
 //   U   <- max(L Xt + Lam/lam, 0);  Lam <- Lam + xi lam (L Xt - U)
 //   V^T <- max(R^T Yt^T + Phi^T/phi, 0);  Phi^T <- Phi^T + xi phi (R^T Yt^T - V^T)
 // The row updates (U, Lam over the m rows of L; V^T, Phi^T over the n rows of
-// R^T) are the same operation on two "sides" and run in one launch
-// (admm_uv_kernel).  That launch also forms the partial sums of
-// basis^T (pen * F - M) for the next iteration's P_U / P_V, so the big
-// matrices are read once per iteration.  admm_reduce_kernel reduces those
-// partials in a fixed order; admm_solve_chol_kernel does the r x r solves by
-// Cholesky in FP64.
+// R^T) are the same operation on two "sides" (admm_uv_body).  It also forms
+// the partial sums of basis^T (pen * F - M) for the next iteration's P_U /
+// P_V, so the big matrices are read once per iteration; admm_reduce_body
+// sums those partials in a fixed order, and the r x r solves are Cholesky
+// factorisations in FP64 in one workgroup.  For one request the iteration
+// runs as two launches plus two reductions (admm_half_kernel): the Yt^T
+// solve beside the U-side row update, then the next Xt solve beside the
+// V-side row update; serving runs both solves and both sides per launch
+// over a batch of requests.
 #include "cnmf_internal.hpp"
 #include "small_dense.hpp"
 
@@ -306,13 +309,6 @@ __device__ __forceinline__ void admm_reduce_body(const double* __restrict__ Pp, 
     block_sum_parts<kRedNT, kRedEPB, T>(P + (int64_t)parts0 * kr, parts1, kr, kr, e0, Pred + kr, red);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kRedNT) void admm_reduce_kernel(const double* __restrict__ Pp, int parts0,
-                                                             int parts1, int64_t kr, double* __restrict__ Pred) {
-  __shared__ double red[kRedNT];
-  admm_reduce_body<T>(Pp, parts0, parts1, kr, Pred, gridDim.x / 2, blockIdx.x, red);
-}
-
 int admm_reduce_blocks(int k, int r) { return 2 * (int)(((int64_t)k * r + kRedEPB - 1) / kRedEPB); }
 
 __global__ __launch_bounds__(kRedNT) void admm_reduce_batch_kernel(const AdmmJob* __restrict__ jobs,
@@ -573,14 +569,6 @@ __device__ __forceinline__ void admm_solve_chol_body(const double* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(kSolveNT) void admm_solve_chol_kernel(const double* __restrict__ Pred,
-                                                                   const double* __restrict__ At, int k, int r,
-                                                                   double lam, double phi, int first,
-                                                                   double* __restrict__ XY, int* flags) {
-  extern __shared__ double sm[];
-  admm_solve_chol_body(Pred, At, k, r, lam, phi, first, XY, flags, sm);
-}
-
 // One workgroup per job.
 __global__ __launch_bounds__(kSolveNT) void admm_solve_batch_kernel(const AdmmJob* __restrict__ jobs) {
   extern __shared__ double sm[];
@@ -588,24 +576,111 @@ __global__ __launch_bounds__(kSolveNT) void admm_solve_batch_kernel(const AdmmJo
   admm_solve_chol_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.flags, sm);
 }
 
+// ---------------------------------------------------------------------------
+// Split schedule for one request.  In Alg. 3 the U-side row update of an
+// iteration reads Xt but not Yt^T, and only the next iteration's Xt solve
+// needs its partial P_U; likewise the V side with Yt^T and the next Yt^T
+// solve.  So the U-side row update shares a launch with the Yt^T solve, and
+// the V-side row update one with the next iteration's Xt solve: block 0 is
+// the solve of one side, the other blocks are the row update.  Each value is
+// computed by the same code as in the one-launch form.
+// ---------------------------------------------------------------------------
+template <int NB, int PASS>
+__device__ __forceinline__ void admm_solve_side_nb(const AdmmHalf& a, double* sm) {
+  constexpr int NT = kSolveNT;
+  constexpr int N = 16 * NB;
+  const int k = a.k, r = a.r;
+  const CholLayout Ly = chol_layout(k, r);
+  double* S = sm + Ly.s_off;
+  const int64_t kr = (int64_t)k * r;
+  const double* XY = a.XY;
+  // S = Yt^T for pass 0 (P_V / phi on the first iteration, Alg. 3's
+  // initialisation), Xt for pass 1; zero padded to kp x N
+  for (int e = threadIdx.x; e < Ly.kp * N; e += NT) {
+    const int i = e / N, j = e - i * N;
+    double v = 0.0;
+    if (i < k && j < r)
+      v = PASS == 1 ? XY[i * r + j] : (a.first ? a.Pred[kr + i * r + j] / a.phi : XY[kr + i * r + j]);
+    S[i * Ly.ld + j] = v;
+  }
+  __syncthreads();
+  float* XYf = reinterpret_cast<float*>(a.XY + 2 * kr);
+  if constexpr (PASS == 0)
+    chol_side<NB, 0>(a.At, a.Pred, k, r, a.lam, a.XY, XYf, a.flags, Ly, sm);
+  else
+    chol_side<NB, 1>(a.At, a.Pred + kr, k, r, a.phi, a.XY + kr, XYf + Ly.kp * N, a.flags, Ly, sm);
+}
+
+template <int PASS>
+__device__ __forceinline__ void admm_solve_side(const AdmmHalf& a, double* sm) {
+  switch ((a.r + 15) / 16) {
+    case 1: admm_solve_side_nb<1, PASS>(a, sm); break;
+    case 2: admm_solve_side_nb<2, PASS>(a, sm); break;
+    case 3: admm_solve_side_nb<3, PASS>(a, sm); break;
+    default: admm_solve_side_nb<4, PASS>(a, sm); break;
+  }
+}
+
+template <typename T, int CH>
+__global__ __launch_bounds__(kSolveNT) void admm_half_kernel(AdmmHalf a) {
+  extern __shared__ double sm[];
+  if (a.solve && blockIdx.x == 0) {
+    if (a.pass == 0)
+      admm_solve_side<0>(a, sm);
+    else
+      admm_solve_side<1>(a, sm);
+    return;
+  }
+  const int b = (int)blockIdx.x - (a.solve ? 1 : 0);
+  admm_uv_body<T, CH>(a.s0, a.s1, a.parts0, a.side ? a.parts0 + b : b, a.XY, a.k, a.r, a.xi, a.mode, a.Pp,
+                      a.rpb0, a.rpb1, reinterpret_cast<char*>(sm));
+}
+
 template <typename T>
-hipError_t launch_admm_solve(const double* Pp, int parts0, int parts1, const double* At, int k, int r,
-                             double lam, double phi, int first, double* XY, double* Pred, int* flags,
-                             hipStream_t st) {
-  if (r > 64 || k > kCholMaxK || admm_solve_lds_bytes(k, r) > 160 * 1024) return hipErrorInvalidValue;
-  int64_t kr = (int64_t)k * r;
-  int nbh = (int)((kr + kRedEPB - 1) / kRedEPB);
-  hipLaunchKernelGGL(admm_reduce_kernel<T>, dim3(2 * nbh), dim3(kRedNT), 0, st, Pp, parts0, parts1, kr, Pred);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const size_t sm = chol_layout(k, r).total * sizeof(double);
-  hipFuncSetAttribute((const void*)admm_solve_chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  hipLaunchKernelGGL(admm_solve_chol_kernel, dim3(1), dim3(kSolveNT), sm, st, Pred, At, k, r, lam, phi, first, XY,
-                     flags);
+hipError_t launch_admm_half(const AdmmHalf& a, hipStream_t st) {
+  const int k = a.k, r = a.r;
+  if (r > 64 || k > kCholMaxK || a.parts0 < 1 || a.parts1 < 1 || (!a.solve && !a.uv)) return hipErrorInvalidValue;
+  const size_t solve_lds = a.solve ? chol_layout(k, r).total * sizeof(double) : 0;
+  if (solve_lds > 160 * 1024) return hipErrorInvalidValue;
+  const int nuv = a.side ? a.parts1 : a.parts0;
+  const int KP = (k + 15) / 16 * 16, RP = (r + 15) / 16 * 16;
+  auto lds = [&](int ch) { return ((size_t)KP * (RP + 1) + (size_t)ch * (KP + 1) + (size_t)ch * (RP + 1)) * sizeof(T); };
+  const dim3 grid((a.uv ? nuv : 0) + (a.solve ? 1 : 0));
+  if (lds(64) <= 160 * 1024) {
+    const size_t sm = std::max(solve_lds, lds(64));
+    hipFuncSetAttribute((const void*)admm_half_kernel<T, 64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    hipLaunchKernelGGL((admm_half_kernel<T, 64>), grid, dim3(kSolveNT), sm, st, a);
+  } else {
+    const size_t sm = std::max(solve_lds, lds(32));
+    hipFuncSetAttribute((const void*)admm_half_kernel<T, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    hipLaunchKernelGGL((admm_half_kernel<T, 32>), grid, dim3(kSolveNT), sm, st, a);
+  }
   CNMF_LAUNCH_CHECK();
 }
-template hipError_t launch_admm_solve<float>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, int*, hipStream_t);
-template hipError_t launch_admm_solve<double>(const double*, int, int, const double*, int, int, double, double, int, double*, double*, int*, hipStream_t);
+template hipError_t launch_admm_half<float>(const AdmmHalf&, hipStream_t);
+template hipError_t launch_admm_half<double>(const AdmmHalf&, hipStream_t);
+
+// The fixed-order sums of one side's partials (side 0: P_U, 1: P_V, 2: both).
+template <typename T>
+__global__ __launch_bounds__(kRedNT) void admm_reduce_side_kernel(const double* __restrict__ Pp, int parts0,
+                                                                  int parts1, int64_t kr, double* __restrict__ Pred,
+                                                                  int nbh, int b0) {
+  __shared__ double red[kRedNT];
+  admm_reduce_body<T>(Pp, parts0, parts1, kr, Pred, nbh, b0 + (int)blockIdx.x, red);
+}
+
+template <typename T>
+hipError_t launch_admm_reduce(const double* Pp, int parts0, int parts1, int k, int r, int side, double* Pred,
+                              hipStream_t st) {
+  if (side < 0 || side > 2) return hipErrorInvalidValue;
+  const int64_t kr = (int64_t)k * r;
+  const int nbh = (int)((kr + kRedEPB - 1) / kRedEPB);
+  hipLaunchKernelGGL(admm_reduce_side_kernel<T>, dim3(side == 2 ? 2 * nbh : nbh), dim3(kRedNT), 0, st, Pp, parts0,
+                     parts1, kr, Pred, nbh, side == 1 ? nbh : 0);
+  CNMF_LAUNCH_CHECK();
+}
+template hipError_t launch_admm_reduce<float>(const double*, int, int, int, int, int, double*, hipStream_t);
+template hipError_t launch_admm_reduce<double>(const double*, int, int, int, int, int, double*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Batched ADMM step (serving): for every job, the fixed-order partial sums,

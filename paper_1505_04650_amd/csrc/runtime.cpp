@@ -353,7 +353,14 @@ struct AdmmWs {
   int rparts = 0;
 };
 
-int uv_parts(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (rows + 63) / 64)); }
+// Row-update blocks of one side: 64-row sweeps, at most 240 blocks, so that
+// the blocks of one side are resident together beside the solve's block when
+// each takes a whole CU (the split schedule's launches).
+int uv_parts(int64_t rows) {
+  const int64_t sweeps = std::max<int64_t>(1, (rows + 63) / 64);
+  const int64_t per = (sweeps + 239) / 240;
+  return (int)((sweeps + per - 1) / per);
+}
 
 template <typename T>
 void layout_admm(Arena& a, AdmmWs<T>& w, int64_t m, int64_t n, int k, int r) {
@@ -877,11 +884,50 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
   if (d->method == CNMF_ADMM) {
     Span sp(h, ST_ITER, (double)d->iters * 4.0 * (double)(m + n) * k * r);
     AdmmJob J = admm_job_of(f, A, d);
+    admm_job_prepare(J);
+    AdmmHalf H{};
+    H.s0 = J.s0;
+    H.s1 = J.s1;
+    H.At = J.At;
+    H.Pred = J.Pred;
+    H.XY = J.XY;
+    H.Pp = J.Pp;
+    H.flags = J.flags;
+    H.lam = J.lam;
+    H.phi = J.phi;
+    H.xi = J.xi;
+    H.k = k;
+    H.r = r;
+    H.parts0 = J.parts0;
+    H.parts1 = J.parts1;
+    H.rpb0 = J.rpb0;
+    H.rpb1 = J.rpb1;
+    // P_U, P_V of the initial U, V^T, then the first Xt (Yt^T from P_V / phi)
+    if (d->iters > 0) {
+      HIPCHK(h, launch_admm_reduce<T>(aw.Pp, aw.parts0, aw.parts1, k, r, 2, aw.Pred, st));
+      H.solve = 1;
+      H.pass = 0;
+      H.first = 1;
+      H.uv = 0;
+      HIPCHK(h, launch_admm_half<T>(H, st));
+    }
+    H.first = 0;
+    H.uv = 1;
     for (int it = 0; it < d->iters; ++it) {
-      HIPCHK(h, launch_admm_solve<T>(aw.Pp, aw.parts0, aw.parts1, w.At, k, r, d->lambda, d->phi, it == 0, aw.XY,
-                                     aw.Pred, w.flags + 2, st));
-      HIPCHK(h, launch_admm_uv<T>(J.s0, J.s1, 2, aw.XY, k, r, d->xi, it + 1 == d->iters ? 2 : 1, aw.Pp, aw.parts0,
-                                  aw.parts1, st));
+      const bool last = it + 1 == d->iters;
+      H.mode = last ? 2 : 1;
+      // Yt^T of this iteration beside the U-side row update (which needs Xt only)
+      H.solve = 1;
+      H.pass = 1;
+      H.side = 0;
+      HIPCHK(h, launch_admm_half<T>(H, st));
+      if (!last) HIPCHK(h, launch_admm_reduce<T>(aw.Pp, aw.parts0, aw.parts1, k, r, 0, aw.Pred, st));
+      // the next iteration's Xt beside the V-side row update
+      H.solve = last ? 0 : 1;
+      H.pass = 0;
+      H.side = 1;
+      HIPCHK(h, launch_admm_half<T>(H, st));
+      if (!last) HIPCHK(h, launch_admm_reduce<T>(aw.Pp, aw.parts0, aw.parts1, k, r, 1, aw.Pred, st));
     }
   } else if (d->method == CNMF_MU) {
     Span sp(h, ST_ITER, (double)d->iters * (4.0 * (double)(m + n) * k * r + 4.0 * (double)(m + n) * r * r));
