@@ -493,45 +493,92 @@ __device__ __forceinline__ void chol_side(const double* __restrict__ At, const d
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int i = 0; i < 4; ++i) z[b][i] = E[xr * ld + 16 * b + g + 4 * i];
+      // The LDS operands of block b + 1 (b - 1 going back) are loaded before
+      // block b's products, and sched_barrier keeps that order, so their
+      // latency overlaps the dependent MFMA chain.  ol[a][s]: -L entries of
+      // the tiles that meet block b, ov[s]: V_b (transposed going back).
+      double ol[2][NB][4], ov[2][4];
+      auto load_fwd = [&](int b, double (&l)[NB][4], double (&v)[4]) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+          if (a < b)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) l[a][s] = -Mb[(16 * b + c) * ld + 16 * a + 4 * s + g];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = V[b * 272 + c * 17 + 4 * s + g];
+      };
+      auto load_bwd = [&](int b, double (&l)[NB][4], double (&v)[4]) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+          if (a > b)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) l[a][s] = -Mb[(16 * a + 4 * s + g) * ld + 16 * b + c];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = V[b * 272 + (4 * s + g) * 17 + c];
+      };
+      load_fwd(0, ol[0], ov[0]);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
+        if (b + 1 < NB)
+          load_fwd(b + 1, ol[(b + 1) & 1], ov[(b + 1) & 1]);
+        else
+          load_bwd(NB - 1, ol[(b + 1) & 1], ov[(b + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
         doublex4 t = z[b];
 #pragma unroll
         for (int a = 0; a < b; ++a)
 #pragma unroll
           for (int s = 0; s < 4; ++s)
-            t = __builtin_amdgcn_mfma_f64_16x16x4f64(-Mb[(16 * b + c) * ld + 16 * a + 4 * s + g], z[a][s], t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f64_16x16x4f64(ol[b & 1][a][s], z[a][s], t, 0, 0, 0);
         doublex4 y = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-          y = __builtin_amdgcn_mfma_f64_16x16x4f64(V[b * 272 + c * 17 + 4 * s + g], t[s], y, 0, 0, 0);
+          y = __builtin_amdgcn_mfma_f64_16x16x4f64(ov[b & 1][s], t[s], y, 0, 0, 0);
         z[b] = y;
+        __builtin_amdgcn_sched_barrier(0);
       }
+      // back: buffer (NB + u) & 1 holds block NB - 1 - u
 #pragma unroll
-      for (int b = NB - 1; b >= 0; --b) {
+      for (int u = 0; u < NB; ++u) {
+        const int b = NB - 1 - u, cur = (NB + u) & 1;
+        if (b > 0) load_bwd(b - 1, ol[cur ^ 1], ov[cur ^ 1]);
+        __builtin_amdgcn_sched_barrier(0);
         doublex4 t = z[b];
 #pragma unroll
-        for (int a = b + 1; a < NB; ++a)
+        for (int a = 0; a < NB; ++a)
+          if (a > b)
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
-            t = __builtin_amdgcn_mfma_f64_16x16x4f64(-Mb[(16 * a + 4 * s + g) * ld + 16 * b + c], z[a][s], t, 0, 0, 0);
+            for (int s = 0; s < 4; ++s)
+              t = __builtin_amdgcn_mfma_f64_16x16x4f64(ol[cur][a][s], z[a][s], t, 0, 0, 0);
         doublex4 x = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-          x = __builtin_amdgcn_mfma_f64_16x16x4f64(V[b * 272 + (4 * s + g) * 17 + c], t[s], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f64_16x16x4f64(ov[cur][s], t[s], x, 0, 0, 0);
         z[b] = x;
+        __builtin_amdgcn_sched_barrier(0);
       }
-      // X[xr][16 b + g + 4 i] = item i of tile b: to XY and, for pass 0,
-      // into S for the other side (no wave reads S in this phase)
+      // X[xr][16 b + g + 4 i] = item i of tile b: back into this wave's rows
+      // of E (and, for pass 0, into S for the other side; no wave reads S in
+      // this phase); then the strip's rows of out (k x r) and outf (kp x N),
+      // one contiguous range each, in coalesced stores
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int col = 16 * b + g + 4 * i;
-          if (xr < k && col < r) out[xr * r + col] = z[b][i];
-          outf[xr * N + col] = (float)z[b][i];
+          E[xr * ld + col] = z[b][i];
           if (PASS == 0) S[xr * ld + col] = z[b][i];
         }
+      const int r0 = 16 * rb;
+      const int nrow = min(16, k - r0);
+      for (int row = 0; row < nrow; ++row)
+        if (lane < r) out[(r0 + row) * r + lane] = E[(r0 + row) * ld + lane];
+      for (int e4 = lane; e4 < 4 * N; e4 += 64) {
+        const int row = e4 / (N / 4), col = 4 * e4 - row * N;
+        const double* src = E + (r0 + row) * ld + col;
+        *reinterpret_cast<float4*>(outf + (r0 + row) * N + col) =
+            make_float4((float)src[0], (float)src[1], (float)src[2], (float)src[3]);
+      }
     }
   }
   __syncthreads();
