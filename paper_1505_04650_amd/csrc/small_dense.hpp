@@ -268,12 +268,16 @@ __device__ __forceinline__ double rsqrt_fast(double d) {
 // only the first `steps` (uniform) are taken.  The dependent chain of a step
 // is: pivot by readlane, floor, 1 / sqrt, the column entry, its readlane by
 // the next pivot row and that row's update.
-template <bool FULL>
+// extra(s) is called before step s (every s < 16, taken or not): the caller
+// issues independent MFMA work there, which runs while the step's dependent
+// VALU chain waits.
+template <bool FULL, typename X>
 __device__ __forceinline__ void wave_panel_steps(double (&a)[16], int c0, int steps, double* colbuf,
-                                                 double floor_piv, double& myinv, int& nbad) {
+                                                 double floor_piv, double& myinv, int& nbad, X extra) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
+    extra(s);
     if (FULL || s < steps) {
       const double d0 = readlane_d(a[s], c0 + s);
       nbad += (d0 > floor_piv) ? 0 : 1;   // also counts NaN
@@ -327,59 +331,80 @@ __device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double
   double* colbuf = W;       // the current column of L
   double* dinv = W + 64;    // 1 / L[i][i]
   int nbad = 0;
+  // The trailing tiles (ti >= tj >= 1) stay in registers in the MFMA result
+  // layout (item i of lane (c, g): row 16 ti + g + 4 i, column 16 tj + c).
+  // After panel P only column P + 1 is updated at once (the next panel needs
+  // it); the updates of the tiles right of it are issued between the next
+  // panel's steps.  Each tile still receives the panels' updates in panel
+  // order, by the same products.
+  constexpr int NT = NB > 1 ? NB * (NB - 1) / 2 : 1;
+  doublex4 tl[NT];
+#pragma unroll
+  for (int ti = 1; ti < NB; ++ti)
+#pragma unroll
+    for (int tj = 1; tj <= ti; ++tj)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tl[(ti - 1) * ti / 2 + tj - 1][i] = M[(16 * ti + g + 4 * i) * ld + 16 * tj + c];
+  constexpr int kMaxT = NB > 1 ? NB - 1 : 1;
+  double lv[kMaxT][4];   // L[16 (P + 1 + u) + c][16 P + 4 s + g] of the last factored panel P
 #pragma unroll
   for (int P = 0; P < NB; ++P) {
     const int c0 = 16 * P;
     const bool act = lane >= c0 && lane < N;
+    if (P >= 1) {
+#pragma unroll
+      for (int ti = P; ti < NB; ++ti)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          M[(16 * ti + g + 4 * i) * ld + c0 + c] = tl[(ti - 1) * ti / 2 + P - 1][i];
+    }
     double a[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) a[t] = act ? M[lane * ld + c0 + t] : 0.0;
     double myinv = 1.0;
     const int steps = n - c0;   // uniform
+    // panel P - 1's updates of the tiles ti >= tj >= P + 1, one product per step
+    auto deferred = [&](int q) {
+      if (P >= 1) {
+        int idx = 0;
+#pragma unroll
+        for (int ti = P + 1; ti < NB; ++ti)
+#pragma unroll
+          for (int tj = P + 1; tj <= ti; ++tj)
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+              if (idx == q) {
+                doublex4& t = tl[(ti - 1) * ti / 2 + tj - 1];
+                t = __builtin_amdgcn_mfma_f64_16x16x4f64(-lv[ti - P][s4], lv[tj - P][s4], t, 0, 0, 0);
+              }
+              ++idx;
+            }
+      }
+    };
     if (steps >= 16)
-      wave_panel_steps<true>(a, c0, steps, colbuf, floor_piv, myinv, nbad);
+      wave_panel_steps<true>(a, c0, steps, colbuf, floor_piv, myinv, nbad, deferred);
     else
-      wave_panel_steps<false>(a, c0, steps, colbuf, floor_piv, myinv, nbad);
+      wave_panel_steps<false>(a, c0, steps, colbuf, floor_piv, myinv, nbad, deferred);
     if (act) {
 #pragma unroll
       for (int t = 0; t < 16; ++t) M[lane * ld + c0 + t] = a[t];
     }
     if (lane >= c0 && lane < c0 + 16) dinv[lane] = myinv;
-    // trailing update of the lower block triangle: M[ti][tj] -= L[ti][P] L[tj][P]^T
     if (P + 1 < NB) {
-      constexpr int kMaxT = NB - 1;
-      double lv[kMaxT > 0 ? kMaxT : 1][4];   // L[16 ti + c][c0 + 4 s + g], ti = P + 1 + u
-      doublex4 acc[kMaxT > 0 ? kMaxT * (kMaxT + 1) / 2 : 1];
+      // column P + 1 now: M[ti][P + 1] -= L[ti][P] L[P + 1][P]^T
 #pragma unroll
-      for (int u = 0; u < kMaxT; ++u) {
+      for (int u = 0; u < kMaxT; ++u)
         if (P + 1 + u < NB) {
 #pragma unroll
-          for (int s = 0; s < 4; ++s) lv[u][s] = M[(16 * (P + 1 + u) + c) * ld + c0 + 4 * s + g];
+          for (int s4 = 0; s4 < 4; ++s4) lv[u][s4] = M[(16 * (P + 1 + u) + c) * ld + c0 + 4 * s4 + g];
         }
+#pragma unroll
+      for (int ti = P + 1; ti < NB; ++ti) {
+        doublex4& t = tl[(ti - 1) * ti / 2 + P];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+          t = __builtin_amdgcn_mfma_f64_16x16x4f64(-lv[ti - P - 1][s4], lv[0][s4], t, 0, 0, 0);
       }
-#pragma unroll
-      for (int u = 0; u < kMaxT; ++u)
-#pragma unroll
-        for (int v = 0; v <= u; ++v) {
-          if (P + 1 + u < NB) {
-            const int ti = P + 1 + u, tj = P + 1 + v;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[u * (u + 1) / 2 + v][i] = M[(16 * ti + g + 4 * i) * ld + 16 * tj + c];
-          }
-        }
-#pragma unroll
-      for (int u = 0; u < kMaxT; ++u)
-#pragma unroll
-        for (int v = 0; v <= u; ++v) {
-          if (P + 1 + u < NB) {
-            const int ti = P + 1 + u, tj = P + 1 + v;
-            doublex4 t = acc[u * (u + 1) / 2 + v];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) t = __builtin_amdgcn_mfma_f64_16x16x4f64(-lv[u][s], lv[v][s], t, 0, 0, 0);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) M[(16 * ti + g + 4 * i) * ld + 16 * tj + c] = t[i];
-          }
-        }
     }
   }
   // V_q = L[q][q]^-1, lanes 16 q + v: column v, x = e_v, then for each i
