@@ -112,9 +112,12 @@ def test_factorize_admm_fp64_parity(c1):
 
 # The r x r solves across block counts (r up to 64) and sketch widths (k up to
 # 128): one and two 16-row strips of X per wave, up to the largest shapes the
-# single-workgroup solve holds in LDS.
+# single-workgroup solve holds in LDS.  The last two shapes have more than
+# 240 64-row sweeps on one side, so its row-update blocks take two sweeps
+# each (129 blocks of 128 rows, the last one ragged).
 @pytest.mark.parametrize("m,n,r,k", [(420, 300, 5, 9), (500, 400, 37, 47), (500, 400, 48, 80), (500, 400, 64, 74),
-                                     (500, 400, 20, 100), (500, 400, 64, 112), (500, 400, 48, 128)])
+                                     (500, 400, 20, 100), (500, 400, 64, 112), (500, 400, 48, 128),
+                                     (16437, 150, 10, 20), (150, 16437, 12, 22)])
 def test_factorize_admm_fp64_solve_shapes(m, n, r, k):
     A = WL.nmf_matrix(m, n, r, 0.05, seed=31 + r, dtype=np.float64)
     g = np.random.default_rng(41 + k)
