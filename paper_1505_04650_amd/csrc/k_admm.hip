@@ -293,7 +293,7 @@ template hipError_t launch_admm_uv<double>(AdmmSide, AdmmSide, int, const double
 // side and P_V over the parts1 blocks of the V side, into Pred[0], Pred[1].
 // Blocks [0, nbh) reduce P_U, blocks [nbh, 2 nbh) reduce P_V.
 constexpr int kRedNT = 256;
-constexpr int kRedEPB = 8;
+constexpr int kRedEPB = 16;
 
 // The partials are stored in the factors' precision T (the row updates
 // accumulate them in T on the MFMA) and summed in FP64.
