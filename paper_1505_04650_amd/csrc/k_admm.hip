@@ -630,7 +630,8 @@ __global__ __launch_bounds__(kSolveNT) void admm_solve_batch_kernel(const AdmmJo
 // solve.  So the U-side row update shares a launch with the Yt^T solve, and
 // the V-side row update one with the next iteration's Xt solve: block 0 is
 // the solve of one side, the other blocks are the row update.  Each value is
-// computed by the same code as in the one-launch form.
+// computed by the same code as in the serving batch, where both solves share
+// a workgroup.
 // ---------------------------------------------------------------------------
 template <int NB, int PASS>
 __device__ __forceinline__ void admm_solve_side_nb(const AdmmHalf& a, double* sm) {
