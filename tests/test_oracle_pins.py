@@ -123,6 +123,26 @@ def test_small_sketches_norms_and_exact_case():
     assert abs(np.linalg.norm(s4["At"]) - np.linalg.norm(A4)) < 1e-12 * np.linalg.norm(A4)
 
 
+def test_ac_is_the_projection_of_a_onto_the_right_basis():
+    """Ac = A R^T (Alg. 2's compressed data): Ac R is the orthogonal projection
+    of A's rows onto range(R^T), so the remainder is orthogonal to R's rows,
+    ||Ac||_F <= ||A||_F, and an A lying in range(R^T) is reproduced exactly;
+    L^T Ac equals At (both are L^T A R^T).  A slip such as A L, A R or R A^T
+    fails one of these."""
+    g = rng(41)
+    m, n, k = 90, 70, 9
+    A = g.random((m, n))
+    s = O.sketch(A, g.standard_normal((n, k)), g.standard_normal((m, k)), q=1)
+    Ac, R, L = s["Ac"], s["R"], s["L"]
+    assert Ac.shape == (m, k)
+    assert np.abs((A - Ac @ R) @ R.T).max() < 1e-12 * np.abs(A).max()
+    assert np.linalg.norm(Ac) <= np.linalg.norm(A) * (1 + 1e-14)
+    assert np.abs(L.T @ Ac - s["At"]).max() < 1e-12 * np.abs(s["At"]).max()
+    A4 = g.random((m, 4)) @ g.random((4, n))
+    s4 = O.sketch(A4, g.standard_normal((n, k)), g.standard_normal((m, k)), q=1)
+    assert np.linalg.norm(A4 - s4["Ac"] @ s4["R"]) <= 1e-13 * np.linalg.norm(A4)
+
+
 # --------------------------------------------------------------------------
 # Alg. 3 (Appendix B)
 # --------------------------------------------------------------------------
