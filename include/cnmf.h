@@ -28,8 +28,10 @@
  *     is enqueued, with outputs untouched.  A HIP launch or allocation error
  *     returns CNMF_EDEVICE / CNMF_ENOMEM.  cnmf_last_error gives a message
  *     for the last failing call on a handle.  A handle is not thread safe.
- *   - Random numbers: the Gaussian test matrices are INPUTS (omega_*), so
- *     results are a pure function of (A, Omega, initial factors, params).
+ *   - Random numbers: the Gaussian test matrices of Alg. 1 are either
+ *     INPUTS (omega_*) or drawn on the device from `seed` by the
+ *     counter-based generator of cnmf_gaussian, so results are a pure
+ *     function of (A, Omega or seed, initial factors, params).
  */
 #ifndef CNMF_H_
 #define CNMF_H_
@@ -46,7 +48,8 @@ typedef enum {
   CNMF_EINVAL = -1,      /* invalid argument (detected before any launch)     */
   CNMF_ENOMEM = -2,      /* device workspace could not be allocated           */
   CNMF_EDEVICE = -3,     /* HIP runtime / launch error                        */
-  CNMF_EBREAKDOWN = -4,  /* orthonormalisation failed (Gram not positive def.) */
+  CNMF_EBREAKDOWN = -4,  /* orthonormalisation breakdown the fallback did not
+                            resolve (reported by cnmf_synchronize)           */
   CNMF_ENOTSUP = -5,     /* valid but unsupported size / precision combination */
   CNMF_EBUSY = -6
 } cnmf_status;
@@ -82,6 +85,26 @@ const char* cnmf_last_error(const cnmf_handle* h);
 const char* cnmf_status_string(cnmf_status s);
 /* Library version string, e.g. "cnmf-mi355x 0.1". */
 const char* cnmf_version(void);
+/* Wait for the work enqueued on the handle's stream.  Returns CNMF_EDEVICE
+ * for an asynchronous HIP fault, CNMF_EBREAKDOWN if a call enqueued since
+ * the previous cnmf_synchronize hit an orthonormalisation breakdown that the
+ * fallback could not resolve (see cnmf_sketch_desc; the count is then
+ * cleared), CNMF_OK otherwise. */
+cnmf_status cnmf_synchronize(cnmf_handle* h);
+
+/* Gaussian test matrix of Alg. 1 (Section 2: "draw a Gaussian random
+ * matrix"), as the sketches draw it: out_dev (device, rows x cols FP64,
+ * row-major, leading dimension ld >= cols) receives iid N(0, 1) entries.
+ * Generator: Philox4x32-10 (Salmon et al., SC'11) with the counter
+ * (col / 2, row, matrix_id, 0) and the key (seed mod 2^32, seed / 2^32);
+ * the output words x0..x3 give u1 = ((x1:x0 >> 11) + 1) 2^-53 and
+ * u2 = (x3:x2 >> 11) 2^-53, and the Box-Muller pair
+ * sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2) fills columns (even, odd).
+ * Entry (i, j) depends only on (seed, matrix_id, i, j).  Errors:
+ * CNMF_EINVAL for a NULL pointer, negative sizes or ld < cols; rows above
+ * 2^30: CNMF_ENOTSUP. */
+cnmf_status cnmf_gaussian(cnmf_handle* h, uint64_t seed, int32_t matrix_id, int64_t rows, int32_t cols,
+                          double* out_dev, int64_t ld);
 
 /* ---------------------------------------------------------------------------
  * Input matrix A (Section 1, problem (nmf)): m x n, row-major, lda >= n.
@@ -111,13 +134,31 @@ typedef struct {
  *   The workspace grows by 4 m n bytes for BF16 copies and 2 m n bytes
  *   for FP8 copies.
  * Orthonormalisation (CholeskyQR2) always runs in FP64.
- * omega_left_dev:  n x k FP64, row-major (ld = k): test matrix for A.
+ * Orthonormalisation breakdown (k > rank A makes Y rank deficient, the
+ *   case Section 2's bound covers with sigma_{r+1} = 0, and plain
+ *   CholeskyQR then fails): the first CholeskyQR pass treats a column whose
+ *   pivot is <= 1e-14 max diag(Y^T Y) as dependent on the earlier ones, the
+ *   second pass does the same for pivots <= 1e-8 max diag(Q1^T Q1) (a
+ *   dependent column that the first pass's Gram could not tell apart);
+ *   each such column is replaced by a fresh Gaussian column (test matrix
+ *   16 + 4 p + side, or 16 + 4 p + 2 + side in the second pass, for the
+ *   product of pass p, drawn from `seed`), and a third CholeskyQR pass runs
+ *   when the second one replaced a column.  range(Q) then contains range(Y)
+ *   and Q^T Q = I.  Replaced columns are counted in stats[2]; a breakdown
+ *   the fallback cannot resolve (a NaN pivot, or a rank-deficient third
+ *   pass) is counted in stats[3] and makes the next cnmf_synchronize
+ *   return CNMF_EBREAKDOWN.
+ * seed: key of the counter-based generator (cnmf_gaussian) for the test
+ *   matrices drawn on the device and for completion columns.
+ * omega_left_dev:  n x k FP64, row-major (ld = k): test matrix for A, or
+ *   NULL to draw it on the device (cnmf_gaussian matrix id 0 under seed).
  * omega_right_dev: m x k FP64, row-major (ld = k): test matrix for A^T
- *   (required when CNMF_RIGHT is set). */
+ *   (used when CNMF_RIGHT is set), or NULL to draw it (matrix id 1). */
 typedef struct {
   int32_t r, k, q, sides;
   cnmf_dtype pass_dtype;
   cnmf_dtype final_dtype;
+  uint64_t seed;
   const double* omega_left_dev;
   const double* omega_right_dev;
 } cnmf_sketch_desc;
@@ -130,8 +171,9 @@ typedef struct {
  *   B_dev  k x n   B = L^T A                 -- needs CNMF_LEFT
  *   At_dev k x k   At = L^T A R^T            -- needs both sides
  *   Ac_dev m x k   Ac = A R^T                -- needs CNMF_RIGHT (one extra pass)
- *   stats_dev FP64[4]: max|L^T L - I|, max|R R^T - I|, number of Cholesky
- *     breakdowns repaired, 0. */
+ *   stats_dev FP64[4]: max|L^T L - I|, max|R R^T - I|, number of
+ *     CholeskyQR breakdowns repaired by the fallback, number left
+ *     unresolved. */
 typedef struct {
   void* L_dev;
   void* R_dev;

@@ -23,7 +23,7 @@ EXPORTED = [
     "cnmf_create", "cnmf_destroy", "cnmf_last_error", "cnmf_status_string", "cnmf_version",
     "cnmf_sketch", "cnmf_factorize", "snmf_select", "cnmf_spa", "cnmf_workspace_bytes",
     "cnmf_set_timing", "cnmf_stage_ms", "cnmf_range_product", "cnmf_stage_flops", "cnmf_stage_launches",
-    "cnmf_range_product_lowp",
+    "cnmf_range_product_lowp", "cnmf_synchronize", "cnmf_gaussian",
     "cnmf_server_start", "cnmf_server_submit", "cnmf_server_poll", "cnmf_server_release",
     "cnmf_server_get_stats", "cnmf_server_stop", "cnmf_server_last_error", "cnmf_server_simulate",
 ]
@@ -36,7 +36,7 @@ class cnmf_input(C.Structure):
 
 class cnmf_sketch_desc(C.Structure):
     _fields_ = [("r", C.c_int32), ("k", C.c_int32), ("q", C.c_int32), ("sides", C.c_int32),
-                ("pass_dtype", C.c_int), ("final_dtype", C.c_int),
+                ("pass_dtype", C.c_int), ("final_dtype", C.c_int), ("seed", C.c_uint64),
                 ("omega_left_dev", C.c_void_p), ("omega_right_dev", C.c_void_p)]
 
 
@@ -103,6 +103,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.cnmf_status_string.restype = C.c_char_p
     lib.cnmf_version.argtypes = []
     lib.cnmf_version.restype = C.c_char_p
+    lib.cnmf_synchronize.argtypes = [vp]
+    lib.cnmf_synchronize.restype = st
+    lib.cnmf_gaussian.argtypes = [vp, C.c_uint64, i32, i64, i32, vp, i64]
+    lib.cnmf_gaussian.restype = st
     lib.cnmf_sketch.argtypes = [vp, C.POINTER(cnmf_input), C.POINTER(cnmf_sketch_desc), C.POINTER(cnmf_sketch_out)]
     lib.cnmf_sketch.restype = st
     lib.cnmf_factorize.argtypes = [vp, C.POINTER(cnmf_input), C.POINTER(cnmf_factorize_desc),

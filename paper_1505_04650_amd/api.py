@@ -89,9 +89,10 @@ def _input(A: torch.Tensor) -> L.cnmf_input:
     return L.cnmf_input(_ptr(A), _DT[A.dtype], A.shape[0], A.shape[1], A.stride(0))
 
 
-def _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype):
+def _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype, seed=0):
     return L.cnmf_sketch_desc(int(r), int(k), int(q), _SIDES[sides] if isinstance(sides, str) else int(sides),
-                              _PREC[pass_dtype], _PREC[final_dtype], _ptr(omega_left), _ptr(omega_right))
+                              _PREC[pass_dtype], _PREC[final_dtype], int(seed) & (2 ** 64 - 1),
+                              _ptr(omega_left), _ptr(omega_right))
 
 
 def _acc_dtype(A, pass_dtype):
@@ -117,9 +118,10 @@ class Sketch:
 
 
 def sketch(A, r, k, q, omega_left=None, omega_right=None, sides="both", pass_dtype=None, final_dtype=None,
-           want_ac=False, handle: Handle | None = None) -> Sketch:
+           want_ac=False, seed=0, handle: Handle | None = None) -> Sketch:
     """Structured random compression (Alg. 1) of A on one or both sides, and
-    the small sketches B = L^T A, At = L^T A R^T, Ac = A R^T."""
+    the small sketches B = L^T A, At = L^T A R^T, Ac = A R^T.  A test matrix
+    left as None is drawn on the device from `seed` (see gaussian())."""
     h = handle or default_handle()
     pass_dtype, final_dtype = _default_prec(A, pass_dtype, final_dtype)
     m, n = A.shape
@@ -134,7 +136,7 @@ def sketch(A, r, k, q, omega_left=None, omega_right=None, sides="both", pass_dty
     Act = torch.empty((m, k), dtype=od, device=dev) if (right and want_ac) else None
     stats = torch.zeros(4, dtype=torch.float64, device=dev)
     inp = _input(A)
-    d = _sketch_desc(r, k, q, sd, omega_left, omega_right, pass_dtype, final_dtype)
+    d = _sketch_desc(r, k, q, sd, omega_left, omega_right, pass_dtype, final_dtype, seed)
     out = L.cnmf_sketch_out(_ptr(Lt), _ptr(Rt), _ptr(Bt), _ptr(Att), _ptr(Act), _ptr(stats))
     L.check(h._lib.cnmf_sketch(h.raw, C.byref(inp), C.byref(d), C.byref(out)), h.raw)
     return Sketch(Lt, Rt, Bt, Att, Act, stats)
@@ -150,7 +152,7 @@ class Factorization:
 
 def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="admm", iters=100,
               lam=1.0, phi=None, xi=1.0, mu_eps=1e-16, pass_dtype=None, final_dtype=None,
-              want_sketch=False, handle: Handle | None = None) -> Factorization:
+              want_sketch=False, seed=0, handle: Handle | None = None) -> Factorization:
     """Compressed NMF: two-sided sketch, then ADMM (Alg. 3) or MU (Alg. 2) on
     the compressed factors, then the FP64 relative residual.  The *_full
     methods run the same iterations uncompressed (L = I, R = I)."""
@@ -174,7 +176,8 @@ def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="adm
     U0 = U0.to(device=dev, dtype=torch.float64).contiguous()
     V0 = V0.to(device=dev, dtype=torch.float64).contiguous()
     inp = _input(A)
-    d = L.cnmf_factorize_desc(_sketch_desc(r, k, q, L.CNMF_BOTH, omega_left, omega_right, pass_dtype, final_dtype),
+    d = L.cnmf_factorize_desc(_sketch_desc(r, k, q, L.CNMF_BOTH, omega_left, omega_right, pass_dtype, final_dtype,
+                                           seed),
                               _METHODS[method], int(iters), float(lam), float(lam if phi is None else phi),
                               float(xi), float(mu_eps), _ptr(U0), _ptr(V0))
     out = L.cnmf_factorize_out(_ptr(U), _ptr(V), _ptr(res), so)
@@ -182,8 +185,8 @@ def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="adm
     return Factorization(U, V, res, sk)
 
 
-def select(A, r, k, q, omega_left, omega_right=None, sides="left", pass_dtype=None, final_dtype=None,
-           want_scores=False, want_B=False, handle: Handle | None = None):
+def select(A, r, k, q, omega_left=None, omega_right=None, sides="left", pass_dtype=None, final_dtype=None,
+           want_scores=False, want_B=False, seed=0, handle: Handle | None = None):
     """Compressed separable NMF column selection (Alg. SNMF steps 1-2): the
     sketch, B = Q^T A, and SPA on B.  Returns int64 indices (device)."""
     h = handle or default_handle()
@@ -193,9 +196,27 @@ def select(A, r, k, q, omega_left, omega_right=None, sides="left", pass_dtype=No
     score = torch.empty(r, dtype=torch.float64, device=dev) if want_scores else None
     B = torch.empty((k, A.shape[1]), dtype=_acc_dtype(A, pass_dtype), device=dev) if want_B else None
     inp = _input(A)
-    d = _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype)
+    d = _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype, seed)
     L.check(h._lib.snmf_select(h.raw, C.byref(inp), C.byref(d), _ptr(K), _ptr(score), _ptr(B)), h.raw)
     return K, score, B
+
+
+def synchronize(handle: Handle | None = None):
+    """Wait for the handle's stream; raises CnmfError(CNMF_EBREAKDOWN) when an
+    orthonormalisation breakdown was left unresolved since the last call."""
+    h = handle or default_handle()
+    L.check(h._lib.cnmf_synchronize(h.raw), h.raw)
+
+
+def gaussian(rows, cols, seed, matrix_id=0, device=None, handle: Handle | None = None):
+    """The library's Gaussian test matrix `matrix_id` under `seed` (rows x
+    cols FP64 on the device): id 0 is the sketch's Omega_L, id 1 Omega_R."""
+    h = handle or default_handle()
+    dev = h.device if device is None else torch.device(device)
+    out = torch.empty((rows, cols), dtype=torch.float64, device=dev)
+    L.check(h._lib.cnmf_gaussian(h.raw, int(seed) & (2 ** 64 - 1), int(matrix_id), int(rows), int(cols), _ptr(out),
+                                 max(int(cols), 1)), h.raw)
+    return out
 
 
 def spa(B, r, want_scores=False, handle: Handle | None = None):
@@ -279,8 +300,8 @@ class Server:
         self.raw = raw
         self.device = torch.device("cuda", device)
 
-    def submit(self, A, r, k, q, U0, V0, omega_left, omega_right, method="admm", iters=100, lam=1.0, phi=None,
-               xi=1.0, mu_eps=1e-16, pass_dtype=None, final_dtype=None, stream=None) -> Ticket:
+    def submit(self, A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="admm", iters=100, lam=1.0,
+               phi=None, xi=1.0, mu_eps=1e-16, pass_dtype=None, final_dtype=None, stream=None, seed=0) -> Ticket:
         pass_dtype, final_dtype = _default_prec(A, pass_dtype, final_dtype)
         m, n = A.shape
         od = _acc_dtype(A, pass_dtype)
@@ -291,7 +312,7 @@ class Server:
         V0 = V0.to(device=A.device, dtype=torch.float64).contiguous()
         inp = _input(A)
         d = L.cnmf_factorize_desc(_sketch_desc(r, k, q, L.CNMF_BOTH, omega_left, omega_right, pass_dtype,
-                                               final_dtype),
+                                               final_dtype, seed),
                                   _METHODS[method], int(iters), float(lam), float(lam if phi is None else phi),
                                   float(xi), float(mu_eps), _ptr(U0), _ptr(V0))
         out = L.cnmf_factorize_out(_ptr(U), _ptr(V), _ptr(res), L.cnmf_sketch_out())

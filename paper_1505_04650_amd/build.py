@@ -1,6 +1,6 @@
 """Build the HIP library libcnmf.so in-tree for gfx950.
 
-    python -m paper_1505_04650_amd.build [--jobs N]
+    python -m paper_1505_04650_amd.build [--jobs N] [--changed]
 
 Every source under csrc/ is compiled with hipcc (packed FP32 instructions
 disabled) into _build/, then linked into paper_1505_04650_amd/libcnmf.so.
@@ -50,12 +50,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
+def _stale(src: str) -> bool:
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(d, f) for d in (CSRC, INCLUDE) for f in os.listdir(d) if f.endswith((".h", ".hpp"))]
+    return any(os.path.getmtime(x) > t for x in deps)
+
+
+def build(jobs: int | None = None, verbose: bool = True, changed_only: bool = False) -> str:
+    """Compile every source (or, with changed_only, those older than a
+    source or header they may include) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    todo = [s for s in srcs if _stale(s)] if changed_only else srcs
     jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -70,8 +83,9 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--changed", action="store_true", help="recompile only out-of-date sources")
     a = ap.parse_args()
-    build(a.jobs)
+    build(a.jobs, changed_only=a.changed)
 
 
 if __name__ == "__main__":

@@ -64,24 +64,53 @@ template <typename T>
 hipError_t launch_reduce_splits(const T* P, int splits, int64_t rows, int ld, T* Y, hipStream_t st);
 // Partials of X[:, x0 + h*hs : +ka]^T Y[:, y0 + h*hs : +kb] (FP64) over `parts`
 // row slices, for h < nh: Cp[(p * nh + h) * ka * kb].
+// With run_if, half h is skipped unless run_if[h] != 0.
 template <typename TX, typename TY>
 hipError_t launch_cross2(const TX* X, int ldx, int x0, const TY* Y, int ldy, int y0, int hs, int nh, int rows,
-                         int ka, int kb, double* Cp, int parts, hipStream_t st);
-// out[e] = sum_p in[p * count + e] in the order p = 0, 1, ...
-hipError_t launch_sum_parts(const double* in, int parts, int64_t count, double* out, hipStream_t st);
+                         int ka, int kb, double* Cp, int parts, hipStream_t st, const int* run_if = nullptr);
+// out[e] = sum_p in[p * count + e] in the order p = 0, 1, ...  With run_if,
+// nothing is done unless one of run_if[0 .. nrun) is nonzero.
+hipError_t launch_sum_parts(const double* in, int parts, int64_t count, double* out, hipStream_t st,
+                            const int* run_if = nullptr, int nrun = 0);
 // For each half h: G_h = fixed-order sum of the Gram partials, then
-// G_h = T^T T (Cholesky, T upper with positive diagonal).  Output per half
-// (kh x kh): for kh <= 64 the factor T itself, otherwise Tinv = T^-1; the
-// matching launch_apply_tinv consumes either form.  A
-// pivot <= 1e-20 max diag(G_h) counts as a breakdown in flags[h] and is
-// repaired.  counters: nh zero-initialised words, left zero on return.
-hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double* G, double* Tinv, int* flags,
-                            unsigned* counters, hipStream_t st);
-// Q64[:, h*kh + c] = sum_{l <= c} Y[:, h*kh + l] Tinv_h[l][c] (FP64), h < nh.
-// In place (Q64 == Y) is allowed.
+// G_h = T^T T (Cholesky, T upper with positive diagonal) and Tinv_h = T^-1
+// (kh x kh).  Breakdown handling, for a pivot <= tau max diag(G_h):
+//   mask != NULL (decoupling): the column is taken as dependent on the
+//     earlier ones, decoupled, counted in repaired[h] and marked in mask[2 h],
+//     mask[2 h + 1] (bit c of word c / 64) for launch_apply_tinv to replace;
+//     need[h] (if given) is set to whether any column of half h was;
+//   mask == NULL: the pivot is floored and counted as unresolved.
+// NaN pivots are unresolved.  Unresolved counts are added to unresolved[0]
+// and unresolved_total[0] (each may be NULL).  run_if (may be NULL): half h
+// runs only if run_if[h] != 0.
+struct CholOpts {
+  double tau;
+  int* repaired;
+  int* unresolved;
+  int* unresolved_total;
+  uint64_t* mask;
+  int* need;
+  const int* run_if;
+};
+hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double* G, double* Tinv, const CholOpts& o,
+                            hipStream_t st);
+// Q64[:, h*kh + c] = sum_{l <= c} Y[:, h*kh + l] Tinv_h[l][c] (FP64), h < nh;
+// columns marked in mask (NULL: none) get entries of Gaussian test matrix
+// id0 + h under `seed`, divided by sqrt(rows).  In place (Q64 == Y) is
+// allowed.  run_if as for launch_gram_chol.
 template <typename TY>
 hipError_t launch_apply_tinv(const TY* Y, int rows, int ldy, int nh, int kh, const double* Tinv, double* Q64,
-                             int ldq, hipStream_t st);
+                             int ldq, const uint64_t* mask, uint64_t seed, uint32_t id0, hipStream_t st,
+                             const int* run_if = nullptr);
+// Ids of the Gaussian test matrices (rng.hpp): Omega_L, Omega_R, and the
+// completion columns of the orthonormalisation after pass p (half h: first
+// CholeskyQR pass kCompletionId0 + 4 p + h, second kCompletionId0 + 4 p + 2 + h).
+constexpr uint32_t kOmegaLeftId = 0;
+constexpr uint32_t kOmegaRightId = 1;
+constexpr uint32_t kCompletionId0 = 16;
+// out (rows x cols, ld) = Gaussian test matrix `id` under `seed` (rng.hpp).
+hipError_t launch_gaussian_fill(double* out, int64_t ld, int rows, int cols, uint64_t seed, uint32_t id,
+                                hipStream_t st);
 // max |Q^T Q - I| for an FP64 Gram (for stats)
 hipError_t launch_orth_error(const double* G, int kh, double* out, hipStream_t st);
 

@@ -7,6 +7,7 @@
 // With diag(T) > 0 this Q is the same basis as the Householder QR with a
 // nonnegative diagonal for full-column-rank Y.
 #include "cnmf_internal.hpp"
+#include "rng.hpp"
 #include "small_dense.hpp"
 
 namespace cnmf {
@@ -51,7 +52,8 @@ template <typename TX, typename TY, int KH16, bool SYM>
 __global__ __launch_bounds__(256) void cross_kernel(const TX* __restrict__ X, int ldx, int x0,
                                                    const TY* __restrict__ Y, int ldy, int y0, int hs,
                                                    int rows, int ka, int kb, double* __restrict__ Cp,
-                                                   int rows_per_part) {
+                                                   int rows_per_part, const int* __restrict__ run_if) {
+  if (run_if && run_if[blockIdx.y] == 0) return;
   constexpr int CR = 32;
   constexpr int KW = KH16 * 16;
   __shared__ double xs[CR][KW + 1];
@@ -115,7 +117,9 @@ __global__ __launch_bounds__(256) void cross_kernel(const TX* __restrict__ X, in
 // FP64, as there.
 template <typename TY, int KB16>
 __global__ __launch_bounds__(256) void gram_mfma_kernel(const TY* __restrict__ Y, int ldy, int y0, int hs, int rows,
-                                                        int k, double* __restrict__ Cp, int rows_per_part) {
+                                                        int k, double* __restrict__ Cp, int rows_per_part,
+                                                        const int* __restrict__ run_if) {
+  if (run_if && run_if[blockIdx.y] == 0) return;
   constexpr int CR = 32, KW = 16 * KB16, LDC = KW + 1;
   constexpr int NT = KB16 * (KB16 + 1) / 2, NQ = (NT + 3) / 4;
   constexpr int PER = CR * KW / 256;   // staged values per thread and chunk
@@ -191,51 +195,58 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const TY* __restrict__ Y
 
 template <typename TX, typename TY, int KH16>
 static hipError_t cross_kh(const TX* X, int ldx, int x0, const TY* Y, int ldy, int y0, int hs, int nh,
-                           int rows, int ka, int kb, double* Cp, int parts, hipStream_t st) {
+                           int rows, int ka, int kb, double* Cp, int parts, const int* run_if, hipStream_t st) {
   int rpp = (rows + parts - 1) / parts;
   const bool sym = (const void*)X == (const void*)Y && ldx == ldy && x0 == y0 && ka == kb;
   if (sym)
     hipLaunchKernelGGL((gram_mfma_kernel<TY, KH16>), dim3(parts, nh), dim3(256), 0, st, Y, ldy, y0, hs, rows, ka, Cp,
-                       rpp);
+                       rpp, run_if);
   else
     hipLaunchKernelGGL((cross_kernel<TX, TY, KH16, false>), dim3(parts, nh), dim3(256), 0, st, X, ldx, x0, Y, ldy,
-                       y0, hs, rows, ka, kb, Cp, rpp);
+                       y0, hs, rows, ka, kb, Cp, rpp, run_if);
   CNMF_LAUNCH_CHECK();
 }
 
 template <typename TX, typename TY>
 hipError_t launch_cross2(const TX* X, int ldx, int x0, const TY* Y, int ldy, int y0, int hs, int nh,
-                         int rows, int ka, int kb, double* Cp, int parts, hipStream_t st) {
+                         int rows, int ka, int kb, double* Cp, int parts, hipStream_t st, const int* run_if) {
   int kmax = std::max(ka, kb);
   int k16 = (kmax + 15) / 16;
   switch (k16) {
-    case 1: return cross_kh<TX, TY, 1>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, st);
-    case 2: return cross_kh<TX, TY, 2>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, st);
-    case 3: return cross_kh<TX, TY, 3>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, st);
-    case 4: return cross_kh<TX, TY, 4>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, st);
-    case 5: return cross_kh<TX, TY, 5>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, st);
-    case 6: return cross_kh<TX, TY, 6>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, st);
-    case 7: return cross_kh<TX, TY, 7>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, st);
-    case 8: return cross_kh<TX, TY, 8>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, st);
+    case 1: return cross_kh<TX, TY, 1>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, run_if, st);
+    case 2: return cross_kh<TX, TY, 2>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, run_if, st);
+    case 3: return cross_kh<TX, TY, 3>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, run_if, st);
+    case 4: return cross_kh<TX, TY, 4>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, run_if, st);
+    case 5: return cross_kh<TX, TY, 5>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, run_if, st);
+    case 6: return cross_kh<TX, TY, 6>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, run_if, st);
+    case 7: return cross_kh<TX, TY, 7>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, run_if, st);
+    case 8: return cross_kh<TX, TY, 8>(X, ldx, x0, Y, ldy, y0, hs, nh, rows, ka, kb, Cp, parts, run_if, st);
     default: return hipErrorInvalidValue;
   }
 }
-template hipError_t launch_cross2<float, float>(const float*, int, int, const float*, int, int, int, int, int, int, int, double*, int, hipStream_t);
-template hipError_t launch_cross2<double, double>(const double*, int, int, const double*, int, int, int, int, int, int, int, double*, int, hipStream_t);
-template hipError_t launch_cross2<float, double>(const float*, int, int, const double*, int, int, int, int, int, int, int, double*, int, hipStream_t);
+template hipError_t launch_cross2<float, float>(const float*, int, int, const float*, int, int, int, int, int, int, int, double*, int, hipStream_t, const int*);
+template hipError_t launch_cross2<double, double>(const double*, int, int, const double*, int, int, int, int, int, int, int, double*, int, hipStream_t, const int*);
+template hipError_t launch_cross2<float, double>(const float*, int, int, const double*, int, int, int, int, int, int, int, double*, int, hipStream_t, const int*);
 
 // ---------------------------------------------------------------------------
 // out[e] = sum_p in[p * count + e], p increasing.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void sum_parts_kernel(const double* __restrict__ in, int parts, int64_t count,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, const int* __restrict__ run_if,
+                                                        int nrun) {
+  if (run_if) {
+    int any = 0;
+    for (int i = 0; i < nrun; ++i) any |= run_if[i];
+    if (!any) return;
+  }
   __shared__ double red[256];
   block_sum_parts<256, 32>(in, parts, count, count, (int64_t)blockIdx.x * 32, out, red);
 }
 
-hipError_t launch_sum_parts(const double* in, int parts, int64_t count, double* out, hipStream_t st) {
+hipError_t launch_sum_parts(const double* in, int parts, int64_t count, double* out, hipStream_t st,
+                            const int* run_if, int nrun) {
   int blocks = (int)((count + 31) / 32);
-  hipLaunchKernelGGL(sum_parts_kernel, dim3(blocks), dim3(256), 0, st, in, parts, count, out);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(blocks), dim3(256), 0, st, in, parts, count, out, run_if, nrun);
   CNMF_LAUNCH_CHECK();
 }
 
@@ -243,9 +254,14 @@ hipError_t launch_sum_parts(const double* in, int parts, int64_t count, double* 
 // G_h = sum of the Gram partials (fixed order; sum_parts kernel), then one
 // workgroup per half: G_h (padded to N = 16 ceil(kh / 16) with an identity
 // block) = T^T T (T upper, positive diagonal) and Tinv_h = T^-1 written to
-// global memory (kh x kh, zero below the diagonal).  A pivot <= 1e-20
-// max_i G_ii (or NaN) counts as a breakdown in flags[h] and is replaced by
-// that floor.
+// global memory (kh x kh, zero below the diagonal).
+// Breakdown (see CholOpts): with o.mask a pivot <= o.tau max_i G_ii marks
+// its column as dependent on the earlier ones; the column is decoupled (its
+// factor column is the unit vector), counted in o.repaired[h] and marked in
+// o.mask[2 h + (column / 64)] for the apply step to replace by a fresh
+// Gaussian column, and o.need[h] tells whether any was.  Without o.mask
+// such a pivot is floored and counted as unresolved.  NaN pivots are always
+// unresolved.  With o.run_if, half h runs only if o.run_if[h] != 0.
 // ---------------------------------------------------------------------------
 constexpr int kFacNT = 256;
 
@@ -257,9 +273,9 @@ constexpr int kFacNT = 256;
 // with the strip's tiles in registers (a 16x16x4 FP64 MFMA result is the
 // right operand of the next product as it stands), and writes Tinv_h =
 // T^-1 = Z^T, since T = L^T.
-template <int NB>
+template <int NB, bool DEC>
 __device__ __forceinline__ void chol_tinv_wave_body(const double* __restrict__ Gh, int kh, double* __restrict__ out,
-                                                    int* flag, double* sm) {
+                                                    double tau, int* flag, int* nanflag, uint64_t* mask, double* sm) {
   constexpr int N = 16 * NB, ld = N + 2;
   double* M = sm;                 // N x ld
   double* V = M + N * ld;         // NB x 272
@@ -275,7 +291,7 @@ __device__ __forceinline__ void chol_tinv_wave_body(const double* __restrict__ G
     double dg = lane < kh ? M[lane * ld + lane] : 0.0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o));
-    wave_chol_lower<NB>(M, ld, kh, V, W, dg > 0.0 ? 1e-20 * dg : 1.0, flag);
+    wave_chol_lower<NB, DEC>(M, ld, kh, V, W, dg > 0.0 ? tau * dg : 1.0, flag, nanflag, mask);
   }
   __syncthreads();
   if (w < NB) {
@@ -324,8 +340,10 @@ __device__ __forceinline__ void chol_tinv_wave_body(const double* __restrict__ G
 // S22 = G22 - L21 L21^T on the MFMA (wave w: block row w);  L22 = chol(S22)
 // (wave 0);  then Z = L^-1 over all 8 block rows, two column strips per
 // wave, and Tinv = Z^T.
+template <bool DEC>
 __device__ __forceinline__ void chol_tinv_wave128_body(const double* __restrict__ Gh, int kh, double* __restrict__ out,
-                                                       int* flag, double* sm) {
+                                                       double tau, int* flag, int* nanflag, uint64_t* mask,
+                                                       double* sm) {
   constexpr int N = 128, ld = N + 2;
   double* M = sm;                 // N x ld
   double* V = M + N * ld;         // 8 x 272: V[b], b < 4 from L11, b >= 4 from L22
@@ -343,9 +361,9 @@ __device__ __forceinline__ void chol_tinv_wave128_body(const double* __restrict_
     for (int i = lane; i < kh; i += 64) dg = fmax(dg, M[i * ld + i]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o));
-    if (dg > 0.0) fl = 1e-20 * dg;
+    if (dg > 0.0) fl = tau * dg;
   }
-  if (w == 0) wave_chol_lower<4>(M, ld, 64, V, W, fl, flag);
+  if (w == 0) wave_chol_lower<4, DEC>(M, ld, 64, V, W, fl, flag, nanflag, mask);
   __syncthreads();
   // L21: wave w solves rows 64 + 16 w .. + 15 of X L11^T = G21 as L11 X^T = G21^T
   {
@@ -395,7 +413,7 @@ __device__ __forceinline__ void chol_tinv_wave128_body(const double* __restrict_
       for (int i = 0; i < 4; ++i) M[(64 + 16 * w + g + 4 * i) * ld + 64 + 16 * jb + c] = acc[jb][i];
   }
   __syncthreads();
-  if (w == 0) wave_chol_lower<4>(M + 64 * ld + 64, ld, kh - 64, V + 4 * 272, W, fl, flag);
+  if (w == 0) wave_chol_lower<4, DEC>(M + 64 * ld + 64, ld, kh - 64, V + 4 * 272, W, fl, flag, nanflag, mask + 1);
   __syncthreads();
   // Z = L^-1, column strips j = w and w + 4
 #pragma unroll
@@ -438,32 +456,65 @@ __device__ __forceinline__ void chol_tinv_wave128_body(const double* __restrict_
   }
 }
 
-__global__ __launch_bounds__(kFacNT) void chol_tinv_wave_kernel(const double* __restrict__ G, int kh,
-                                                                double* __restrict__ Tinv, int* flags) {
-  extern __shared__ double sm[];
-  const int h = blockIdx.x;
-  const int64_t cnt = (int64_t)kh * kh;
-  int* flag = flags ? flags + h : nullptr;
+template <bool DEC>
+__device__ __forceinline__ void chol_tinv_dispatch(const double* Gh, int kh, double* out, double tau, int* flag,
+                                                   int* nanflag, uint64_t* mask, double* sm) {
   switch ((kh + 15) / 16) {
-    case 1: chol_tinv_wave_body<1>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
-    case 2: chol_tinv_wave_body<2>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
-    case 3: chol_tinv_wave_body<3>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
-    case 4: chol_tinv_wave_body<4>(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
-    default: chol_tinv_wave128_body(G + h * cnt, kh, Tinv + h * cnt, flag, sm); break;
+    case 1: chol_tinv_wave_body<1, DEC>(Gh, kh, out, tau, flag, nanflag, mask, sm); break;
+    case 2: chol_tinv_wave_body<2, DEC>(Gh, kh, out, tau, flag, nanflag, mask, sm); break;
+    case 3: chol_tinv_wave_body<3, DEC>(Gh, kh, out, tau, flag, nanflag, mask, sm); break;
+    case 4: chol_tinv_wave_body<4, DEC>(Gh, kh, out, tau, flag, nanflag, mask, sm); break;
+    default: chol_tinv_wave128_body<DEC>(Gh, kh, out, tau, flag, nanflag, mask, sm); break;
   }
 }
 
-hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double* G, double* Tinv, int* flags,
-                            unsigned* /*counters*/, hipStream_t st) {
+__global__ __launch_bounds__(kFacNT) void chol_tinv_wave_kernel(const double* __restrict__ G, int kh,
+                                                                double* __restrict__ Tinv, CholOpts o) {
+  const int h = blockIdx.x;
+  if (o.run_if && o.run_if[h] == 0) return;
+  extern __shared__ double sm[];
+  __shared__ int cnt_s[2];        // [0] pivots below the threshold, [1] NaN pivots
+  __shared__ uint64_t mask_s[2];
+  const int64_t cnt = (int64_t)kh * kh;
+  if (threadIdx.x < 2) {
+    cnt_s[threadIdx.x] = 0;
+    mask_s[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  if (o.mask)
+    chol_tinv_dispatch<true>(G + h * cnt, kh, Tinv + h * cnt, o.tau, &cnt_s[0], &cnt_s[1], mask_s, sm);
+  else
+    chol_tinv_dispatch<false>(G + h * cnt, kh, Tinv + h * cnt, o.tau, &cnt_s[0], nullptr, nullptr, sm);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // decoupling: low pivots are repaired, NaN ones are not; otherwise every
+    // low (or NaN) pivot is unresolved
+    const int unres = o.mask ? cnt_s[1] : cnt_s[0];
+    if (o.mask) {
+      const int fixed = cnt_s[0] - cnt_s[1];
+      o.mask[2 * h] = mask_s[0];
+      o.mask[2 * h + 1] = mask_s[1];
+      if (o.repaired && fixed > 0) atomicAdd(o.repaired + h, fixed);
+      if (o.need) o.need[h] = cnt_s[0] > 0 ? 1 : 0;
+    }
+    if (unres) {
+      if (o.unresolved) atomicAdd(o.unresolved, unres);
+      if (o.unresolved_total) atomicAdd(o.unresolved_total, unres);
+    }
+  }
+}
+
+hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double* G, double* Tinv, const CholOpts& o,
+                            hipStream_t st) {
   if (kh > 128) return hipErrorInvalidValue;
-  hipError_t e = launch_sum_parts(Gp, parts, (int64_t)nh * kh * kh, G, st);
+  hipError_t e = launch_sum_parts(Gp, parts, (int64_t)nh * kh * kh, G, st, o.run_if, nh);
   if (e != hipSuccess) return e;
   const int NB = (kh + 15) / 16, N = 16 * NB;
   // kh <= 64: N x (N + 2) + NB x 272 + 128 doubles; kh > 64: 128 x 130 + 8 x 272 + 128
   const size_t smw = kh <= 64 ? ((size_t)N * (N + 2) + (size_t)NB * 272 + 128) * sizeof(double)
                               : ((size_t)128 * 130 + 8 * 272 + 128) * sizeof(double);
   hipFuncSetAttribute((const void*)chol_tinv_wave_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smw);
-  hipLaunchKernelGGL(chol_tinv_wave_kernel, dim3(nh), dim3(kFacNT), smw, st, G, kh, Tinv, flags);
+  hipLaunchKernelGGL(chol_tinv_wave_kernel, dim3(nh), dim3(kFacNT), smw, st, G, kh, Tinv, o);
   CNMF_LAUNCH_CHECK();
 }
 
@@ -473,20 +524,28 @@ hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double*
 // one half; each lane first loads its K values of Y (lane (r, g) supplies
 // Y[row r][4 s + g]), then the 64-column slabs of Tinv_h are staged in LDS
 // one after the other.  All reads of a row precede the writes of that row,
-// so Q64 == Y (in place) is allowed.
+// so Q64 == Y (in place) is allowed.  Columns marked in mask (2 words per
+// half, see launch_gram_chol) receive entries of the Gaussian test matrix
+// id0 + h (seed `seed`) divided by sqrt(rows) instead, a unit-scale column
+// that the second CholeskyQR pass orthonormalises against the others.
 // ---------------------------------------------------------------------------
 template <typename TY>
 __global__ __launch_bounds__(256, 2) void apply_mfma_kernel(const TY* __restrict__ Y, int rows, int ldy, int kh,
-                                                            const double* __restrict__ Tinv, double* Q, int ldq) {
+                                                            const double* __restrict__ Tinv, double* Q, int ldq,
+                                                            const uint64_t* __restrict__ mask, uint64_t seed,
+                                                            uint32_t id0, const int* __restrict__ run_if) {
   constexpr int SL = 64, LDT = SL + 4, KS = 32;   // kh <= 128: at most 32 K steps of 4
   __shared__ double Ts[4 * KS * LDT];
   const int h = blockIdx.y;
+  if (run_if && run_if[h] == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r = lane & 15, g = lane >> 4;
   const int row0 = blockIdx.x * 64 + w * 16;
   const int row = row0 + r;
   const int nsteps = (kh + 3) >> 2;
   const double* Th = Tinv + (int64_t)h * kh * kh;
+  const uint64_t mk0 = mask ? mask[2 * h] : 0ull, mk1 = mask ? mask[2 * h + 1] : 0ull;
+  const double inv_sqrt_rows = 1.0 / sqrt((double)rows);
   double yv[KS];
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
@@ -512,25 +571,33 @@ __global__ __launch_bounds__(256, 2) void apply_mfma_kernel(const TY* __restrict
 #pragma unroll
       for (int s = 0; s < KS; ++s)
         if (s < smax) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[s], Ts[(4 * s + g) * LDT + 16 * cb + r], acc, 0, 0, 0);
+      const int col = cbase + r;
+      const bool fresh = (mk0 | mk1) && col < kh && (((col < 64 ? mk0 >> col : mk1 >> (col - 64)) & 1ull) != 0);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int orow = row0 + g + 4 * i, col = cbase + r;
-        if (orow < rows && col < kh) Q[(int64_t)orow * ldq + h * kh + col] = acc[i];
+        const int orow = row0 + g + 4 * i;
+        double v = acc[i];
+        if (fresh && orow < rows) v = gauss_entry(seed, id0 + h, (uint32_t)orow, (uint32_t)col) * inv_sqrt_rows;
+        if (orow < rows && col < kh) Q[(int64_t)orow * ldq + h * kh + col] = v;
       }
     }
   }
 }
 
 template <typename TY>
-hipError_t launch_apply_tinv(const TY* Y, int rows, int ldy, int nh, int kh, const double* Tinv,
-                             double* Q64, int ldq, hipStream_t st) {
+hipError_t launch_apply_tinv(const TY* Y, int rows, int ldy, int nh, int kh, const double* Tinv, double* Q64,
+                             int ldq, const uint64_t* mask, uint64_t seed, uint32_t id0, hipStream_t st,
+                             const int* run_if) {
   if (kh > 128) return hipErrorInvalidValue;
   dim3 grid((rows + 63) / 64, nh);
-  hipLaunchKernelGGL(apply_mfma_kernel<TY>, grid, dim3(256), 0, st, Y, rows, ldy, kh, Tinv, Q64, ldq);
+  hipLaunchKernelGGL(apply_mfma_kernel<TY>, grid, dim3(256), 0, st, Y, rows, ldy, kh, Tinv, Q64, ldq, mask, seed,
+                     id0, run_if);
   CNMF_LAUNCH_CHECK();
 }
-template hipError_t launch_apply_tinv<float>(const float*, int, int, int, int, const double*, double*, int, hipStream_t);
-template hipError_t launch_apply_tinv<double>(const double*, int, int, int, int, const double*, double*, int, hipStream_t);
+template hipError_t launch_apply_tinv<float>(const float*, int, int, int, int, const double*, double*, int,
+                                             const uint64_t*, uint64_t, uint32_t, hipStream_t, const int*);
+template hipError_t launch_apply_tinv<double>(const double*, int, int, int, int, const double*, double*, int,
+                                              const uint64_t*, uint64_t, uint32_t, hipStream_t, const int*);
 
 // ---------------------------------------------------------------------------
 // max |G - I| (G the Gram of an orthonormalised half)

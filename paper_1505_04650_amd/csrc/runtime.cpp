@@ -40,6 +40,9 @@ struct cnmf_handle {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool ext_ws = false;  // ws belongs to the caller (serving arena): never freed or grown
+  // device word: CholeskyQR2 breakdowns the fallback could not resolve since
+  // the last cnmf_synchronize (allocated at creation; serving handles: none)
+  int* unresolved_dev = nullptr;
   std::string err;
   // per-stage timing of the last call (HIP events on the handle's stream)
   bool timing = false;
@@ -209,8 +212,6 @@ cnmf_status check_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_
   if (d->q < 0) return fail(h, CNMF_EINVAL, "q must be >= 0");
   if (d->q > 64) return fail(h, CNMF_EINVAL, "q=%d is unreasonably large (max 64)", d->q);
   if (d->sides < 1 || d->sides > 3) return fail(h, CNMF_EINVAL, "sides must be CNMF_LEFT, CNMF_RIGHT or CNMF_BOTH");
-  if ((d->sides & CNMF_LEFT) && !d->omega_left_dev) return fail(h, CNMF_EINVAL, "omega_left_dev is NULL");
-  if ((d->sides & CNMF_RIGHT) && !d->omega_right_dev) return fail(h, CNMF_EINVAL, "omega_right_dev is NULL");
   if (A->dtype == CNMF_F64) {
     if (d->pass_dtype != CNMF_F64 || d->final_dtype != CNMF_F64)
       return fail(h, CNMF_EINVAL, "an F64 input runs with pass_dtype = final_dtype = CNMF_F64");
@@ -240,9 +241,14 @@ struct SketchWs {
   double* Gp = nullptr;
   double* G = nullptr;
   double* Tinv = nullptr;
+  // flags: [0], [1] breakdowns repaired per half (left, right chain),
+  // [2] floored pivots of the ADMM solves, [3] unresolved breakdowns
   int* flags = nullptr;
   unsigned* counters = nullptr;
   double* orth_err = nullptr;
+  uint64_t* mask = nullptr;    // decoupled columns of the first CholeskyQR pass (2 words per half)
+  double* OmL = nullptr;       // n x k Omega_L drawn on the device (seeded sketches)
+  double* OmR = nullptr;       // m x k Omega_R
   T* Lb = nullptr;      // m x k
   T* RTb = nullptr;     // n x k  (R^T)
   T* BTb = nullptr;     // n x k  (B^T)
@@ -274,7 +280,7 @@ int gram_parts(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t
 
 template <typename T>
 void layout_sketch(Arena& a, SketchWs<T>& w, int64_t m, int64_t n, int k, const std::vector<Pass>& passes,
-                   bool want_ac) {
+                   bool want_ac, const cnmf_sketch_desc* d) {
   int kkmax = 16;
   size_t pmax = 0;
   bool need16 = false, need8 = false, wide = false;
@@ -306,9 +312,12 @@ void layout_sketch(Arena& a, SketchWs<T>& w, int64_t m, int64_t n, int k, const 
   w.Gp = a.take<double>((size_t)w.gparts * 2 * k * k);
   w.G = a.take<double>(2 * (size_t)k * k);
   w.Tinv = a.take<double>(2 * (size_t)k * k);
-  w.flags = a.take<int>(4);
+  w.flags = a.take<int>(8);
   w.counters = a.take<unsigned>(4);
   w.orth_err = a.take<double>(4);
+  w.mask = a.take<uint64_t>(4);
+  if ((d->sides & CNMF_LEFT) && !d->omega_left_dev) w.OmL = a.take<double>((size_t)n * k);
+  if ((d->sides & CNMF_RIGHT) && !d->omega_right_dev) w.OmR = a.take<double>((size_t)m * k);
   w.Lb = a.take<T>((size_t)m * k);
   w.RTb = a.take<T>((size_t)n * k);
   w.BTb = a.take<T>((size_t)n * k);
@@ -463,20 +472,56 @@ void timing_resolve(cnmf_handle* h) {
 // -------------------------------------------------------------------------
 // Orthonormalise nh column blocks [col0 + i*k, +k) of Y (rows x kk, already
 // reduced) by CholeskyQR2; result in Q64 (same columns, FP64).
+// Rank-deficient Y (k > rank A; plain CholeskyQR breaks down there):
+//   pass 1 decouples the columns whose pivot is <= 1e-14 max diag(Y^T Y)
+//     (dependent on the earlier columns to within the accuracy of the Gram)
+//     and puts unit-scale Gaussian columns there;
+//   pass 2 decouples the columns of Q1 with a pivot <= 1e-8 max diag: Q1's
+//     independent columns are orthonormal to within rounding, so a column
+//     it left in their span has a pivot at rounding level and is detected
+//     reliably; they are replaced in the same way, and
+//   pass 3, only for halves where pass 2 replaced a column (the kernels test
+//     a device flag and return at once otherwise), orthonormalises the
+//     completed matrix once more; a breakdown there, or a NaN pivot
+//     anywhere, is unresolved (flags[3]).
+// range(Q) contains range(Y) and Q^T Q = I.  The flags words [4], [5] hold
+// the per-half "pass 3 needed" results of pass 2.
 // -------------------------------------------------------------------------
 template <typename T>
-cnmf_status orth_blocks(cnmf_handle* h, SketchWs<T>& w, const T* Y, int rows, int kk, int col0, int nh, int k) {
+cnmf_status orth_blocks(cnmf_handle* h, SketchWs<T>& w, const T* Y, int rows, int kk, int col0, int nh, int k,
+                        uint64_t seed, uint32_t id0) {
   hipStream_t st = h->stream;
   const int parts = std::min(w.gparts, std::max(1, rows / 32));
-  // pass 1: G = Y^T Y, T1, Q1 = Y T1^-1
+  int* need = w.flags + 4;
+  CholOpts o{};
+  o.repaired = w.flags;
+  o.unresolved = w.flags + 3;
+  o.unresolved_total = h->unresolved_dev;
+  // pass 1: G = Y^T Y, T1, Q1 = Y T1^-1 (decoupled columns replaced)
+  o.tau = 1e-14;
+  o.mask = w.mask;
   HIPCHK(h, (launch_cross2<T, T>(Y, kk, col0, Y, kk, col0, k, nh, rows, k, k, w.Gp, parts, st)));
-  HIPCHK(h, launch_gram_chol(w.Gp, parts, nh, k, w.G, w.Tinv, w.flags, w.counters, st));
+  HIPCHK(h, launch_gram_chol(w.Gp, parts, nh, k, w.G, w.Tinv, o, st));
   // apply writes Q64 columns col0 + h*k via an offset view
-  HIPCHK(h, (launch_apply_tinv<T>(Y + col0, rows, kk, nh, k, w.Tinv, w.Q64 + col0, kk, st)));
+  HIPCHK(h, (launch_apply_tinv<T>(Y + col0, rows, kk, nh, k, w.Tinv, w.Q64 + col0, kk, w.mask, seed, id0, st)));
   // pass 2 on Q1
+  o.tau = 1e-8;
+  o.need = need;
   HIPCHK(h, (launch_cross2<double, double>(w.Q64, kk, col0, w.Q64, kk, col0, k, nh, rows, k, k, w.Gp, parts, st)));
-  HIPCHK(h, launch_gram_chol(w.Gp, parts, nh, k, w.G, w.Tinv, w.flags, w.counters, st));
-  HIPCHK(h, (launch_apply_tinv<double>(w.Q64 + col0, rows, kk, nh, k, w.Tinv, w.Q64 + col0, kk, st)));
+  HIPCHK(h, launch_gram_chol(w.Gp, parts, nh, k, w.G, w.Tinv, o, st));
+  HIPCHK(h, (launch_apply_tinv<double>(w.Q64 + col0, rows, kk, nh, k, w.Tinv, w.Q64 + col0, kk, w.mask, seed,
+                                       id0 + 2, st)));
+  // pass 3, conditional on pass 2 having replaced a column
+  o.tau = 1e-14;
+  o.mask = nullptr;
+  o.need = nullptr;
+  o.repaired = nullptr;
+  o.run_if = need;
+  HIPCHK(h, (launch_cross2<double, double>(w.Q64, kk, col0, w.Q64, kk, col0, k, nh, rows, k, k, w.Gp, parts, st,
+                                           need)));
+  HIPCHK(h, launch_gram_chol(w.Gp, parts, nh, k, w.G, w.Tinv, o, st));
+  HIPCHK(h, (launch_apply_tinv<double>(w.Q64 + col0, rows, kk, nh, k, w.Tinv, w.Q64 + col0, kk, nullptr, 0, 0, st,
+                                       need)));
   return CNMF_OK;
 }
 
@@ -488,7 +533,7 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
   const int m = (int)A->m, n = (int)A->n, k = d->k;
   const T* Ap = (const T*)A->data_dev;
   const int64_t lda = A->lda;
-  HIPCHK(h, launch_fill(w.flags, 4 * sizeof(int), st));
+  HIPCHK(h, launch_fill(w.flags, 8 * sizeof(int), st));
   HIPCHK(h, launch_fill(w.counters, 4 * sizeof(unsigned), st));
 
   // A pass multiplies an operand with one row per column of the matrix it
@@ -529,6 +574,18 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
       return fail(h, CNMF_EINVAL, "internal: reduced-precision passes need an F32 input");
     }
   }
+  // Gaussian test matrices (Alg. 1's first step) drawn on the device when
+  // the caller gives none
+  const double* omL = d->omega_left_dev;
+  const double* omR = d->omega_right_dev;
+  if (w.OmL) {
+    HIPCHK(h, launch_gaussian_fill(w.OmL, k, n, k, d->seed, kOmegaLeftId, st));
+    omL = w.OmL;
+  }
+  if (w.OmR) {
+    HIPCHK(h, launch_gaussian_fill(w.OmR, k, m, k, d->seed, kOmegaRightId, st));
+    omR = w.OmR;
+  }
   // stage the first operands (Omegas) of the chains
   for (size_t pi = 0; pi < passes.size(); ++pi) {
     const Pass& p = passes[pi];
@@ -539,7 +596,7 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
           RUN(clear_operand(p));
           zeroed = true;
         }
-        const double* om = b.kind == L_RANGE ? d->omega_left_dev : d->omega_right_dev;
+        const double* om = b.kind == L_RANGE ? omL : omR;
         int rows = b.kind == L_RANGE ? n : m;
         RUN(store_operand(p, om, rows, k, 0, b.col0));
       }
@@ -599,7 +656,8 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
         ++nh;
       }
     if (nh > 0) {
-      cnmf_status s = orth_blocks<T>(h, w, w.Y, rows, p.kk, rcol0, nh, k);
+      cnmf_status s = orth_blocks<T>(h, w, w.Y, rows, p.kk, rcol0, nh, k, d->seed,
+                                     kCompletionId0 + 4 * (uint32_t)pi);
       if (s != CNMF_OK) return s;
     }
     // route results
@@ -672,11 +730,13 @@ cnmf_status write_sketch_outputs(cnmf_handle* h, const cnmf_input* A, const cnmf
   if (o->At_dev && L && R) HIPCHK(h, (launch_copy2d<double, T>(w.At, k, (T*)o->At_dev, k, k, k, 1.0, st)));
   if (o->Ac_dev && R && w.Acb) HIPCHK(h, (launch_copy2d<T, T>(w.Acb, k, (T*)o->Ac_dev, k, m, k, 1.0, st)));
   if (o->stats_dev) {
-    // stats: [0] max|L^T L - I|, [1] max|R R^T - I|, [2] breakdowns, [3] 0
+    // stats: [0] max|L^T L - I|, [1] max|R R^T - I|, [2] breakdowns repaired,
+    // [3] breakdowns unresolved
     HIPCHK(h, launch_fill(o->stats_dev, 4 * sizeof(double), st));
     if (L) HIPCHK(h, (launch_copy2d<double, double>(w.orth_err, 1, o->stats_dev, 1, 1, 1, 1.0, st)));
     if (R) HIPCHK(h, (launch_copy2d<double, double>(w.orth_err + 1, 1, o->stats_dev + 1, 1, 1, 1, 1.0, st)));
     HIPCHK(h, launch_flags_to_stats(w.flags, 2, o->stats_dev + 2, st));
+    HIPCHK(h, launch_flags_to_stats(w.flags + 3, 1, o->stats_dev + 3, st));
   }
   return CNMF_OK;
 }
@@ -688,11 +748,11 @@ cnmf_status do_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_des
   if (passes.empty()) return fail(h, CNMF_EINVAL, "internal: empty pass plan");
   Arena dry(nullptr);
   SketchWs<T> w;
-  layout_sketch<T>(dry, w, A->m, A->n, d->k, passes, want_ac);
+  layout_sketch<T>(dry, w, A->m, A->n, d->k, passes, want_ac, d);
   cnmf_status s = ensure_ws(h, dry.off);
   if (s != CNMF_OK) return s;
   Arena a(h->ws);
-  layout_sketch<T>(a, w, A->m, A->n, d->k, passes, want_ac);
+  layout_sketch<T>(a, w, A->m, A->n, d->k, passes, want_ac, d);
   s = run_sketch<T>(h, A, d, w, passes, o ? o->stats_dev : nullptr);
   if (s != CNMF_OK) return s;
   return write_sketch_outputs<T>(h, A, d, w, o);
@@ -784,9 +844,9 @@ template <typename T>
 void fact_layout(Arena& a, FactState<T>& f, int64_t m, int64_t n, const cnmf_factorize_desc* d) {
   const int k = d->sk.k, r = d->sk.r;
   if (!f.full)
-    layout_sketch<T>(a, f.w, m, n, k, f.passes, f.want_ac);
+    layout_sketch<T>(a, f.w, m, n, k, f.passes, f.want_ac, &d->sk);
   else
-    f.w.flags = a.take<int>(4);
+    f.w.flags = a.take<int>(8);
   layout_admm<T>(a, f.aw, m, n, k, r);
   if (d->method != CNMF_ADMM) layout_iter<T>(a, f.iw, m, n, k, r, f.full);
 }
@@ -822,7 +882,7 @@ cnmf_status fact_prologue(cnmf_handle* h, const cnmf_input* A, const cnmf_factor
     cnmf_status s = run_sketch<T>(h, A, &d->sk, f.w, f.passes, o->sk_out.stats_dev);
     if (s != CNMF_OK) return s;
   } else {
-    HIPCHK(h, launch_fill(f.w.flags, 4 * sizeof(int), st));
+    HIPCHK(h, launch_fill(f.w.flags, 8 * sizeof(int), st));
   }
   AdmmWs<T>& aw = f.aw;
   // state: U = U0, V^T = V0^T, Lam = Phi = 0
@@ -1014,7 +1074,7 @@ cnmf_status do_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_des
   const int m = (int)A->m, n = (int)A->n, k = d->k;
   Arena dry(nullptr);
   SketchWs<T> w;
-  layout_sketch<T>(dry, w, m, n, k, passes, false);
+  layout_sketch<T>(dry, w, m, n, k, passes, false, d);
   double* Bt64 = dry.take<double>((size_t)n * k);
   const int nblk = (n + 63) / 64;
   double* u = dry.take<double>(k);
@@ -1024,7 +1084,7 @@ cnmf_status do_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_des
   cnmf_status s = ensure_ws(h, dry.off);
   if (s != CNMF_OK) return s;
   Arena a(h->ws);
-  layout_sketch<T>(a, w, m, n, k, passes, false);
+  layout_sketch<T>(a, w, m, n, k, passes, false, d);
   Bt64 = a.take<double>((size_t)n * k);
   u = a.take<double>(k);
   wb = a.take<double>(nblk);
@@ -1158,10 +1218,19 @@ cnmf_status cnmf_create(int device, void* hip_stream, size_t workspace_limit, cn
   if (device < 0 || device >= ndev) return fail(nullptr, CNMF_EINVAL, "device %d out of range [0, %d)", device, ndev);
   e = hipSetDevice(device);
   if (e != hipSuccess) return fail(nullptr, CNMF_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  void* ud = nullptr;
+  e = hipMalloc(&ud, 256);
+  if (e != hipSuccess) return fail(nullptr, CNMF_ENOMEM, "hipMalloc(256) failed: %s", hipGetErrorString(e));
+  e = launch_fill(ud, 256, (hipStream_t)hip_stream);
+  if (e != hipSuccess) {
+    hipFree(ud);
+    return fail(nullptr, CNMF_EDEVICE, "clearing the breakdown counter failed: %s", hipGetErrorString(e));
+  }
   cnmf_handle* h = new cnmf_handle();
   h->device = device;
   h->stream = (hipStream_t)hip_stream;
   h->limit = workspace_limit;
+  h->unresolved_dev = (int*)ud;
   timing_reset(h);
   *out = h;
   return CNMF_OK;
@@ -1169,12 +1238,42 @@ cnmf_status cnmf_create(int device, void* hip_stream, size_t workspace_limit, cn
 
 cnmf_status cnmf_destroy(cnmf_handle* h) {
   if (!h) return CNMF_OK;
-  if (h->ws) {
-    hipStreamSynchronize(h->stream);
-    hipFree(h->ws);
-  }
+  hipSetDevice(h->device);
+  hipStreamSynchronize(h->stream);
+  if (h->ws) hipFree(h->ws);
+  if (h->unresolved_dev) hipFree(h->unresolved_dev);
   for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
   delete h;
+  return CNMF_OK;
+}
+
+cnmf_status cnmf_synchronize(cnmf_handle* h) {
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int unres = 0;
+  HIPCHK(h, hipMemcpy(&unres, h->unresolved_dev, sizeof(int), hipMemcpyDeviceToHost));
+  if (unres) {
+    HIPCHK(h, launch_fill(h->unresolved_dev, sizeof(int), h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return fail(h, CNMF_EBREAKDOWN,
+                "%d CholeskyQR2 breakdown(s) not resolved by the fallback (NaN or Inf in the input, or a basis that "
+                "stayed rank deficient)",
+                unres);
+  }
+  return CNMF_OK;
+}
+
+cnmf_status cnmf_gaussian(cnmf_handle* h, uint64_t seed, int32_t matrix_id, int64_t rows, int32_t cols,
+                          double* out_dev, int64_t ld) {
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  if (!out_dev) return fail(h, CNMF_EINVAL, "out_dev is NULL");
+  if (rows < 0 || cols < 0 || ld < cols) return fail(h, CNMF_EINVAL, "bad shape rows=%lld cols=%d ld=%lld",
+                                                      (long long)rows, cols, (long long)ld);
+  if (rows > INT32_MAX / 2) return fail(h, CNMF_ENOTSUP, "rows above 2^30 are not supported");
+  if (matrix_id < 0) return fail(h, CNMF_EINVAL, "matrix_id must be >= 0");
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, launch_gaussian_fill(out_dev, ld, (int)rows, cols, seed, (uint32_t)matrix_id, h->stream));
   return CNMF_OK;
 }
 
@@ -1220,7 +1319,6 @@ static cnmf_status check_factorize(cnmf_handle* h, const cnmf_input* A, const cn
     sk.k = sk.r + 1 <= std::min(A->m, A->n) ? sk.r + 1 : sk.r;
     sk.sides = CNMF_LEFT;
     sk.q = 0;
-    sk.omega_left_dev = (const double*)1;
     cnmf_status s = check_sketch(h, A, &sk);
     if (s != CNMF_OK) return s;
   } else {
@@ -1438,9 +1536,9 @@ cnmf_status cnmf_workspace_bytes(int64_t m, int64_t n, const cnmf_factorize_desc
     AdmmWs<T> aw;
     IterWs<T> iw;
     if (!full)
-      layout_sketch<T>(dry, w, m, n, k, passes, want_ac);
+      layout_sketch<T>(dry, w, m, n, k, passes, want_ac, &d->sk);
     else
-      dry.take<int>(4);
+      dry.take<int>(8);
     layout_admm<T>(dry, aw, m, n, k, r);
     if (d->method != CNMF_ADMM) layout_iter<T>(dry, iw, m, n, k, r, full);
   };

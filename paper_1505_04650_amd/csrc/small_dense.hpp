@@ -271,21 +271,38 @@ __device__ __forceinline__ double rsqrt_fast(double d) {
 // extra(s) is called before step s (every s < 16, taken or not): the caller
 // issues independent MFMA work there, which runs while the step's dependent
 // VALU chain waits.
-template <bool FULL, typename X>
+// DEC (decoupling): a pivot <= floor_piv (or NaN) marks its column as
+// dependent on the earlier ones: the column of the factor becomes the unit
+// vector (1 on the diagonal, 0 below), so the column takes no part in the
+// later steps; bit c0 + s of mbits records it and NaN pivots are also
+// counted in nnan.  Without DEC such a pivot is replaced by floor_piv.
+template <bool FULL, bool DEC, typename X>
 __device__ __forceinline__ void wave_panel_steps(double (&a)[16], int c0, int steps, double* colbuf,
-                                                 double floor_piv, double& myinv, int& nbad, X extra) {
+                                                 double floor_piv, double& myinv, int& nbad, uint64_t& mbits,
+                                                 int& nnan, X extra) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     extra(s);
     if (FULL || s < steps) {
       const double d0 = readlane_d(a[s], c0 + s);
-      nbad += (d0 > floor_piv) ? 0 : 1;   // also counts NaN
-      const double d = fmax(d0, floor_piv);
+      const bool bad = !(d0 > floor_piv);   // also true for NaN
+      nbad += bad ? 1 : 0;
       const bool piv = lane == c0 + s;
-      const double as = piv ? d : a[s];
-      const double y = rsqrt_fast(d);
-      const double l = as * y;   // L[lane][c0 + s]; sqrt(d) on the pivot lane
+      double l, y;
+      if constexpr (DEC) {
+        nnan += (d0 != d0) ? 1 : 0;
+        mbits |= bad ? (1ull << (c0 + s)) : 0ull;
+        const double d = bad ? 1.0 : d0;
+        const double as = piv ? d : a[s];
+        y = rsqrt_fast(d);
+        l = bad ? (piv ? 1.0 : 0.0) : as * y;
+      } else {
+        const double d = fmax(d0, floor_piv);
+        const double as = piv ? d : a[s];
+        y = rsqrt_fast(d);
+        l = as * y;   // L[lane][c0 + s]; sqrt(d) on the pivot lane
+      }
       a[s] = l;
       myinv = piv ? y : myinv;
       if (s + 1 < 16) {
@@ -309,8 +326,11 @@ __device__ __forceinline__ void wave_panel_steps(double (&a)[16], int c0, int st
 // holds the inverse of the diagonal block L[b][b] (lower, zeros above).
 // Rows and columns from n on must be those of the identity (no coupling),
 // so their steps are skipped and L is the identity there too.  A pivot
-// <= floor (or NaN) is replaced by floor (floor > 0); the number of such
-// pivots is added to *flag.  W: 128 doubles of LDS scratch.
+// <= floor (or NaN) is replaced by floor (floor > 0), or with DEC its column
+// is decoupled (see wave_panel_steps); the number of such pivots is added to
+// *flag, with DEC the number of NaN pivots to *nanflag and the decoupled
+// columns (bit j: column j) are or-ed into *mask (one wave-uniform word,
+// N <= 64).  W: 128 doubles of LDS scratch.
 //
 // Right-looking by 16-column panels: lane j keeps row j of the panel in
 // registers.  Step s takes the pivot of lane c0 + s by readlane; the entry
@@ -322,15 +342,16 @@ __device__ __forceinline__ void wave_panel_steps(double (&a)[16], int c0, int st
 // substitution.  A wave's LDS operations complete in order, so no barrier
 // is needed between them.
 // ---------------------------------------------------------------------------
-template <int NB>
+template <int NB, bool DEC = false>
 __device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double* V, double* W, double floor_piv,
-                                                int* flag) {
+                                                int* flag, int* nanflag = nullptr, uint64_t* mask = nullptr) {
   constexpr int N = 16 * NB;
   const int lane = threadIdx.x & 63;
   const int c = lane & 15, g = lane >> 4;
   double* colbuf = W;       // the current column of L
   double* dinv = W + 64;    // 1 / L[i][i]
-  int nbad = 0;
+  int nbad = 0, nnan = 0;
+  uint64_t mbits = 0;
   // The trailing tiles (ti >= tj >= 1) stay in registers in the MFMA result
   // layout (item i of lane (c, g): row 16 ti + g + 4 i, column 16 tj + c).
   // After panel P only column P + 1 is updated at once (the next panel needs
@@ -382,9 +403,9 @@ __device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double
       }
     };
     if (steps >= 16)
-      wave_panel_steps<true>(a, c0, steps, colbuf, floor_piv, myinv, nbad, deferred);
+      wave_panel_steps<true, DEC>(a, c0, steps, colbuf, floor_piv, myinv, nbad, mbits, nnan, deferred);
     else
-      wave_panel_steps<false>(a, c0, steps, colbuf, floor_piv, myinv, nbad, deferred);
+      wave_panel_steps<false, DEC>(a, c0, steps, colbuf, floor_piv, myinv, nbad, mbits, nnan, deferred);
     if (act) {
 #pragma unroll
       for (int t = 0; t < 16; ++t) M[lane * ld + c0 + t] = a[t];
@@ -424,6 +445,10 @@ __device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double
     for (int i = 0; i < 16; ++i) V[g * 272 + i * 17 + c] = x[i];
   }
   if (nbad && lane == 0 && flag) atomicAdd(flag, nbad);
+  if constexpr (DEC) {
+    if (nnan && lane == 0 && nanflag) atomicAdd(nanflag, nnan);
+    if (lane == 0 && mask) *mask |= mbits;
+  }
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
 }

@@ -39,7 +39,7 @@ def test_version_and_status_strings(lib):
 
 
 def _desc(r=10, k=20, q=2, sides=L.CNMF_BOTH, method=L.CNMF_ADMM, iters=10, prec=L.CNMF_F32):
-    sk = L.cnmf_sketch_desc(r, k, q, sides, prec, prec, C.c_void_p(16), C.c_void_p(16))
+    sk = L.cnmf_sketch_desc(r, k, q, sides, prec, prec, 0, C.c_void_p(16), C.c_void_p(16))
     return L.cnmf_factorize_desc(sk, method, iters, 1.0, 1.0, 1.0, 0.0, C.c_void_p(16), C.c_void_p(16))
 
 
@@ -63,7 +63,7 @@ def test_workspace_bytes_rejects_bad_shapes(lib, r, k, m, n):
 
 def test_calls_without_handle_or_data_fail_cleanly(lib):
     A = L.cnmf_input(C.c_void_p(0), L.CNMF_F32, 100, 50, 50)
-    sk = L.cnmf_sketch_desc(5, 10, 1, L.CNMF_BOTH, L.CNMF_F32, L.CNMF_F32, None, None)
+    sk = L.cnmf_sketch_desc(5, 10, 1, L.CNMF_BOTH, L.CNMF_F32, L.CNMF_F32, 0, None, None)
     out = L.cnmf_sketch_out()
     assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL
     A.data_dev = C.c_void_p(16)
@@ -71,7 +71,9 @@ def test_calls_without_handle_or_data_fail_cleanly(lib):
     assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL
     assert b"lda" in lib.cnmf_last_error(None)
     A.lda = 50
-    assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL  # omega NULL
+    # NULL test matrices are valid (drawn on the device from the seed): only the handle is missing
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_EINVAL
+    assert b"handle" in lib.cnmf_last_error(None)
     sk.omega_left_dev = C.c_void_p(16)
     sk.omega_right_dev = C.c_void_p(16)
     sk.k = 51
@@ -114,6 +116,24 @@ def test_admm_solve_lds_limit(lib, r, k, ok):
     assert lib.cnmf_factorize(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
 
 
+def test_gaussian_and_synchronize_argument_checks(lib):
+    out = C.c_void_p(16)
+    assert lib.cnmf_gaussian(None, 1, 0, 10, 4, out, 4) == L.CNMF_EINVAL
+    assert b"handle" in lib.cnmf_last_error(None)
+    assert lib.cnmf_synchronize(None) == L.CNMF_EINVAL
+
+
+def test_seeded_sketch_workspace_holds_the_test_matrices(lib):
+    """NULL test matrices are drawn into the workspace: (m + n) k doubles more."""
+    given, seeded = _desc(r=50, k=60, q=4), _desc(r=50, k=60, q=4)
+    seeded.sk.omega_left_dev = None
+    seeded.sk.omega_right_dev = None
+    a, b = C.c_size_t(), C.c_size_t()
+    assert lib.cnmf_workspace_bytes(20000, 5000, C.byref(given), C.byref(a)) == L.CNMF_OK
+    assert lib.cnmf_workspace_bytes(20000, 5000, C.byref(seeded), C.byref(b)) == L.CNMF_OK
+    assert b.value - a.value >= 8 * (20000 + 5000) * 60
+
+
 def test_python_binding_fails_loudly_without_library(tmp_path):
     with pytest.raises(FileNotFoundError):
         L._lib_backup = L._lib
@@ -128,7 +148,7 @@ def test_precision_combinations(lib):
     """Reduced-precision passes need an FP32 input; B and the last range
     pass need at least BF16; the workspace grows by the A / A^T copies."""
     A = L.cnmf_input(C.c_void_p(16), L.CNMF_F32, 100, 50, 50)
-    sk = L.cnmf_sketch_desc(5, 10, 1, L.CNMF_BOTH, L.CNMF_FP8_E4M3, L.CNMF_FP8_E4M3, C.c_void_p(16),
+    sk = L.cnmf_sketch_desc(5, 10, 1, L.CNMF_BOTH, L.CNMF_FP8_E4M3, L.CNMF_FP8_E4M3, 0, C.c_void_p(16),
                             C.c_void_p(16))
     out = L.cnmf_sketch_out()
     assert lib.cnmf_sketch(None, C.byref(A), C.byref(sk), C.byref(out)) == L.CNMF_ENOTSUP
