@@ -235,6 +235,21 @@ cnmf_status snmf_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_d
 cnmf_status cnmf_spa(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n,
                      int64_t ldb, int32_t r, int64_t* K_dev, double* score_dev);
 
+/* cnmf_spa for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and results as cnmf_spa, with its working storage (B^T
+ * in FP64, the unit pivot, per-block winners: about (k + 2) n doubles) in a
+ * fixed 32 MiB device array that the library holds on every GPU it runs on
+ * until the process ends; no call allocates or frees anything.  The array's
+ * address is looked up when a handle is created on a device.  Inputs and
+ * outputs as for cnmf_spa.  Errors: as cnmf_spa; CNMF_ENOTSUP when the
+ * working storage would exceed the 32 MiB (use cnmf_spa).  Every call on a
+ * GPU shares that GPU's array (it keeps the last call's contents; nothing in
+ * it needs clearing): calls that may overlap on one GPU (other streams or
+ * host threads) race and must be serialised by the caller. */
+cnmf_status cnmf_spa_noalloc(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n,
+                             int64_t ldb, int32_t r, int64_t* K_dev, double* score_dev);
+
 /* One streaming pass of the range finder (Alg. 1, the product step):
  *   trans == 0: Y = A X    X is n x kx, Y is m x kx
  *   trans == 1: Y = A^T X  X is m x kx, Y is n x kx

@@ -219,15 +219,20 @@ def gaussian(rows, cols, seed, matrix_id=0, device=None, handle: Handle | None =
     return out
 
 
-def spa(B, r, want_scores=False, handle: Handle | None = None):
-    """SPA on the columns of a given k x n device matrix B (FP64 arithmetic)."""
+def spa(B, r, want_scores=False, noalloc=False, K=None, score=None, handle: Handle | None = None):
+    """SPA on the columns of a given k x n device matrix B (FP64 arithmetic).
+    noalloc: use cnmf_spa_noalloc (working storage in the library's fixed
+    device scratch); K / score may then be passed in preallocated."""
     h = handle or default_handle()
     if B.dtype not in _DT or B.dim() != 2 or B.stride(1) != 1:
         raise ValueError("B must be a row-major float64/float32 2-D tensor")
-    K = torch.empty(r, dtype=torch.int64, device=B.device)
-    score = torch.empty(r, dtype=torch.float64, device=B.device) if want_scores else None
-    L.check(h._lib.cnmf_spa(h.raw, _ptr(B), _DT[B.dtype], B.shape[0], B.shape[1], B.stride(0), int(r),
-                            _ptr(K), _ptr(score)), h.raw)
+    if K is None:
+        K = torch.empty(r, dtype=torch.int64, device=B.device)
+    if score is None and want_scores:
+        score = torch.empty(r, dtype=torch.float64, device=B.device)
+    fn = h._lib.cnmf_spa_noalloc if noalloc else h._lib.cnmf_spa
+    L.check(fn(h.raw, _ptr(B), _DT[B.dtype], B.shape[0], B.shape[1], B.stride(0), int(r), _ptr(K), _ptr(score)),
+            h.raw)
     return K, score
 
 

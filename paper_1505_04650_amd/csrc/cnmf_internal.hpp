@@ -227,6 +227,12 @@ hipError_t launch_residual_finish(const double* partial, int parts, double* out,
 // Partial count of the residual launch for an m x n A.
 int residual_blocks(int m, int n);
 hipError_t launch_flags_to_stats(const int* flags, int nflags, double* out, hipStream_t st);
+// Fixed per-device scratch of cnmf_spa_noalloc (k_scratch.hip): bytes, the
+// address lookup (once per device, with that device current) and the
+// device address found (NULL before the lookup).
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+hipError_t noalloc_scratch_init(int device);
+void* noalloc_scratch(int device);
 hipError_t launch_spa_step(double* Bt, int n, int k, int ldb, int t, int64_t* K, double* score,
                            double* u, double* wg_best, int64_t* wg_idx, unsigned* counter,
                            int nblocks, hipStream_t st);

@@ -1218,6 +1218,10 @@ cnmf_status cnmf_create(int device, void* hip_stream, size_t workspace_limit, cn
   if (device < 0 || device >= ndev) return fail(nullptr, CNMF_EINVAL, "device %d out of range [0, %d)", device, ndev);
   e = hipSetDevice(device);
   if (e != hipSuccess) return fail(nullptr, CNMF_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  e = noalloc_scratch_init(device);
+  if (e != hipSuccess)
+    return fail(nullptr, CNMF_EDEVICE, "looking up the fixed scratch of cnmf_spa_noalloc failed: %s",
+                hipGetErrorString(e));
   void* ud = nullptr;
   e = hipMalloc(&ud, 256);
   if (e != hipSuccess) return fail(nullptr, CNMF_ENOMEM, "hipMalloc(256) failed: %s", hipGetErrorString(e));
@@ -1386,8 +1390,8 @@ cnmf_status snmf_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_d
   return do_select<float>(h, A, d, K_dev, score_dev, B_dev);
 }
 
-cnmf_status cnmf_spa(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n, int64_t ldb,
-                     int32_t r, int64_t* K_dev, double* score_dev) {
+static cnmf_status check_spa(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n, int64_t ldb,
+                             int32_t r, const int64_t* K_dev) {
   if (!B_dev || !K_dev) return fail(h, CNMF_EINVAL, "B_dev and K_dev are required");
   if (dtype != CNMF_F64 && dtype != CNMF_F32) return fail(h, CNMF_EINVAL, "B must be F64 or F32");
   if (k < 1 || n < 1 || ldb < n) return fail(h, CNMF_EINVAL, "bad B shape k=%lld n=%lld ldb=%lld", (long long)k, (long long)n, (long long)ldb);
@@ -1395,31 +1399,72 @@ cnmf_status cnmf_spa(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_
   if (n > INT32_MAX / 2) return fail(h, CNMF_ENOTSUP, "n above 2^30 is not supported");
   if (r < 1 || r > std::min<int64_t>(k, n)) return fail(h, CNMF_EINVAL, "r=%d must be in [1, min(k, n)]", r);
   if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
-  HIPCHK(h, hipSetDevice(h->device));
-  const int nblk = (int)((n + 63) / 64);
-  Arena dry(nullptr);
-  dry.take<double>((size_t)n * k);
-  dry.take<double>(k);
-  dry.take<double>(nblk);
-  dry.take<int64_t>(nblk);
-  dry.take<unsigned>(4);
-  cnmf_status s = ensure_ws(h, dry.off);
-  if (s != CNMF_OK) return s;
-  Arena a(h->ws);
-  double* Bt64 = a.take<double>((size_t)n * k);
-  double* u = a.take<double>(k);
-  double* wb = a.take<double>(nblk);
-  int64_t* wi = a.take<int64_t>(nblk);
-  unsigned* ctr = a.take<unsigned>(4);
-  hipStream_t st = h->stream;
-  if (dtype == CNMF_F64)
-    HIPCHK(h, (launch_transpose<double, double>((const double*)B_dev, ldb, Bt64, k, (int)k, (int)n, st)));
-  else
-    HIPCHK(h, (launch_transpose<float, double>((const float*)B_dev, ldb, Bt64, k, (int)k, (int)n, st)));
-  HIPCHK(h, launch_fill(ctr, 4 * sizeof(unsigned), st));
-  for (int t = 0; t < r; ++t)
-    HIPCHK(h, launch_spa_step(Bt64, (int)n, (int)k, (int)k, t, K_dev, score_dev, u, wb, wi, ctr, nblk, st));
   return CNMF_OK;
+}
+
+// SPA working storage (B^T in FP64, the unit pivot, per-block winners),
+// laid out from `base` (NULL: sizing only); returns the bytes used.
+struct SpaWs {
+  double* Bt64;
+  double* u;
+  double* wb;
+  int64_t* wi;
+};
+static size_t layout_spa(char* base, int64_t k, int64_t n, SpaWs& w) {
+  const int nblk = (int)((n + 63) / 64);
+  Arena a(base);
+  w.Bt64 = a.take<double>((size_t)n * k);
+  w.u = a.take<double>(k);
+  w.wb = a.take<double>(nblk);
+  w.wi = a.take<int64_t>(nblk);
+  return a.off;
+}
+
+// Every word of the working storage is written before it is read (B^T by
+// the transpose, u by step 0's pick, the winners by each step's norms), so
+// nothing needs clearing.
+static cnmf_status run_spa(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n, int64_t ldb,
+                           int32_t r, int64_t* K_dev, double* score_dev, const SpaWs& w) {
+  hipStream_t st = h->stream;
+  const int nblk = (int)((n + 63) / 64);
+  if (dtype == CNMF_F64)
+    HIPCHK(h, (launch_transpose<double, double>((const double*)B_dev, ldb, w.Bt64, k, (int)k, (int)n, st)));
+  else
+    HIPCHK(h, (launch_transpose<float, double>((const float*)B_dev, ldb, w.Bt64, k, (int)k, (int)n, st)));
+  for (int t = 0; t < r; ++t)
+    HIPCHK(h, launch_spa_step(w.Bt64, (int)n, (int)k, (int)k, t, K_dev, score_dev, w.u, w.wb, w.wi, nullptr, nblk,
+                              st));
+  return CNMF_OK;
+}
+
+cnmf_status cnmf_spa(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n, int64_t ldb,
+                     int32_t r, int64_t* K_dev, double* score_dev) {
+  cnmf_status s = check_spa(h, B_dev, dtype, k, n, ldb, r, K_dev);
+  if (s != CNMF_OK) return s;
+  HIPCHK(h, hipSetDevice(h->device));
+  SpaWs w;
+  s = ensure_ws(h, layout_spa(nullptr, k, n, w));
+  if (s != CNMF_OK) return s;
+  layout_spa(h->ws, k, n, w);
+  return run_spa(h, B_dev, dtype, k, n, ldb, r, K_dev, score_dev, w);
+}
+
+cnmf_status cnmf_spa_noalloc(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n,
+                             int64_t ldb, int32_t r, int64_t* K_dev, double* score_dev) {
+  cnmf_status s = check_spa(h, B_dev, dtype, k, n, ldb, r, K_dev);
+  if (s != CNMF_OK) return s;
+  SpaWs w;
+  const size_t need = layout_spa(nullptr, k, n, w);
+  if (need > kNoAllocScratchBytes)
+    return fail(h, CNMF_ENOTSUP,
+                "SPA of a %lld x %lld B needs %zu bytes of scratch; the fixed scratch holds %zu "
+                "(about (k + 2) n <= 4.19e6 doubles); use cnmf_spa",
+                (long long)k, (long long)n, need, kNoAllocScratchBytes);
+  HIPCHK(h, hipSetDevice(h->device));
+  char* base = (char*)noalloc_scratch(h->device);
+  if (!base) return fail(h, CNMF_EDEVICE, "internal: the fixed scratch of device %d was not looked up", h->device);
+  layout_spa(base, k, n, w);
+  return run_spa(h, B_dev, dtype, k, n, ldb, r, K_dev, score_dev, w);
 }
 
 cnmf_status cnmf_range_product(cnmf_handle* h, const cnmf_input* A, int trans, const void* X_dev, int32_t kx,
