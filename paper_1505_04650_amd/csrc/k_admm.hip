@@ -448,7 +448,7 @@ __device__ __forceinline__ void chol_side(const double* __restrict__ At, const d
     double dg = lane < r ? Mb[lane * ld + lane] : 0.0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o));
-    wave_chol_lower<NB>(Mb, ld, r, V, W, 1e-300 * dg, flags);
+    wave_chol_lower<double, NB>(Mb, ld, r, V, W, 1e-300 * dg, flags);
   } else {
     // (b) strips of RHS into E (kp x ld, row xr = 16 rb + c): the lane's At
     // and P values are loaded up front, then RHS^T tiles = S^T At^T (+ P^T)

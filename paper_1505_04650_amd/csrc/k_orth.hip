@@ -291,7 +291,7 @@ __device__ __forceinline__ void chol_tinv_wave_body(const double* __restrict__ G
     double dg = lane < kh ? M[lane * ld + lane] : 0.0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o));
-    wave_chol_lower<NB, DEC>(M, ld, kh, V, W, dg > 0.0 ? tau * dg : 1.0, flag, nanflag, mask);
+    wave_chol_lower<double, NB, DEC>(M, ld, kh, V, W, dg > 0.0 ? tau * dg : 1.0, flag, nanflag, mask);
   }
   __syncthreads();
   if (w < NB) {
@@ -363,7 +363,7 @@ __device__ __forceinline__ void chol_tinv_wave128_body(const double* __restrict_
     for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o));
     if (dg > 0.0) fl = tau * dg;
   }
-  if (w == 0) wave_chol_lower<4, DEC>(M, ld, 64, V, W, fl, flag, nanflag, mask);
+  if (w == 0) wave_chol_lower<double, 4, DEC>(M, ld, 64, V, W, fl, flag, nanflag, mask);
   __syncthreads();
   // L21: wave w solves rows 64 + 16 w .. + 15 of X L11^T = G21 as L11 X^T = G21^T
   {
@@ -413,7 +413,7 @@ __device__ __forceinline__ void chol_tinv_wave128_body(const double* __restrict_
       for (int i = 0; i < 4; ++i) M[(64 + 16 * w + g + 4 * i) * ld + 64 + 16 * jb + c] = acc[jb][i];
   }
   __syncthreads();
-  if (w == 0) wave_chol_lower<4, DEC>(M + 64 * ld + 64, ld, kh - 64, V + 4 * 272, W, fl, flag, nanflag, mask + 1);
+  if (w == 0) wave_chol_lower<double, 4, DEC>(M + 64 * ld + 64, ld, kh - 64, V + 4 * 272, W, fl, flag, nanflag, mask + 1);
   __syncthreads();
   // Z = L^-1, column strips j = w and w + 4
 #pragma unroll

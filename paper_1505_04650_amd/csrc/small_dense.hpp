@@ -263,6 +263,46 @@ __device__ __forceinline__ double rsqrt_fast(double d) {
   return fma(y0 * e, fma(e, 0.375, 0.5), y0);
 }
 
+// Scalar-type traits of the single-wave factorisation and the solves built
+// on it: the 16x16x4 MFMA of the type, where its result item i of lane
+// group g = lane / 16 sits (row out_row(g, i) of the tile, column lane % 16:
+// g + 4 i for FP64, 4 g + i for FP32, measured), and the K index a lane
+// group supplies in K step s when a result tile is fed back as the right
+// operand of the next product (kx(s, g), the row of item s), so chained
+// products need no data movement.  Operands loaded from memory may use any
+// K order as long as both operands agree.
+template <typename T>
+struct SD;
+template <>
+struct SD<double> {
+  typedef doublex4 v4;
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int i) { return g + 4 * i; }
+  static __device__ __forceinline__ int kx(int s, int g) { return 4 * s + g; }
+  static __device__ __forceinline__ double readlane(double x, int l) { return readlane_d(x, l); }
+  static __device__ __forceinline__ double rsq(double d) { return rsqrt_fast(d); }
+  static __device__ __forceinline__ double fmax_(double a, double b) { return fmax(a, b); }
+  static __device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
+};
+template <>
+struct SD<float> {
+  typedef floatx4 v4;
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int i) { return 4 * g + i; }
+  static __device__ __forceinline__ int kx(int s, int g) { return 4 * g + s; }
+  static __device__ __forceinline__ float readlane(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+  }
+  // hardware reciprocal square root (about 1 ulp)
+  static __device__ __forceinline__ float rsq(float d) { return __builtin_amdgcn_rsqf(d); }
+  static __device__ __forceinline__ float fmax_(float a, float b) { return fmaxf(a, b); }
+  static __device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+};
+
 // Steps of one 16-column panel (see wave_chol_lower).  FULL: all 16 steps,
 // no branches, so the scheduler can overlap consecutive steps; otherwise
 // only the first `steps` (uniform) are taken.  The dependent chain of a step
@@ -276,41 +316,41 @@ __device__ __forceinline__ double rsqrt_fast(double d) {
 // vector (1 on the diagonal, 0 below), so the column takes no part in the
 // later steps; bit c0 + s of mbits records it and NaN pivots are also
 // counted in nnan.  Without DEC such a pivot is replaced by floor_piv.
-template <bool FULL, bool DEC, typename X>
-__device__ __forceinline__ void wave_panel_steps(double (&a)[16], int c0, int steps, double* colbuf,
-                                                 double floor_piv, double& myinv, int& nbad, uint64_t& mbits,
-                                                 int& nnan, X extra) {
+template <typename T, bool FULL, bool DEC, typename X>
+__device__ __forceinline__ void wave_panel_steps(T (&a)[16], int c0, int steps, T* colbuf, T floor_piv, T& myinv,
+                                                 int& nbad, uint64_t& mbits, int& nnan, X extra) {
+  typedef SD<T> D;
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     extra(s);
     if (FULL || s < steps) {
-      const double d0 = readlane_d(a[s], c0 + s);
+      const T d0 = D::readlane(a[s], c0 + s);
       const bool bad = !(d0 > floor_piv);   // also true for NaN
       nbad += bad ? 1 : 0;
       const bool piv = lane == c0 + s;
-      double l, y;
+      T l, y;
       if constexpr (DEC) {
         nnan += (d0 != d0) ? 1 : 0;
         mbits |= bad ? (1ull << (c0 + s)) : 0ull;
-        const double d = bad ? 1.0 : d0;
-        const double as = piv ? d : a[s];
-        y = rsqrt_fast(d);
-        l = bad ? (piv ? 1.0 : 0.0) : as * y;
+        const T d = bad ? T(1) : d0;
+        const T as = piv ? d : a[s];
+        y = D::rsq(d);
+        l = bad ? (piv ? T(1) : T(0)) : as * y;
       } else {
-        const double d = fmax(d0, floor_piv);
-        const double as = piv ? d : a[s];
-        y = rsqrt_fast(d);
+        const T d = D::fmax_(d0, floor_piv);
+        const T as = piv ? d : a[s];
+        y = D::rsq(d);
         l = as * y;   // L[lane][c0 + s]; sqrt(d) on the pivot lane
       }
       a[s] = l;
       myinv = piv ? y : myinv;
       if (s + 1 < 16) {
-        a[s + 1] = fma(-l, readlane_d(l, c0 + s + 1), a[s + 1]);
+        a[s + 1] = D::fma_(-l, D::readlane(l, c0 + s + 1), a[s + 1]);
         if (s + 2 < 16) {
           colbuf[lane] = l;
 #pragma unroll
-          for (int t = s + 2; t < 16; ++t) a[t] = fma(-l, colbuf[c0 + t], a[t]);
+          for (int t = s + 2; t < 16; ++t) a[t] = D::fma_(-l, colbuf[c0 + t], a[t]);
         }
       }
     }
@@ -319,55 +359,59 @@ __device__ __forceinline__ void wave_panel_steps(double (&a)[16], int c0, int st
 
 // ---------------------------------------------------------------------------
 // One wave, no barriers: M (N x N, N = 16 NB <= 64, LDS, row stride ld) =
-// L L^T with L lower triangular and a positive diagonal.  Read: the lower
-// triangle and diagonal of M (the strict upper triangle of the diagonal
-// 16 x 16 blocks may hold anything).  On return L is in M's lower triangle
-// (the strict upper triangle is left undefined) and V[b] (16 x 17 each)
-// holds the inverse of the diagonal block L[b][b] (lower, zeros above).
-// Rows and columns from n on must be those of the identity (no coupling),
-// so their steps are skipped and L is the identity there too.  A pivot
-// <= floor (or NaN) is replaced by floor (floor > 0), or with DEC its column
-// is decoupled (see wave_panel_steps); the number of such pivots is added to
-// *flag, with DEC the number of NaN pivots to *nanflag and the decoupled
-// columns (bit j: column j) are or-ed into *mask (one wave-uniform word,
-// N <= 64).  W: 128 doubles of LDS scratch.
+// L L^T with L lower triangular and a positive diagonal, in T (FP64 or FP32,
+// the products on that type's MFMA).  Read: the lower triangle and diagonal
+// of M (the strict upper triangle of the diagonal 16 x 16 blocks may hold
+// anything).  On return L is in M's lower triangle (the strict upper
+// triangle is left undefined) and V[b] (16 x 17 each) holds the inverse of
+// the diagonal block L[b][b] (lower, zeros above).  Rows and columns from n
+// on must be those of the identity (no coupling), so their steps are skipped
+// and L is the identity there too.  A pivot <= floor (or NaN) is replaced by
+// floor (floor > 0), or with DEC its column is decoupled (see
+// wave_panel_steps); the number of such pivots is added to *flag, with DEC
+// the number of NaN pivots to *nanflag and the decoupled columns (bit j:
+// column j) are or-ed into *mask (one wave-uniform word, N <= 64).  W: 128
+// elements of LDS scratch.
 //
 // Right-looking by 16-column panels: lane j keeps row j of the panel in
 // registers.  Step s takes the pivot of lane c0 + s by readlane; the entry
 // of the next pivot row comes by readlane too, so the dependent chain of a
 // step is short, and the rest of the column is broadcast through LDS.  The
-// trailing lower block triangle is updated with 16x16x4 FP64 MFMA tile
-// products, all operands loaded before the first product.  At the end the
-// lanes 16 q + v (v < 16) invert block q, column v, by forward
-// substitution.  A wave's LDS operations complete in order, so no barrier
-// is needed between them.
+// trailing lower block triangle is updated with 16x16x4 MFMA tile products,
+// all operands loaded before the first product.  At the end the lanes
+// 16 q + v (v < 16) invert block q, column v, by forward substitution.  A
+// wave's LDS operations complete in order, so no barrier is needed between
+// them.
 // ---------------------------------------------------------------------------
-template <int NB, bool DEC = false>
-__device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double* V, double* W, double floor_piv,
-                                                int* flag, int* nanflag = nullptr, uint64_t* mask = nullptr) {
+template <typename T, int NB, bool DEC = false>
+__device__ __forceinline__ void wave_chol_lower(T* M, int ld, int n, T* V, T* W, T floor_piv, int* flag,
+                                                int* nanflag = nullptr, uint64_t* mask = nullptr) {
+  typedef SD<T> D;
+  typedef typename D::v4 v4;
   constexpr int N = 16 * NB;
   const int lane = threadIdx.x & 63;
   const int c = lane & 15, g = lane >> 4;
-  double* colbuf = W;       // the current column of L
-  double* dinv = W + 64;    // 1 / L[i][i]
+  T* colbuf = W;       // the current column of L
+  T* dinv = W + 64;    // 1 / L[i][i]
   int nbad = 0, nnan = 0;
   uint64_t mbits = 0;
   // The trailing tiles (ti >= tj >= 1) stay in registers in the MFMA result
-  // layout (item i of lane (c, g): row 16 ti + g + 4 i, column 16 tj + c).
-  // After panel P only column P + 1 is updated at once (the next panel needs
-  // it); the updates of the tiles right of it are issued between the next
-  // panel's steps.  Each tile still receives the panels' updates in panel
-  // order, by the same products.
+  // layout (item i of lane (c, g): row 16 ti + out_row(g, i), column
+  // 16 tj + c).  After panel P only column P + 1 is updated at once (the
+  // next panel needs it); the updates of the tiles right of it are issued
+  // between the next panel's steps.  Each tile still receives the panels'
+  // updates in panel order, by the same products.
   constexpr int NT = NB > 1 ? NB * (NB - 1) / 2 : 1;
-  doublex4 tl[NT];
+  v4 tl[NT];
 #pragma unroll
   for (int ti = 1; ti < NB; ++ti)
 #pragma unroll
     for (int tj = 1; tj <= ti; ++tj)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) tl[(ti - 1) * ti / 2 + tj - 1][i] = M[(16 * ti + g + 4 * i) * ld + 16 * tj + c];
+      for (int i = 0; i < 4; ++i)
+        tl[(ti - 1) * ti / 2 + tj - 1][i] = M[(16 * ti + D::out_row(g, i)) * ld + 16 * tj + c];
   constexpr int kMaxT = NB > 1 ? NB - 1 : 1;
-  double lv[kMaxT][4];   // L[16 (P + 1 + u) + c][16 P + 4 s + g] of the last factored panel P
+  T lv[kMaxT][4];   // L[16 (P + 1 + u) + c][16 P + 4 s + g] of the last factored panel P
 #pragma unroll
   for (int P = 0; P < NB; ++P) {
     const int c0 = 16 * P;
@@ -377,12 +421,12 @@ __device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double
       for (int ti = P; ti < NB; ++ti)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          M[(16 * ti + g + 4 * i) * ld + c0 + c] = tl[(ti - 1) * ti / 2 + P - 1][i];
+          M[(16 * ti + D::out_row(g, i)) * ld + c0 + c] = tl[(ti - 1) * ti / 2 + P - 1][i];
     }
-    double a[16];
+    T a[16];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) a[t] = act ? M[lane * ld + c0 + t] : 0.0;
-    double myinv = 1.0;
+    for (int t = 0; t < 16; ++t) a[t] = act ? M[lane * ld + c0 + t] : T(0);
+    T myinv = T(1);
     const int steps = n - c0;   // uniform
     // panel P - 1's updates of the tiles ti >= tj >= P + 1, one product per step
     auto deferred = [&](int q) {
@@ -395,17 +439,17 @@ __device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {
               if (idx == q) {
-                doublex4& t = tl[(ti - 1) * ti / 2 + tj - 1];
-                t = __builtin_amdgcn_mfma_f64_16x16x4f64(-lv[ti - P][s4], lv[tj - P][s4], t, 0, 0, 0);
+                v4& t = tl[(ti - 1) * ti / 2 + tj - 1];
+                t = D::mma(-lv[ti - P][s4], lv[tj - P][s4], t);
               }
               ++idx;
             }
       }
     };
     if (steps >= 16)
-      wave_panel_steps<true, DEC>(a, c0, steps, colbuf, floor_piv, myinv, nbad, mbits, nnan, deferred);
+      wave_panel_steps<T, true, DEC>(a, c0, steps, colbuf, floor_piv, myinv, nbad, mbits, nnan, deferred);
     else
-      wave_panel_steps<false, DEC>(a, c0, steps, colbuf, floor_piv, myinv, nbad, mbits, nnan, deferred);
+      wave_panel_steps<T, false, DEC>(a, c0, steps, colbuf, floor_piv, myinv, nbad, mbits, nnan, deferred);
     if (act) {
 #pragma unroll
       for (int t = 0; t < 16; ++t) M[lane * ld + c0 + t] = a[t];
@@ -421,10 +465,9 @@ __device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double
         }
 #pragma unroll
       for (int ti = P + 1; ti < NB; ++ti) {
-        doublex4& t = tl[(ti - 1) * ti / 2 + P];
+        v4& t = tl[(ti - 1) * ti / 2 + P];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-          t = __builtin_amdgcn_mfma_f64_16x16x4f64(-lv[ti - P - 1][s4], lv[0][s4], t, 0, 0, 0);
+        for (int s4 = 0; s4 < 4; ++s4) t = D::mma(-lv[ti - P - 1][s4], lv[0][s4], t);
       }
     }
   }
@@ -432,14 +475,14 @@ __device__ __forceinline__ void wave_chol_lower(double* M, int ld, int n, double
   // x_i /= L[i][i] and x_t -= L[t][i] x_i (t > i)
   if (g < NB) {
     const int q0 = 16 * g;
-    double x[16];
+    T x[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = i == c ? 1.0 : 0.0;
+    for (int i = 0; i < 16; ++i) x[i] = i == c ? T(1) : T(0);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       x[i] *= dinv[q0 + i];
 #pragma unroll
-      for (int t = i + 1; t < 16; ++t) x[t] = fma(-M[(q0 + t) * ld + q0 + i], x[i], x[t]);
+      for (int t = i + 1; t < 16; ++t) x[t] = D::fma_(-M[(q0 + t) * ld + q0 + i], x[i], x[t]);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) V[g * 272 + i * 17 + c] = x[i];
