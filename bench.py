@@ -79,20 +79,69 @@ def cpu_baseline(inp, w, lam, budget_s=15.0):
         if el >= budget_s or el / done * (done + 1) > 2.5 * budget_s:
             break
     el = time.perf_counter() - t0
+    hi = host_info()
     return {"value": done / el, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "cpu_model": hi["cpu_model"], "blas": hi["blas"], "logical_cpus": hi["logical_cpus"],
             "sample": f"{done} full solve(s) of the same 20000x5000 workload (FP64 NumPy, "
                       f"sketch q=4 + {w.iters} ADMM iterations + residual) in {el:.1f} s"}, res
 
 
-def _proj_residual(A, L, norm_a):
-    """||A - L L^T A||_F / ||A||_F = sqrt(||A||^2 - ||L^T A||^2) / ||A|| for
-    orthonormal L, with L^T A accumulated in FP64 over row blocks."""
+def _proj_residual(A, L, norm_a, blk=8192):
+    """||A - L (L^T A)||_F / ||A||_F formed directly (not through ||A||^2 -
+    ||L^T A||^2, which assumes L^T L = I) in FP64 over row blocks, and the
+    orthonormality error max|L^T L - I|, from plain PyTorch FP64 products."""
     import torch
     k, n = L.shape[1], A.shape[1]
+    Ld = L.double()
     B = torch.zeros(k, n, dtype=torch.float64, device=A.device)
-    for i in range(0, A.shape[0], 8192):
-        B += L[i:i + 8192].double().T @ A[i:i + 8192].double()
-    return math.sqrt(max(0.0, norm_a ** 2 - float((B * B).sum()))) / norm_a
+    for i in range(0, A.shape[0], blk):
+        B += Ld[i:i + blk].T @ A[i:i + blk].double()
+    ss = 0.0
+    for i in range(0, A.shape[0], blk):
+        R = A[i:i + blk].double() - Ld[i:i + blk] @ B
+        ss += float((R * R).sum())
+    orth = float((Ld.T @ Ld - torch.eye(k, dtype=torch.float64, device=A.device)).abs().max())
+    return math.sqrt(ss) / norm_a, orth
+
+
+def _fp64_reference_sketch(A, oml, omr, q, blk=8192):
+    """An FP64 reference of the two-sided sketch with plain PyTorch on the
+    device: A in FP64, Householder QR (torch.linalg.qr) after every product,
+    signs fixed so that diag(R) >= 0.  Returns L (m x k), R (k x n), B, At."""
+    import torch
+
+    def orth(Y):
+        Q, Rr = torch.linalg.qr(Y)
+        sg = torch.sign(torch.diagonal(Rr))
+        sg[sg == 0] = 1.0
+        return Q * sg
+
+    def av(X):   # A X, X n x k
+        return torch.cat([A[i:i + blk].double() @ X for i in range(0, A.shape[0], blk)])
+
+    def atv(Z):  # A^T Z, Z m x k
+        out = torch.zeros(A.shape[1], Z.shape[1], dtype=torch.float64, device=A.device)
+        for i in range(0, A.shape[0], blk):
+            out += A[i:i + blk].double().T @ Z[i:i + blk]
+        return out
+
+    Lq = orth(av(oml))
+    for _ in range(q):
+        Lq = orth(av(orth(atv(Lq))))
+    Rq = orth(atv(omr))
+    for _ in range(q):
+        Rq = orth(atv(orth(av(Rq))))
+    B = atv(Lq).T.contiguous()          # k x n
+    At = B @ Rq                          # k x k  (B R^T with R = Rq^T)
+    return Lq, Rq.T.contiguous(), B, At
+
+
+def _sin_max_angle(Q1, Q2):
+    """sin of the largest principal angle between the column spans of the
+    orthonormal Q1, Q2 (2-norm of Q1's part outside span(Q2))."""
+    import torch
+    D = Q1 - Q2 @ (Q2.T @ Q1)
+    return float(torch.linalg.matrix_norm(D, ord=2))
 
 
 def precision_section(h, steps, warmup):
@@ -109,6 +158,12 @@ def precision_section(h, steps, warmup):
     oml = torch.randn(w.n, w.k, device=dev, dtype=torch.float64, generator=g)
     omr = torch.randn(w.m, w.k, device=dev, dtype=torch.float64, generator=g)
     norm_a = math.sqrt(sum(float((A[i:i + 8192].double() ** 2).sum()) for i in range(0, w.m, 8192)))
+    t_ref = time.perf_counter()
+    refL, refR, refB, refAt = _fp64_reference_sketch(A, oml, omr, w.q)
+    ref_res, ref_orth = _proj_residual(A, refL, norm_a)
+    torch.cuda.synchronize()
+    log(f"precision: FP64 reference sketch (PyTorch FP64, Householder QR) in {time.perf_counter() - t_ref:.1f} s, "
+        f"projection residual {ref_res:.6e}")
     flops = 2.0 * w.m * w.n * w.k * (2 * (1 + 2 * w.q) + 1)  # two chains of 2q + 1 products, and B
     out = {"workload": w.name, "m": w.m, "n": w.n, "r": w.r, "k": w.k, "q": w.q, "sides": "both",
            "data": "synthetic, generated on the device"}
@@ -136,16 +191,187 @@ def precision_section(h, steps, warmup):
         ms = e0.elapsed_time(e1) / steps
         pn, pt = agg.get("pass_AX", [0, 0, 0]), agg.get("pass_ATZ", [0, 0, 0])
         pass_ms = (pn[0] + pt[0]) / steps
+        pres, porth = _proj_residual(A, sk.L, norm_a)
+        r_ = w.r
+        vs_ref = {"proj_residual_gap": abs(pres - ref_res),
+                  "orth_err_L": porth,
+                  "sin_angle_L_leading_r": _sin_max_angle(sk.L.double()[:, :r_], refL[:, :r_]),
+                  "sin_angle_R_leading_r": _sin_max_angle(sk.R.double().T[:, :r_].contiguous(), refR.T[:, :r_]),
+                  "rel_err_B": float(torch.linalg.norm(sk.B.double() - refB) / torch.linalg.norm(refB)),
+                  "rel_err_At": float(torch.linalg.norm(sk.At.double() - refAt) / torch.linalg.norm(refAt))}
         out[pd] = {"final_dtype": fd, "sketch_ms": ms, "sketch_tflops": flops / (ms * 1e-3) / 1e12,
                    "pass_ms": pass_ms, "pass_tflops": flops / (pass_ms * 1e-3) / 1e12,
                    "stages_ms": {k: v[0] / steps for k, v in agg.items() if v[2]},
-                   "proj_residual": _proj_residual(A, sk.L, norm_a)}
+                   "proj_residual": pres, "vs_fp64_reference": vs_ref}
         log(f"precision {pd}/{fd}: {ms:.3f} ms per sketch, projection residual {out[pd]['proj_residual']:.6e}")
     ref = out["f32"]["proj_residual"]
     for pd in ("bf16", "fp8"):
         out[pd]["proj_residual_gap_vs_f32"] = abs(out[pd]["proj_residual"] - ref)
         out[pd]["speedup_vs_f32"] = out["f32"]["sketch_ms"] / out[pd]["sketch_ms"]
+    out["fp64_reference"] = {"kind": "PyTorch FP64 on the device (A cast to FP64 per row block, Householder QR "
+                                     "after every product, diag(R) >= 0), the same test matrices",
+                             "proj_residual": ref_res, "orth_err_L": ref_orth}
+    del A, refL, refR, refB, refAt
+    torch.cuda.empty_cache()
+    return out
+
+
+def host_info():
+    """CPU model, logical cores and the BLAS NumPy uses (for cpu_baseline)."""
+    info = {"cpu_model": None, "logical_cpus": os.cpu_count(), "blas": None}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        libs = [f"{d.get('internal_api')} {d.get('version')} ({d.get('num_threads')} threads)"
+                for d in threadpool_info() if d.get("user_api") == "blas"]
+        info["blas"] = ", ".join(libs) or None
+    except Exception:  # pragma: no cover
+        pass
+    return info
+
+
+def attainable_peaks():
+    """Measured attainable peaks on this GPU: HBM (a 4 GiB device copy,
+    bytes read + written per second) and the dense matrix engines through
+    the vendor GEMM (hipBLASLt via torch.matmul, 8192^3) in FP32, BF16, FP64."""
+    import torch
+    dev = torch.device("cuda", 0)
+    out = {}
+    src = torch.empty(1 << 30, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 5
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out["hbm_copy_GBps"] = 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
+    del src, dst
+    nn = 8192
+    for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16), ("fp64", torch.float64)):
+        a = torch.randn(nn, nn, device=dev, dtype=torch.float32).to(dt)
+        b = torch.randn(nn, nn, device=dev, dtype=torch.float32).to(dt)
+        for _ in range(2):
+            c = a @ b
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"gemm_{name}_TFLOPs"] = 2.0 * nn ** 3 / (ms * 1e-3) / 1e12
+        del a, b, c
+    torch.cuda.empty_cache()
+    out["note"] = ("vendor GEMM through torch.matmul (8192^3, square) and a device copy; fractions in the "
+                   "roofline objects are against the published peaks")
+    return out
+
+
+def extra_workloads_section(h, lam_c2, inp_c2, w_c2):
+    """The other workloads, measured beside the headline:
+    * 1000 x 500 FP64 (q 4, 100 ADMM iterations): device time per stage and
+      the factors' gap to the oracle (the parity workload);
+    * 20000 x 5000 FP32: compressed MU, and uncompressed ADMM / MU (L = I,
+      R = I), 200 iterations each, time and FP64 residual beside compressed
+      ADMM;
+    * 10000 x 100000 separable FP32 (two-sided, q 2): sketch time and GB/s of
+      A read, SPA time, and whether SPA returns exactly the planted columns."""
+    import torch
+    from oracle import cnmf_oracle as O
+    from paper_1505_04650_amd import api
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.as_tensor(x, dtype=torch.float64, device=dev)
+    out = {}
+    # 1000 x 500 FP64
+    w = WL.WORKLOADS["plain_fp64_1000x500"]
+    inp = WL.make_inputs(w)
+    sk = O.sketch(inp["A"], inp["Omega_L"], inp["Omega_R"], w.q)
+    lam = float(np.linalg.svd(sk["At"], compute_uv=False)[w.r - 1])
+    ref = O.admm(sk["At"], sk["L"], sk["R"], inp["U1"], inp["V1"], lam, lam, 1.0, w.iters)
+    args = (t(inp["A"]), w.r, w.k, w.q, t(inp["U1"]), t(inp["V1"]), t(inp["Omega_L"]), t(inp["Omega_R"]))
+    for _ in range(2):
+        api.factorize(*args, iters=w.iters, lam=lam, phi=lam, handle=h)
+    torch.cuda.synchronize()
+    h.set_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(h.stream)
+    f = api.factorize(*args, iters=w.iters, lam=lam, phi=lam, handle=h)
+    e1.record(h.stream)
+    torch.cuda.synchronize()
+    st = {k: (v[0] * 1e3 if not math.isnan(v[0]) else None) for k, v in h.stages().items() if v[2]}
+    h.set_timing(False)
+    U = f.U.cpu().numpy()
+    out["plain_fp64_1000x500"] = {
+        "us_per_solve": e0.elapsed_time(e1) * 1e3, "us_per_stage": st,
+        "rel_diff_U_vs_oracle": float(np.linalg.norm(U - ref["U"]) / np.linalg.norm(ref["U"])),
+        "rel_residual": float(f.rel_residual.item()),
+        "rel_residual_oracle": O.rel_residual(inp["A"], ref["U"], ref["V"])}
+    log(f"1000x500 FP64: {out['plain_fp64_1000x500']['us_per_solve']:.0f} us per solve")
+    # 20000 x 5000: compressed MU and the uncompressed comparators
+    A = torch.as_tensor(inp_c2["A"], device=dev)
+    c2 = {}
+    for method in ("mu", "admm_full", "mu_full"):
+        fa = (A, w_c2.r, w_c2.k, w_c2.q, t(inp_c2["U1"]), t(inp_c2["V1"]), t(inp_c2["Omega_L"]),
+              t(inp_c2["Omega_R"]))
+        api.factorize(*fa, method=method, iters=w_c2.iters, lam=lam_c2, phi=lam_c2, mu_eps=1e-16, handle=h)
+        torch.cuda.synchronize()
+        e0.record(h.stream)
+        f = api.factorize(*fa, method=method, iters=w_c2.iters, lam=lam_c2, phi=lam_c2, mu_eps=1e-16, handle=h)
+        e1.record(h.stream)
+        torch.cuda.synchronize()
+        c2[method] = {"ms_per_solve": e0.elapsed_time(e1), "rel_residual": float(f.rel_residual.item())}
+        log(f"20000x5000 {method}: {c2[method]['ms_per_solve']:.2f} ms, residual {c2[method]['rel_residual']:.6e}")
+    out["nmf_fp32_20000x5000_methods"] = dict(c2, iters=w_c2.iters, lam=lam_c2)
     del A
+    # 10000 x 100000 separable, two-sided
+    ws = WL.WORKLOADS["separable_fp32_10000x100000"]
+    g = torch.Generator(device=dev)
+    g.manual_seed(100 * ws.index)
+    Wm = torch.rand(ws.m, ws.r, device=dev, generator=g)
+    E = -torch.log1p(-torch.rand(ws.r, ws.n - ws.r, device=dev, dtype=torch.float64, generator=g))
+    Hp = E / E.sum(dim=0, keepdim=True)
+    Hp *= 1.0 - torch.rand(1, ws.n - ws.r, device=dev, dtype=torch.float64, generator=g)
+    H = torch.cat([torch.eye(ws.r, device=dev, dtype=torch.float64), Hp], dim=1).float()
+    perm = torch.randperm(ws.n, device=dev, generator=g)
+    As = (Wm @ H)[:, perm].contiguous()
+    As += ws.sep_noise * torch.randn(ws.m, ws.n, device=dev, generator=g)
+    planted = sorted(torch.nonzero(perm < ws.r).flatten().cpu().tolist())
+    del Wm, E, Hp, H
+    for _ in range(2):
+        K, _, _ = api.select(As, ws.r, ws.k, ws.q, sides="both", seed=300, handle=h)
+    torch.cuda.synchronize()
+    h.set_timing(True)
+    e0.record(h.stream)
+    K, score, _ = api.select(As, ws.r, ws.k, ws.q, sides="both", seed=300, want_scores=True, handle=h)
+    e1.record(h.stream)
+    torch.cuda.synchronize()
+    stg = {k: v for k, v in h.stages().items() if v[2]}
+    h.set_timing(False)
+    total = e0.elapsed_time(e1)
+    spa_ms = stg.get("spa", (float("nan"),))[0]
+    sketch_ms = total - spa_ms
+    npass = 2 * ws.q + 2
+    out["separable_fp32_10000x100000"] = {
+        "ms_total": total, "ms_sketch": sketch_ms, "ms_spa": spa_ms, "passes": npass,
+        "sketch_GBps_of_A": npass * ws.m * ws.n * 4 / (sketch_ms * 1e-3) / 1e9,
+        "K_equals_planted_set": sorted(K.cpu().tolist()) == planted,
+        "K": K.cpu().tolist()}
+    log(f"10000x100000 separable: sketch {sketch_ms:.2f} ms, SPA {spa_ms:.3f} ms, planted recovered "
+        f"{out['separable_fp32_10000x100000']['K_equals_planted_set']}")
+    del As
     torch.cuda.empty_cache()
     return out
 
@@ -293,6 +519,8 @@ def main():
     ap.add_argument("--precision-only", action="store_true",
                     help="only the precision sketches (for kernel profiles); prints that object")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads, the attainable peaks and the host information")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 1 GiB FP32 tensor three times (a plain copy kernel of known size, so that "
                          "hardware byte counters can be scaled)")
@@ -408,6 +636,10 @@ def main():
                       "method": "compressed ADMM (two-sided)", "lambda": lam, "rel_residual": res_gpu},
            "sketch_tflops": sketch_tflops, "sketch_ms": sketch_ms, "stages": stages, "roofline": roofline}
 
+    if not args.no_extras:
+        out["workloads"] = extra_workloads_section(h, lam, inp, w)
+        out["attainable_peaks"] = attainable_peaks()
+        out["host"] = host_info()
     if not args.no_precision:
         out["precision"] = precision_section(h, max(2, min(args.steps, 5)), 1)
     if not args.no_serving:

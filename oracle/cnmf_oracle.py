@@ -36,6 +36,7 @@ import scipy.linalg
 __all__ = [
     "orth_plus", "range_finder", "sketch", "admm", "mu", "spa",
     "rel_residual", "nnls_bruteforce", "admm_uncompressed", "mu_uncompressed",
+    "snmf_right_factor",
 ]
 
 
@@ -298,3 +299,21 @@ def nnls_bruteforce(C, b):
             if val < best:
                 best, best_h = val, h
     return best_h
+
+
+def snmf_right_factor(B, K):
+    """Section 4, Alg. SNMF, last step: the right factor H (r x n) of
+    separable NMF, A ~ A[:, K] H, computed on the compressed matrix
+    B = Q^T A column by column (Eq. snmf_right_factor_col):
+        H[:, j] = argmin_{h >= 0} ||B[:, j] - B[:, K] h||_2.
+    Each column is one nonnegative least-squares problem, solved here by
+    the Lawson-Hanson active-set method (scipy.optimize.nnls) as a library
+    step.  (The paper writes h in R^{r + r_ov}; with |K| = r it is R^r.)
+    """
+    import scipy.optimize
+    B = np.asarray(B, dtype=np.float64)
+    C = B[:, list(K)]
+    H = np.zeros((C.shape[1], B.shape[1]))
+    for j in range(B.shape[1]):
+        H[:, j], _ = scipy.optimize.nnls(C, B[:, j])
+    return H

@@ -374,3 +374,35 @@ def test_nnls_bruteforce_matches_lawson_hanson(seed):
     h = O.nnls_bruteforce(C, b)
     ref, _ = scipy.optimize.nnls(C, b)
     assert np.abs(h - ref).max() < 1e-10
+
+
+def test_snmf_right_factor_equals_bruteforce_and_kkt():
+    """Each column of H solves its NNLS problem: equal to the brute-force
+    minimiser over all supports (r = 6), and the KKT conditions hold
+    (h >= 0, gradient >= 0, complementarity)."""
+    g = rng(170)
+    k, n, r = 12, 40, 6
+    B = g.standard_normal((k, n))
+    K = [3, 17, 0, 25, 9, 31]
+    H = O.snmf_right_factor(B, K)
+    C = B[:, K]
+    for j in range(n):
+        assert np.abs(H[:, j] - O.nnls_bruteforce(C, B[:, j])).max() < 1e-10
+    assert (H >= 0).all()
+    grad = C.T @ (C @ H - B)                   # gradient of 1/2 ||C h - b||^2
+    assert (grad > -1e-10).all()
+    assert np.abs(grad * H).max() < 1e-10
+
+
+def test_snmf_right_factor_recovers_the_planted_factor():
+    """A = W [I_r H'] P exactly separable: with K the planted columns and a
+    basis Q of range(W), B = Q^T A gives H = [I_r H'] P exactly (W has full
+    column rank, so the NNLS optimum is the true nonnegative factor)."""
+    A, planted = WL.separable_matrix(300, 800, 7, 0.0, seed=171)
+    g = rng(172)
+    s = O.sketch(A, g.standard_normal((800, 12)), None, q=1)
+    K = O.spa(s["B"], 7)
+    assert sorted(K) == list(planted)
+    H = O.snmf_right_factor(s["B"], K)
+    assert np.linalg.norm(A - A[:, K] @ H) < 1e-10 * np.linalg.norm(A)
+    assert np.abs(H[np.arange(7), K] - 1.0).max() < 1e-10       # the selected columns map to themselves
