@@ -338,24 +338,14 @@ def extra_workloads_section(h, lam_c2, inp_c2, w_c2):
     del A
     # 10000 x 100000 separable, two-sided
     ws = WL.WORKLOADS["separable_fp32_10000x100000"]
-    g = torch.Generator(device=dev)
-    g.manual_seed(100 * ws.index)
-    Wm = torch.rand(ws.m, ws.r, device=dev, generator=g)
-    E = -torch.log1p(-torch.rand(ws.r, ws.n - ws.r, device=dev, dtype=torch.float64, generator=g))
-    Hp = E / E.sum(dim=0, keepdim=True)
-    Hp *= 1.0 - torch.rand(1, ws.n - ws.r, device=dev, dtype=torch.float64, generator=g)
-    H = torch.cat([torch.eye(ws.r, device=dev, dtype=torch.float64), Hp], dim=1).float()
-    perm = torch.randperm(ws.n, device=dev, generator=g)
-    As = (Wm @ H)[:, perm].contiguous()
-    As += ws.sep_noise * torch.randn(ws.m, ws.n, device=dev, generator=g)
-    planted = sorted(torch.nonzero(perm < ws.r).flatten().cpu().tolist())
-    del Wm, E, Hp, H
+    As, planted = WL.separable_on_device(ws.m, ws.n, ws.r, ws.sep_noise, 100 * ws.index, dev)
+    planted = planted.tolist()
     for _ in range(2):
         K, _, _ = api.select(As, ws.r, ws.k, ws.q, sides="both", seed=300, handle=h)
     torch.cuda.synchronize()
     h.set_timing(True)
     e0.record(h.stream)
-    K, score, _ = api.select(As, ws.r, ws.k, ws.q, sides="both", seed=300, want_scores=True, handle=h)
+    K, score, Bsk = api.select(As, ws.r, ws.k, ws.q, sides="both", seed=300, want_scores=True, want_B=True, handle=h)
     e1.record(h.stream)
     torch.cuda.synchronize()
     stg = {k: v for k, v in h.stages().items() if v[2]}
@@ -364,14 +354,24 @@ def extra_workloads_section(h, lam_c2, inp_c2, w_c2):
     spa_ms = stg.get("spa", (float("nan"),))[0]
     sketch_ms = total - spa_ms
     npass = 2 * ws.q + 2
+    # the right factor H (r x n) by per-column NNLS on B
+    api.snmf_nnls(Bsk, K, handle=h)
+    torch.cuda.synchronize()
+    e0.record(h.stream)
+    Hn, ninfo = api.snmf_nnls(Bsk, K, want_info=True, handle=h)
+    e1.record(h.stream)
+    torch.cuda.synchronize()
+    nnls_ms = e0.elapsed_time(e1)
+    ninfo = ninfo.cpu().tolist()
     out["separable_fp32_10000x100000"] = {
         "ms_total": total, "ms_sketch": sketch_ms, "ms_spa": spa_ms, "passes": npass,
+        "ms_right_factor_nnls": nnls_ms, "nnls_columns_not_converged": ninfo[0], "nnls_max_steps": ninfo[1],
         "sketch_GBps_of_A": npass * ws.m * ws.n * 4 / (sketch_ms * 1e-3) / 1e9,
         "K_equals_planted_set": sorted(K.cpu().tolist()) == planted,
         "K": K.cpu().tolist()}
     log(f"10000x100000 separable: sketch {sketch_ms:.2f} ms, SPA {spa_ms:.3f} ms, planted recovered "
         f"{out['separable_fp32_10000x100000']['K_equals_planted_set']}")
-    del As
+    del As, Bsk, Hn
     torch.cuda.empty_cache()
     return out
 

@@ -235,6 +235,24 @@ cnmf_status snmf_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_d
 cnmf_status cnmf_spa(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n,
                      int64_t ldb, int32_t r, int64_t* K_dev, double* score_dev);
 
+/* Right factor of compressed separable NMF (Section 4, Alg. SNMF, last
+ * step, Eq. snmf_right_factor_col): for every column j of B (k x n,
+ * row-major, ld ldb >= n, FP64 or FP32 device matrix; B = Q^T A from
+ * snmf_select) and the r selected columns K_dev (int64 device, 0-based),
+ *   H[:, j] = argmin_{h >= 0} ||B[:, j] - B[:, K] h||_2,
+ * written to H_dev (r x n FP64 device, row-major, ld ldh >= n).  Each
+ * column is solved exactly (to rounding) by the Lawson-Hanson active-set
+ * method on the normal equations G h = B[:, K]^T B[:, j], G = B[:, K]^T
+ * B[:, K], in FP64, one wave per column; a variable is freed while its dual
+ * exceeds 1e-13 max_i |(B[:, K]^T B[:, j])_i|.  info_dev (optional device
+ * int32[3]): columns that needed more than 3 r active-set steps (their last
+ * feasible iterate is returned), the most steps any column took, and the
+ * number of entries of K outside [0, n) (treated as zero columns).
+ * B[:, K] must have full column rank (SPA's selection does).  Limits:
+ * k <= 128, r <= 64 (CNMF_ENOTSUP); 1 <= r <= min(k, n) (CNMF_EINVAL). */
+cnmf_status snmf_nnls(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n, int64_t ldb,
+                      int32_t r, const int64_t* K_dev, double* H_dev, int64_t ldh, int32_t* info_dev);
+
 /* cnmf_spa for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same computation and results as cnmf_spa, with its working storage (B^T

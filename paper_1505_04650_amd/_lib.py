@@ -23,7 +23,7 @@ EXPORTED = [
     "cnmf_create", "cnmf_destroy", "cnmf_last_error", "cnmf_status_string", "cnmf_version",
     "cnmf_sketch", "cnmf_factorize", "snmf_select", "cnmf_spa", "cnmf_workspace_bytes",
     "cnmf_set_timing", "cnmf_stage_ms", "cnmf_range_product", "cnmf_stage_flops", "cnmf_stage_launches",
-    "cnmf_range_product_lowp", "cnmf_synchronize", "cnmf_gaussian", "cnmf_spa_noalloc",
+    "cnmf_range_product_lowp", "cnmf_synchronize", "cnmf_gaussian", "cnmf_spa_noalloc", "snmf_nnls",
     "cnmf_server_start", "cnmf_server_submit", "cnmf_server_poll", "cnmf_server_release",
     "cnmf_server_get_stats", "cnmf_server_stop", "cnmf_server_last_error", "cnmf_server_simulate",
 ]
@@ -118,6 +118,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.cnmf_spa.restype = st
     lib.cnmf_spa_noalloc.argtypes = [vp, vp, st, i64, i64, i64, i32, vp, vp]
     lib.cnmf_spa_noalloc.restype = st
+    lib.snmf_nnls.argtypes = [vp, vp, st, i64, i64, i64, i32, vp, vp, i64, vp]
+    lib.snmf_nnls.restype = st
     lib.cnmf_workspace_bytes.argtypes = [i64, i64, C.POINTER(cnmf_factorize_desc), C.POINTER(C.c_size_t)]
     lib.cnmf_workspace_bytes.restype = st
     lib.cnmf_range_product.argtypes = [vp, C.POINTER(cnmf_input), C.c_int, vp, i32, vp]

@@ -201,6 +201,23 @@ def select(A, r, k, q, omega_left=None, omega_right=None, sides="left", pass_dty
     return K, score, B
 
 
+def snmf_nnls(B, K, want_info=False, handle: Handle | None = None):
+    """Right factor of separable NMF on the compressed B (k x n device
+    matrix) for the selected columns K (int64 device): H (r x n, FP64) with
+    H[:, j] = argmin_{h >= 0} ||B[:, j] - B[:, K] h||."""
+    h = handle or default_handle()
+    if B.dtype not in _DT or B.dim() != 2 or B.stride(1) != 1:
+        raise ValueError("B must be a row-major float64/float32 2-D tensor")
+    if K.dtype != torch.int64 or K.dim() != 1 or not K.is_contiguous():
+        raise ValueError("K must be a contiguous int64 vector")
+    r = K.shape[0]
+    H = torch.empty((r, B.shape[1]), dtype=torch.float64, device=B.device)
+    info = torch.zeros(3, dtype=torch.int32, device=B.device)
+    L.check(h._lib.snmf_nnls(h.raw, _ptr(B), _DT[B.dtype], B.shape[0], B.shape[1], B.stride(0), int(r), _ptr(K),
+                             _ptr(H), H.stride(0), _ptr(info)), h.raw)
+    return (H, info) if want_info else H
+
+
 def synchronize(handle: Handle | None = None):
     """Wait for the handle's stream; raises CnmfError(CNMF_EBREAKDOWN) when an
     orthonormalisation breakdown was left unresolved since the last call."""

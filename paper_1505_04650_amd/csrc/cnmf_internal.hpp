@@ -227,6 +227,12 @@ hipError_t launch_residual_finish(const double* partial, int parts, double* out,
 // Partial count of the residual launch for an m x n A.
 int residual_blocks(int m, int n);
 hipError_t launch_flags_to_stats(const int* flags, int nflags, double* out, hipStream_t st);
+// SNMF right factor (k_nnls.hip): Bt = B^T (n x k FP64, ld ldbt), K (r
+// column indices), H (r x n, ld ldh) = per-column NNLS solutions; Cr: n x r
+// workspace; info: 3 zeroed words (columns not converged, most outer steps,
+// invalid indices).
+hipError_t launch_snmf_nnls(const double* Bt, int64_t ldbt, int n, int k, int r, const int64_t* K, double* Cr,
+                            double* H, int64_t ldh, int* info, hipStream_t st);
 // Fixed per-device scratch of cnmf_spa_noalloc (k_scratch.hip): bytes, the
 // address lookup (once per device, with that device current) and the
 // device address found (NULL before the lookup).

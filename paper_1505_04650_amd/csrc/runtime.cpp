@@ -1449,6 +1449,41 @@ cnmf_status cnmf_spa(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_
   return run_spa(h, B_dev, dtype, k, n, ldb, r, K_dev, score_dev, w);
 }
 
+cnmf_status snmf_nnls(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n, int64_t ldb,
+                      int32_t r, const int64_t* K_dev, double* H_dev, int64_t ldh, int32_t* info_dev) {
+  if (!B_dev || !K_dev || !H_dev) return fail(h, CNMF_EINVAL, "B_dev, K_dev and H_dev are required");
+  if (dtype != CNMF_F64 && dtype != CNMF_F32) return fail(h, CNMF_EINVAL, "B must be F64 or F32");
+  if (k < 1 || n < 1 || ldb < n) return fail(h, CNMF_EINVAL, "bad B shape k=%lld n=%lld ldb=%lld", (long long)k, (long long)n, (long long)ldb);
+  if (k > 128) return fail(h, CNMF_ENOTSUP, "k > 128 is not supported");
+  if (n > INT32_MAX / 2) return fail(h, CNMF_ENOTSUP, "n above 2^30 is not supported");
+  if (r < 1 || r > std::min<int64_t>(k, n)) return fail(h, CNMF_EINVAL, "r=%d must be in [1, min(k, n)]", r);
+  if (r > 64) return fail(h, CNMF_ENOTSUP, "r=%d > 64 is not supported", r);
+  if (ldh < n) return fail(h, CNMF_EINVAL, "ldh (%lld) < n (%lld)", (long long)ldh, (long long)n);
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  HIPCHK(h, hipSetDevice(h->device));
+  auto lay = [&](char* base, double** Bt, double** Cr, int** info) {
+    Arena a(base);
+    *Bt = a.take<double>((size_t)n * k);
+    *Cr = a.take<double>((size_t)n * r);
+    *info = a.take<int>(4);
+    return a.off;
+  };
+  double *Bt, *Cr;
+  int* info;
+  cnmf_status s = ensure_ws(h, lay(nullptr, &Bt, &Cr, &info));
+  if (s != CNMF_OK) return s;
+  lay(h->ws, &Bt, &Cr, &info);
+  int* inf = info_dev ? info_dev : info;
+  hipStream_t st = h->stream;
+  if (dtype == CNMF_F64)
+    HIPCHK(h, (launch_transpose<double, double>((const double*)B_dev, ldb, Bt, k, (int)k, (int)n, st)));
+  else
+    HIPCHK(h, (launch_transpose<float, double>((const float*)B_dev, ldb, Bt, k, (int)k, (int)n, st)));
+  HIPCHK(h, launch_fill(inf, 3 * sizeof(int), st));
+  HIPCHK(h, launch_snmf_nnls(Bt, k, (int)n, (int)k, r, K_dev, Cr, H_dev, ldh, inf, st));
+  return CNMF_OK;
+}
+
 cnmf_status cnmf_spa_noalloc(cnmf_handle* h, const void* B_dev, cnmf_dtype dtype, int64_t k, int64_t n,
                              int64_t ldb, int32_t r, int64_t* K_dev, double* score_dev) {
   cnmf_status s = check_spa(h, B_dev, dtype, k, n, ldb, r, K_dev);

@@ -26,7 +26,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "nmf_matrix", "separable_matrix", "gaussian",
+__all__ = ["Workload", "WORKLOADS", "nmf_matrix", "separable_matrix", "separable_on_device", "gaussian",
            "init_factors", "make_inputs"]
 
 
@@ -68,6 +68,27 @@ def separable_matrix(m: int, n: int, r: int, noise: float, seed: int, dtype=np.f
     inv[perm] = np.arange(n)
     planted = np.sort(inv[:r])
     return A.astype(dtype, copy=False), planted
+
+
+def separable_on_device(m: int, n: int, r: int, noise: float, seed: int, device):
+    """The near-separable recipe of separable_matrix, drawn on a torch device
+    with torch's seeded generator (for sizes whose host copy would be slow):
+    A = W [I_r H'] P + noise * Z in FP32, H' columns Dirichlet(1) (normalised
+    Exponential(1) draws) scaled by U(0, 1].  Returns (A, planted indices)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    W = torch.rand(m, r, device=device, generator=g)
+    E = -torch.log1p(-torch.rand(r, n - r, device=device, dtype=torch.float64, generator=g))
+    Hp = E / E.sum(dim=0, keepdim=True)
+    Hp *= 1.0 - torch.rand(1, n - r, device=device, dtype=torch.float64, generator=g)
+    H = torch.cat([torch.eye(r, device=device, dtype=torch.float64), Hp], dim=1).float()
+    perm = torch.randperm(n, device=device, generator=g)
+    A = (W @ H)[:, perm].contiguous()
+    if noise:
+        A += noise * torch.randn(m, n, device=device, generator=g)
+    planted = torch.nonzero(perm < r).flatten().cpu().numpy()
+    return A, np.sort(planted)
 
 
 def gaussian(rows: int, cols: int, seed: int) -> np.ndarray:

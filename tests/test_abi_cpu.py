@@ -134,6 +134,16 @@ def test_seeded_sketch_workspace_holds_the_test_matrices(lib):
     assert b.value - a.value >= 8 * (20000 + 5000) * 60
 
 
+def test_snmf_nnls_argument_checks(lib):
+    p = C.c_void_p(16)
+    assert lib.snmf_nnls(None, p, L.CNMF_F32, 30, 100, 100, 20, p, p, 100, None) == L.CNMF_EINVAL
+    assert b"handle" in lib.cnmf_last_error(None)
+    assert lib.snmf_nnls(None, p, L.CNMF_F32, 30, 100, 100, 31, p, p, 100, None) == L.CNMF_EINVAL   # r > k
+    assert lib.snmf_nnls(None, p, L.CNMF_F32, 30, 100, 100, 20, p, p, 99, None) == L.CNMF_EINVAL    # ldh < n
+    assert lib.snmf_nnls(None, p, L.CNMF_F32, 100, 100, 100, 65, p, p, 100, None) == L.CNMF_ENOTSUP
+    assert lib.snmf_nnls(None, None, L.CNMF_F32, 30, 100, 100, 20, p, p, 100, None) == L.CNMF_EINVAL
+
+
 def test_python_binding_fails_loudly_without_library(tmp_path):
     with pytest.raises(FileNotFoundError):
         L._lib_backup = L._lib

@@ -299,19 +299,7 @@ def test_factorize_fp32_methods_residual_gap(method):
 # --------------------------------------------------------------------------
 
 def separable_on_device(m, n, r, noise, seed):
-    g = torch.Generator(device=DEV)
-    g.manual_seed(seed)
-    W = torch.rand(m, r, device=DEV, generator=g)
-    # Dirichlet(1) columns from normalised Exponential(1) draws, scaled by U(0, 1]
-    E = -torch.log1p(-torch.rand(r, n - r, device=DEV, dtype=torch.float64, generator=g))
-    Hp = E / E.sum(dim=0, keepdim=True)
-    Hp *= 1.0 - torch.rand(1, n - r, device=DEV, dtype=torch.float64, generator=g)
-    H = torch.cat([torch.eye(r, device=DEV, dtype=torch.float64), Hp], dim=1).float()
-    perm = torch.randperm(n, device=DEV, generator=g)
-    A = (W @ H)[:, perm].contiguous()
-    A += noise * torch.randn(m, n, device=DEV, generator=g)
-    planted = torch.nonzero(perm < r).flatten().cpu().numpy()
-    return A, np.sort(planted)
+    return WL.separable_on_device(m, n, r, noise, seed, DEV)
 
 
 def test_select_separable_full_size_two_sided():
