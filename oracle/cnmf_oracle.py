@@ -23,6 +23,12 @@ design notes):
   * MU is the semi-NMF rule of Ding, Li & Jordan (2010), Eq. (8), applied to
     each compressed half-step of Alg. 2.  The paper cites it without printing
     it; the rule is restated here from that publication.
+  * Alternating NNLS (Eq. alternateLS_nmf_compressed) is the argmin form, the
+    one the paper runs with an active-set NNLS solver (its "respectively"
+    pairs the solvers with the two forms the other way round).  Each
+    subproblem has a unique minimiser when its k x r matrix has full column
+    rank, so any exact NNLS solver gives the same iterates; ``anls`` uses
+    Lawson-Hanson.
   * SPA (Araujo et al. 2001; Gillis & Vavasis 2014) uses squared Euclidean
     column norms, lowest index on ties, 0-based indices.
 """
@@ -36,7 +42,7 @@ import scipy.linalg
 __all__ = [
     "orth_plus", "range_finder", "sketch", "admm", "mu", "spa",
     "rel_residual", "nnls_bruteforce", "admm_uncompressed", "mu_uncompressed",
-    "snmf_right_factor",
+    "snmf_right_factor", "anls", "anls_uncompressed",
 ]
 
 
@@ -317,3 +323,54 @@ def snmf_right_factor(B, K):
     for j in range(B.shape[1]):
         H[:, j], _ = scipy.optimize.nnls(C, B[:, j])
     return H
+
+
+# ---------------------------------------------------------------------------
+# Section 3, Eq. alternateLS_nmf_compressed: alternating nonnegative least
+# squares on the compressed matrices (the paper runs it with an active-set
+# NNLS solver)
+# ---------------------------------------------------------------------------
+
+def anls(Ac, B, L, R, Y1, iters: int = 100, history: bool = False):
+    """Compressed alternating nonnegative least squares (Section 3,
+    Eq. alternateLS_nmf_compressed_X and _Y), each half-step minimised to
+    the end:
+      X <- argmin_{X >= 0} || Ac - X (Y R^T) ||_F      (Ac = A R^T, m x k)
+      Y <- argmin_{Y >= 0} || B  - (L^T X) Y ||_F      (B  = L^T A, k x n)
+    Both problems separate: row i of X is the NNLS problem with matrix
+    (Y R^T)^T (k x r) and right-hand side Ac[i]; column j of Y the NNLS
+    problem with matrix L^T X (k x r) and right-hand side B[:, j].  Each is
+    solved by the Lawson-Hanson active-set method (scipy.optimize.nnls) as a
+    library step.  Only Y1 enters: the first X-step depends on Y alone.
+    L None means I_m and R None means I_n (then Ac = B = A).
+    """
+    import scipy.optimize
+    Ac = np.asarray(Ac, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    Y = np.array(Y1, dtype=np.float64)
+    r = Y.shape[0]
+    X = np.zeros((Ac.shape[0], r))
+    hist = []
+    for _ in range(int(iters)):
+        Yc = Y if R is None else Y @ R.T                    # r x k
+        CX = Yc.T                                            # k x r
+        for i in range(Ac.shape[0]):
+            X[i], _ = scipy.optimize.nnls(CX, Ac[i])
+        if history:
+            hist.append(("X", X.copy(), Y.copy()))
+        CY = X if L is None else L.T @ X                     # k x r
+        Y = np.empty((r, B.shape[1]))
+        for j in range(B.shape[1]):
+            Y[:, j], _ = scipy.optimize.nnls(CY, B[:, j])
+        if history:
+            hist.append(("Y", X.copy(), Y.copy()))
+    out = dict(X=X, Y=Y)
+    if history:
+        out["history"] = hist
+    return out
+
+
+def anls_uncompressed(A, Y1, iters=100):
+    """Uncompressed alternating NNLS (Section 3, Eq. alternateLS_nmf):
+    ``anls`` with L = I, R = I, Ac = B = A."""
+    return anls(A, A, None, None, Y1, iters)

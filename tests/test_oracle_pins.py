@@ -406,3 +406,108 @@ def test_snmf_right_factor_recovers_the_planted_factor():
     H = O.snmf_right_factor(s["B"], K)
     assert np.linalg.norm(A - A[:, K] @ H) < 1e-10 * np.linalg.norm(A)
     assert np.abs(H[np.arange(7), K] - 1.0).max() < 1e-10       # the selected columns map to themselves
+
+
+# --------------------------------------------------------------------------
+# Section 3, Eq. alternateLS_nmf_compressed: alternating NNLS
+# --------------------------------------------------------------------------
+
+def _half_step_problem(tag, X, Y, L, R, Ac, B):
+    """Matrix and right-hand sides of the half-step that produced ``tag``:
+    rows of X against (Y R^T)^T, or columns of Y against L^T X."""
+    if tag == "X":
+        return (Y @ R.T).T, Ac.T          # k x r, k x m
+    return L.T @ X, B                     # k x r, k x n
+
+
+def test_anls_half_steps_satisfy_nnls_kkt():
+    """Every half-step is minimised to the end: for each row of X (column of
+    Y), h >= 0, the gradient C^T (C h - b) >= 0 and h o gradient = 0, the
+    optimality conditions of the convex subproblem."""
+    A, s, U1, V1, _ = _small_problem(seed=180)
+    L, R, Ac, B = s["L"], s["R"], s["Ac"], s["B"]
+    out = O.anls(Ac, B, L, R, V1, 8, history=True)
+    X, Y = U1, V1
+    for tag, Xn, Yn in out["history"]:
+        C, rhs = _half_step_problem(tag, X, Y, L, R, Ac, B)
+        H = Xn.T if tag == "X" else Yn
+        grad = C.T @ (C @ H - rhs)
+        scale = np.abs(C.T @ rhs).max()
+        assert (H >= 0).all()
+        assert grad.min() > -1e-10 * scale
+        assert np.abs(grad * H).max() < 1e-10 * scale * max(1.0, np.abs(H).max())
+        X, Y = Xn, Yn
+
+
+def test_anls_equals_bruteforce_on_tiny_problems():
+    """r = 3: every row of X and column of Y equals the minimiser found by
+    enumerating all supports."""
+    A, s, U1, V1, _ = _small_problem(seed=181, m=14, n=11, r=3, k=6)
+    L, R, Ac, B = s["L"], s["R"], s["Ac"], s["B"]
+    out = O.anls(Ac, B, L, R, V1, 3, history=True)
+    X, Y = U1, V1
+    for tag, Xn, Yn in out["history"]:
+        C, rhs = _half_step_problem(tag, X, Y, L, R, Ac, B)
+        H = Xn.T if tag == "X" else Yn
+        for j in range(rhs.shape[1]):
+            assert np.abs(H[:, j] - O.nnls_bruteforce(C, rhs[:, j])).max() < 1e-10
+        X, Y = Xn, Yn
+
+
+def test_anls_half_steps_do_at_least_as_well_as_mu():
+    """An exact minimiser cannot lose to any feasible point: from the same
+    Y, the ANLS X-step's objective is at most the MU X-step's, and both are
+    at most the objective before the step (Alg. 2's requirement)."""
+    A, s, U1, V1, _ = _small_problem(seed=182)
+    L, R, Ac, B = s["L"], s["R"], s["Ac"], s["B"]
+    Yc = V1 @ R.T
+    x_anls = O.anls(Ac, B, L, R, V1, 1, history=True)["history"][0][1]
+    x_mu = O.mu(Ac, B, L, R, U1, V1, 1, 1e-300, history=True)["history"][0][1]
+    before = np.linalg.norm(Ac - U1 @ Yc)
+    f_mu = np.linalg.norm(Ac - x_mu @ Yc)
+    f_anls = np.linalg.norm(Ac - x_anls @ Yc)
+    assert f_anls <= f_mu * (1 + 1e-12) and f_mu <= before * (1 + 1e-12)
+    assert f_anls < 0.999 * f_mu          # and it is strictly better here
+
+
+def test_anls_objectives_never_increase():
+    """Alg. 2's monotonicity, for the compressed objectives and, with
+    identity bases, for ||A - X Y||_F itself."""
+    A, s, U1, V1, _ = _small_problem(seed=183)
+    L, R, Ac, B = s["L"], s["R"], s["Ac"], s["B"]
+    out = O.anls(Ac, B, L, R, V1, 15, history=True)
+    X, Y = U1, V1
+    first = True
+    for tag, Xn, Yn in out["history"]:
+        if tag == "X":
+            before = np.linalg.norm(Ac - X @ (Y @ R.T))
+            after = np.linalg.norm(Ac - Xn @ (Y @ R.T))
+        else:
+            before = np.linalg.norm(B - (L.T @ X) @ Y)
+            after = np.linalg.norm(B - (L.T @ X) @ Yn)
+        if not first:                      # U1 is not the previous X-step's output
+            assert after <= before * (1 + 1e-12)
+        first = False
+        X, Y = Xn, Yn
+    full = O.anls(A, A, None, None, V1, 10, history=True)["history"]
+    objs = [np.linalg.norm(A - Xn @ Yn) for _, Xn, Yn in full]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(objs, objs[1:]))
+
+
+@pytest.mark.parametrize("compressed", [True, False])
+def test_anls_recovers_the_planted_factor_in_one_half_step(compressed):
+    """A = W H exactly, rank r, W and H of full rank and nonnegative: with
+    Y = H the X-step's unique minimiser is W (zero residual is reachable
+    and the matrix has full column rank); the compressed X-step too, since
+    R's rows span the row space of A when k >= r."""
+    g = rng(184)
+    m, n, r, k = 80, 60, 5, 9
+    W, H = g.random((m, r)), g.random((r, n))
+    A = W @ H
+    if compressed:
+        s = O.sketch(A, g.standard_normal((n, k)), g.standard_normal((m, k)), q=1)
+        out = O.anls(s["Ac"], s["B"], s["L"], s["R"], H, 1)
+    else:
+        out = O.anls_uncompressed(A, H, 1)
+    assert np.abs(out["X"] - W).max() < 1e-10
+    assert np.abs(out["Y"] - H).max() < 1e-9
