@@ -49,7 +49,8 @@ typedef enum {
   CNMF_ENOMEM = -2,      /* device workspace could not be allocated           */
   CNMF_EDEVICE = -3,     /* HIP runtime / launch error                        */
   CNMF_EBREAKDOWN = -4,  /* orthonormalisation breakdown the fallback did not
-                            resolve (reported by cnmf_synchronize)           */
+                            resolve, or an NNLS problem of CNMF_ANLS that did
+                            not finish (reported by cnmf_synchronize)        */
   CNMF_ENOTSUP = -5,     /* valid but unsupported size / precision combination */
   CNMF_EBUSY = -6
 } cnmf_status;
@@ -67,7 +68,10 @@ enum {
   CNMF_ADMM = 0,       /* compressed ADMM, Appendix B Alg. 3                    */
   CNMF_MU = 1,         /* compressed alternating MU, Section 3 Alg. 2           */
   CNMF_ADMM_FULL = 2,  /* Alg. 3 with L = I_m, R = I_n (uncompressed ADMM)      */
-  CNMF_MU_FULL = 3     /* Alg. 2 with L = I_m, R = I_n (uncompressed MU)        */
+  CNMF_MU_FULL = 3,    /* Alg. 2 with L = I_m, R = I_n (uncompressed MU)        */
+  CNMF_ANLS = 4,       /* compressed alternating NNLS, Section 3
+                          Eq. alternateLS_nmf_compressed (active set)         */
+  CNMF_ANLS_FULL = 5   /* the same with L = I_m, R = I_n (Eq. alternateLS_nmf) */
 };
 
 typedef struct cnmf_handle cnmf_handle;
@@ -88,7 +92,8 @@ const char* cnmf_version(void);
 /* Wait for the work enqueued on the handle's stream.  Returns CNMF_EDEVICE
  * for an asynchronous HIP fault, CNMF_EBREAKDOWN if a call enqueued since
  * the previous cnmf_synchronize hit an orthonormalisation breakdown that the
- * fallback could not resolve (see cnmf_sketch_desc; the count is then
+ * fallback could not resolve (see cnmf_sketch_desc) or an alternating-NNLS
+ * problem that did not finish (see cnmf_factorize_desc; the count is then
  * cleared), CNMF_OK otherwise. */
 cnmf_status cnmf_synchronize(cnmf_handle* h);
 
@@ -186,13 +191,20 @@ typedef struct {
 cnmf_status cnmf_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d,
                         cnmf_sketch_out* out);
 
-/* Factorisation parameters.  method: CNMF_ADMM / CNMF_MU use the two-sided
- * sketch `sk` (sides must be CNMF_BOTH); the *_FULL methods ignore `sk`
- * except for sk.r and run on A itself.  iters: fixed number of iterations
- * (no early stop).  lambda, phi > 0: ADMM penalties; xi > 0: ADMM step
- * (1 in the paper).  mu_eps >= 0: added to every MU denominator.
+/* Factorisation parameters.  method: CNMF_ADMM / CNMF_MU / CNMF_ANLS use
+ * the two-sided sketch `sk` (sides must be CNMF_BOTH); the *_FULL methods
+ * ignore `sk` except for sk.r and run on A itself.  iters: fixed number of
+ * iterations (no early stop).  lambda, phi > 0: ADMM penalties; xi > 0:
+ * ADMM step (1 in the paper).  mu_eps >= 0: added to every MU denominator.
  * U0_dev (m x r) and V0_dev (r x n): FP64 initial factors (Alg. 2 / Alg. 3
- * "Initialize"), row-major, required.  Limits: r <= 64 (CNMF_ENOTSUP
+ * "Initialize"), row-major, required.  CNMF_ANLS / CNMF_ANLS_FULL minimise
+ * every half-step to the end (each row of U against (V R^T)^T, each column
+ * of V against L^T U, as nonnegative least-squares problems solved on their
+ * normal equations in FP64 by an active-set method); the iterates depend on
+ * V0 only (U0 is the warm start of the first half-step's active sets).  A
+ * problem that needs more than 3 r active-set steps keeps its last feasible
+ * value and is counted: cnmf_synchronize then returns CNMF_EBREAKDOWN.
+ * Limits: r <= 64 (CNMF_ENOTSUP
  * otherwise); CNMF_ADMM solves its two r x r systems per iteration in one
  * workgroup whose LDS must hold three k x r FP64 blocks and the r x r
  * system, so it also needs k <= 112 when r > 48 (CNMF_ENOTSUP). */

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcnmf.so"
 CNMF_OK, CNMF_EINVAL, CNMF_ENOMEM, CNMF_EDEVICE, CNMF_EBREAKDOWN, CNMF_ENOTSUP, CNMF_EBUSY = 0, -1, -2, -3, -4, -5, -6
 CNMF_F64, CNMF_F32, CNMF_BF16, CNMF_FP8_E4M3 = 0, 1, 2, 3
 CNMF_LEFT, CNMF_RIGHT, CNMF_BOTH = 1, 2, 3
-CNMF_ADMM, CNMF_MU, CNMF_ADMM_FULL, CNMF_MU_FULL = 0, 1, 2, 3
+CNMF_ADMM, CNMF_MU, CNMF_ADMM_FULL, CNMF_MU_FULL, CNMF_ANLS, CNMF_ANLS_FULL = 0, 1, 2, 3, 4, 5
 
 STATUS_NAMES = {0: "CNMF_OK", -1: "CNMF_EINVAL", -2: "CNMF_ENOMEM", -3: "CNMF_EDEVICE",
                 -4: "CNMF_EBREAKDOWN", -5: "CNMF_ENOTSUP", -6: "CNMF_EBUSY"}

@@ -17,7 +17,8 @@ from . import _lib as L
 _DT = {torch.float64: L.CNMF_F64, torch.float32: L.CNMF_F32}
 _PREC = {"f64": L.CNMF_F64, "f32": L.CNMF_F32, "bf16": L.CNMF_BF16, "fp8": L.CNMF_FP8_E4M3}
 _SIDES = {"left": L.CNMF_LEFT, "right": L.CNMF_RIGHT, "both": L.CNMF_BOTH}
-_METHODS = {"admm": L.CNMF_ADMM, "mu": L.CNMF_MU, "admm_full": L.CNMF_ADMM_FULL, "mu_full": L.CNMF_MU_FULL}
+_METHODS = {"admm": L.CNMF_ADMM, "mu": L.CNMF_MU, "admm_full": L.CNMF_ADMM_FULL, "mu_full": L.CNMF_MU_FULL,
+            "anls": L.CNMF_ANLS, "anls_full": L.CNMF_ANLS_FULL}
 
 
 def _ptr(t):
@@ -153,9 +154,10 @@ class Factorization:
 def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="admm", iters=100,
               lam=1.0, phi=None, xi=1.0, mu_eps=1e-16, pass_dtype=None, final_dtype=None,
               want_sketch=False, seed=0, handle: Handle | None = None) -> Factorization:
-    """Compressed NMF: two-sided sketch, then ADMM (Alg. 3) or MU (Alg. 2) on
-    the compressed factors, then the FP64 relative residual.  The *_full
-    methods run the same iterations uncompressed (L = I, R = I)."""
+    """Compressed NMF: two-sided sketch, then ADMM (Alg. 3), MU (Alg. 2) or
+    alternating NNLS (Section 3, Eq. alternateLS_nmf_compressed) on the
+    compressed factors, then the FP64 relative residual.  The *_full methods
+    run the same iterations uncompressed (L = I, R = I)."""
     h = handle or default_handle()
     pass_dtype, final_dtype = _default_prec(A, pass_dtype, final_dtype)
     m, n = A.shape
@@ -168,7 +170,7 @@ def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="adm
     if want_sketch:
         sk = Sketch(torch.empty((m, k), dtype=od, device=dev), torch.empty((k, n), dtype=od, device=dev),
                     torch.empty((k, n), dtype=od, device=dev), torch.empty((k, k), dtype=od, device=dev),
-                    torch.empty((m, k), dtype=od, device=dev) if method == "mu" else None,
+                    torch.empty((m, k), dtype=od, device=dev) if method in ("mu", "anls") else None,
                     torch.zeros(4, dtype=torch.float64, device=dev))
         so = L.cnmf_sketch_out(_ptr(sk.L), _ptr(sk.R), _ptr(sk.B), _ptr(sk.At), _ptr(sk.Ac), _ptr(sk.stats))
     else:

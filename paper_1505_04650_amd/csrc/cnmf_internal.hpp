@@ -206,7 +206,7 @@ struct RowArgs {
 template <typename T>
 hipError_t launch_nmf_row(const RowArgs& a, int blocks, hipStream_t st);
 // mode 0: G = C^T C (C = S, k x r) -> G+, G-; mode 1: G = S (r x r) -> G+, G-;
-// mode 2: Gp = (S + pen I)^-1 (S the r x r Gram).
+// mode 2: Gp = (S + pen I)^-1 (S the r x r Gram); mode 3: Gp = S^T S (C = S, k x r).
 hipError_t launch_nmf_small(const double* S, int k, int r, int mode, double pen, double* Gp, double* Gm, int* flags,
                             hipStream_t st);
 
@@ -231,6 +231,28 @@ hipError_t launch_flags_to_stats(const int* flags, int nflags, double* out, hipS
 // column indices), H (r x n, ld ldh) = per-column NNLS solutions; Cr: n x r
 // workspace; info: 3 zeroed words (columns not converged, most outer steps,
 // invalid indices).
+// One half-step of alternating NNLS (k_nnls.hip): for every row i of F
+// (rows x r, ld ldf, the current values are the warm start),
+//   F[i] = argmin_{h >= 0} 1/2 h^T G h - c^T h,
+//   c = C^T B1[i] (C k1 x r, FP64) or c = B1[i] (C == nullptr; ld ldb1),
+// G (r x r, FP64) shared; the new rows are also copied to Op (ld ldop) when
+// it is set.  info[0] += rows that needed more than 3 r steps, info[1] =
+// max(info[1], steps).
+struct AnlsArgs {
+  int rows, r, k1;
+  const void* B1;
+  int64_t ldb1;
+  const double* C;
+  const double* G;
+  void* F;
+  int64_t ldf;
+  void* Op;
+  int64_t ldop;
+  int* info;
+};
+template <typename T>
+hipError_t launch_anls_rows(const AnlsArgs& a, hipStream_t st);
+hipError_t launch_add_count(const int* src, int* dst, hipStream_t st);
 hipError_t launch_snmf_nnls(const double* Bt, int64_t ldbt, int n, int k, int r, const int64_t* K, double* Cr,
                             double* H, int64_t ldh, int* info, hipStream_t st);
 // Fixed per-device scratch of cnmf_spa_noalloc (k_scratch.hip): bytes, the

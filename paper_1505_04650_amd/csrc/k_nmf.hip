@@ -212,6 +212,7 @@ template hipError_t launch_nmf_row<double>(const RowArgs&, int, hipStream_t);
 //   MU, C form:    C = S (k x r), G = C^T C, G+ = max(G, 0), G- = max(-G, 0)
 //   MU, Gram form: G = S (r x r), G+, G-
 //   ADMM:          Minv = (S + pen I)^-1 (S is the Gram, r x r)
+//   ANLS, C form:  G = C^T C (C = S, k x r), unsplit
 // ---------------------------------------------------------------------------
 constexpr int kSmallNT = 256;
 
@@ -220,6 +221,20 @@ __global__ __launch_bounds__(kSmallNT) void nmf_small_kernel(const double* __res
                                                              double* __restrict__ Gm, int* flags) {
   const int tid = threadIdx.x;
   extern __shared__ double sm[];
+  if (mode == 3) {
+    for (int e = tid; e < r * r; e += kSmallNT) {
+      const int a = e / r, b = e - a * r;
+      double s0 = 0.0, s1 = 0.0;
+      int l = 0;
+      for (; l + 1 < k; l += 2) {
+        s0 = fma(S[l * r + a], S[l * r + b], s0);
+        s1 = fma(S[(l + 1) * r + a], S[(l + 1) * r + b], s1);
+      }
+      if (l < k) s0 = fma(S[l * r + a], S[l * r + b], s0);
+      Gp[e] = s0 + s1;
+    }
+    return;
+  }
   if (mode == 0 || mode == 1) {
     for (int e = tid; e < r * r; e += kSmallNT) {
       const int a = e / r, b = e - a * r;

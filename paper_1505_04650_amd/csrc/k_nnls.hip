@@ -1,11 +1,14 @@
-// Right factor of compressed separable NMF (Section 4, Alg. SNMF, last
-// step; Eq. snmf_right_factor_col): for every column j of the compressed
-// matrix B (k x n) and the selected columns K (r of them),
-//   H[:, j] = argmin_{h >= 0} || B[:, j] - B[:, K] h ||_2,
-// n independent nonnegative least-squares problems with the same matrix
-// C = B[:, K].  They are solved on the normal equations, G h = c_j with
-// G = C^T C (shared) and c_j = C^T B[:, j], by the Lawson-Hanson
-// active-set method, one wave per column, FP64.
+// Batched nonnegative least squares on one wave per problem, FP64, for
+//  * the right factor of compressed separable NMF (Section 4, Alg. SNMF,
+//    last step; Eq. snmf_right_factor_col): for every column j of the
+//    compressed matrix B (k x n) and the selected columns K (r of them),
+//      H[:, j] = argmin_{h >= 0} || B[:, j] - B[:, K] h ||_2;
+//  * the half-steps of compressed alternating NNLS (Section 3,
+//    Eq. alternateLS_nmf_compressed): every row of X against (Y R^T)^T and
+//    every column of Y against L^T X (and their uncompressed forms).
+// Every problem of a launch shares its matrix C (k x r), so the problems are
+// solved on the normal equations, G h = c with G = C^T C shared (in LDS) and
+// c = C^T b per problem, by the Lawson-Hanson active-set method.
 #include "cnmf_internal.hpp"
 #include "small_dense.hpp"
 
@@ -76,15 +79,90 @@ __device__ __forceinline__ double wave_min_d(double v) {
   return v;
 }
 
-// One wave per column (grid-stride over the columns).  Lawson-Hanson:
-// start from h = 0 with every variable at its bound; repeatedly free the
-// bound variable whose dual w_i = (c - G h)_i is largest (lowest index on
-// ties) while it exceeds tol = 1e-13 max|c|; solve the free system; if a
-// free variable comes out <= 0, move from h towards the solution until the
-// first one reaches 0, bind every variable at 0 and solve again (a variable
-// bound again within its own step is not freed again).  At most
-// 3 r outer steps; a column that needs more is counted in info[0] (its last
-// feasible h is kept).  info[1]: largest number of outer steps.
+// Lawson-Hanson on one wave (lane i: variable i, lanes >= r idle):
+// minimise 1/2 h^T G h - c^T h over h >= 0.  h0 is a feasible start (>= 0;
+// its support is the first passive set, 0 for a cold start): the free
+// system is solved on it and, where a free variable comes out <= 0, the
+// iterate moves from h towards the solution until the first one reaches 0,
+// which is bound again (repeatedly).  Then the bound variable whose dual
+// w_i = (c - G h)_i is largest (lowest index on ties) is freed while it
+// exceeds tol = 1e-13 max|c|, and the free system is solved again (a
+// variable bound again within its own step is not freed again).  The
+// minimiser is unique for positive definite G, so the start changes the
+// number of steps, not the result.  At most 3 r freeing steps; *ok = false
+// when a problem needs more (its last feasible h is returned).
+template <int RM>
+__device__ double lh_wave(const double* Gs, int r, double c, double h0, int* outer_out, bool* ok) {
+  const int lane = threadIdx.x & 63;
+  const bool real = lane < r;
+  const double tol = 1e-13 * wave_max_d(fabs(c));
+  double h = (real && h0 > 0.0) ? h0 : 0.0;
+  uint64_t pm = __ballot(h > 0.0);
+  uint64_t excl = 0;   // variables that came straight back to their bound (anti-cycling)
+  int outer = 0, p = -1;
+  bool solve = pm != 0;
+  *ok = true;
+  while (true) {
+    if (solve) {
+      for (int inner = 0; inner <= r; ++inner) {
+        const double z = nnls_masked_solve<RM>(Gs, r, pm, c);
+        const bool pi = (pm >> lane) & 1ull;
+        const bool bad = pi && !(z > 0.0);
+        if (__ballot(bad) == 0) {
+          h = z;
+          break;
+        }
+        // step from h towards z until the first free variable reaches 0
+        const double ratio = bad ? (h - z > 0.0 ? h / (h - z) : 0.0) : 2.0;
+        const double alpha = wave_min_d(ratio);
+        const double hn = h + alpha * (z - h);
+        const bool drop = pi && (bad ? ratio <= alpha : false);
+        const bool keep = pi && !drop && hn > 0.0;
+        pm = __ballot(keep);
+        h = keep ? hn : 0.0;
+      }
+      // a variable freed and bound again at once (its dual was positive only
+      // by rounding) is not freed again for this problem
+      if (p >= 0 && !((pm >> p) & 1ull)) excl |= 1ull << p;
+    }
+    // dual w = c - G h over the free variables
+    double gh = 0.0;
+    uint64_t rest = pm;
+    while (rest) {
+      const int l = __builtin_ctzll(rest);
+      rest &= rest - 1;
+      gh = fma(Gs[min(lane, RM - 1) * RM + l], readlane_d(h, l), gh);
+    }
+    const double wdual = c - gh;
+    // the bound variable with the largest dual above tol (lowest index on ties)
+    const double cand = (real && !(((pm | excl) >> lane) & 1ull) && wdual > tol) ? wdual : -1.0;
+    const double best = wave_max_d(cand);
+    if (!(best > 0.0)) break;
+    const uint64_t at = __ballot(cand == best);
+    p = __builtin_ctzll(at);
+    if (++outer > 3 * r) {
+      *ok = false;
+      break;
+    }
+    pm |= 1ull << p;
+    solve = true;
+  }
+  *outer_out = outer;
+  return h;
+}
+
+// G (r x r, row-major, FP64) into LDS, padded to RM x RM with zeros.
+template <int RM>
+__device__ __forceinline__ void stage_gram(double* Gs, const double* __restrict__ G, int r) {
+  for (int e = threadIdx.x; e < RM * RM; e += blockDim.x) {
+    const int i = e / RM, l = e - i * RM;
+    Gs[e] = (i < r && l < r) ? G[i * r + l] : 0.0;
+  }
+}
+
+// Right factor: one wave per column (grid-stride over the columns), cold
+// start.  info[0]: columns that needed more than 3 r steps; info[1]:
+// largest number of freeing steps.
 template <int RM>
 __global__ __launch_bounds__(256) void nnls_kernel(const double* __restrict__ Bt, int64_t ldbt, int n, int k, int r,
                                                    const int64_t* __restrict__ K, const double* __restrict__ Cr,
@@ -110,56 +188,9 @@ __global__ __launch_bounds__(256) void nnls_kernel(const double* __restrict__ Bt
   int worst = 0, failed = 0;
   for (int j = blockIdx.x * 4 + w; j < n; j += gridDim.x * 4) {
     const double c = real ? Cr[(int64_t)j * r + lane] : 0.0;
-    const double tol = 1e-13 * wave_max_d(fabs(c));
-    double h = 0.0;
-    uint64_t pm = 0;
-    int outer = 0;
-    bool ok = true;
-    double wdual = c;
-    uint64_t excl = 0;   // variables that came straight back to their bound (anti-cycling)
-    while (true) {
-      // the bound variable with the largest dual above tol (lowest index on ties)
-      const double cand =
-          (real && !(((pm | excl) >> lane) & 1ull) && wdual > tol) ? wdual : -1.0;
-      const double best = wave_max_d(cand);
-      if (!(best > 0.0)) break;
-      const uint64_t at = __ballot(cand == best);
-      const int p = __builtin_ctzll(at);
-      if (++outer > 3 * r) {
-        ok = false;
-        break;
-      }
-      pm |= 1ull << p;
-      for (int inner = 0; inner <= r; ++inner) {
-        const double z = nnls_masked_solve<RM>(Gs, r, pm, c);
-        const bool pi = (pm >> lane) & 1ull;
-        const bool bad = pi && !(z > 0.0);
-        if (__ballot(bad) == 0) {
-          h = z;
-          break;
-        }
-        // step from h towards z until the first free variable reaches 0
-        const double ratio = bad ? (h - z > 0.0 ? h / (h - z) : 0.0) : 2.0;
-        const double alpha = wave_min_d(ratio);
-        const double hn = h + alpha * (z - h);
-        const bool drop = pi && (bad ? ratio <= alpha : false);
-        const bool keep = pi && !drop && hn > 0.0;
-        pm = __ballot(keep);
-        h = keep ? hn : 0.0;
-      }
-      // a variable freed and bound again at once (its dual was positive only
-      // by rounding) is not freed again for this column
-      if (!((pm >> p) & 1ull)) excl |= 1ull << p;
-      // dual w = c - G h over the free variables
-      double gh = 0.0;
-      uint64_t rest = pm;
-      while (rest) {
-        const int l = __builtin_ctzll(rest);
-        rest &= rest - 1;
-        gh = fma(Gs[min(lane, RM - 1) * RM + l], readlane_d(h, l), gh);
-      }
-      wdual = c - gh;
-    }
+    int outer;
+    bool ok;
+    const double h = lh_wave<RM>(Gs, r, c, 0.0, &outer, &ok);
     worst = max(worst, outer);
     failed += ok ? 0 : 1;
     if (real) H[(int64_t)lane * ldh + j] = h;
@@ -168,6 +199,87 @@ __global__ __launch_bounds__(256) void nnls_kernel(const double* __restrict__ Bt
     if (failed) atomicAdd(info, failed);
     atomicMax(info + 1, worst);
   }
+}
+
+// One half-step of alternating NNLS: one wave per row of F (grid-stride),
+// the right-hand side c = C^T b of row i formed in the wave, warm start
+// from the row's current values.
+template <typename T, int RM>
+__global__ __launch_bounds__(256) void anls_rows_kernel(AnlsArgs a) {
+  __shared__ double Gs[RM * RM];
+  stage_gram<RM>(Gs, a.G, a.r);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = a.r;
+  const bool real = lane < r;
+  const int col = min(lane, r - 1);
+  const T* __restrict__ B1 = (const T*)a.B1;
+  T* __restrict__ F = (T*)a.F;
+  T* __restrict__ Op = (T*)a.Op;
+  int worst = 0, failed = 0;
+  for (int i = blockIdx.x * 4 + w; i < a.rows; i += gridDim.x * 4) {
+    const T* b = B1 + (int64_t)i * a.ldb1;
+    double c = 0.0;
+    if (a.C) {
+      // c_l = sum_t b_t C[t][l] (C^T b with C stored k1 x r)
+      double s0 = 0.0, s1 = 0.0;
+      int t = 0;
+      for (; t + 1 < a.k1; t += 2) {
+        s0 = fma((double)b[t], a.C[t * r + col], s0);
+        s1 = fma((double)b[t + 1], a.C[(t + 1) * r + col], s1);
+      }
+      if (t < a.k1) s0 = fma((double)b[t], a.C[t * r + col], s0);
+      c = s0 + s1;
+    } else {
+      c = (double)b[col];
+    }
+    c = real ? c : 0.0;
+    const double h0 = real ? (double)F[(int64_t)i * a.ldf + col] : 0.0;
+    int outer;
+    bool ok;
+    const double h = lh_wave<RM>(Gs, r, c, h0, &outer, &ok);
+    worst = max(worst, outer);
+    failed += ok ? 0 : 1;
+    if (real) {
+      F[(int64_t)i * a.ldf + lane] = (T)h;
+      if (Op) Op[(int64_t)i * a.ldop + lane] = (T)h;
+    }
+  }
+  if (lane == 0 && a.info) {
+    if (failed) atomicAdd(a.info, failed);
+    atomicMax(a.info + 1, worst);
+  }
+}
+
+template <typename T>
+hipError_t launch_anls_rows(const AnlsArgs& a, hipStream_t st) {
+  if (a.r < 1 || a.r > 64 || a.rows < 0 || (a.C && a.k1 < 1)) return hipErrorInvalidValue;
+  if (a.rows == 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(((int64_t)a.rows + 3) / 4, 4096);
+  if (a.r <= 8)
+    hipLaunchKernelGGL((anls_rows_kernel<T, 8>), dim3(grid), dim3(256), 0, st, a);
+  else if (a.r <= 16)
+    hipLaunchKernelGGL((anls_rows_kernel<T, 16>), dim3(grid), dim3(256), 0, st, a);
+  else if (a.r <= 24)
+    hipLaunchKernelGGL((anls_rows_kernel<T, 24>), dim3(grid), dim3(256), 0, st, a);
+  else if (a.r <= 32)
+    hipLaunchKernelGGL((anls_rows_kernel<T, 32>), dim3(grid), dim3(256), 0, st, a);
+  else if (a.r <= 48)
+    hipLaunchKernelGGL((anls_rows_kernel<T, 48>), dim3(grid), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((anls_rows_kernel<T, 64>), dim3(grid), dim3(256), 0, st, a);
+  CNMF_LAUNCH_CHECK();
+}
+template hipError_t launch_anls_rows<float>(const AnlsArgs&, hipStream_t);
+template hipError_t launch_anls_rows<double>(const AnlsArgs&, hipStream_t);
+
+// *dst += *src (one thread): folds a launch's failure count into a running total.
+__global__ void add_count_kernel(const int* __restrict__ src, int* __restrict__ dst) {
+  if (threadIdx.x == 0 && *src) atomicAdd(dst, *src);
+}
+hipError_t launch_add_count(const int* src, int* dst, hipStream_t st) {
+  hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(64), 0, st, src, dst);
+  CNMF_LAUNCH_CHECK();
 }
 
 hipError_t launch_snmf_nnls(const double* Bt, int64_t ldbt, int n, int k, int r, const int64_t* K, double* Cr,

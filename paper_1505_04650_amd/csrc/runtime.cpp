@@ -242,7 +242,9 @@ struct SketchWs {
   double* G = nullptr;
   double* Tinv = nullptr;
   // flags: [0], [1] breakdowns repaired per half (left, right chain),
-  // [2] floored pivots of the ADMM solves, [3] unresolved breakdowns
+  // [2] floored pivots of the ADMM solves, [3] unresolved breakdowns,
+  // [4], [5] third CholeskyQR pass needed per half, [6], [7] alternating
+  // NNLS: unfinished problems, largest number of active-set steps
   int* flags = nullptr;
   unsigned* counters = nullptr;
   double* orth_err = nullptr;
@@ -819,6 +821,11 @@ cnmf_status pass_full(cnmf_handle* h, const cnmf_input* A, bool dirN, const T* o
 // A factorisation in four phases (the serving loop drives them separately):
 // layout of the workspace, prologue (sketch, initial state and, for ADMM,
 // the first partials), the iterations, and the epilogue (outputs, residual).
+// The uncompressed comparators run on A itself (L = I, R = I); MU and
+// alternating NNLS need Ac = A R^T besides B.
+static bool full_method(int m) { return m == CNMF_ADMM_FULL || m == CNMF_MU_FULL || m == CNMF_ANLS_FULL; }
+static bool method_wants_ac(int m) { return m == CNMF_MU || m == CNMF_ANLS; }
+
 template <typename T>
 struct FactState {
   std::vector<Pass> passes;
@@ -831,8 +838,8 @@ struct FactState {
 template <typename T>
 cnmf_status fact_plan(cnmf_handle* h, const cnmf_factorize_desc* d, FactState<T>& f) {
   const cnmf_sketch_desc* sk = &d->sk;
-  f.full = d->method == CNMF_ADMM_FULL || d->method == CNMF_MU_FULL;
-  f.want_ac = d->method == CNMF_MU;
+  f.full = full_method(d->method);
+  f.want_ac = method_wants_ac(d->method);
   if (!f.full) {
     f.passes = plan_passes(sk->k, sk->q, CNMF_BOTH, f.want_ac, sk->pass_dtype, sk->final_dtype);
     if (f.passes.empty()) return fail(h, CNMF_EINVAL, "internal: empty pass plan");
@@ -1003,6 +1010,67 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
       RUN(row(n, iw.by, w.BTb, k, iw.S, k, aw.Vt, nullptr, iw.Gp, iw.Gm, nullptr, 0.0, 0, w.RTb, k, nullptr,
               iw.PpY));
     }
+  } else if (d->method == CNMF_ANLS || d->method == CNMF_ANLS_FULL) {
+    // alternating NNLS: per half-step the shared Gram G and the k x r (or
+    // r x r) product C are formed from the other factor, every row is solved
+    // to the end by the active-set kernel, and the row kernel's partial-sum
+    // mode forms the next half-step's C from the new rows
+    const bool cf = d->method == CNMF_ANLS;
+    const int kk = iw.kk;
+    int* info = w.flags + 6;
+    HIPCHK(h, launch_fill(info, 2 * sizeof(int), st));
+    auto half = [&](int rows, int blocks, const void* B1, int64_t ldb1, T* F, T* Op, const void* B2,
+                    double* Pp) -> cnmf_status {
+      AnlsArgs an{};
+      an.rows = rows;
+      an.r = r;
+      an.k1 = cf ? k : r;
+      an.B1 = B1;
+      an.ldb1 = ldb1;
+      an.C = cf ? iw.S : nullptr;
+      an.G = cf ? iw.Gp : iw.S;
+      an.F = F;
+      an.ldf = r;
+      an.Op = Op;
+      an.ldop = kk;
+      an.info = info;
+      if (cf) HIPCHK(h, launch_nmf_small(iw.S, k, r, 3, 0.0, iw.Gp, nullptr, nullptr, st));
+      HIPCHK(h, launch_anls_rows<T>(an, st));
+      // partial sums of the next C: B2^T F (k x r) or the Gram F^T F
+      RUN(row(rows, blocks, nullptr, 0, nullptr, cf ? k : r, F, nullptr, nullptr, nullptr, nullptr, 0.0, 2, B2,
+              cf ? k : r, nullptr, Pp));
+      return CNMF_OK;
+    };
+    if (cf) {
+      Span sp(h, ST_ITER, (double)d->iters * 4.0 * (double)(m + n) * k * r);
+      // initial Yc^T = R V0^T
+      RUN(row(n, iw.by, nullptr, 0, nullptr, k, aw.Vt, nullptr, nullptr, nullptr, nullptr, 0.0, 2, w.RTb, k,
+              nullptr, iw.PpY));
+      for (int it = 0; it < d->iters; ++it) {
+        HIPCHK(h, launch_sum_parts(iw.PpY, iw.by, (int64_t)k * r, iw.S, st));
+        RUN(half(m, iw.bx, w.Acb, k, aw.U, nullptr, w.Lb, iw.PpX));
+        HIPCHK(h, launch_sum_parts(iw.PpX, iw.bx, (int64_t)k * r, iw.S, st));
+        RUN(half(n, iw.by, w.BTb, k, aw.Vt, nullptr, w.RTb, iw.PpY));
+      }
+    } else {
+      Span sp(h, ST_ITER, (double)d->iters * 4.0 * (double)m * n * r);
+      HIPCHK(h, launch_fill(iw.Xop, sizeof(T) * (size_t)n * kk, st));
+      HIPCHK(h, launch_fill(iw.Zop, sizeof(T) * (size_t)m * kk, st));
+      HIPCHK(h, (launch_copy2d<T, T>(aw.Vt, r, iw.Xop, kk, n, r, 1.0, st)));
+      // initial Gram of V0^T
+      RUN(row(n, iw.by, nullptr, 0, nullptr, r, aw.Vt, nullptr, nullptr, nullptr, nullptr, 0.0, 2, nullptr, r,
+              nullptr, iw.PpY));
+      for (int it = 0; it < d->iters; ++it) {
+        HIPCHK(h, launch_sum_parts(iw.PpY, iw.by, (int64_t)r * r, iw.S, st));
+        RUN(pass_full<T>(h, A, true, iw.Xop, kk, iw.Pn, iw.Ppart));
+        RUN(half(m, iw.bx, iw.Pn, kk, aw.U, iw.Zop, nullptr, iw.PpX));
+        HIPCHK(h, launch_sum_parts(iw.PpX, iw.bx, (int64_t)r * r, iw.S, st));
+        RUN(pass_full<T>(h, A, false, iw.Zop, kk, iw.Pt, iw.Ppart));
+        RUN(half(n, iw.by, iw.Pt, kk, aw.Vt, iw.Xop, nullptr, iw.PpY));
+      }
+    }
+    // problems that did not finish reach cnmf_synchronize
+    HIPCHK(h, launch_add_count(info, h->unresolved_dev, st));
   } else {
     // uncompressed comparators: L = I, R = I, two streaming passes per iteration
     const bool admm = d->method == CNMF_ADMM_FULL;
@@ -1318,7 +1386,7 @@ cnmf_status cnmf_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_d
 
 static cnmf_status check_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d) {
   if (!d) return fail(h, CNMF_EINVAL, "factorize descriptor is NULL");
-  if (d->method == CNMF_ADMM_FULL || d->method == CNMF_MU_FULL) {
+  if (full_method(d->method)) {
     cnmf_sketch_desc sk = d->sk;  // only r and the precision matter
     sk.k = sk.r + 1 <= std::min(A->m, A->n) ? sk.r + 1 : sk.r;
     sk.sides = CNMF_LEFT;
@@ -1330,8 +1398,8 @@ static cnmf_status check_factorize(cnmf_handle* h, const cnmf_input* A, const cn
     if (s != CNMF_OK) return s;
   }
   cnmf_status s = CNMF_OK;
-  if (d->method < CNMF_ADMM || d->method > CNMF_MU_FULL) return fail(h, CNMF_EINVAL, "unknown method %d", d->method);
-  if ((d->method == CNMF_ADMM || d->method == CNMF_MU) && d->sk.sides != CNMF_BOTH)
+  if (d->method < CNMF_ADMM || d->method > CNMF_ANLS_FULL) return fail(h, CNMF_EINVAL, "unknown method %d", d->method);
+  if (!full_method(d->method) && d->sk.sides != CNMF_BOTH)
     return fail(h, CNMF_EINVAL, "compressed NMF needs sides = CNMF_BOTH");
   if (d->iters < 0) return fail(h, CNMF_EINVAL, "iters must be >= 0");
   if (d->method == CNMF_ADMM || d->method == CNMF_ADMM_FULL) {
@@ -1605,8 +1673,8 @@ cnmf_status cnmf_workspace_bytes(int64_t m, int64_t n, const cnmf_factorize_desc
   if (r < 1 || k <= r || k > std::min<int64_t>(m, n) || k > 128)
     return fail(nullptr, CNMF_EINVAL, "need 1 <= r < k <= min(m, n), k <= 128");
   const bool f64 = d->sk.pass_dtype == CNMF_F64;
-  const bool want_ac = d->method == CNMF_MU;
-  const bool full = d->method == CNMF_ADMM_FULL || d->method == CNMF_MU_FULL;
+  const bool want_ac = method_wants_ac(d->method);
+  const bool full = full_method(d->method);
   std::vector<Pass> passes = plan_passes(k, d->sk.q, d->sk.sides ? d->sk.sides : CNMF_BOTH, want_ac,
                                          d->sk.pass_dtype, d->sk.final_dtype);
   Arena dry(nullptr);

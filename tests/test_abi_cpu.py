@@ -194,3 +194,26 @@ def test_lowp_range_product_argument_checks(lib):
     assert lib.cnmf_range_product_lowp(None, C.byref(A64), 0, L.CNMF_BF16, X, 8, X) == L.CNMF_EINVAL
     assert lib.cnmf_range_product_lowp(None, C.byref(A), 0, L.CNMF_FP8_E4M3, X, 8, X) == L.CNMF_EINVAL
     assert b"handle" in lib.cnmf_last_error(None)
+
+
+def test_anls_method_checks(lib):
+    """Alternating NNLS: a known method; compressed form needs both sides;
+    unknown method numbers are refused."""
+    A = L.cnmf_input(C.c_void_p(16), L.CNMF_F32, 2000, 1000, 1000)
+    out = L.cnmf_factorize_out()
+    d = _desc(method=L.CNMF_ANLS)
+    st = lib.cnmf_factorize(None, C.byref(A), C.byref(d), C.byref(out))
+    assert st == L.CNMF_EINVAL and b"handle" in lib.cnmf_last_error(None)
+    d.sk.sides = L.CNMF_LEFT
+    assert lib.cnmf_factorize(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
+    assert b"sides" in lib.cnmf_last_error(None)
+    d = _desc(method=6)
+    assert lib.cnmf_factorize(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
+    assert b"unknown method" in lib.cnmf_last_error(None)
+    # the compressed form keeps Ac = A R^T in its workspace, the full form two pass operands
+    a, b, c = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    assert lib.cnmf_workspace_bytes(20000, 5000, C.byref(_desc(r=50, k=60, method=L.CNMF_ADMM)), C.byref(a)) == 0
+    assert lib.cnmf_workspace_bytes(20000, 5000, C.byref(_desc(r=50, k=60, method=L.CNMF_ANLS)), C.byref(b)) == 0
+    assert lib.cnmf_workspace_bytes(20000, 5000, C.byref(_desc(r=50, k=60, method=L.CNMF_ANLS_FULL)),
+                                    C.byref(c)) == 0
+    assert b.value > a.value and c.value > 0
