@@ -284,9 +284,9 @@ def extra_workloads_section(h, lam_c2, inp_c2, w_c2):
     """The other workloads, measured beside the headline:
     * 1000 x 500 FP64 (q 4, 100 ADMM iterations): device time per stage and
       the factors' gap to the oracle (the parity workload);
-    * 20000 x 5000 FP32: compressed MU, and uncompressed ADMM / MU (L = I,
-      R = I), 200 iterations each, time and FP64 residual beside compressed
-      ADMM;
+    * 20000 x 5000 FP32: compressed MU and alternating NNLS, and
+      uncompressed ADMM / MU / alternating NNLS (L = I, R = I), 200
+      iterations each, time and FP64 residual beside compressed ADMM;
     * 10000 x 100000 separable FP32 (two-sided, q 2): sketch time and GB/s of
       A read, SPA time, and whether SPA returns exactly the planted columns."""
     import torch
@@ -323,7 +323,7 @@ def extra_workloads_section(h, lam_c2, inp_c2, w_c2):
     # 20000 x 5000: compressed MU and the uncompressed comparators
     A = torch.as_tensor(inp_c2["A"], device=dev)
     c2 = {}
-    for method in ("mu", "admm_full", "mu_full"):
+    for method in ("mu", "anls", "admm_full", "mu_full", "anls_full"):
         fa = (A, w_c2.r, w_c2.k, w_c2.q, t(inp_c2["U1"]), t(inp_c2["V1"]), t(inp_c2["Omega_L"]),
               t(inp_c2["Omega_R"]))
         api.factorize(*fa, method=method, iters=w_c2.iters, lam=lam_c2, phi=lam_c2, mu_eps=1e-16, handle=h)
