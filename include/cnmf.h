@@ -339,8 +339,10 @@ int cnmf_stage_launches(cnmf_handle* h, int stage);
  * still cover it, at most 64 times) -> prologue on a worker stream (Alg. 1
  * sketch, small sketches, initial state) -> for FP32 compressed ADMM
  * (CNMF_ADMM, F32 input, iters > 0): member of the batch, where one step
- * advances every member by one iteration of Appendix B Alg. 3 with three
- * launches covering all members (at most max_batch) -> epilogue (U, V, FP64
+ * advances every member by one iteration of Appendix B Alg. 3 (a copy of
+ * the step's descriptor table and three descriptor-driven launches covering
+ * all members, at most max_batch; optionally a replayed graph, see
+ * CNMF_SERVER_GRAPHS) -> epilogue (U, V, FP64
  * residual, sketch outputs) on a worker stream -> done.  Other requests
  * (MU, uncompressed, FP64) run whole on a worker stream.  Each member runs
  * the same per-request code as cnmf_factorize, so its results equal those of
@@ -364,9 +366,20 @@ typedef struct {
   int32_t device;
   int32_t max_batch;          /* members of a batched step, 1..4096          */
   int32_t workers;            /* worker streams, 1..3                        */
-  int32_t reserved;
+  int32_t flags;              /* CNMF_SERVER_* bits, 0 = defaults            */
   uint64_t hbm_budget_bytes;  /* device arena for request workspaces         */
 } cnmf_server_config;
+/* CNMF_SERVER_GRAPHS: issue every batched step as the replay of a captured
+ * graph (the descriptor copy and three fixed-grid kernels whose workgroups
+ * take the step's blocks from counters in the descriptor; one graph per
+ * descriptor slot and shape class) instead of direct launches whose grids
+ * are sized to the batch.  Both run the same per-block code, so the results
+ * are the same bit for bit; which is faster depends on the mix (direct
+ * launches are the default).
+ * CNMF_SERVER_ONE_STEP: at most one batched step in flight instead of two
+ * (the next step is built when the previous one has ended, so it gathers
+ * the requests whose prologues finished meanwhile). */
+enum { CNMF_SERVER_GRAPHS = 1, CNMF_SERVER_ONE_STEP = 2 };
 
 typedef struct {
   int32_t state;              /* 0 queued, 1 prologue, 2 ready, 3 in batch,
@@ -384,6 +397,9 @@ typedef struct {
   int64_t batch_steps;        /* batched launches of the iteration step      */
   int64_t batched_iterations; /* request-iterations they advanced            */
   int64_t max_batch_seen;     /* largest batch                               */
+  int64_t graph_replays;      /* steps issued as a replay of a captured graph */
+  int64_t graphs_built;       /* graphs captured (per descriptor slot and
+                                 shape class: k, r rounded up to 16)         */
   int64_t queued, in_flight;
   uint64_t arena_bytes, arena_free_bytes, peak_arena_bytes;
 } cnmf_server_stats;

@@ -14,6 +14,7 @@ CNMF_OK, CNMF_EINVAL, CNMF_ENOMEM, CNMF_EDEVICE, CNMF_EBREAKDOWN, CNMF_ENOTSUP, 
 CNMF_F64, CNMF_F32, CNMF_BF16, CNMF_FP8_E4M3 = 0, 1, 2, 3
 CNMF_LEFT, CNMF_RIGHT, CNMF_BOTH = 1, 2, 3
 CNMF_ADMM, CNMF_MU, CNMF_ADMM_FULL, CNMF_MU_FULL, CNMF_ANLS, CNMF_ANLS_FULL = 0, 1, 2, 3, 4, 5
+CNMF_SERVER_GRAPHS, CNMF_SERVER_ONE_STEP = 1, 2
 
 STATUS_NAMES = {0: "CNMF_OK", -1: "CNMF_EINVAL", -2: "CNMF_ENOMEM", -3: "CNMF_EDEVICE",
                 -4: "CNMF_EBREAKDOWN", -5: "CNMF_ENOTSUP", -6: "CNMF_EBUSY"}
@@ -57,7 +58,7 @@ class cnmf_factorize_out(C.Structure):
 
 
 class cnmf_server_config(C.Structure):
-    _fields_ = [("device", C.c_int32), ("max_batch", C.c_int32), ("workers", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("device", C.c_int32), ("max_batch", C.c_int32), ("workers", C.c_int32), ("flags", C.c_int32),
                 ("hbm_budget_bytes", C.c_uint64)]
 
 
@@ -69,6 +70,7 @@ class cnmf_ticket_info(C.Structure):
 class cnmf_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("batch_steps", C.c_int64), ("batched_iterations", C.c_int64), ("max_batch_seen", C.c_int64),
+                ("graph_replays", C.c_int64), ("graphs_built", C.c_int64),
                 ("queued", C.c_int64), ("in_flight", C.c_int64), ("arena_bytes", C.c_uint64),
                 ("arena_free_bytes", C.c_uint64), ("peak_arena_bytes", C.c_uint64)]
 

@@ -316,9 +316,11 @@ class Server:
 
     STATES = ("queued", "prologue", "ready", "batch", "epilogue", "done")
 
-    def __init__(self, hbm_budget_bytes: int, max_batch: int = 128, workers: int = 3, device: int = 0):
+    def __init__(self, hbm_budget_bytes: int, max_batch: int = 128, workers: int = 3, device: int = 0,
+                 graphs: bool = False, one_step: bool = False):
         self._lib = L.load()
-        cfg = L.cnmf_server_config(int(device), int(max_batch), int(workers), 0, int(hbm_budget_bytes))
+        flags = (L.CNMF_SERVER_GRAPHS if graphs else 0) | (L.CNMF_SERVER_ONE_STEP if one_step else 0)
+        cfg = L.cnmf_server_config(int(device), int(max_batch), int(workers), flags, int(hbm_budget_bytes))
         raw = C.c_void_p()
         L.check_server(self._lib.cnmf_server_start(C.byref(cfg), C.byref(raw)))
         self.raw = raw

@@ -182,6 +182,26 @@ hipError_t launch_admm_step_batch(const AdmmJob* jobs_dev, const int* uv_first_d
                                   int njobs, int uv_blocks, int red_blocks, int max_k, int max_r, size_t solve_lds,
                                   hipStream_t st);
 
+// The batched step with fixed grids (for capture in a graph and replay): one
+// device buffer holds a BatchHeader at offset 0, the job table at off_jobs
+// and the first-block tables at off_uv / off_red; the kernels read the
+// counts from the header.  uv_lds = admm_batch_uv_lds(max k, max r) and
+// solve_lds >= every job's admm_job_solve_lds (both <= 160 KiB); grid_solve
+// >= 1 workgroups loop over the jobs, grid_red / grid_uv workgroups take the
+// step's reduce / row-update blocks one at a time from the header's counters
+// (which the copy of the header sets to 0).  admm_step_fixed_init() raises the kernels'
+// dynamic-LDS limit (once, outside any capture).
+struct BatchHeader {
+  int njobs, uv_total, red_total;
+  int red_next, uv_next;   // work counters of the two block loops (0 when copied in)
+  int reserved[3];
+};
+size_t admm_batch_uv_lds(int max_k, int max_r);
+hipError_t admm_step_fixed_init();
+hipError_t launch_admm_step_fixed(char* desc_dev, size_t off_jobs, size_t off_uv, size_t off_red,
+                                  int grid_solve, int grid_red, int grid_uv, size_t uv_lds, size_t solve_lds,
+                                  hipStream_t st);
+
 // Generic row update for MU and the uncompressed comparators (k_nmf.hip).
 struct RowArgs {
   int rows, k1, r, k2;

@@ -767,6 +767,107 @@ hipError_t launch_admm_step_batch(const AdmmJob* jobs_dev, const int* uv_first_d
   CNMF_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------------------
+// The same batched step with fixed grids, for replay as a captured graph:
+// the counts come from the descriptor's header in device memory (written by
+// the copy that precedes the launches), so the launch configuration does not
+// depend on the batch.  The workgroups of the reduce and row-update launches
+// take the step's block indices one at a time from a counter in the header
+// and run, for index b, exactly the code of block b of
+// launch_admm_step_batch, so the results do not depend on which workgroup
+// takes which index.
+// ---------------------------------------------------------------------------
+// Next block index of a work loop for the whole workgroup.
+__device__ __forceinline__ int take_index(int* counter, int* slot) {
+  __syncthreads();   // every wave is done with the previous index (and its LDS)
+  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+  __syncthreads();
+  return *slot;
+}
+
+__global__ __launch_bounds__(kRedNT) void admm_reduce_fixed_kernel(char* __restrict__ desc, size_t off_jobs,
+                                                                   size_t off_red) {
+  __shared__ double red[kRedNT];
+  __shared__ int bslot;
+  BatchHeader* hp = reinterpret_cast<BatchHeader*>(desc);
+  const int njobs = hp->njobs, total = hp->red_total;
+  const AdmmJob* jobs = reinterpret_cast<const AdmmJob*>(desc + off_jobs);
+  const int* red_first = reinterpret_cast<const int*>(desc + off_red);
+  for (;;) {
+    const int b = take_index(&hp->red_next, &bslot);
+    if (b >= total) break;
+    const int j = batch_job(red_first, njobs, b);
+    const AdmmJob& J = jobs[j];
+    const int64_t kr = (int64_t)J.k * J.r;
+    const int nbh = (int)((kr + kRedEPB - 1) / kRedEPB);
+    admm_reduce_body<float>(J.Pp, J.parts0, J.parts1, kr, J.Pred, nbh, b - red_first[j], red);
+  }
+}
+
+__global__ __launch_bounds__(kSolveNT) void admm_solve_fixed_kernel(const char* __restrict__ desc, size_t off_jobs) {
+  extern __shared__ double sm[];
+  const int njobs = reinterpret_cast<const BatchHeader*>(desc)->njobs;
+  const AdmmJob* jobs = reinterpret_cast<const AdmmJob*>(desc + off_jobs);
+  for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
+    __syncthreads();
+    const AdmmJob& J = jobs[j];
+    admm_solve_chol_body(J.Pred, J.At, J.k, J.r, J.lam, J.phi, J.first, J.XY, J.flags, sm);
+  }
+}
+
+template <typename T, int CH>
+__global__ __launch_bounds__(256) void admm_uv_fixed_kernel(char* __restrict__ desc, size_t off_jobs,
+                                                            size_t off_uv) {
+  extern __shared__ char smraw[];
+  __shared__ int bslot;
+  BatchHeader* hp = reinterpret_cast<BatchHeader*>(desc);
+  const int njobs = hp->njobs, total = hp->uv_total;
+  const AdmmJob* jobs = reinterpret_cast<const AdmmJob*>(desc + off_jobs);
+  const int* uv_first = reinterpret_cast<const int*>(desc + off_uv);
+  for (;;) {
+    const int b = take_index(&hp->uv_next, &bslot);
+    if (b >= total) break;
+    const int j = batch_job(uv_first, njobs, b);
+    const AdmmJob& J = jobs[j];
+    admm_uv_body<T, CH>(J.s0, J.s1, J.parts0, b - uv_first[j], J.XY, J.k, J.r, J.xi, J.last ? 2 : 1, J.Pp, J.rpb0,
+                        J.rpb1, smraw);
+  }
+}
+
+constexpr size_t kUvFixedLdsMax = 128 * 1024;
+
+size_t admm_batch_uv_lds(int max_k, int max_r) {
+  const int KP = (max_k + 15) / 16 * 16, RP = (max_r + 15) / 16 * 16;
+  return ((size_t)KP * (RP + 1) + 64 * (size_t)(KP + 1) + 64 * (size_t)(RP + 1)) * sizeof(float);
+}
+
+hipError_t admm_step_fixed_init() {
+  hipError_t e = hipFuncSetAttribute((const void*)admm_solve_fixed_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  // the row update needs at most admm_batch_uv_lds(128, 64) = 83 KB (its
+  // static LDS is not part of this limit)
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)admm_uv_fixed_kernel<float, 64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kUvFixedLdsMax);
+  return e;
+}
+
+hipError_t launch_admm_step_fixed(char* desc_dev, size_t off_jobs, size_t off_uv, size_t off_red,
+                                  int grid_solve, int grid_red, int grid_uv, size_t uv_lds, size_t solve_lds,
+                                  hipStream_t st) {
+  if (solve_lds > 160 * 1024 || uv_lds > kUvFixedLdsMax || grid_solve < 1 || grid_red < 1 || grid_uv < 1)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(admm_reduce_fixed_kernel, dim3(grid_red), dim3(kRedNT), 0, st, desc_dev, off_jobs, off_red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(admm_solve_fixed_kernel, dim3(grid_solve), dim3(kSolveNT), solve_lds, st, desc_dev, off_jobs);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((admm_uv_fixed_kernel<float, 64>), dim3(grid_uv), dim3(256), uv_lds, st, desc_dev, off_jobs,
+                     off_uv);
+  CNMF_LAUNCH_CHECK();
+}
+
 size_t admm_job_solve_lds(const AdmmJob& J) {
   return chol_layout(J.k, J.r).total * sizeof(double);
 }

@@ -11,9 +11,13 @@
 //     the passes of new requests overlap the iterations of the others;
 //   * batched iterations: every request whose prologue has finished joins
 //     the batch; one batch step advances all of them by one ADMM iteration
-//     (Appendix B, Alg. 3) with three launches whose grids cover all jobs
-//     (descriptor-driven kernels), and a request leaves the batch after its
-//     last iteration;
+//     (Appendix B, Alg. 3): the step's descriptor table is copied to the
+//     device and three descriptor-driven kernels cover every job's blocks.
+//     Either the grids are sized to the step (direct launches), or
+//     (CNMF_SERVER_GRAPHS) fixed-grid kernels take the blocks from counters
+//     in the table, and the copy and the three launches are captured once
+//     per descriptor slot and shape class as a graph and replayed for every
+//     step.  A request leaves the batch after its last iteration;
 //   * epilogue: outputs and the FP64 residual on a worker stream.
 // Each job in a batched launch runs the same per-request code as
 // cnmf_factorize, so a result does not depend on the other requests.
@@ -160,6 +164,10 @@ struct cnmf_server {
   char* desc_dev[kRing] = {};
   hipEvent_t step_ev[kRing] = {};
   long steps_issued = 0, steps_done = 0;
+  // captured batch steps: (slot, k and r rounded up to 16) -> executable graph
+  std::unordered_map<int, hipGraphExec_t> graphs;
+  bool use_graphs = false;
+  int max_steps_in_flight = 2;   // at most kRing - 1
   // shared with submitting threads (guarded by mu)
   std::mutex mu;
   std::condition_variable cv;
@@ -177,8 +185,11 @@ struct cnmf_server {
 
 namespace {
 
+// [BatchHeader][jobs x max_batch][uv_first x (max_batch + 1)][red_first x (max_batch + 1)]
+constexpr size_t kOffJobs = 256;
+
 size_t desc_layout(int max_batch, size_t* off_uv, size_t* off_red) {
-  size_t o = (size_t)max_batch * sizeof(AdmmJob);
+  size_t o = kOffJobs + (size_t)max_batch * sizeof(AdmmJob);
   o = (o + 255) / 256 * 256;
   *off_uv = o;
   o += (size_t)(max_batch + 1) * sizeof(int);
@@ -265,11 +276,12 @@ bool batch_step(cnmf_server* S) {
     set_state(S, r, kActive);
     S->active.push_back(r);
   }
-  if (S->active.empty() || S->steps_issued - S->steps_done >= 2) return false;
+  if (S->active.empty() || S->steps_issued - S->steps_done >= S->max_steps_in_flight) return false;
   const int slot = (int)(S->steps_issued % kRing);
   size_t off_uv, off_red;
   desc_layout(S->max_batch, &off_uv, &off_red);
-  AdmmJob* jobs = reinterpret_cast<AdmmJob*>(S->desc_host[slot]);
+  BatchHeader* hd = reinterpret_cast<BatchHeader*>(S->desc_host[slot]);
+  AdmmJob* jobs = reinterpret_cast<AdmmJob*>(S->desc_host[slot] + kOffJobs);
   int* uvf = reinterpret_cast<int*>(S->desc_host[slot] + off_uv);
   int* rdf = reinterpret_cast<int*>(S->desc_host[slot] + off_red);
   int uv_total = 0, red_total = 0, max_k = 1, max_r = 1;
@@ -290,13 +302,70 @@ bool batch_step(cnmf_server* S) {
   }
   uvf[nj] = uv_total;
   rdf[nj] = red_total;
-  hipError_t e = hipMemcpyAsync(S->desc_dev[slot], S->desc_host[slot], S->desc_bytes, hipMemcpyHostToDevice,
-                                S->batch_stream);
-  if (e == hipSuccess)
-    e = launch_admm_step_batch(reinterpret_cast<const AdmmJob*>(S->desc_dev[slot]),
-                               reinterpret_cast<const int*>(S->desc_dev[slot] + off_uv),
-                               reinterpret_cast<const int*>(S->desc_dev[slot] + off_red), nj, uv_total, red_total,
-                               max_k, max_r, lds, S->batch_stream);
+  *hd = BatchHeader{};
+  hd->njobs = nj;
+  hd->uv_total = uv_total;
+  hd->red_total = red_total;
+  // shape class: the launch configuration depends on k and r rounded up to 16
+  const int KP = (max_k + 15) / 16 * 16, RP = (max_r + 15) / 16 * 16;
+  const size_t uv_lds = admm_batch_uv_lds(KP, RP);
+  const size_t solve_lds = std::min<size_t>(admm_solve_lds_bytes(KP, RP), 160 * 1024);
+  const int grid_solve = S->max_batch;
+  const int grid_red = 1024;
+  const int grid_uv = 256 * (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / uv_lds));
+  hipError_t e = hipSuccess;
+  auto enqueue = [&]() -> hipError_t {
+    hipError_t x = hipMemcpyAsync(S->desc_dev[slot], S->desc_host[slot], S->desc_bytes, hipMemcpyHostToDevice,
+                                  S->batch_stream);
+    if (x == hipSuccess)
+      x = launch_admm_step_fixed(S->desc_dev[slot], kOffJobs, off_uv, off_red, grid_solve, grid_red, grid_uv,
+                                 uv_lds, solve_lds, S->batch_stream);
+    return x;
+  };
+  bool replayed = false;
+  if (lds > solve_lds || !S->use_graphs) {
+    // direct launches sized to this batch (also when a job needs more LDS
+    // than its class provides)
+    e = hipMemcpyAsync(S->desc_dev[slot], S->desc_host[slot], S->desc_bytes, hipMemcpyHostToDevice,
+                       S->batch_stream);
+    if (e == hipSuccess)
+      e = launch_admm_step_batch(reinterpret_cast<const AdmmJob*>(S->desc_dev[slot] + kOffJobs),
+                                 reinterpret_cast<const int*>(S->desc_dev[slot] + off_uv),
+                                 reinterpret_cast<const int*>(S->desc_dev[slot] + off_red), nj, uv_total, red_total,
+                                 max_k, max_r, lds, S->batch_stream);
+  } else {
+    const int key = (slot * 16 + KP / 16) * 16 + RP / 16;
+    auto it = S->graphs.find(key);
+    if (it == S->graphs.end()) {
+      // capture the copy and the three launches once for this slot and class
+      hipGraph_t g = nullptr;
+      hipGraphExec_t x = nullptr;
+      e = hipStreamBeginCapture(S->batch_stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t e1 = enqueue();
+        e = hipStreamEndCapture(S->batch_stream, &g);
+        if (e1 != hipSuccess) e = e1;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      if (g) hipGraphDestroy(g);
+      if (e == hipSuccess) {
+        it = S->graphs.emplace(key, x).first;
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stats.graphs_built += 1;
+      } else {
+        // no graphs on this device or runtime: direct launches from now on
+        (void)hipGetLastError();
+        S->use_graphs = false;
+        e = hipSuccess;
+      }
+    }
+    if (S->use_graphs) {
+      e = hipGraphLaunch(it->second, S->batch_stream);
+      replayed = e == hipSuccess;
+    } else {
+      e = enqueue();
+    }
+  }
   if (e == hipSuccess) e = hipEventRecord(S->step_ev[slot], S->batch_stream);
   if (e != hipSuccess) {
     // nothing more can run for these requests: drain and fail them
@@ -309,6 +378,7 @@ bool batch_step(cnmf_server* S) {
   {
     std::lock_guard<std::mutex> lk(S->mu);
     S->stats.batch_steps += 1;
+    S->stats.graph_replays += replayed ? 1 : 0;
     S->stats.batched_iterations += nj;
     S->stats.max_batch_seen = std::max<int64_t>(S->stats.max_batch_seen, nj);
   }
@@ -411,6 +481,7 @@ void destroy_server(cnmf_server* S) {
     hipStreamSynchronize(S->batch_stream);
     hipStreamDestroy(S->batch_stream);
   }
+  for (auto& kv : S->graphs) hipGraphExecDestroy(kv.second);
   for (int i = 0; i < kRing; ++i) {
     if (S->step_ev[i]) hipEventDestroy(S->step_ev[i]);
     if (S->desc_host[i]) hipHostFree(S->desc_host[i]);
@@ -438,6 +509,8 @@ cnmf_status cnmf_server_start(const cnmf_server_config* cfg, cnmf_server** out) 
   *out = nullptr;
   if (cfg->hbm_budget_bytes < (1u << 20)) return sfail(CNMF_EINVAL, "hbm_budget_bytes must be at least 1 MiB");
   if (cfg->max_batch < 1 || cfg->max_batch > 4096) return sfail(CNMF_EINVAL, "max_batch must be in [1, 4096]");
+  if (cfg->flags & ~(CNMF_SERVER_GRAPHS | CNMF_SERVER_ONE_STEP))
+    return sfail(CNMF_EINVAL, "unknown server flags 0x%x", cfg->flags);
   if (cfg->workers < 1 || cfg->workers > 3)
     return sfail(CNMF_EINVAL, "workers must be in [1, 3] (one more stream runs the batched steps)");
   int ndev = 0;
@@ -451,6 +524,8 @@ cnmf_status cnmf_server_start(const cnmf_server_config* cfg, cnmf_server** out) 
   S->budget = cfg->hbm_budget_bytes / BlockArena::kGranule * BlockArena::kGranule;
   S->max_batch = cfg->max_batch;
   S->nworkers = cfg->workers;
+  S->use_graphs = (cfg->flags & CNMF_SERVER_GRAPHS) != 0;
+  S->max_steps_in_flight = (cfg->flags & CNMF_SERVER_ONE_STEP) ? 1 : 2;
   S->max_inflight = cfg->max_batch + 2 * cfg->workers;
   S->arena = BlockArena(S->budget);
   auto bail = [&](cnmf_status st, const char* what, hipError_t e) {
@@ -478,6 +553,8 @@ cnmf_status cnmf_server_start(const cnmf_server_config* cfg, cnmf_server** out) 
     e = hipEventCreateWithFlags(&S->step_ev[i], hipEventDisableTiming);
     if (e != hipSuccess) return bail(CNMF_EDEVICE, "hipEventCreate", e);
   }
+  e = admm_step_fixed_init();
+  if (e != hipSuccess) return bail(CNMF_EDEVICE, "kernel attributes", e);
   S->th = std::thread(dispatcher, S);
   hipSetDevice(old);
   *out = S;

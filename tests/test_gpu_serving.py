@@ -65,13 +65,14 @@ def submit(srv, req, **kw):
                       req["omega_right"], iters=req["iters"], lam=req["lam"], phi=req["lam"], **kw)
 
 
-def test_each_result_same_alone_and_in_the_mix(requests):
+@pytest.mark.parametrize("graphs,one_step", [(False, False), (True, False), (True, True)])
+def test_each_result_same_alone_and_in_the_mix(requests, graphs, one_step):
     ref = [alone(q) for q in requests]
     # a small batch and a tight budget: requests queue, join and leave the
     # batch at different steps
     budget = 3 * max(api.workspace_bytes(q["A"].shape[0], q["A"].shape[1], q["r"], q["k"], q["q"])
                      for q in requests)
-    with api.Server(budget, max_batch=4, workers=3) as srv:
+    with api.Server(budget, max_batch=4, workers=3, graphs=graphs, one_step=one_step) as srv:
         tickets = [submit(srv, q) for q in requests]
         infos = [srv.wait(t) for t in tickets]
         st = srv.stats()
@@ -83,6 +84,13 @@ def test_each_result_same_alone_and_in_the_mix(requests):
             solo.append(t)
     assert st["completed"] == len(requests) and st["failed"] == 0
     assert st["max_batch_seen"] > 1
+    # with graphs, every batched step was a replay of a captured graph (one
+    # per descriptor slot and shape class); without, none
+    assert st["batch_steps"] > 0
+    if graphs:
+        assert st["graph_replays"] == st["batch_steps"] and 1 <= st["graphs_built"] <= st["batch_steps"]
+    else:
+        assert st["graph_replays"] == 0 and st["graphs_built"] == 0
     assert st["peak_arena_bytes"] <= budget
     assert any(i["queue_ms"] > 0 for i in infos)
     for i, (t, s, (U, V, res)) in enumerate(zip(tickets, solo, ref)):
