@@ -112,13 +112,36 @@ cnmf_status cnmf_gaussian(cnmf_handle* h, uint64_t seed, int32_t matrix_id, int6
                           double* out_dev, int64_t ld);
 
 /* ---------------------------------------------------------------------------
- * Input matrix A (Section 1, problem (nmf)): m x n, row-major, lda >= n.
- * dtype CNMF_F64 or CNMF_F32.  Device pointer.
+ * Input matrix A (Section 1, problem (nmf)): m x n, dtype CNMF_F64 or
+ * CNMF_F32, in one of three formats:
+ *   CNMF_DENSE (0): row-major on the device, lda >= n, at data_dev.
+ *   CNMF_DENSE_HOST (1): row-major in host memory, lda >= n, at data_dev
+ *     (a host pointer; pinned memory, hipHostMalloc, lets the copies
+ *     overlap the passes).  For matrices larger than device memory (Section
+ *     2.1, algorithmic solutions for big data): every pass streams A through
+ *     the device in blocks of block_rows rows (0 = about 64 MiB per block),
+ *     two blocks in flight; only the k-column sketches live on the device.
+ *     The host buffer must stay unchanged until the call's work has run.
+ *     Passes in F32 / F64 only (no reduced-precision copies of A).
+ *   CNMF_CSR (2): sparse on the device, compressed rows: rowptr_dev (m + 1
+ *     int64 offsets, rowptr[0] = 0, nondecreasing, rowptr[m] = nnz),
+ *     colind_dev (nnz int32 column indices in [0, n), ascending within each
+ *     row) and the nnz values at data_dev; lda is ignored.  The passes
+ *     multiply with A and A^T directly (the transpose is formed once per
+ *     call in the workspace); passes in F32 / F64 only.
+ * A is never written.
  * ------------------------------------------------------------------------- */
+enum { CNMF_DENSE = 0, CNMF_DENSE_HOST = 1, CNMF_CSR = 2 };
 typedef struct {
   const void* data_dev;
   cnmf_dtype dtype;
   int64_t m, n, lda;
+  int32_t format;
+  int32_t reserved;
+  const int64_t* rowptr_dev;
+  const int32_t* colind_dev;
+  int64_t nnz;
+  int64_t block_rows;
 } cnmf_input;
 
 /* Sketch parameters (Alg. 1 inputs: target rank r, oversampling r_ov with

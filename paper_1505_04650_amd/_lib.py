@@ -15,6 +15,7 @@ CNMF_F64, CNMF_F32, CNMF_BF16, CNMF_FP8_E4M3 = 0, 1, 2, 3
 CNMF_LEFT, CNMF_RIGHT, CNMF_BOTH = 1, 2, 3
 CNMF_ADMM, CNMF_MU, CNMF_ADMM_FULL, CNMF_MU_FULL, CNMF_ANLS, CNMF_ANLS_FULL = 0, 1, 2, 3, 4, 5
 CNMF_SERVER_GRAPHS, CNMF_SERVER_ONE_STEP = 1, 2
+CNMF_DENSE, CNMF_DENSE_HOST, CNMF_CSR = 0, 1, 2
 
 STATUS_NAMES = {0: "CNMF_OK", -1: "CNMF_EINVAL", -2: "CNMF_ENOMEM", -3: "CNMF_EDEVICE",
                 -4: "CNMF_EBREAKDOWN", -5: "CNMF_ENOTSUP", -6: "CNMF_EBUSY"}
@@ -32,7 +33,8 @@ EXPORTED = [
 
 class cnmf_input(C.Structure):
     _fields_ = [("data_dev", C.c_void_p), ("dtype", C.c_int), ("m", C.c_int64), ("n", C.c_int64),
-                ("lda", C.c_int64)]
+                ("lda", C.c_int64), ("format", C.c_int32), ("reserved", C.c_int32), ("rowptr_dev", C.c_void_p),
+                ("colind_dev", C.c_void_p), ("nnz", C.c_int64), ("block_rows", C.c_int64)]
 
 
 class cnmf_sketch_desc(C.Structure):

@@ -82,12 +82,40 @@ def default_handle() -> Handle:
     return h
 
 
-def _input(A: torch.Tensor) -> L.cnmf_input:
+def _input(A: torch.Tensor, block_rows: int = 0) -> L.cnmf_input:
+    """A as the library's input: a dense device tensor; a dense host tensor
+    (streamed through the device in row blocks; pin it for overlapped
+    copies); or a sparse CSR device tensor (torch.sparse_csr_tensor)."""
     if A.dtype not in _DT:
         raise TypeError("A must be float64 or float32")
+    if A.layout == torch.sparse_csr:
+        if A.device.type != "cuda":
+            raise ValueError("a sparse A must be on the device")
+        crow = A.crow_indices()
+        col = A.col_indices().to(torch.int32).contiguous()
+        vals = A.values().contiguous()
+        if crow.dtype != torch.int64:
+            crow = crow.to(torch.int64)
+        inp = L.cnmf_input(_ptr(vals), _DT[A.dtype], A.shape[0], A.shape[1], A.shape[1], L.CNMF_CSR, 0,
+                           _ptr(crow), _ptr(col), vals.numel(), 0)
+        inp._keep = (crow, col, vals)       # alive until the call has enqueued its work
+        return inp
     if A.dim() != 2 or A.stride(1) != 1:
         raise ValueError("A must be a 2-D row-major tensor (unit column stride)")
-    return L.cnmf_input(_ptr(A), _DT[A.dtype], A.shape[0], A.shape[1], A.stride(0))
+    fmt = L.CNMF_DENSE if A.device.type == "cuda" else L.CNMF_DENSE_HOST
+    return L.cnmf_input(_ptr(A), _DT[A.dtype], A.shape[0], A.shape[1], A.stride(0), fmt, 0, None, None, 0,
+                        int(block_rows))
+
+
+def _out_device(A, h) -> torch.device:
+    return A.device if A.device.type == "cuda" else h.device
+
+
+def _after(A, h):
+    """A host input is read by copies that run after the call returns: wait
+    for them, so the caller may release or change A afterwards."""
+    if A.device.type != "cuda":
+        h.stream.synchronize()
 
 
 def _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype, seed=0):
@@ -119,14 +147,14 @@ class Sketch:
 
 
 def sketch(A, r, k, q, omega_left=None, omega_right=None, sides="both", pass_dtype=None, final_dtype=None,
-           want_ac=False, seed=0, handle: Handle | None = None) -> Sketch:
+           want_ac=False, seed=0, block_rows=0, handle: Handle | None = None) -> Sketch:
     """Structured random compression (Alg. 1) of A on one or both sides, and
     the small sketches B = L^T A, At = L^T A R^T, Ac = A R^T.  A test matrix
     left as None is drawn on the device from `seed` (see gaussian())."""
     h = handle or default_handle()
     pass_dtype, final_dtype = _default_prec(A, pass_dtype, final_dtype)
     m, n = A.shape
-    dev = A.device
+    dev = _out_device(A, h)
     od = _acc_dtype(A, pass_dtype)
     sd = _SIDES[sides] if isinstance(sides, str) else sides
     left, right = bool(sd & 1), bool(sd & 2)
@@ -136,10 +164,11 @@ def sketch(A, r, k, q, omega_left=None, omega_right=None, sides="both", pass_dty
     Att = torch.empty((k, k), dtype=od, device=dev) if (left and right) else None
     Act = torch.empty((m, k), dtype=od, device=dev) if (right and want_ac) else None
     stats = torch.zeros(4, dtype=torch.float64, device=dev)
-    inp = _input(A)
+    inp = _input(A, block_rows)
     d = _sketch_desc(r, k, q, sd, omega_left, omega_right, pass_dtype, final_dtype, seed)
     out = L.cnmf_sketch_out(_ptr(Lt), _ptr(Rt), _ptr(Bt), _ptr(Att), _ptr(Act), _ptr(stats))
     L.check(h._lib.cnmf_sketch(h.raw, C.byref(inp), C.byref(d), C.byref(out)), h.raw)
+    _after(A, h)
     return Sketch(Lt, Rt, Bt, Att, Act, stats)
 
 
@@ -153,7 +182,7 @@ class Factorization:
 
 def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="admm", iters=100,
               lam=1.0, phi=None, xi=1.0, mu_eps=1e-16, pass_dtype=None, final_dtype=None,
-              want_sketch=False, seed=0, handle: Handle | None = None) -> Factorization:
+              want_sketch=False, seed=0, block_rows=0, handle: Handle | None = None) -> Factorization:
     """Compressed NMF: two-sided sketch, then ADMM (Alg. 3), MU (Alg. 2) or
     alternating NNLS (Section 3, Eq. alternateLS_nmf_compressed) on the
     compressed factors, then the FP64 relative residual.  The *_full methods
@@ -161,7 +190,7 @@ def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="adm
     h = handle or default_handle()
     pass_dtype, final_dtype = _default_prec(A, pass_dtype, final_dtype)
     m, n = A.shape
-    dev = A.device
+    dev = _out_device(A, h)
     od = _acc_dtype(A, pass_dtype)
     U = torch.empty((m, r), dtype=od, device=dev)
     V = torch.empty((r, n), dtype=od, device=dev)
@@ -177,29 +206,31 @@ def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="adm
         so = L.cnmf_sketch_out()
     U0 = U0.to(device=dev, dtype=torch.float64).contiguous()
     V0 = V0.to(device=dev, dtype=torch.float64).contiguous()
-    inp = _input(A)
+    inp = _input(A, block_rows)
     d = L.cnmf_factorize_desc(_sketch_desc(r, k, q, L.CNMF_BOTH, omega_left, omega_right, pass_dtype, final_dtype,
                                            seed),
                               _METHODS[method], int(iters), float(lam), float(lam if phi is None else phi),
                               float(xi), float(mu_eps), _ptr(U0), _ptr(V0))
     out = L.cnmf_factorize_out(_ptr(U), _ptr(V), _ptr(res), so)
     L.check(h._lib.cnmf_factorize(h.raw, C.byref(inp), C.byref(d), C.byref(out)), h.raw)
+    _after(A, h)
     return Factorization(U, V, res, sk)
 
 
 def select(A, r, k, q, omega_left=None, omega_right=None, sides="left", pass_dtype=None, final_dtype=None,
-           want_scores=False, want_B=False, seed=0, handle: Handle | None = None):
+           want_scores=False, want_B=False, seed=0, block_rows=0, handle: Handle | None = None):
     """Compressed separable NMF column selection (Alg. SNMF steps 1-2): the
     sketch, B = Q^T A, and SPA on B.  Returns int64 indices (device)."""
     h = handle or default_handle()
     pass_dtype, final_dtype = _default_prec(A, pass_dtype, final_dtype)
-    dev = A.device
+    dev = _out_device(A, h)
     K = torch.empty(r, dtype=torch.int64, device=dev)
     score = torch.empty(r, dtype=torch.float64, device=dev) if want_scores else None
     B = torch.empty((k, A.shape[1]), dtype=_acc_dtype(A, pass_dtype), device=dev) if want_B else None
-    inp = _input(A)
+    inp = _input(A, block_rows)
     d = _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype, seed)
     L.check(h._lib.snmf_select(h.raw, C.byref(inp), C.byref(d), _ptr(K), _ptr(score), _ptr(B)), h.raw)
+    _after(A, h)
     return K, score, B
 
 

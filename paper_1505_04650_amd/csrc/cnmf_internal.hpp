@@ -240,6 +240,32 @@ template <typename TS, typename TD>
 hipError_t launch_transpose(const TS* src, int64_t lds, TD* dst, int64_t ldd, int rows, int cols,
                             hipStream_t st);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
+// Sparse A in CSR form (k_sparse.hip).  Transpose: trow (n + 1), tcol / tval
+// (nnz) from rowptr / col / val, with scratch keys, perm, keys_out, perm_out
+// (nnz each) and tmp (csr_sort_temp_bytes); column indices outside [0, n)
+// are counted in *bad (and skipped everywhere).  spmm: Y (rows x kk) = S X,
+// kk <= 256, row offsets clamped to [0, nnz].  resid: per
+// workgroup (csr_resid_blocks(rows) of them) the FP64 sums of a^2 and
+// a (U V)_ij over the nonzeros; finish: the relative residual from those and
+// the Grams GU = U^T U, GV = V V^T (r x r).
+size_t csr_sort_temp_bytes(int nnz, int n);
+template <typename T>
+hipError_t launch_csr_transpose(const int64_t* rowptr, const int32_t* col, const T* val, int m, int n, int64_t nnz,
+                                int64_t* trow, int32_t* tcol, T* tval, int32_t* keys, int32_t* perm,
+                                int32_t* keys_out, int32_t* perm_out, void* tmp, size_t tmp_bytes, int* bad,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_csr_spmm(const int64_t* rowptr, const int32_t* col, const T* val, int rows, int cols, int64_t nnz,
+                           const T* X, int kk, T* Y, hipStream_t st);
+int csr_resid_blocks(int rows);
+template <typename T>
+hipError_t launch_csr_resid(const int64_t* rowptr, const int32_t* col, const T* val, int rows, int cols, int64_t nnz,
+                            const T* U, const T* Vt, int r, double* part, hipStream_t st);
+hipError_t launch_csr_resid_finish(const double* part, int parts, const double* GU, const double* GV, int r,
+                                   double* out, hipStream_t st);
+// dst += src (rows x cols, leading dimensions lds / ldd)
+template <typename T>
+hipError_t launch_add2d(const T* src, int64_t lds, T* dst, int64_t ldd, int rows, int cols, hipStream_t st);
 template <typename T>
 hipError_t launch_residual(const T* A, int64_t lda, int m, int n, const T* U, int ldu, const T* Vt,
                            int ldv, int r, double* partial, int parts, hipStream_t st);

@@ -45,6 +45,30 @@ template hipError_t launch_copy2d<float, float>(const float*, int64_t, float*, i
 template hipError_t launch_copy2d<float, double>(const float*, int64_t, double*, int64_t, int, int, double, hipStream_t);
 template hipError_t launch_copy2d<double, __hip_bfloat16>(const double*, int64_t, __hip_bfloat16*, int64_t, int, int, double, hipStream_t);
 
+// dst[i][j] += src[i][j] (sums over the row blocks of a streamed A^T Z pass,
+// added in block order)
+template <typename T>
+__global__ void add2d_kernel(const T* __restrict__ src, int64_t lds, T* __restrict__ dst, int64_t ldd, int rows,
+                             int cols) {
+  int64_t total = (int64_t)rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = e / cols, j = e - i * cols;
+    dst[i * ldd + j] += src[i * lds + j];
+  }
+}
+
+template <typename T>
+hipError_t launch_add2d(const T* src, int64_t lds, T* dst, int64_t ldd, int rows, int cols, hipStream_t st) {
+  int64_t total = (int64_t)rows * cols;
+  if (total == 0) return hipSuccess;
+  int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL((add2d_kernel<T>), dim3(blocks), dim3(256), 0, st, src, lds, dst, ldd, rows, cols);
+  CNMF_LAUNCH_CHECK();
+}
+template hipError_t launch_add2d<float>(const float*, int64_t, float*, int64_t, int, int, hipStream_t);
+template hipError_t launch_add2d<double>(const double*, int64_t, double*, int64_t, int, int, hipStream_t);
+
 // ---------------------------------------------------------------------------
 // dst[j][i] = src[i][j] through a 32 x 32 LDS tile
 // ---------------------------------------------------------------------------

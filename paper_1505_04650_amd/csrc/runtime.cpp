@@ -43,6 +43,11 @@ struct cnmf_handle {
   // device word: CholeskyQR2 breakdowns the fallback could not resolve since
   // the last cnmf_synchronize (allocated at creation; serving handles: none)
   int* unresolved_dev = nullptr;
+  // inputs in host memory: a copy stream and the staging events (created on
+  // first use)
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t stage_ready[2] = {nullptr, nullptr};
+  hipEvent_t stage_free[2] = {nullptr, nullptr};
   std::string err;
   // per-stage timing of the last call (HIP events on the handle's stream)
   bool timing = false;
@@ -192,13 +197,22 @@ std::vector<Pass> plan_passes(int k, int q, int sides, bool want_ac, cnmf_dtype 
 // -------------------------------------------------------------------------
 cnmf_status check_input(cnmf_handle* h, const cnmf_input* A) {
   if (!A) return fail(h, CNMF_EINVAL, "A is NULL");
-  if (!A->data_dev) return fail(h, CNMF_EINVAL, "A->data_dev is NULL");
+  if (A->format != CNMF_DENSE && A->format != CNMF_DENSE_HOST && A->format != CNMF_CSR)
+    return fail(h, CNMF_EINVAL, "unknown A->format %d", A->format);
   if (A->dtype != CNMF_F64 && A->dtype != CNMF_F32)
     return fail(h, CNMF_EINVAL, "A->dtype must be CNMF_F64 or CNMF_F32");
   if (A->m < 1 || A->n < 1) return fail(h, CNMF_EINVAL, "A must be non-empty (m=%lld n=%lld)", (long long)A->m, (long long)A->n);
   if (A->m > INT32_MAX / 2 || A->n > INT32_MAX / 2)
     return fail(h, CNMF_ENOTSUP, "dimensions above 2^30 are not supported");
+  if (A->format == CNMF_CSR) {
+    if (!A->rowptr_dev || !A->colind_dev) return fail(h, CNMF_EINVAL, "CSR input needs rowptr_dev and colind_dev");
+    if (A->nnz < 0 || A->nnz > INT32_MAX) return fail(h, CNMF_EINVAL, "nnz must be in [0, 2^31)");
+    if (A->nnz > 0 && !A->data_dev) return fail(h, CNMF_EINVAL, "A->data_dev (the values) is NULL");
+    return CNMF_OK;
+  }
+  if (!A->data_dev) return fail(h, CNMF_EINVAL, "A->data_dev is NULL");
   if (A->lda < A->n) return fail(h, CNMF_EINVAL, "lda (%lld) < n (%lld)", (long long)A->lda, (long long)A->n);
+  if (A->block_rows < 0) return fail(h, CNMF_EINVAL, "block_rows must be >= 0");
   return CNMF_OK;
 }
 
@@ -224,6 +238,8 @@ cnmf_status check_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_
       return fail(h, CNMF_ENOTSUP, "the last range pass and B = L^T A need at least BF16 (final_dtype)");
     if (d->final_dtype != CNMF_F32 && d->final_dtype != CNMF_BF16)
       return fail(h, CNMF_EINVAL, "unknown final_dtype %d", (int)d->final_dtype);
+    if (A->format != CNMF_DENSE && (d->pass_dtype != CNMF_F32 || d->final_dtype != CNMF_F32))
+      return fail(h, CNMF_ENOTSUP, "reduced-precision passes need A dense on the device");
   }
   return CNMF_OK;
 }
@@ -528,9 +544,268 @@ cnmf_status orth_blocks(cnmf_handle* h, SketchWs<T>& w, const T* Y, int rows, in
 }
 
 // Sketch driver for T = double (F64 input) or float (F32 input).
+// -------------------------------------------------------------------------
+// Products with A in its three formats.  Dense on the device: one streaming
+// GEMM (split-K partials reduced in a fixed order).  Dense in host memory:
+// the same GEMM on row blocks copied in on a second stream, two blocks in
+// flight (block b + 2 is copied while block b + 1 is multiplied); A X writes
+// each block's rows, A^T Z adds the blocks' products in block order.  CSR
+// on the device: sparse products (A^T as CSR formed once per call).
+// -------------------------------------------------------------------------
+template <typename T>
+struct AOpWs {
+  T* stage[2] = {nullptr, nullptr};  // host format: staging blocks (brows x n, tight)
+  int64_t brows = 0;
+  int nblocks = 0;
+  T* ysum = nullptr;                 // host format: one block's A_b^T Z_b (n x kkmax)
+  T* hpart = nullptr;                // host format: split-K partials of a block's product
+  double* rpart = nullptr;           // host format: residual partials of all blocks
+  int rparts = 0;
+  // CSR: A^T in CSR form
+  int64_t* trow = nullptr;
+  int32_t* tcol = nullptr;
+  T* tval = nullptr;
+  void* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  int32_t* keys = nullptr;
+  int32_t* perm = nullptr;
+  int32_t* keys_out = nullptr;
+  int32_t* perm_out = nullptr;
+  int* bad = nullptr;                // column indices outside [0, n)
+  double* gpart = nullptr;           // Gram partials of the residual (kCsrGramParts x 64 x 64)
+  double* GU = nullptr;              // U^T U, V V^T (64 x 64 each)
+  double* GV = nullptr;
+  double* cpart = nullptr;           // residual partials over the nonzeros
+  bool t_built = false;
+};
+constexpr int kCsrGramParts = 64;
+
+int64_t host_block_rows(const cnmf_input* A) {
+  const int64_t es = A->dtype == CNMF_F64 ? 8 : 4;
+  int64_t b = A->block_rows;
+  if (b <= 0) b = std::max<int64_t>(64, ((int64_t)64 << 20) / (A->n * es) / 64 * 64);
+  return std::min<int64_t>(b, A->m);
+}
+
+template <typename T>
+void layout_aop(Arena& a, AOpWs<T>& ao, const cnmf_input* A, int kkmax) {
+  if (A->format == CNMF_DENSE_HOST) {
+    ao.brows = host_block_rows(A);
+    ao.nblocks = (int)((A->m + ao.brows - 1) / ao.brows);
+    ao.stage[0] = a.take<T>((size_t)ao.brows * A->n);
+    ao.stage[1] = a.take<T>((size_t)ao.brows * A->n);
+    ao.ysum = a.take<T>((size_t)A->n * kkmax);
+    // split-K partials of one block's product: the largest over the block
+    // heights and operand widths (the split count grows as blocks shrink)
+    size_t hp = 1;
+    const int64_t last = A->m - (int64_t)(ao.nblocks - 1) * ao.brows;
+    for (int64_t mb : {ao.brows, last})
+      for (int kk = 16; kk <= std::min(kkmax, 128); kk += 16) {
+        const size_t sn = choose_splits_n((int)mb, (int)A->n, kk, sizeof(T));
+        const size_t stt = choose_splits_t((int)mb, (int)A->n, kk, sizeof(T));
+        hp = std::max({hp, sn > 1 ? sn * mb * kk : 0, stt > 1 ? stt * A->n * kk : 0});
+      }
+    ao.hpart = a.take<T>(hp);
+    int parts = 0;
+    for (int b = 0; b < ao.nblocks; ++b) {
+      const int64_t mb = std::min<int64_t>(ao.brows, A->m - (int64_t)b * ao.brows);
+      parts += residual_blocks((int)mb, (int)A->n);
+    }
+    ao.rparts = parts;
+    ao.rpart = a.take<double>(2 * (size_t)parts);
+  } else if (A->format == CNMF_CSR) {
+    const size_t nnz = (size_t)A->nnz;
+    ao.trow = a.take<int64_t>((size_t)A->n + 1);
+    ao.tcol = a.take<int32_t>(std::max<size_t>(nnz, 1));
+    ao.tval = a.take<T>(std::max<size_t>(nnz, 1));
+    ao.keys = a.take<int32_t>(std::max<size_t>(nnz, 1));
+    ao.perm = a.take<int32_t>(std::max<size_t>(nnz, 1));
+    ao.keys_out = a.take<int32_t>(std::max<size_t>(nnz, 1));
+    ao.perm_out = a.take<int32_t>(std::max<size_t>(nnz, 1));
+    ao.sort_tmp_bytes = csr_sort_temp_bytes((int)nnz, (int)A->n);
+    ao.sort_tmp = a.take<char>(std::max<size_t>(ao.sort_tmp_bytes, 1));
+    ao.bad = a.take<int>(1);
+    ao.gpart = a.take<double>((size_t)kCsrGramParts * 64 * 64);
+    ao.GU = a.take<double>(64 * 64);
+    ao.GV = a.take<double>(64 * 64);
+    ao.cpart = a.take<double>(2 * (size_t)csr_resid_blocks((int)A->m));
+  }
+}
+
+// out (rows x kk) = A X (dirN; X n x kk) or A^T Z (Z m x kk) for a dense
+// device A; k and nblk: the operand's chain blocks (k columns each), used when
+// kk > 128 (the GEMM kernels take at most 128 columns).  Partial sums of
+// split-K launches go through ppart; xg / yg hold one block's columns.
+template <typename T>
+cnmf_status dense_product(cnmf_handle* h, const T* Ap, int64_t lda, int m, int n, bool dirN, const T* op, int kk,
+                          int k, int nblk, T* out, T* ppart, T* xg, T* yg) {
+  hipStream_t st = h->stream;
+  const int rows = dirN ? m : n, in_rows = dirN ? n : m;
+  if (kk <= 128) {
+    const int splits = dirN ? choose_splits_n(m, n, kk, sizeof(T)) : choose_splits_t(m, n, kk, sizeof(T));
+    T* dst = splits > 1 ? ppart : out;
+    if (dirN)
+      HIPCHK(h, launch_gemm_n<T>(Ap, lda, m, n, op, kk, dst, splits, st));
+    else
+      HIPCHK(h, launch_gemm_t<T>(Ap, lda, m, n, op, kk, dst, splits, st));
+    if (splits > 1) HIPCHK(h, launch_reduce_splits<T>(ppart, splits, rows, kk, out, st));
+    return CNMF_OK;
+  }
+  // one product per chain block (k <= 128 columns each)
+  const int kb = ru16(k);
+  const int sb = dirN ? choose_splits_n(m, n, kb, sizeof(T)) : choose_splits_t(m, n, kb, sizeof(T));
+  for (int b = 0; b < nblk; ++b) {
+    const int col0 = b * k;
+    if (kb != k) HIPCHK(h, launch_fill(xg, sizeof(T) * (size_t)in_rows * kb, st));
+    HIPCHK(h, (launch_copy2d<T, T>(op + col0, kk, xg, kb, in_rows, k, 1.0, st)));
+    T* db = sb > 1 ? ppart : yg;
+    if (dirN)
+      HIPCHK(h, launch_gemm_n<T>(Ap, lda, m, n, xg, kb, db, sb, st));
+    else
+      HIPCHK(h, launch_gemm_t<T>(Ap, lda, m, n, xg, kb, db, sb, st));
+    if (sb > 1) HIPCHK(h, launch_reduce_splits<T>(ppart, sb, rows, kb, yg, st));
+    HIPCHK(h, (launch_copy2d<T, T>(yg, kb, out + col0, kk, rows, k, 1.0, st)));
+  }
+  return CNMF_OK;
+}
+
+cnmf_status ensure_copy_stream(cnmf_handle* h) {
+  if (h->copy_stream) return CNMF_OK;
+  HIPCHK(h, hipStreamCreateWithFlags(&h->copy_stream, hipStreamNonBlocking));
+  for (int i = 0; i < 2; ++i) {
+    HIPCHK(h, hipEventCreateWithFlags(&h->stage_ready[i], hipEventDisableTiming));
+    HIPCHK(h, hipEventCreateWithFlags(&h->stage_free[i], hipEventDisableTiming));
+  }
+  return CNMF_OK;
+}
+
+// Streams the row blocks of a host A through the staging buffers and calls
+// body(b, stage, row0, rows) on the handle's stream for each, in order.
+template <typename T, typename F>
+cnmf_status host_blocks(cnmf_handle* h, const cnmf_input* A, AOpWs<T>& ao, F&& body) {
+  cnmf_status s = ensure_copy_stream(h);
+  if (s != CNMF_OK) return s;
+  hipStream_t st = h->stream, cs = h->copy_stream;
+  const int64_t m = A->m, n = A->n, es = sizeof(T);
+  const char* src = (const char*)A->data_dev;
+  // the stages may still be read by work already on the handle's stream
+  HIPCHK(h, hipEventRecord(h->stage_free[0], st));
+  HIPCHK(h, hipEventRecord(h->stage_free[1], st));
+  auto copy_in = [&](int b) -> cnmf_status {
+    const int sl = b & 1;
+    const int64_t i0 = (int64_t)b * ao.brows, mb = std::min<int64_t>(ao.brows, m - i0);
+    HIPCHK(h, hipStreamWaitEvent(cs, h->stage_free[sl], 0));
+    HIPCHK(h, hipMemcpy2DAsync(ao.stage[sl], (size_t)(n * es), src + i0 * A->lda * es, (size_t)(A->lda * es),
+                               (size_t)(n * es), (size_t)mb, hipMemcpyHostToDevice, cs));
+    HIPCHK(h, hipEventRecord(h->stage_ready[sl], cs));
+    return CNMF_OK;
+  };
+  s = copy_in(0);
+  if (s == CNMF_OK && ao.nblocks > 1) s = copy_in(1);
+  if (s != CNMF_OK) return s;
+  for (int b = 0; b < ao.nblocks; ++b) {
+    const int sl = b & 1;
+    const int64_t i0 = (int64_t)b * ao.brows, mb = std::min<int64_t>(ao.brows, m - i0);
+    HIPCHK(h, hipStreamWaitEvent(st, h->stage_ready[sl], 0));
+    s = body(b, (const T*)ao.stage[sl], (int)i0, (int)mb);
+    if (s != CNMF_OK) return s;
+    HIPCHK(h, hipEventRecord(h->stage_free[sl], st));
+    if (b + 2 < ao.nblocks) {
+      s = copy_in(b + 2);
+      if (s != CNMF_OK) return s;
+    }
+  }
+  return CNMF_OK;
+}
+
+// CSR products: A X from the caller's rows; A^T Z from the transpose, built
+// on the first A^T product of the call.  Column indices outside [0, n) are
+// skipped and reported through the handle's unresolved count.
+template <typename T>
+cnmf_status csr_product(cnmf_handle* h, const cnmf_input* A, AOpWs<T>& ao, bool dirN, const T* op, int kk, T* out) {
+  hipStream_t st = h->stream;
+  const int m = (int)A->m, n = (int)A->n;
+  const T* val = (const T*)A->data_dev;
+  if (!ao.t_built) {
+    HIPCHK(h, launch_fill(ao.bad, sizeof(int), st));
+    HIPCHK(h, launch_csr_transpose<T>(A->rowptr_dev, A->colind_dev, val, m, n, A->nnz, ao.trow, ao.tcol, ao.tval,
+                                      ao.keys, ao.perm, ao.keys_out, ao.perm_out, ao.sort_tmp, ao.sort_tmp_bytes,
+                                      ao.bad, st));
+    HIPCHK(h, launch_add_count(ao.bad, h->unresolved_dev, st));
+    ao.t_built = true;
+  }
+  if (dirN)
+    HIPCHK(h, launch_csr_spmm<T>(A->rowptr_dev, A->colind_dev, val, m, n, A->nnz, op, kk, out, st));
+  else
+    HIPCHK(h, launch_csr_spmm<T>(ao.trow, ao.tcol, ao.tval, n, m, A->nnz, op, kk, out, st));
+  return CNMF_OK;
+}
+
+// out (rows x kk) = A X or A^T Z for any input format.
+template <typename T>
+cnmf_status a_product(cnmf_handle* h, const cnmf_input* A, AOpWs<T>& ao, bool dirN, const T* op, int kk, int k,
+                      int nblk, T* out, T* ppart, T* xg, T* yg) {
+  const int m = (int)A->m, n = (int)A->n;
+  if (A->format == CNMF_DENSE)
+    return dense_product<T>(h, (const T*)A->data_dev, A->lda, m, n, dirN, op, kk, k, nblk, out, ppart, xg, yg);
+  if (A->format == CNMF_CSR) return csr_product<T>(h, A, ao, dirN, op, kk, out);
+  // host: A X row block by row block; A^T Z as the block-ordered sum
+  return host_blocks<T>(h, A, ao, [&](int b, const T* blk, int i0, int mb) -> cnmf_status {
+    if (dirN)
+      return dense_product<T>(h, blk, n, mb, n, true, op, kk, k, nblk, out + (int64_t)i0 * kk, ao.hpart, xg, yg);
+    T* dst = b == 0 ? out : ao.ysum;
+    cnmf_status s =
+        dense_product<T>(h, blk, n, mb, n, false, op + (int64_t)i0 * kk, kk, k, nblk, dst, ao.hpart, xg, yg);
+    if (s != CNMF_OK || b == 0) return s;
+    HIPCHK(h, launch_add2d<T>(ao.ysum, kk, out, kk, n, kk, h->stream));
+    return CNMF_OK;
+  });
+}
+
+template <typename T>
+cnmf_status csr_residual(cnmf_handle* h, const cnmf_input* A, AOpWs<T>& ao, const T* U, const T* Vt, int r,
+                         double* out) {
+  hipStream_t st = h->stream;
+  const int m = (int)A->m, n = (int)A->n;
+  if (r > 64) return fail(h, CNMF_ENOTSUP, "r > 64");
+  HIPCHK(h, launch_csr_resid<T>(A->rowptr_dev, A->colind_dev, (const T*)A->data_dev, m, n, A->nnz, U, Vt, r,
+                                ao.cpart, st));
+  const int pu = std::min(kCsrGramParts, std::max(1, m / 32)), pv = std::min(kCsrGramParts, std::max(1, n / 32));
+  HIPCHK(h, (launch_cross2<T, T>(U, r, 0, U, r, 0, 0, 1, m, r, r, ao.gpart, pu, st)));
+  HIPCHK(h, launch_sum_parts(ao.gpart, pu, (int64_t)r * r, ao.GU, st));
+  HIPCHK(h, (launch_cross2<T, T>(Vt, r, 0, Vt, r, 0, 0, 1, n, r, r, ao.gpart, pv, st)));
+  HIPCHK(h, launch_sum_parts(ao.gpart, pv, (int64_t)r * r, ao.GV, st));
+  HIPCHK(h, launch_csr_resid_finish(ao.cpart, csr_resid_blocks(m), ao.GU, ao.GV, r, out, st));
+  return CNMF_OK;
+}
+
+// ||A - U V||_F / ||A||_F (U m x r, V^T n x r; ld r) into *out (FP64).
+template <typename T>
+cnmf_status a_residual(cnmf_handle* h, const cnmf_input* A, AOpWs<T>& ao, const T* U, const T* Vt, int r,
+                       double* rpart, int rparts, double* out) {
+  hipStream_t st = h->stream;
+  const int m = (int)A->m, n = (int)A->n;
+  if (A->format == CNMF_DENSE) {
+    HIPCHK(h, launch_residual<T>((const T*)A->data_dev, A->lda, m, n, U, r, Vt, r, r, rpart, rparts, st));
+    HIPCHK(h, launch_residual_finish(rpart, rparts, out, st));
+    return CNMF_OK;
+  }
+  if (A->format == CNMF_CSR) return csr_residual<T>(h, A, ao, U, Vt, r, out);
+  int off = 0;
+  cnmf_status s = host_blocks<T>(h, A, ao, [&](int, const T* blk, int i0, int mb) -> cnmf_status {
+    const int p = residual_blocks(mb, n);
+    HIPCHK(h, launch_residual<T>(blk, n, mb, n, U + (int64_t)i0 * r, r, Vt, r, r, ao.rpart + 2 * (int64_t)off, p, st));
+    off += p;
+    return CNMF_OK;
+  });
+  if (s != CNMF_OK) return s;
+  HIPCHK(h, launch_residual_finish(ao.rpart, ao.rparts, out, st));
+  return CNMF_OK;
+}
+
 template <typename T>
 cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, SketchWs<T>& w,
-                       const std::vector<Pass>& passes, double* stats_dev) {
+                       AOpWs<T>& ao, const std::vector<Pass>& passes, double* stats_dev) {
   hipStream_t st = h->stream;
   const int m = (int)A->m, n = (int)A->n, k = d->k;
   const T* Ap = (const T*)A->data_dev;
@@ -610,11 +885,7 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
     const int rows = p.dirN ? m : n;
     T* op = operand_for(p);
     const bool lp = is_lowp(p.prec);
-    const bool wide = !lp && p.kk > 128;
-    int splits = lp ? choose_splits_lowp(rows, p.dirN ? n : m, p.kk, lowp_es(p.prec))
-                    : (p.dirN ? choose_splits_n(m, n, p.kk, sizeof(T)) : choose_splits_t(m, n, p.kk, sizeof(T)));
-    if (wide) splits = 1;  // reduced per block below
-    T* dst = splits > 1 ? w.Ppart : w.Y;
+    const int splits = lp ? choose_splits_lowp(rows, p.dirN ? n : m, p.kk, lowp_es(p.prec)) : 1;
     {
       const double flops = 2.0 * m * n * (double)(k * (int)p.blocks.size());
       Span sp(h, p.dirN ? ST_PASS_N : ST_PASS_T, flops);
@@ -624,31 +895,14 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
           const void* M = es == 2 ? (p.dirN ? (const void*)w.A16 : (const void*)w.At16)
                                   : (p.dirN ? (const void*)w.A8 : (const void*)w.At8);
           HIPCHK(h, launch_gemm_lowp(es, M, p.dirN ? w.ldo : w.ldt, rows, p.dirN ? n : m, xt_for(p), xt_ld(p), p.kk,
-                                     dst, splits, w.tscale, w.ntj, p.dirN ? 0 : 1, st));
+                                     splits > 1 ? w.Ppart : w.Y, splits, w.tscale, w.ntj, p.dirN ? 0 : 1, st));
         }
-      } else if (wide) {
-        // one product per chain block (k <= 128 columns each)
-        const int kb = ru16(k), in_rows = p.dirN ? n : m;
-        const int sb = p.dirN ? choose_splits_n(m, n, kb, sizeof(T)) : choose_splits_t(m, n, kb, sizeof(T));
-        for (const Block& b : p.blocks) {
-          if (kb != k) HIPCHK(h, launch_fill(w.Xg, sizeof(T) * (size_t)in_rows * kb, st));
-          HIPCHK(h, (launch_copy2d<T, T>(op + b.col0, p.kk, w.Xg, kb, in_rows, k, 1.0, st)));
-          T* db = sb > 1 ? w.Ppart : w.Yg;
-          if (p.dirN)
-            HIPCHK(h, launch_gemm_n<T>(Ap, lda, m, n, w.Xg, kb, db, sb, st));
-          else
-            HIPCHK(h, launch_gemm_t<T>(Ap, lda, m, n, w.Xg, kb, db, sb, st));
-          if (sb > 1) HIPCHK(h, launch_reduce_splits<T>(w.Ppart, sb, rows, kb, w.Yg, st));
-          HIPCHK(h, (launch_copy2d<T, T>(w.Yg, kb, w.Y + b.col0, p.kk, rows, k, 1.0, st)));
-        }
-      } else if (p.dirN) {
-        HIPCHK(h, launch_gemm_n<T>(Ap, lda, m, n, op, p.kk, dst, splits, st));
       } else {
-        HIPCHK(h, launch_gemm_t<T>(Ap, lda, m, n, op, p.kk, dst, splits, st));
+        RUN(a_product<T>(h, A, ao, p.dirN, op, p.kk, k, (int)p.blocks.size(), w.Y, w.Ppart, w.Xg, w.Yg));
       }
     }
     Span orth_span(h, ST_ORTH);
-    if (splits > 1) HIPCHK(h, launch_reduce_splits<T>(w.Ppart, splits, rows, p.kk, w.Y, st));
+    if (lp && splits > 1) HIPCHK(h, launch_reduce_splits<T>(w.Ppart, splits, rows, p.kk, w.Y, st));
 
     // orthonormalise the range blocks (contiguous)
     int rcol0 = -1, nh = 0;
@@ -743,6 +997,12 @@ cnmf_status write_sketch_outputs(cnmf_handle* h, const cnmf_input* A, const cnmf
   return CNMF_OK;
 }
 
+int passes_kkmax(const std::vector<Pass>& passes) {
+  int kk = 16;
+  for (const Pass& p : passes) kk = std::max(kk, p.kk);
+  return kk;
+}
+
 template <typename T>
 cnmf_status do_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, const cnmf_sketch_out* o,
                       bool want_ac) {
@@ -750,12 +1010,15 @@ cnmf_status do_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_des
   if (passes.empty()) return fail(h, CNMF_EINVAL, "internal: empty pass plan");
   Arena dry(nullptr);
   SketchWs<T> w;
+  AOpWs<T> ao;
   layout_sketch<T>(dry, w, A->m, A->n, d->k, passes, want_ac, d);
+  layout_aop<T>(dry, ao, A, passes_kkmax(passes));
   cnmf_status s = ensure_ws(h, dry.off);
   if (s != CNMF_OK) return s;
   Arena a(h->ws);
   layout_sketch<T>(a, w, A->m, A->n, d->k, passes, want_ac, d);
-  s = run_sketch<T>(h, A, d, w, passes, o ? o->stats_dev : nullptr);
+  layout_aop<T>(a, ao, A, passes_kkmax(passes));
+  s = run_sketch<T>(h, A, d, w, ao, passes, o ? o->stats_dev : nullptr);
   if (s != CNMF_OK) return s;
   return write_sketch_outputs<T>(h, A, d, w, o);
 }
@@ -801,21 +1064,11 @@ void layout_iter(Arena& a, IterWs<T>& w, int64_t m, int64_t n, int k, int r, boo
 }
 
 template <typename T>
-cnmf_status pass_full(cnmf_handle* h, const cnmf_input* A, bool dirN, const T* op, int kk, T* out, T* ppart) {
-  hipStream_t st = h->stream;
-  const int m = (int)A->m, n = (int)A->n;
-  const T* Ap = (const T*)A->data_dev;
-  const int splits = dirN ? choose_splits_n(m, n, kk, sizeof(T)) : choose_splits_t(m, n, kk, sizeof(T));
-  T* dst = splits > 1 ? ppart : out;
-  {
-    Span sp(h, dirN ? ST_PASS_N : ST_PASS_T, 2.0 * m * n * (double)kk);
-    if (dirN)
-      HIPCHK(h, launch_gemm_n<T>(Ap, A->lda, m, n, op, kk, dst, splits, st));
-    else
-      HIPCHK(h, launch_gemm_t<T>(Ap, A->lda, m, n, op, kk, dst, splits, st));
-  }
-  if (splits > 1) HIPCHK(h, launch_reduce_splits<T>(ppart, splits, dirN ? m : n, kk, out, st));
-  return CNMF_OK;
+cnmf_status pass_full(cnmf_handle* h, const cnmf_input* A, AOpWs<T>& ao, bool dirN, const T* op, int kk, T* out,
+                      T* ppart) {
+  Span sp(h, dirN ? ST_PASS_N : ST_PASS_T, 2.0 * A->m * A->n * (double)kk);
+  // kk = r rounded up to 16 <= 64: one product
+  return a_product<T>(h, A, ao, dirN, op, kk, kk, 1, out, ppart, nullptr, nullptr);
 }
 
 // A factorisation in four phases (the serving loop drives them separately):
@@ -833,6 +1086,7 @@ struct FactState {
   SketchWs<T> w;
   AdmmWs<T> aw;
   IterWs<T> iw;
+  AOpWs<T> ao;
 };
 
 template <typename T>
@@ -848,7 +1102,8 @@ cnmf_status fact_plan(cnmf_handle* h, const cnmf_factorize_desc* d, FactState<T>
 }
 
 template <typename T>
-void fact_layout(Arena& a, FactState<T>& f, int64_t m, int64_t n, const cnmf_factorize_desc* d) {
+void fact_layout(Arena& a, FactState<T>& f, int64_t m, int64_t n, const cnmf_factorize_desc* d,
+                 const cnmf_input* A = nullptr) {
   const int k = d->sk.k, r = d->sk.r;
   if (!f.full)
     layout_sketch<T>(a, f.w, m, n, k, f.passes, f.want_ac, &d->sk);
@@ -856,6 +1111,7 @@ void fact_layout(Arena& a, FactState<T>& f, int64_t m, int64_t n, const cnmf_fac
     f.w.flags = a.take<int>(8);
   layout_admm<T>(a, f.aw, m, n, k, r);
   if (d->method != CNMF_ADMM) layout_iter<T>(a, f.iw, m, n, k, r, f.full);
+  if (A) layout_aop<T>(a, f.ao, A, std::max(f.full ? ru16(r) : 16, f.full ? 16 : passes_kkmax(f.passes)));
 }
 
 template <typename T>
@@ -886,7 +1142,7 @@ cnmf_status fact_prologue(cnmf_handle* h, const cnmf_input* A, const cnmf_factor
   const int m = (int)A->m, n = (int)A->n, k = d->sk.k, r = d->sk.r;
   hipStream_t st = h->stream;
   if (!f.full) {
-    cnmf_status s = run_sketch<T>(h, A, &d->sk, f.w, f.passes, o->sk_out.stats_dev);
+    cnmf_status s = run_sketch<T>(h, A, &d->sk, f.w, f.ao, f.passes, o->sk_out.stats_dev);
     if (s != CNMF_OK) return s;
   } else {
     HIPCHK(h, launch_fill(f.w.flags, 8 * sizeof(int), st));
@@ -1062,10 +1318,10 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
               nullptr, iw.PpY));
       for (int it = 0; it < d->iters; ++it) {
         HIPCHK(h, launch_sum_parts(iw.PpY, iw.by, (int64_t)r * r, iw.S, st));
-        RUN(pass_full<T>(h, A, true, iw.Xop, kk, iw.Pn, iw.Ppart));
+        RUN(pass_full<T>(h, A, f.ao, true, iw.Xop, kk, iw.Pn, iw.Ppart));
         RUN(half(m, iw.bx, iw.Pn, kk, aw.U, iw.Zop, nullptr, iw.PpX));
         HIPCHK(h, launch_sum_parts(iw.PpX, iw.bx, (int64_t)r * r, iw.S, st));
-        RUN(pass_full<T>(h, A, false, iw.Zop, kk, iw.Pt, iw.Ppart));
+        RUN(pass_full<T>(h, A, f.ao, false, iw.Zop, kk, iw.Pt, iw.Ppart));
         RUN(half(n, iw.by, iw.Pt, kk, aw.Vt, iw.Xop, nullptr, iw.PpY));
       }
     }
@@ -1085,12 +1341,12 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
     for (int it = 0; it < d->iters; ++it) {
       HIPCHK(h, launch_sum_parts(iw.PpY, iw.by, (int64_t)r * r, iw.S, st));
       HIPCHK(h, launch_nmf_small(iw.S, r, r, admm ? 2 : 1, d->lambda, iw.Gp, iw.Gm, w.flags + 2, st));
-      RUN(pass_full<T>(h, A, true, iw.Xop, kk, iw.Pn, iw.Ppart));
+      RUN(pass_full<T>(h, A, f.ao, true, iw.Xop, kk, iw.Pn, iw.Ppart));
       RUN(row(m, iw.bx, iw.Pn, kk, nullptr, r, aw.U, admm ? aw.Lam : nullptr, iw.Gp, iw.Gm, iw.Gp, d->lambda,
               admm ? 1 : 0, nullptr, r, iw.Zop, iw.PpX));
       HIPCHK(h, launch_sum_parts(iw.PpX, iw.bx, (int64_t)r * r, iw.S, st));
       HIPCHK(h, launch_nmf_small(iw.S, r, r, admm ? 2 : 1, d->phi, iw.Gp, iw.Gm, w.flags + 2, st));
-      RUN(pass_full<T>(h, A, false, iw.Zop, kk, iw.Pt, iw.Ppart));
+      RUN(pass_full<T>(h, A, f.ao, false, iw.Zop, kk, iw.Pt, iw.Ppart));
       RUN(row(n, iw.by, iw.Pt, kk, nullptr, r, aw.Vt, admm ? aw.Phit : nullptr, iw.Gp, iw.Gm, iw.Gp, d->phi,
               admm ? 1 : 0, nullptr, r, iw.Xop, iw.PpY));
     }
@@ -1109,8 +1365,8 @@ cnmf_status fact_epilogue(cnmf_handle* h, const cnmf_input* A, const cnmf_factor
   if (o->V_dev) HIPCHK(h, (launch_transpose<T, T>(aw.Vt, r, (T*)o->V_dev, n, n, r, st)));
   if (o->rel_residual_dev) {
     Span sp(h, ST_RESID, 2.0 * m * n * (double)r);
-    HIPCHK(h, launch_residual<T>((const T*)A->data_dev, A->lda, m, n, aw.U, r, aw.Vt, r, r, aw.rpart, aw.rparts, st));
-    HIPCHK(h, launch_residual_finish(aw.rpart, aw.rparts, o->rel_residual_dev, st));
+    cnmf_status s = a_residual<T>(h, A, f.ao, aw.U, aw.Vt, r, aw.rpart, aw.rparts, o->rel_residual_dev);
+    if (s != CNMF_OK) return s;
   }
   if (f.full) return CNMF_OK;
   return write_sketch_outputs<T>(h, A, &d->sk, f.w, &o->sk_out);
@@ -1123,11 +1379,11 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
   cnmf_status s = fact_plan<T>(h, d, f);
   if (s != CNMF_OK) return s;
   Arena dry(nullptr);
-  fact_layout<T>(dry, f, A->m, A->n, d);
+  fact_layout<T>(dry, f, A->m, A->n, d, A);
   s = ensure_ws(h, dry.off);
   if (s != CNMF_OK) return s;
   Arena a(h->ws);
-  fact_layout<T>(a, f, A->m, A->n, d);
+  fact_layout<T>(a, f, A->m, A->n, d, A);
   s = fact_prologue<T>(h, A, d, o, f);
   if (s != CNMF_OK) return s;
   s = fact_iterations<T>(h, A, d, f);
@@ -1149,6 +1405,8 @@ cnmf_status do_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_des
   double* wb = dry.take<double>(nblk);
   int64_t* wi = dry.take<int64_t>(nblk);
   unsigned* ctr = dry.take<unsigned>(4);
+  AOpWs<T> ao;
+  layout_aop<T>(dry, ao, A, passes_kkmax(passes));
   cnmf_status s = ensure_ws(h, dry.off);
   if (s != CNMF_OK) return s;
   Arena a(h->ws);
@@ -1158,8 +1416,9 @@ cnmf_status do_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_des
   wb = a.take<double>(nblk);
   wi = a.take<int64_t>(nblk);
   ctr = a.take<unsigned>(4);
+  layout_aop<T>(a, ao, A, passes_kkmax(passes));
   hipStream_t st = h->stream;
-  s = run_sketch<T>(h, A, d, w, passes, nullptr);
+  s = run_sketch<T>(h, A, d, w, ao, passes, nullptr);
   if (s != CNMF_OK) return s;
   HIPCHK(h, (launch_copy2d<T, double>(w.BTb, k, Bt64, k, n, k, 1.0, st)));
   {
@@ -1314,6 +1573,14 @@ cnmf_status cnmf_destroy(cnmf_handle* h) {
   hipStreamSynchronize(h->stream);
   if (h->ws) hipFree(h->ws);
   if (h->unresolved_dev) hipFree(h->unresolved_dev);
+  if (h->copy_stream) {
+    hipStreamSynchronize(h->copy_stream);
+    hipStreamDestroy(h->copy_stream);
+  }
+  for (int i = 0; i < 2; ++i) {
+    if (h->stage_ready[i]) hipEventDestroy(h->stage_ready[i]);
+    if (h->stage_free[i]) hipEventDestroy(h->stage_free[i]);
+  }
   for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
   delete h;
   return CNMF_OK;
@@ -1421,6 +1688,7 @@ static cnmf_status check_factorize(cnmf_handle* h, const cnmf_input* A, const cn
 cnmf_status cnmf::serve_check(const cnmf_input* A, const cnmf_factorize_desc* d, const cnmf_factorize_out* o) {
   cnmf_status s = check_input(nullptr, A);
   if (s != CNMF_OK) return s;
+  if (A->format != CNMF_DENSE) return fail(nullptr, CNMF_ENOTSUP, "the server takes dense device inputs");
   s = check_factorize(nullptr, A, d);
   if (s != CNMF_OK) return s;
   if (!o) return fail(nullptr, CNMF_EINVAL, "out is NULL");
@@ -1574,6 +1842,7 @@ cnmf_status cnmf_range_product(cnmf_handle* h, const cnmf_input* A, int trans, c
                                void* Y_dev) {
   cnmf_status s = check_input(h, A);
   if (s != CNMF_OK) return s;
+  if (A->format != CNMF_DENSE) return fail(h, CNMF_ENOTSUP, "cnmf_range_product takes a dense device A");
   if (trans != 0 && trans != 1) return fail(h, CNMF_EINVAL, "trans must be 0 or 1");
   if (!X_dev || !Y_dev) return fail(h, CNMF_EINVAL, "X_dev and Y_dev are required");
   if (kx < 1 || kx > 128) return fail(h, CNMF_EINVAL, "kx=%d must be in [1, 128]", kx);
@@ -1615,6 +1884,7 @@ cnmf_status cnmf_range_product_lowp(cnmf_handle* h, const cnmf_input* A, int tra
                                     const double* X_dev, int32_t kx, float* Y_dev) {
   cnmf_status s = check_input(h, A);
   if (s != CNMF_OK) return s;
+  if (A->format != CNMF_DENSE) return fail(h, CNMF_ENOTSUP, "reduced-precision passes take a dense device A");
   if (A->dtype != CNMF_F32) return fail(h, CNMF_EINVAL, "reduced-precision passes need an F32 input");
   if (pass_dtype != CNMF_BF16 && pass_dtype != CNMF_FP8_E4M3)
     return fail(h, CNMF_EINVAL, "pass_dtype must be CNMF_BF16 or CNMF_FP8_E4M3");

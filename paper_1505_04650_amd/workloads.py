@@ -15,6 +15,11 @@ caption, with the dense density delta = 1):
                 of H' are Dirichlet(1) draws scaled by s_j ~ U(0, 1], P a
                 seeded column permutation; the planted (extreme) columns are
                 where the identity columns land after P.
+  * Sparse NMF data (the same figure's sparse case): entries of W (m x r)
+                and H (r x n) are U[0,1) with probability delta and 0
+                otherwise, N is standard normal with probability delta^2
+                and 0 otherwise, A = W H + N (n = 0.75 m and delta = 1e-2
+                in the paper), returned in compressed-row form.
   * Test matrices Omega: iid N(0, 1) (Section 2).
   * Initial factors: c * U[0,1) with c = sqrt(4 mean(A) / r), so that
     E[U V] = mean(A).
@@ -27,7 +32,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["Workload", "WORKLOADS", "nmf_matrix", "separable_matrix", "separable_on_device", "gaussian",
-           "init_factors", "make_inputs"]
+           "init_factors", "make_inputs", "sparse_nmf_matrix"]
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -89,6 +94,22 @@ def separable_on_device(m: int, n: int, r: int, noise: float, seed: int, device)
         A += noise * torch.randn(m, n, device=device, generator=g)
     planted = torch.nonzero(perm < r).flatten().cpu().numpy()
     return A, np.sort(planted)
+
+
+def sparse_nmf_matrix(m: int, n: int, r: int, delta: float, seed: int, dtype=np.float64):
+    """The sparse synthetic recipe: (rowptr int64, colind int32, values, dense)
+    of A = W H + N in compressed-row form (column indices ascending within
+    each row), and the dense copy for the oracle side."""
+    g = _rng(seed)
+    W = np.where(g.random((m, r)) < delta, g.random((m, r)), 0.0)
+    H = np.where(g.random((r, n)) < delta, g.random((r, n)), 0.0)
+    N = np.where(g.random((m, n)) < delta * delta, g.standard_normal((m, n)), 0.0)
+    A = (W @ H + N).astype(dtype)
+    mask = A != 0
+    rowptr = np.zeros(m + 1, dtype=np.int64)
+    rowptr[1:] = np.cumsum(mask.sum(axis=1))
+    rows, cols = np.nonzero(mask)            # row-major order, columns ascending
+    return rowptr, cols.astype(np.int32), A[rows, cols], A
 
 
 def gaussian(rows: int, cols: int, seed: int) -> np.ndarray:

@@ -217,3 +217,25 @@ def test_anls_method_checks(lib):
     assert lib.cnmf_workspace_bytes(20000, 5000, C.byref(_desc(r=50, k=60, method=L.CNMF_ANLS_FULL)),
                                     C.byref(c)) == 0
     assert b.value > a.value and c.value > 0
+
+
+def test_input_format_checks(lib):
+    """Unknown formats, CSR without its index arrays, a negative block size
+    and reduced-precision passes on a non-dense input are refused before
+    anything runs."""
+    out = L.cnmf_sketch_out()
+    d = _desc().sk
+    A = L.cnmf_input(C.c_void_p(16), L.CNMF_F32, 2000, 1000, 1000, 7)
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
+    assert b"format" in lib.cnmf_last_error(None)
+    A = L.cnmf_input(C.c_void_p(16), L.CNMF_F32, 2000, 1000, 1000, L.CNMF_CSR, 0, None, None, 10, 0)
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
+    assert b"rowptr" in lib.cnmf_last_error(None)
+    A = L.cnmf_input(C.c_void_p(16), L.CNMF_F32, 2000, 1000, 1000, L.CNMF_DENSE_HOST, 0, None, None, 0, -5)
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
+    assert b"block_rows" in lib.cnmf_last_error(None)
+    A = L.cnmf_input(C.c_void_p(16), L.CNMF_F32, 2000, 1000, 1000, L.CNMF_DENSE_HOST)
+    d.pass_dtype = L.CNMF_BF16
+    d.final_dtype = L.CNMF_BF16
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_ENOTSUP
+    assert b"dense on the device" in lib.cnmf_last_error(None)
