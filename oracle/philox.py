@@ -18,6 +18,19 @@ Definitions (each side implements them from the publications):
     two independent standard normals: rho = sqrt(-2 ln u1),
     (z0, z1) = (rho cos 2 pi u2, rho sin 2 pi u2).
 
+The subsampled randomized Hadamard transform (SRHT) test matrix that the
+paper names as an alternative to the Gaussian one (Section 2, remark after
+Thm. 3; Halko, Martinsson and Tropp 2011, Sec. 4.6; Tropp 2011): for
+`rows` rows padded to p = 2^ceil(log2 rows), Omega = D H S / sqrt(k) with D
+a diagonal of random signs, H the p x p Walsh-Hadamard (Sylvester) matrix
+with entries (-1)^popcount(i & j), and S the selection of k distinct
+columns drawn uniformly; entry (i, c) = d_i (-1)^popcount(i & s_c) / sqrt(k).
+Randomness (a reading of its own): d_i = -1 when bit 0 of word x0 of the
+counter (0, i, matrix_id, 1) is set; s_c is drawn in order c = 0, 1, ...
+from the words x0 of the counters (c, t, matrix_id, 2), t = 0, 1, ...,
+masked to [0, p), the first value not taken by s_0..s_{c-1}; after 64
+taken draws, the first free index at or after the last draw (cyclically).
+
 The matrix recipe (a reading of its own, as the paper fixes no generator):
 entry (i, j) of test matrix `matrix_id` drawn with `seed` comes from the
 counter (j // 2, i, matrix_id, 0) under the key (seed mod 2^32, seed div
@@ -71,3 +84,40 @@ def gaussian_matrix(seed: int, matrix_id: int, rows: int, cols: int) -> np.ndarr
     th = TWO_PI * u2
     z = np.stack([rho * np.cos(th), rho * np.sin(th)], axis=1).reshape(rows, 2 * pairs)
     return np.ascontiguousarray(z[:, :cols])
+
+
+def _words0(seed: int, ctrs) -> np.ndarray:
+    x = philox4x32_10(np.asarray(ctrs, dtype=np.uint64).reshape(-1, 4), (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
+    return x[:, 0].astype(np.uint64)
+
+
+def srht_columns(seed: int, matrix_id: int, rows: int, cols: int) -> list:
+    """The k = cols distinct sampled Hadamard column indices s_c in [0, p)."""
+    p = 1
+    while p < rows:
+        p *= 2
+    taken = []
+    for c in range(cols):
+        v = None
+        for t in range(64):
+            cand = int(_words0(seed, [c, t, matrix_id, 2])[0]) & (p - 1)
+            if cand not in taken:
+                v = cand
+                break
+        if v is None:
+            v = cand
+            while v in taken:
+                v = (v + 1) % p
+        taken.append(v)
+    return taken
+
+
+def srht_matrix(seed: int, matrix_id: int, rows: int, cols: int) -> np.ndarray:
+    """rows x cols FP64 SRHT test matrix by the recipe above."""
+    s = np.array(srht_columns(seed, matrix_id, rows, cols), dtype=np.int64)
+    i = np.arange(rows, dtype=np.uint64)
+    ctr = np.stack([np.zeros_like(i), i, np.full_like(i, matrix_id), np.ones_like(i)], axis=1)
+    d = np.where(_words0(seed, ctr) & np.uint64(1), -1.0, 1.0)
+    bits = np.bitwise_and(np.arange(rows, dtype=np.int64)[:, None], s[None, :])
+    par = np.array([[bin(int(v)).count("1") & 1 for v in row] for row in bits], dtype=np.int64)
+    return d[:, None] * np.where(par == 1, -1.0, 1.0) / np.sqrt(cols)

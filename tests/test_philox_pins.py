@@ -1,4 +1,4 @@
-"""Pins of the host Gaussian test-matrix generator (oracle side).
+"""Pins of the host test-matrix generators (oracle side): Gaussian and SRHT.
 
 The generator is Philox4x32-10 (Salmon et al., SC'11) followed by the
 Box-Muller transform; the device implements the same definitions on its own.
@@ -9,6 +9,7 @@ CDF, independence of the pair members and of the streams).
 import os
 
 import numpy as np
+import pytest
 import scipy.stats
 
 from oracle import philox as P
@@ -78,3 +79,43 @@ def test_prefix_and_odd_widths_are_consistent():
     assert np.array_equal(P.gaussian_matrix(99, 3, 37, 11), full[:, :11])
     assert np.array_equal(P.gaussian_matrix(99, 3, 20, 12), full[:20])
     assert np.array_equal(P.gaussian_matrix(99, 3, 37, 12), full)
+
+
+# --------------------------------------------------------------------------
+# SRHT test matrices (Section 2, remark after Thm. 3)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rows,cols", [(64, 10), (100, 20), (257, 37), (5, 5)])
+def test_srht_is_signed_sampled_hadamard(rows, cols):
+    """Omega = D H[:rows, S] / sqrt(k) with H the Sylvester-Hadamard matrix
+    of the padded size (the library's construction), D = diag(+-1), S a
+    selection of distinct columns."""
+    import scipy.linalg
+    seed, mid = 1234567, 3
+    Om = P.srht_matrix(seed, mid, rows, cols)
+    p = 1
+    while p < rows:
+        p *= 2
+    S = P.srht_columns(seed, mid, rows, cols)
+    assert len(set(S)) == cols and all(0 <= s < p for s in S)
+    H = scipy.linalg.hadamard(p).astype(np.float64)
+    Hs = H[:rows][:, S] / np.sqrt(cols)
+    d = Om[:, 0] / Hs[:, 0]
+    assert set(np.unique(d)) <= {-1.0, 1.0}
+    assert np.array_equal(Om, d[:, None] * Hs)
+    assert np.all(np.abs(Om) == 1.0 / np.sqrt(cols))
+
+
+def test_srht_columns_are_orthogonal_for_power_of_two_rows():
+    """Distinct Hadamard columns are orthogonal: Omega^T Omega = (p / k) I."""
+    Om = P.srht_matrix(99, 0, 128, 24)
+    assert np.abs(Om.T @ Om - (128 / 24) * np.eye(24)).max() < 1e-13
+
+
+def test_srht_signs_and_samples_are_spread():
+    """Signs are balanced and the sampled columns cover the padded range."""
+    Om = P.srht_matrix(7, 1, 4096, 64)
+    assert abs(float(np.mean(np.sign(Om[:, 1])))) < 0.1
+    S = np.array(P.srht_columns(7, 1, 4096, 64))
+    assert S.min() < 512 and S.max() > 3584
+    assert len(set(S.tolist())) == 64
