@@ -111,6 +111,23 @@ cnmf_status cnmf_synchronize(cnmf_handle* h);
 cnmf_status cnmf_gaussian(cnmf_handle* h, uint64_t seed, int32_t matrix_id, int64_t rows, int32_t cols,
                           double* out_dev, int64_t ld);
 
+/* SRHT test matrix (Section 2, remark after Thm. 3: subsampled randomized
+ * Hadamard transform; Halko, Martinsson and Tropp 2011, Sec. 4.6), as the
+ * sketches draw it for test_matrix = CNMF_TEST_SRHT: out_dev (device,
+ * rows x cols FP64, ld >= cols) = D H S / sqrt(cols) with p =
+ * 2^ceil(log2 rows), D = diag(d_i) random signs, H the p x p Walsh-Hadamard
+ * (Sylvester) matrix with entries (-1)^popcount(i & j), S the selection of
+ * cols distinct columns s_c; entry (i, c) = d_i (-1)^popcount(i & s_c) /
+ * sqrt(cols).  Randomness from the same Philox4x32-10 as cnmf_gaussian:
+ * d_i = -1 when bit 0 of output word 0 of the counter (0, i, matrix_id, 1)
+ * is set; s_c (c = 0, 1, ...) is the first of the words 0 of the counters
+ * (c, t, matrix_id, 2), t = 0, 1, ..., masked to [0, p), not taken by an
+ * earlier column, and after 64 taken draws the first free index at or
+ * after the last draw (cyclically).  Errors: CNMF_EINVAL for a NULL
+ * pointer, rows < 1, cols outside [1, min(128, p)] or ld < cols. */
+cnmf_status cnmf_srht(cnmf_handle* h, uint64_t seed, int32_t matrix_id, int64_t rows, int32_t cols, double* out_dev,
+                      int64_t ld);
+
 /* ---------------------------------------------------------------------------
  * Input matrix A (Section 1, problem (nmf)): m x n, dtype CNMF_F64 or
  * CNMF_F32, in one of three formats:
@@ -181,7 +198,11 @@ typedef struct {
  * omega_left_dev:  n x k FP64, row-major (ld = k): test matrix for A, or
  *   NULL to draw it on the device (cnmf_gaussian matrix id 0 under seed).
  * omega_right_dev: m x k FP64, row-major (ld = k): test matrix for A^T
- *   (used when CNMF_RIGHT is set), or NULL to draw it (matrix id 1). */
+ *   (used when CNMF_RIGHT is set), or NULL to draw it (matrix id 1).
+ * test_matrix: the kind drawn for a NULL omega: CNMF_TEST_GAUSSIAN (0,
+ *   cnmf_gaussian) or CNMF_TEST_SRHT (1, cnmf_srht: the subsampled
+ *   randomized Hadamard transform Section 2 names as an alternative). */
+enum { CNMF_TEST_GAUSSIAN = 0, CNMF_TEST_SRHT = 1 };
 typedef struct {
   int32_t r, k, q, sides;
   cnmf_dtype pass_dtype;
@@ -189,6 +210,8 @@ typedef struct {
   uint64_t seed;
   const double* omega_left_dev;
   const double* omega_right_dev;
+  int32_t test_matrix;
+  int32_t reserved;
 } cnmf_sketch_desc;
 
 /* Sketch outputs.  Every pointer may be NULL (= not wanted).  Element type

@@ -16,6 +16,7 @@ CNMF_LEFT, CNMF_RIGHT, CNMF_BOTH = 1, 2, 3
 CNMF_ADMM, CNMF_MU, CNMF_ADMM_FULL, CNMF_MU_FULL, CNMF_ANLS, CNMF_ANLS_FULL = 0, 1, 2, 3, 4, 5
 CNMF_SERVER_GRAPHS, CNMF_SERVER_ONE_STEP = 1, 2
 CNMF_DENSE, CNMF_DENSE_HOST, CNMF_CSR = 0, 1, 2
+CNMF_TEST_GAUSSIAN, CNMF_TEST_SRHT = 0, 1
 
 STATUS_NAMES = {0: "CNMF_OK", -1: "CNMF_EINVAL", -2: "CNMF_ENOMEM", -3: "CNMF_EDEVICE",
                 -4: "CNMF_EBREAKDOWN", -5: "CNMF_ENOTSUP", -6: "CNMF_EBUSY"}
@@ -25,7 +26,7 @@ EXPORTED = [
     "cnmf_create", "cnmf_destroy", "cnmf_last_error", "cnmf_status_string", "cnmf_version",
     "cnmf_sketch", "cnmf_factorize", "snmf_select", "cnmf_spa", "cnmf_workspace_bytes",
     "cnmf_set_timing", "cnmf_stage_ms", "cnmf_range_product", "cnmf_stage_flops", "cnmf_stage_launches",
-    "cnmf_range_product_lowp", "cnmf_synchronize", "cnmf_gaussian", "cnmf_spa_noalloc", "snmf_nnls",
+    "cnmf_range_product_lowp", "cnmf_synchronize", "cnmf_gaussian", "cnmf_srht", "cnmf_spa_noalloc", "snmf_nnls",
     "cnmf_server_start", "cnmf_server_submit", "cnmf_server_poll", "cnmf_server_release",
     "cnmf_server_get_stats", "cnmf_server_stop", "cnmf_server_last_error", "cnmf_server_simulate",
 ]
@@ -40,7 +41,8 @@ class cnmf_input(C.Structure):
 class cnmf_sketch_desc(C.Structure):
     _fields_ = [("r", C.c_int32), ("k", C.c_int32), ("q", C.c_int32), ("sides", C.c_int32),
                 ("pass_dtype", C.c_int), ("final_dtype", C.c_int), ("seed", C.c_uint64),
-                ("omega_left_dev", C.c_void_p), ("omega_right_dev", C.c_void_p)]
+                ("omega_left_dev", C.c_void_p), ("omega_right_dev", C.c_void_p), ("test_matrix", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class cnmf_sketch_out(C.Structure):
@@ -111,6 +113,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.cnmf_synchronize.restype = st
     lib.cnmf_gaussian.argtypes = [vp, C.c_uint64, i32, i64, i32, vp, i64]
     lib.cnmf_gaussian.restype = st
+    lib.cnmf_srht.argtypes = [vp, C.c_uint64, i32, i64, i32, vp, i64]
+    lib.cnmf_srht.restype = st
     lib.cnmf_sketch.argtypes = [vp, C.POINTER(cnmf_input), C.POINTER(cnmf_sketch_desc), C.POINTER(cnmf_sketch_out)]
     lib.cnmf_sketch.restype = st
     lib.cnmf_factorize.argtypes = [vp, C.POINTER(cnmf_input), C.POINTER(cnmf_factorize_desc),

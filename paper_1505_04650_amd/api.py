@@ -118,10 +118,13 @@ def _after(A, h):
         h.stream.synchronize()
 
 
-def _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype, seed=0):
+_TEST = {"gaussian": L.CNMF_TEST_GAUSSIAN, "srht": L.CNMF_TEST_SRHT}
+
+
+def _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype, seed=0, test_matrix="gaussian"):
     return L.cnmf_sketch_desc(int(r), int(k), int(q), _SIDES[sides] if isinstance(sides, str) else int(sides),
                               _PREC[pass_dtype], _PREC[final_dtype], int(seed) & (2 ** 64 - 1),
-                              _ptr(omega_left), _ptr(omega_right))
+                              _ptr(omega_left), _ptr(omega_right), _TEST[test_matrix], 0)
 
 
 def _acc_dtype(A, pass_dtype):
@@ -147,7 +150,7 @@ class Sketch:
 
 
 def sketch(A, r, k, q, omega_left=None, omega_right=None, sides="both", pass_dtype=None, final_dtype=None,
-           want_ac=False, seed=0, block_rows=0, handle: Handle | None = None) -> Sketch:
+           want_ac=False, seed=0, block_rows=0, test_matrix="gaussian", handle: Handle | None = None) -> Sketch:
     """Structured random compression (Alg. 1) of A on one or both sides, and
     the small sketches B = L^T A, At = L^T A R^T, Ac = A R^T.  A test matrix
     left as None is drawn on the device from `seed` (see gaussian())."""
@@ -165,7 +168,7 @@ def sketch(A, r, k, q, omega_left=None, omega_right=None, sides="both", pass_dty
     Act = torch.empty((m, k), dtype=od, device=dev) if (right and want_ac) else None
     stats = torch.zeros(4, dtype=torch.float64, device=dev)
     inp = _input(A, block_rows)
-    d = _sketch_desc(r, k, q, sd, omega_left, omega_right, pass_dtype, final_dtype, seed)
+    d = _sketch_desc(r, k, q, sd, omega_left, omega_right, pass_dtype, final_dtype, seed, test_matrix)
     out = L.cnmf_sketch_out(_ptr(Lt), _ptr(Rt), _ptr(Bt), _ptr(Att), _ptr(Act), _ptr(stats))
     L.check(h._lib.cnmf_sketch(h.raw, C.byref(inp), C.byref(d), C.byref(out)), h.raw)
     _after(A, h)
@@ -182,7 +185,8 @@ class Factorization:
 
 def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="admm", iters=100,
               lam=1.0, phi=None, xi=1.0, mu_eps=1e-16, pass_dtype=None, final_dtype=None,
-              want_sketch=False, seed=0, block_rows=0, handle: Handle | None = None) -> Factorization:
+              want_sketch=False, seed=0, block_rows=0, test_matrix="gaussian",
+              handle: Handle | None = None) -> Factorization:
     """Compressed NMF: two-sided sketch, then ADMM (Alg. 3), MU (Alg. 2) or
     alternating NNLS (Section 3, Eq. alternateLS_nmf_compressed) on the
     compressed factors, then the FP64 relative residual.  The *_full methods
@@ -208,7 +212,7 @@ def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="adm
     V0 = V0.to(device=dev, dtype=torch.float64).contiguous()
     inp = _input(A, block_rows)
     d = L.cnmf_factorize_desc(_sketch_desc(r, k, q, L.CNMF_BOTH, omega_left, omega_right, pass_dtype, final_dtype,
-                                           seed),
+                                           seed, test_matrix),
                               _METHODS[method], int(iters), float(lam), float(lam if phi is None else phi),
                               float(xi), float(mu_eps), _ptr(U0), _ptr(V0))
     out = L.cnmf_factorize_out(_ptr(U), _ptr(V), _ptr(res), so)
@@ -218,7 +222,8 @@ def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="adm
 
 
 def select(A, r, k, q, omega_left=None, omega_right=None, sides="left", pass_dtype=None, final_dtype=None,
-           want_scores=False, want_B=False, seed=0, block_rows=0, handle: Handle | None = None):
+           want_scores=False, want_B=False, seed=0, block_rows=0, test_matrix="gaussian",
+           handle: Handle | None = None):
     """Compressed separable NMF column selection (Alg. SNMF steps 1-2): the
     sketch, B = Q^T A, and SPA on B.  Returns int64 indices (device)."""
     h = handle or default_handle()
@@ -228,7 +233,7 @@ def select(A, r, k, q, omega_left=None, omega_right=None, sides="left", pass_dty
     score = torch.empty(r, dtype=torch.float64, device=dev) if want_scores else None
     B = torch.empty((k, A.shape[1]), dtype=_acc_dtype(A, pass_dtype), device=dev) if want_B else None
     inp = _input(A, block_rows)
-    d = _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype, seed)
+    d = _sketch_desc(r, k, q, sides, omega_left, omega_right, pass_dtype, final_dtype, seed, test_matrix)
     L.check(h._lib.snmf_select(h.raw, C.byref(inp), C.byref(d), _ptr(K), _ptr(score), _ptr(B)), h.raw)
     _after(A, h)
     return K, score, B
@@ -266,6 +271,17 @@ def gaussian(rows, cols, seed, matrix_id=0, device=None, handle: Handle | None =
     out = torch.empty((rows, cols), dtype=torch.float64, device=dev)
     L.check(h._lib.cnmf_gaussian(h.raw, int(seed) & (2 ** 64 - 1), int(matrix_id), int(rows), int(cols), _ptr(out),
                                  max(int(cols), 1)), h.raw)
+    return out
+
+
+def srht(rows, cols, seed, matrix_id=0, device=None, handle: Handle | None = None):
+    """The library's SRHT test matrix `matrix_id` under `seed` (rows x cols
+    FP64 on the device), as a sketch with test_matrix="srht" draws it."""
+    h = handle or default_handle()
+    dev = h.device if device is None else torch.device(device)
+    out = torch.empty((rows, cols), dtype=torch.float64, device=dev)
+    L.check(h._lib.cnmf_srht(h.raw, int(seed) & (2 ** 64 - 1), int(matrix_id), int(rows), int(cols), _ptr(out),
+                             max(int(cols), 1)), h.raw)
     return out
 
 

@@ -111,6 +111,10 @@ constexpr uint32_t kCompletionId0 = 16;
 // out (rows x cols, ld) = Gaussian test matrix `id` under `seed` (rng.hpp).
 hipError_t launch_gaussian_fill(double* out, int64_t ld, int rows, int cols, uint64_t seed, uint32_t id,
                                 hipStream_t st);
+// SRHT test matrix (k_rng.hip): rows x cols (cols <= 128) into out (ld);
+// S receives the cols sampled Hadamard column indices (device, 128 ints).
+hipError_t launch_srht_fill(double* out, int64_t ld, int rows, int cols, uint64_t seed, uint32_t id, int32_t* S,
+                            hipStream_t st);
 // max |Q^T Q - I| for an FP64 Gram (for stats)
 hipError_t launch_orth_error(const double* G, int kh, double* out, hipStream_t st);
 

@@ -226,6 +226,8 @@ cnmf_status check_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_
   if (d->q < 0) return fail(h, CNMF_EINVAL, "q must be >= 0");
   if (d->q > 64) return fail(h, CNMF_EINVAL, "q=%d is unreasonably large (max 64)", d->q);
   if (d->sides < 1 || d->sides > 3) return fail(h, CNMF_EINVAL, "sides must be CNMF_LEFT, CNMF_RIGHT or CNMF_BOTH");
+  if (d->test_matrix != CNMF_TEST_GAUSSIAN && d->test_matrix != CNMF_TEST_SRHT)
+    return fail(h, CNMF_EINVAL, "unknown test_matrix %d", d->test_matrix);
   if (A->dtype == CNMF_F64) {
     if (d->pass_dtype != CNMF_F64 || d->final_dtype != CNMF_F64)
       return fail(h, CNMF_EINVAL, "an F64 input runs with pass_dtype = final_dtype = CNMF_F64");
@@ -267,6 +269,7 @@ struct SketchWs {
   uint64_t* mask = nullptr;    // decoupled columns of the first CholeskyQR pass (2 words per half)
   double* OmL = nullptr;       // n x k Omega_L drawn on the device (seeded sketches)
   double* OmR = nullptr;       // m x k Omega_R
+  int32_t* srht_s = nullptr;   // sampled Hadamard columns of the SRHT test matrices (2 x 128)
   T* Lb = nullptr;      // m x k
   T* RTb = nullptr;     // n x k  (R^T)
   T* BTb = nullptr;     // n x k  (B^T)
@@ -336,6 +339,7 @@ void layout_sketch(Arena& a, SketchWs<T>& w, int64_t m, int64_t n, int k, const 
   w.mask = a.take<uint64_t>(4);
   if ((d->sides & CNMF_LEFT) && !d->omega_left_dev) w.OmL = a.take<double>((size_t)n * k);
   if ((d->sides & CNMF_RIGHT) && !d->omega_right_dev) w.OmR = a.take<double>((size_t)m * k);
+  w.srht_s = a.take<int32_t>(256);
   w.Lb = a.take<T>((size_t)m * k);
   w.RTb = a.take<T>((size_t)n * k);
   w.BTb = a.take<T>((size_t)n * k);
@@ -855,12 +859,19 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
   // the caller gives none
   const double* omL = d->omega_left_dev;
   const double* omR = d->omega_right_dev;
+  const bool srht = d->test_matrix == CNMF_TEST_SRHT;
   if (w.OmL) {
-    HIPCHK(h, launch_gaussian_fill(w.OmL, k, n, k, d->seed, kOmegaLeftId, st));
+    if (srht)
+      HIPCHK(h, launch_srht_fill(w.OmL, k, n, k, d->seed, kOmegaLeftId, w.srht_s, st));
+    else
+      HIPCHK(h, launch_gaussian_fill(w.OmL, k, n, k, d->seed, kOmegaLeftId, st));
     omL = w.OmL;
   }
   if (w.OmR) {
-    HIPCHK(h, launch_gaussian_fill(w.OmR, k, m, k, d->seed, kOmegaRightId, st));
+    if (srht)
+      HIPCHK(h, launch_srht_fill(w.OmR, k, m, k, d->seed, kOmegaRightId, w.srht_s + 128, st));
+    else
+      HIPCHK(h, launch_gaussian_fill(w.OmR, k, m, k, d->seed, kOmegaRightId, st));
     omR = w.OmR;
   }
   // stage the first operands (Omegas) of the chains
@@ -1613,6 +1624,24 @@ cnmf_status cnmf_gaussian(cnmf_handle* h, uint64_t seed, int32_t matrix_id, int6
   if (matrix_id < 0) return fail(h, CNMF_EINVAL, "matrix_id must be >= 0");
   HIPCHK(h, hipSetDevice(h->device));
   HIPCHK(h, launch_gaussian_fill(out_dev, ld, (int)rows, cols, seed, (uint32_t)matrix_id, h->stream));
+  return CNMF_OK;
+}
+
+cnmf_status cnmf_srht(cnmf_handle* h, uint64_t seed, int32_t matrix_id, int64_t rows, int32_t cols, double* out_dev,
+                      int64_t ld) {
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  if (!out_dev) return fail(h, CNMF_EINVAL, "out_dev is NULL");
+  if (rows < 1 || rows > INT32_MAX / 2) return fail(h, CNMF_EINVAL, "rows=%lld must be in [1, 2^30]", (long long)rows);
+  int64_t p = 1;
+  while (p < rows) p <<= 1;
+  if (cols < 1 || cols > 128 || cols > p || ld < cols)
+    return fail(h, CNMF_EINVAL, "cols=%d must be in [1, min(128, %lld)] and <= ld=%lld", cols, (long long)p,
+                (long long)ld);
+  if (matrix_id < 0) return fail(h, CNMF_EINVAL, "matrix_id must be >= 0");
+  HIPCHK(h, hipSetDevice(h->device));
+  cnmf_status s = ensure_ws(h, 128 * sizeof(int32_t));
+  if (s != CNMF_OK) return s;
+  HIPCHK(h, launch_srht_fill(out_dev, ld, (int)rows, cols, seed, (uint32_t)matrix_id, (int32_t*)h->ws, h->stream));
   return CNMF_OK;
 }
 

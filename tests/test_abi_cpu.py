@@ -239,3 +239,14 @@ def test_input_format_checks(lib):
     d.final_dtype = L.CNMF_BF16
     assert lib.cnmf_sketch(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_ENOTSUP
     assert b"dense on the device" in lib.cnmf_last_error(None)
+
+
+def test_test_matrix_kind_checks(lib):
+    out = L.cnmf_sketch_out()
+    d = _desc().sk
+    d.test_matrix = 5
+    A = L.cnmf_input(C.c_void_p(16), L.CNMF_F32, 2000, 1000, 1000)
+    assert lib.cnmf_sketch(None, C.byref(A), C.byref(d), C.byref(out)) == L.CNMF_EINVAL
+    assert b"test_matrix" in lib.cnmf_last_error(None)
+    assert lib.cnmf_srht(None, 1, 0, 100, 10, C.c_void_p(16), 10) == L.CNMF_EINVAL
+    assert b"handle" in lib.cnmf_last_error(None)

@@ -214,3 +214,46 @@ def test_spa_exact_ties_take_lowest_index(dtype):
     Kref = O.spa(Bq, 5)
     assert Kref[:4] == [900, 2500, 77, 1500]
     assert Kg == Kref
+
+
+# --------------------------------------------------------------------------
+# SRHT test matrices (Section 2, remark after Thm. 3)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,mid,rows,cols", [(0, 0, 1000, 20), (0xDEADBEEF12345678, 1, 777, 61),
+                                                (5, 2, 128, 128), (9, 3, 5, 5), (31, 0, 100000, 30)])
+def test_srht_matches_host_generator(seed, mid, rows, cols):
+    """Bit for bit: signs, sampled columns (including the probing after 64
+    taken draws when every column of a small Hadamard matrix is sampled)
+    and the scale 1 / sqrt(cols)."""
+    got = host(api.srht(rows, cols, seed, mid))
+    ref = P.srht_matrix(seed, mid, rows, cols)
+    assert np.array_equal(got, ref)
+
+
+def test_srht_sketch_matches_oracle():
+    w = WL.WORKLOADS["plain_fp64_1000x500"]
+    A = WL.make_inputs(w)["A"]
+    m, n = A.shape
+    seed = 4242
+    out = api.sketch(dev(A), w.r, w.k, w.q, None, None, want_ac=True, seed=seed, test_matrix="srht")
+    ref = O.sketch(A, P.srht_matrix(seed, 0, n, w.k), P.srht_matrix(seed, 1, m, w.k), w.q)
+    for name in ("L", "R", "B", "At", "Ac"):
+        got = host(getattr(out, name))
+        assert rel(got, ref[name]) < 1e-10, name
+    assert host(out.stats)[3] == 0
+
+
+@pytest.mark.parametrize("q", [0, 2])
+def test_srht_sketch_captures_the_range_like_gaussian(q):
+    """Same projection error as the Gaussian test matrix to a few percent
+    (20000 x 5000 recipe at reduced size, FP32)."""
+    w = WL.WORKLOADS["nmf_fp32_20000x5000"]
+    A = WL.make_inputs(w, m=4000, n=3000)["A"]
+    Ad = dev(A, torch.float32)
+    A64 = A.astype(np.float64)
+    res = {}
+    for kind in ("gaussian", "srht"):
+        Lg = host(api.sketch(Ad, w.r, w.k, q, None, None, sides="left", seed=77, test_matrix=kind).L)
+        res[kind] = np.linalg.norm(A64 - Lg @ (Lg.T @ A64)) / np.linalg.norm(A64)
+    assert res["srht"] <= 1.05 * res["gaussian"]
