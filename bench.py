@@ -373,6 +373,105 @@ def extra_workloads_section(h, lam_c2, inp_c2, w_c2):
         f"{out['separable_fp32_10000x100000']['K_equals_planted_set']}")
     del As, Bsk, Hn
     torch.cuda.empty_cache()
+    out.update(input_formats_section(h, inp_c2, w_c2))
+    return out
+
+
+def _timed(h, fn, reps=3):
+    """Median wall time (ms) of fn() with the device synchronised around it."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts)), fn
+
+
+def input_formats_section(h, inp_c2, w_c2):
+    """The other input forms and test matrices, measured beside the dense
+    device-resident path:
+    * 20000 x 5000 FP32 in pinned host memory, streamed through the device
+      (two-sided sketch, q 4: 10 passes over A);
+    * SRHT instead of Gaussian test matrices on the same sketch;
+    * a sparse A from the paper's sparse recipe (W, H with density 0.01, N
+      with density 1e-4; n = 0.75 m), 40000 x 30000, r 50, as CSR: sketch
+      and 100 compressed ADMM iterations."""
+    import torch
+    from paper_1505_04650_amd import api
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.as_tensor(x, dtype=torch.float64, device=dev)
+    out = {}
+    w = w_c2
+    A = torch.as_tensor(inp_c2["A"])
+    Ah = A.pin_memory()
+    Ad = A.to(dev)
+    oml, omr = t(inp_c2["Omega_L"]), t(inp_c2["Omega_R"])
+    npass = 2 * w.q + 2
+    ms_dev, _ = _timed(h, lambda: api.sketch(Ad, w.r, w.k, w.q, oml, omr, handle=h))
+    ms_host, _ = _timed(h, lambda: api.sketch(Ah, w.r, w.k, w.q, oml, omr, handle=h))
+    Lh = api.sketch(Ah, w.r, w.k, w.q, oml, omr, handle=h).L
+    Ld = api.sketch(Ad, w.r, w.k, w.q, oml, omr, handle=h).L
+    A64 = Ad.double()
+    nA = float(torch.linalg.norm(A64))
+    pr = lambda L_: float(torch.linalg.norm(A64 - L_.double() @ (L_.double().T @ A64))) / nA
+    out["host_streamed_fp32_20000x5000"] = {
+        "sketch_ms": ms_host, "device_resident_sketch_ms": ms_dev, "passes": npass,
+        "block_rows": int(max(64, (64 << 20) // (w.n * 4) // 64 * 64)),
+        "host_to_device_GBps": npass * w.m * w.n * 4 / (ms_host * 1e-3) / 1e9,
+        "proj_residual": pr(Lh), "proj_residual_device_path": pr(Ld)}
+    log(f"host-streamed 20000x5000 sketch: {ms_host:.1f} ms ({out['host_streamed_fp32_20000x5000']['host_to_device_GBps']:.1f}"
+        f" GB/s of A), device-resident {ms_dev:.2f} ms")
+    ms_srht, _ = _timed(h, lambda: api.sketch(Ad, w.r, w.k, w.q, seed=5, test_matrix="srht", handle=h))
+    ms_gauss, _ = _timed(h, lambda: api.sketch(Ad, w.r, w.k, w.q, seed=5, handle=h))
+    Ls = api.sketch(Ad, w.r, w.k, w.q, seed=5, test_matrix="srht", handle=h).L
+    Lg = api.sketch(Ad, w.r, w.k, w.q, seed=5, handle=h).L
+    out["srht_vs_gaussian_fp32_20000x5000"] = {
+        "sketch_ms_srht": ms_srht, "sketch_ms_gaussian": ms_gauss,
+        "proj_residual_srht": pr(Ls), "proj_residual_gaussian": pr(Lg)}
+    del Ah, Ad, A64, Lh, Ld, Ls, Lg
+    torch.cuda.empty_cache()
+    # sparse recipe on the device
+    m, n, r, k, delta = 40000, 30000, 50, 60, 0.01
+    g = torch.Generator(device=dev)
+    g.manual_seed(7000)
+    W = torch.rand(m, r, device=dev, generator=g) * (torch.rand(m, r, device=dev, generator=g) < delta)
+    H = torch.rand(r, n, device=dev, generator=g) * (torch.rand(r, n, device=dev, generator=g) < delta)
+    Ad = W @ H
+    Ad += torch.randn(m, n, device=dev, generator=g) * (torch.rand(m, n, device=dev, generator=g) < delta * delta)
+    As = Ad.to_sparse_csr()
+    nnz = int(As.values().numel())
+    # the initialisation and penalties of the dense workloads: c U[0,1)
+    # factors with E[U V] = mean(A), lambda = phi = sigma_r(At)
+    c = math.sqrt(4.0 * max(float(Ad.mean()), 1e-12) / r)
+    U0 = c * torch.rand(m, r, device=dev, dtype=torch.float64, generator=g)
+    V0 = c * torch.rand(r, n, device=dev, dtype=torch.float64, generator=g)
+    ms_sk, _ = _timed(h, lambda: api.sketch(As, r, k, 4, seed=9, handle=h))
+    lam = float(torch.linalg.svdvals(api.sketch(As, r, k, 4, seed=9, handle=h).At.double())[r - 1])
+    f = None
+
+    def fz():
+        nonlocal f
+        f = api.factorize(As, r, k, 4, U0, V0, None, None, iters=100, lam=lam, phi=lam, seed=9, handle=h)
+    ms_f, _ = _timed(h, fz)
+    res_sparse = float(f.rel_residual.item())
+    # the same factors against the dense copy (FP64 on the device): the
+    # sparse residual formula must agree
+    Ud, Vd = f.U.double(), f.V.double()
+    A64 = Ad.double()
+    res_dense = float(torch.linalg.norm(A64 - Ud @ Vd) / torch.linalg.norm(A64))
+    out["sparse_fp32_40000x30000"] = {
+        "recipe": "W, H density 0.01, N density 1e-4 (the paper's sparse synthetic case), n = 0.75 m",
+        "nnz": nnz, "density": nnz / (m * n), "r": r, "k": k, "q": 4,
+        "sketch_ms": ms_sk, "factorize_ms_100_admm_iterations": ms_f, "lambda": lam,
+        "rel_residual": res_sparse, "rel_residual_dense_check": res_dense}
+    log(f"sparse 40000x30000 ({nnz} nonzeros): sketch {ms_sk:.2f} ms, factorize {ms_f:.2f} ms, residual "
+        f"{res_sparse:.6f} (dense check {res_dense:.6f})")
+    del W, H, Ad, As, A64, f
+    torch.cuda.empty_cache()
     return out
 
 
