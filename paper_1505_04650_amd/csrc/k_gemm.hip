@@ -64,10 +64,26 @@ __device__ __forceinline__ void load_run(const T* __restrict__ p, int col, int k
 // holds columns [g*G, g*G + G) of its rows (a permutation of the MFMA K
 // index that both operands share, so the contraction is unchanged).
 // ---------------------------------------------------------------------------
+// Tile and split of this workgroup (1-D grid of ntiles * nsplits).  The
+// hardware hands workgroups to the 8 XCDs round-robin by id, so consecutive
+// ids run on different XCDs, each with its own L2.  The ids are renumbered so
+// that every XCD takes one contiguous run of (tile, split) pairs, tiles
+// fastest: the workgroups that read the same split's slice of the operand
+// then run on the same XCD and share it in that L2.  Any numbering computes
+// the same tiles; only the cache reuse changes.
+__device__ __forceinline__ void xcd_tile(int ntiles, int nsplits, int& tile, int& split) {
+  const int nb = ntiles * nsplits, b = blockIdx.x;
+  const int q = nb / 8, rem = nb % 8, x = b % 8, slot = b / 8;
+  const int lid = x * q + min(x, rem) + slot;
+  tile = lid % ntiles;
+  split = lid / ntiles;
+}
+
 template <typename T, int KB, int RB, bool VEC>
 __global__ __launch_bounds__(256, 2) void gemm_n_kernel(const T* __restrict__ A, int64_t lda, int m,
                                                         int n, const T* __restrict__ X,
-                                                        T* __restrict__ P, int cols_per_split) {
+                                                        T* __restrict__ P, int cols_per_split, int ntiles,
+                                                        int nsplits) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int KC = sizeof(T) == 4 ? 64 : 32;
   constexpr int G = KC / 4;
@@ -81,11 +97,12 @@ __global__ __launch_bounds__(256, 2) void gemm_n_kernel(const T* __restrict__ A,
   const int w = tid >> 6;
   const int r = lane & 15;
   const int g = lane >> 4;
-  const int split = blockIdx.y;
+  int tile, split;
+  xcd_tile(ntiles, nsplits, tile, split);
   const int kbeg = split * cols_per_split;
   const int kend = min(n, kbeg + cols_per_split);
   const int nchunk = kend > kbeg ? (kend - kbeg + KC - 1) / KC : 0;
-  const int row_base = blockIdx.x * (64 * RB) + w * 16 * RB;
+  const int row_base = tile * (64 * RB) + w * 16 * RB;
 
   const T* arow[RB];
   bool rok[RB];
@@ -185,7 +202,8 @@ __global__ __launch_bounds__(256, 2) void gemm_n_kernel(const T* __restrict__ A,
 template <typename T, int KB, int VW, bool VEC>
 __global__ __launch_bounds__(256, 2) void gemm_t_kernel(const T* __restrict__ A, int64_t lda, int m,
                                                         int n, const T* __restrict__ Z,
-                                                        T* __restrict__ P, int rows_per_split) {
+                                                        T* __restrict__ P, int rows_per_split, int ntiles,
+                                                        int nsplits) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int KC = 32;
   constexpr int G = KC / 4;
@@ -200,11 +218,12 @@ __global__ __launch_bounds__(256, 2) void gemm_t_kernel(const T* __restrict__ A,
   const int w = tid >> 6;
   const int r = lane & 15;
   const int g = lane >> 4;
-  const int split = blockIdx.y;
+  int tile, split;
+  xcd_tile(ntiles, nsplits, tile, split);
   const int ibeg = split * rows_per_split;
   const int iend = min(m, ibeg + rows_per_split);
   const int nchunk = iend > ibeg ? (iend - ibeg + KC - 1) / KC : 0;
-  const int colw = blockIdx.x * (4 * CW) + w * CW;
+  const int colw = tile * (4 * CW) + w * CW;
   const int mycol = colw + VW * r;
   const bool vec_ok = VEC && (mycol + VW <= n);
 
@@ -370,12 +389,15 @@ static hipError_t gemm_n_kb(const T* A, int64_t lda, int m, int n, const T* X, T
   constexpr int KC = sizeof(T) == 4 ? 64 : 32;
   int per = (n + splits - 1) / splits;
   per = (per + KC - 1) / KC * KC;
-  dim3 grid((m + 64 * RB - 1) / (64 * RB), splits);
+  const int ntiles = (m + 64 * RB - 1) / (64 * RB);
+  dim3 grid(ntiles * splits);
   bool vec = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(T)) % 16 == 0);
   if (vec)
-    hipLaunchKernelGGL((gemm_n_kernel<T, KB, RB, true>), grid, dim3(256), 0, st, A, lda, m, n, X, P, per);
+    hipLaunchKernelGGL((gemm_n_kernel<T, KB, RB, true>), grid, dim3(256), 0, st, A, lda, m, n, X, P, per, ntiles,
+                       splits);
   else
-    hipLaunchKernelGGL((gemm_n_kernel<T, KB, RB, false>), grid, dim3(256), 0, st, A, lda, m, n, X, P, per);
+    hipLaunchKernelGGL((gemm_n_kernel<T, KB, RB, false>), grid, dim3(256), 0, st, A, lda, m, n, X, P, per, ntiles,
+                       splits);
   CNMF_LAUNCH_CHECK();
 }
 
@@ -402,12 +424,15 @@ static hipError_t gemm_t_kb(const T* A, int64_t lda, int m, int n, const T* Z, T
   constexpr int KC = 32;
   int per = (m + splits - 1) / splits;
   per = (per + KC - 1) / KC * KC;
-  dim3 grid((n + 64 * VW - 1) / (64 * VW), splits);
+  const int ntiles = (n + 64 * VW - 1) / (64 * VW);
+  dim3 grid(ntiles * splits);
   bool vec = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(T)) % 16 == 0);
   if (vec)
-    hipLaunchKernelGGL((gemm_t_kernel<T, KB, VW, true>), grid, dim3(256), 0, st, A, lda, m, n, Z, P, per);
+    hipLaunchKernelGGL((gemm_t_kernel<T, KB, VW, true>), grid, dim3(256), 0, st, A, lda, m, n, Z, P, per, ntiles,
+                       splits);
   else
-    hipLaunchKernelGGL((gemm_t_kernel<T, KB, VW, false>), grid, dim3(256), 0, st, A, lda, m, n, Z, P, per);
+    hipLaunchKernelGGL((gemm_t_kernel<T, KB, VW, false>), grid, dim3(256), 0, st, A, lda, m, n, Z, P, per, ntiles,
+                       splits);
   CNMF_LAUNCH_CHECK();
 }
 

@@ -110,16 +110,37 @@ __global__ __launch_bounds__(256) void csr_spmm_kernel(const int64_t* __restrict
 #pragma unroll
     for (int j = 0; j < NC; ++j) acc[j] = (T)0;
     const int64_t p0 = max((int64_t)0, rowptr[i]), p1 = min(nnz, rowptr[i + 1]);
-    for (int64_t p = p0; p < p1; ++p) {
-      const int c = col[p];
-      if (c < 0 || c >= cols) continue;
-      const T a = val[p];
-      const T* x = X + (int64_t)c * kk;
+    // eight nonzeros at a time: their indices and values first, then the
+    // operand rows, so that the gathers of a group are in flight together
+    // (the order of the additions is still p0, p0 + 1, ...)
+    constexpr int G = 8;
+    for (int64_t q = p0; q < p1; q += G) {
+      int cg[G];
+      T ag[G];
+      bool okg[G];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const int cc = lane + 64 * j;
-        if (cc < kk) acc[j] = fma(a, x[cc], acc[j]);
+      for (int u = 0; u < G; ++u) {
+        const bool in = q + u < p1;
+        const int c = in ? col[q + u] : -1;
+        okg[u] = c >= 0 && c < cols;
+        cg[u] = okg[u] ? c : 0;
+        ag[u] = okg[u] ? val[q + u] : (T)0;
       }
+      T xg[G][NC];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const T* x = X + (int64_t)cg[u] * kk;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const int cc = lane + 64 * j;
+          xg[u][j] = cc < kk ? x[cc] : (T)0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+        if (okg[u])   // the same for every lane: col and the bounds are wave-uniform
+#pragma unroll
+          for (int j = 0; j < NC; ++j) acc[j] = fma(ag[u], xg[u][j], acc[j]);
     }
     T* y = Y + (int64_t)i * kk;
 #pragma unroll
