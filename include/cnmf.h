@@ -246,10 +246,11 @@ cnmf_status cnmf_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_d
  * "Initialize"), row-major, required.  CNMF_ANLS / CNMF_ANLS_FULL minimise
  * every half-step to the end (each row of U against (V R^T)^T, each column
  * of V against L^T U, as nonnegative least-squares problems solved on their
- * normal equations in FP64 by an active-set method); the iterates depend on
- * V0 only (U0 is the warm start of the first half-step's active sets).  A
- * problem that needs more than 3 r active-set steps keeps its last feasible
- * value and is counted: cnmf_synchronize then returns CNMF_EBREAKDOWN.
+ * normal equations in FP64 by block principal pivoting, an active-set
+ * method); the iterates depend on V0 only (U0 gives the first half-step's
+ * starting active sets).  A problem that needs more than 5 r exchanges, or
+ * whose free system breaks down, keeps its last iterate clamped at 0 and is
+ * counted: cnmf_synchronize then returns CNMF_EBREAKDOWN.
  * Limits: r <= 64 (CNMF_ENOTSUP
  * otherwise); CNMF_ADMM solves its two r x r systems per iteration in one
  * workgroup whose LDS must hold three k x r FP64 blocks and the r x r

@@ -230,7 +230,8 @@ struct RowArgs {
 template <typename T>
 hipError_t launch_nmf_row(const RowArgs& a, int blocks, hipStream_t st);
 // mode 0: G = C^T C (C = S, k x r) -> G+, G-; mode 1: G = S (r x r) -> G+, G-;
-// mode 2: Gp = (S + pen I)^-1 (S the r x r Gram); mode 3: Gp = S^T S (C = S, k x r).
+// mode 2: Gp = (S + pen I)^-1 (S the r x r Gram); mode 3: Gp = S^T S (C = S, k x r);
+// mode 4: Gp = S^-1 and *flags = 1 if max |S Gp - I| <= 1e-8 (else 0).
 hipError_t launch_nmf_small(const double* S, int k, int r, int mode, double pen, double* Gp, double* Gm, int* flags,
                             hipStream_t st);
 
@@ -286,14 +287,20 @@ hipError_t launch_flags_to_stats(const int* flags, int nflags, double* out, hipS
 //   F[i] = argmin_{h >= 0} 1/2 h^T G h - c^T h,
 //   c = C^T B1[i] (C k1 x r, FP64) or c = B1[i] (C == nullptr; ld ldb1),
 // G (r x r, FP64) shared; the new rows are also copied to Op (ld ldop) when
-// it is set.  info[0] += rows that needed more than 3 r steps, info[1] =
-// max(info[1], steps).
+// it is set.  With H = G^-1 (checked, *hok), a free system with fewer bound
+// than free variables is solved through H (the Schur complement of the
+// bound block) instead of G.  Block principal pivoting from the support of
+// the current row;
+// info[0] += rows that needed more than 5 r exchanges (or broke down),
+// info[1] = max(info[1], exchanges).
 struct AnlsArgs {
   int rows, r, k1;
   const void* B1;
   int64_t ldb1;
   const double* C;
   const double* G;
+  const double* H;     // G^-1 (r x r) or nullptr; used when *hok != 0
+  const int* hok;
   void* F;
   int64_t ldf;
   void* Op;

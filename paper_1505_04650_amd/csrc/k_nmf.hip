@@ -257,6 +257,8 @@ __global__ __launch_bounds__(kSmallNT) void nmf_small_kernel(const double* __res
     return;
   }
   // mode 2: Minv = (S + pen I)^-1 via the blocked Cholesky, then X = I X M^-1
+  // (mode 4: the same with pen = 0, then *flags = 1 when the inverse checks
+  // out, max |S X - I| <= 1e-8 with no floored pivot, else 0)
   const int NB = (r + 15) / 16, N = 16 * NB, ld = N + 1;
   double* M = sm;              // N x ld
   double* TI = M + N * ld;     // NB x 272
@@ -273,18 +275,39 @@ __global__ __launch_bounds__(kSmallNT) void nmf_small_kernel(const double* __res
   __syncthreads();
   double mx = 0.0;
   for (int i = 0; i < r; ++i) mx = fmax(mx, M[i * ld + i]);
-  wg_chol_blocked<kSmallNT>(M, ld, NB, TI, PN, 1e-300 * mx, flags);
+  __shared__ int floored;
+  if (tid == 0) floored = 0;
+  __syncthreads();
+  wg_chol_blocked<kSmallNT>(M, ld, NB, TI, PN, 1e-300 * mx, mode == 4 ? &floored : flags);
   wg_right_solve_blocked<kSmallNT>(X, N, ld, NB, M, ld, TI, R);
   for (int e = tid; e < r * r; e += kSmallNT) {
     const int i = e / r, j = e - i * r;
     Gp[e] = X[i * ld + j];
+  }
+  if (mode == 4) {
+    __shared__ double worst[kSmallNT];
+    double err = 0.0;
+    for (int e = tid; e < r * r; e += kSmallNT) {
+      const int i = e / r, j = e - i * r;
+      double s = (i == j) ? -1.0 : 0.0;
+      for (int l = 0; l < r; ++l) s = fma(0.5 * (S[i * r + l] + S[l * r + i]), X[l * ld + j], s);
+      err = fmax(err, fabs(s));
+      if (!(s == s)) err = INFINITY;
+    }
+    worst[tid] = err;
+    __syncthreads();
+    for (int w = kSmallNT / 2; w > 0; w >>= 1) {
+      if (tid < w) worst[tid] = fmax(worst[tid], worst[tid + w]);
+      __syncthreads();
+    }
+    if (tid == 0) *flags = (worst[0] <= 1e-8 && floored == 0) ? 1 : 0;
   }
 }
 
 hipError_t launch_nmf_small(const double* S, int k, int r, int mode, double pen, double* Gp, double* Gm, int* flags,
                             hipStream_t st) {
   size_t sm = 0;
-  if (mode == 2) {
+  if (mode == 2 || mode == 4) {
     const int NB = (r + 15) / 16, N = 16 * NB, ld = N + 1;
     sm = ((size_t)N * ld * 2 + (size_t)NB * 272 + 16 * (size_t)ld + (size_t)N * 17) * sizeof(double);
     hipFuncSetAttribute((const void*)nmf_small_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);

@@ -39,10 +39,12 @@ __global__ __launch_bounds__(256) void nnls_rhs_kernel(const double* __restrict_
 // G_PP z_P = c_P and z_i = 0 off P, P given as the wave-uniform bit mask pm.
 // Gauss-Jordan on the rows held in registers (row i of [M | rhs] by lane i,
 // M = G on P x P, the identity elsewhere); only the passive pivots are
-// eliminated (the other columns are already unit columns).  G is SPD, so
-// no pivoting is needed.
+// eliminated, and a pivot row is applied only to the columns still needed:
+// the later passive ones and the right-hand side (the other entries of the
+// pivot row are zero, and eliminated columns are not read again).  G is SPD,
+// so no pivoting is needed.
 template <int RM>
-__device__ __forceinline__ double nnls_masked_solve(const double* Gs, int r, uint64_t pm, double c) {
+__device__ __noinline__ double nnls_masked_solve(const double* Gs, int r, uint64_t pm, double c) {
   const int lane = threadIdx.x & 63;
   const int row = min(lane, RM - 1);   // lanes past RM hold identity rows; keep their reads inside G
   const bool pi = (pm >> lane) & 1ull;
@@ -62,10 +64,47 @@ __device__ __forceinline__ double nnls_masked_solve(const double* Gs, int r, uin
       mydiag = lane == j ? piv : mydiag;
       const double f = lane == j ? 0.0 : aug[j] / piv;
 #pragma unroll
-      for (int l = j; l <= RM; ++l) aug[l] = fma(-f, readlane_d(aug[l], j), aug[l]);
+      for (int l = j + 1; l < RM; ++l)
+        if ((pm >> l) & 1ull) aug[l] = fma(-f, readlane_d(aug[l], j), aug[l]);
+      aug[RM] = fma(-f, readlane_d(aug[RM], j), aug[RM]);
     }
   }
   return pi ? aug[RM] / mydiag : 0.0;
+}
+
+// The same solution through H = G^-1 when few variables are bound: with the
+// bound set B (live, off P), G_PP^-1 = H_PP - H_PB H_BB^-1 H_BP (the Schur
+// complement identity), so z_P is the right-hand side of rows P of
+// [H | H c~] (c~ = c on P, 0 on B) after eliminating the pivots B.  Only the
+// columns of B and the right-hand side are updated.
+template <int RM>
+__device__ __noinline__ double nnls_masked_solve_h(const double* Hs, int r, uint64_t pm, uint64_t bm, double c) {
+  const int lane = threadIdx.x & 63;
+  const int row = min(lane, RM - 1);
+  const bool pi = (pm >> lane) & 1ull;
+  double y = 0.0;
+  uint64_t rest = pm;
+  while (rest) {
+    const int l = __builtin_ctzll(rest);
+    rest &= rest - 1;
+    y = fma(Hs[row * RM + l], readlane_d(c, l), y);
+  }
+  double aug[RM + 1];
+#pragma unroll
+  for (int l = 0; l < RM; ++l) aug[l] = ((bm >> l) & 1ull) ? Hs[row * RM + l] : 0.0;
+  aug[RM] = y;
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    if (j < r && ((bm >> j) & 1ull)) {
+      const double piv = readlane_d(aug[j], j);
+      const double f = lane == j ? 0.0 : aug[j] / piv;
+#pragma unroll
+      for (int l = j + 1; l < RM; ++l)
+        if ((bm >> l) & 1ull) aug[l] = fma(-f, readlane_d(aug[l], j), aug[l]);
+      aug[RM] = fma(-f, readlane_d(aug[RM], j), aug[RM]);
+    }
+  }
+  return pi ? aug[RM] : 0.0;
 }
 
 __device__ __forceinline__ double wave_max_d(double v) {
@@ -151,6 +190,82 @@ __device__ double lh_wave(const double* Gs, int r, double c, double h0, int* out
   return h;
 }
 
+// Block principal pivoting (Kim and Park, "Fast nonnegative matrix
+// factorization: an active-set-like method and comparisons", SIAM J. Sci.
+// Comput. 2011) on one wave, for the same problem as lh_wave: with a free set
+// F (the rest bound at 0), solve G_FF z_F = c_F and form the dual
+// y = G z - c; the variables with z_i < 0 in F or y_i < 0 off F are
+// infeasible.  All of them change sides at once while their number keeps
+// falling (at most three tries without a decrease); otherwise only the one of
+// largest index does (the finite backup rule).  It stops when none is
+// infeasible, which is the optimality condition, so the minimiser is the same
+// as Lawson-Hanson's; a good first F (the support of h0) usually needs one or
+// two solves.  Tolerances: z_i < -1e-13 max|z_F|, y_i < -1e-13 max|c|.  A
+// variable with G_ii = 0 (its column of C is zero) stays at 0.  With Hs =
+// G^-1 (checked), a free system with fewer bound than free variables is
+// solved through H (nnls_masked_solve_h), which eliminates only the bound
+// pivots.  At most 5 r exchanges; *ok = false when a problem needs more or a
+// solve breaks down (the last iterate, clamped at 0, is returned).
+template <int RM>
+__device__ double bpp_wave(const double* Gs, const double* Hs, int r, double c, double h0, int* steps_out,
+                           bool* ok) {
+  const int lane = threadIdx.x & 63;
+  const int row = min(lane, RM - 1);
+  const bool real = lane < r;
+  const bool live = real && Gs[row * RM + row] > 0.0;
+  const uint64_t lm = __ballot(live);
+  const double tol_y = 1e-13 * wave_max_d(fabs(c));
+  uint64_t F = __ballot(live && h0 > 0.0);
+  int alpha = 3, beta = r + 1, steps = 0;
+  double z = 0.0;
+  bool good = true;
+  while (true) {
+    const uint64_t Bm = lm & ~F;
+    if (Hs && __popcll(Bm) < __popcll(F))
+      z = nnls_masked_solve_h<RM>(Hs, r, F, Bm, c);
+    else
+      z = nnls_masked_solve<RM>(Gs, r, F, c);
+    double gz = 0.0;
+    uint64_t rest = F;
+    while (rest) {
+      const int l = __builtin_ctzll(rest);
+      rest &= rest - 1;
+      gz = fma(Gs[row * RM + l], readlane_d(z, l), gz);
+    }
+    const double y = gz - c;
+    const bool inF = (F >> lane) & 1ull;
+    if (__ballot(inF && !(z == z)) != 0) {   // a NaN: the free system broke down
+      good = false;
+      break;
+    }
+    const double zmax = wave_max_d(inF ? fabs(z) : 0.0);
+    const bool bad = live && (inF ? (z < -1e-13 * zmax) : (y < -tol_y));
+    const uint64_t V = __ballot(bad);
+    if (V == 0) break;
+    if (++steps > 5 * r) {
+      good = false;
+      break;
+    }
+    const int nv = __popcll(V);
+    uint64_t X;
+    if (nv < beta) {
+      beta = nv;
+      alpha = 3;
+      X = V;
+    } else if (alpha >= 1) {
+      alpha -= 1;
+      X = V;
+    } else {
+      X = 1ull << (63 - __clzll(V));
+    }
+    F ^= X;   // infeasible free variables are bound, infeasible bound ones freed
+  }
+  *steps_out = steps;
+  *ok = good;
+  const bool inF = (F >> lane) & 1ull;
+  return (inF && z > 0.0) ? z : 0.0;
+}
+
 // G (r x r, row-major, FP64) into LDS, padded to RM x RM with zeros.
 template <int RM>
 __device__ __forceinline__ void stage_gram(double* Gs, const double* __restrict__ G, int r) {
@@ -202,12 +317,15 @@ __global__ __launch_bounds__(256) void nnls_kernel(const double* __restrict__ Bt
 }
 
 // One half-step of alternating NNLS: one wave per row of F (grid-stride),
-// the right-hand side c = C^T b of row i formed in the wave, warm start
-// from the row's current values.
+// the right-hand side c = C^T b of row i formed in the wave, solved by block
+// principal pivoting from the row's current support.
 template <typename T, int RM>
 __global__ __launch_bounds__(256) void anls_rows_kernel(AnlsArgs a) {
   __shared__ double Gs[RM * RM];
+  __shared__ double Hs[RM * RM];
   stage_gram<RM>(Gs, a.G, a.r);
+  const bool use_h = a.H && a.hok && *a.hok;
+  if (use_h) stage_gram<RM>(Hs, a.H, a.r);
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = a.r;
@@ -235,10 +353,10 @@ __global__ __launch_bounds__(256) void anls_rows_kernel(AnlsArgs a) {
     }
     c = real ? c : 0.0;
     const double h0 = real ? (double)F[(int64_t)i * a.ldf + col] : 0.0;
-    int outer;
+    int steps;
     bool ok;
-    const double h = lh_wave<RM>(Gs, r, c, h0, &outer, &ok);
-    worst = max(worst, outer);
+    const double h = bpp_wave<RM>(Gs, use_h ? Hs : nullptr, r, c, h0, &steps, &ok);
+    worst = max(worst, steps);
     failed += ok ? 0 : 1;
     if (real) {
       F[(int64_t)i * a.ldf + lane] = (T)h;

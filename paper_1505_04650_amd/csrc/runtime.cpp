@@ -1047,6 +1047,7 @@ struct IterWs {
   double* S = nullptr;
   double* Gp = nullptr;
   double* Gm = nullptr;
+  int* hok = nullptr;     // alternating NNLS: Gm holds a checked G^-1
   int kk = 16, bx = 1, by = 1;
 };
 
@@ -1072,6 +1073,7 @@ void layout_iter(Arena& a, IterWs<T>& w, int64_t m, int64_t n, int k, int r, boo
   w.S = a.take<double>((size_t)std::max(k2, r) * r);
   w.Gp = a.take<double>((size_t)r * r);
   w.Gm = a.take<double>((size_t)r * r);
+  w.hok = a.take<int>(1);
 }
 
 template <typename T>
@@ -1296,12 +1298,16 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
       an.ldb1 = ldb1;
       an.C = cf ? iw.S : nullptr;
       an.G = cf ? iw.Gp : iw.S;
+      an.H = iw.Gm;
+      an.hok = iw.hok;
       an.F = F;
       an.ldf = r;
       an.Op = Op;
       an.ldop = kk;
       an.info = info;
       if (cf) HIPCHK(h, launch_nmf_small(iw.S, k, r, 3, 0.0, iw.Gp, nullptr, nullptr, st));
+      // G^-1 and whether it checks out (the rows with few bound variables use it)
+      HIPCHK(h, launch_nmf_small(an.G, r, r, 4, 0.0, iw.Gm, nullptr, iw.hok, st));
       HIPCHK(h, launch_anls_rows<T>(an, st));
       // partial sums of the next C: B2^T F (k x r) or the Gram F^T F
       RUN(row(rows, blocks, nullptr, 0, nullptr, cf ? k : r, F, nullptr, nullptr, nullptr, nullptr, 0.0, 2, B2,
