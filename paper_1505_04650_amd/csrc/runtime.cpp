@@ -1309,20 +1309,25 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
       // G^-1 and whether it checks out (the rows with few bound variables use it)
       HIPCHK(h, launch_nmf_small(an.G, r, r, 4, 0.0, iw.Gm, nullptr, iw.hok, st));
       HIPCHK(h, launch_anls_rows<T>(an, st));
-      // partial sums of the next C: B2^T F (k x r) or the Gram F^T F
-      RUN(row(rows, blocks, nullptr, 0, nullptr, cf ? k : r, F, nullptr, nullptr, nullptr, nullptr, 0.0, 2, B2,
-              cf ? k : r, nullptr, Pp));
+      // partial sums of the next C over row slices (FP64 MFMA): B2^T F
+      // (k x r) or the Gram F^T F
+      const int parts = gram_parts(rows);
+      if (cf)
+        HIPCHK(h, (launch_cross2<T, T>((const T*)B2, k, 0, F, r, 0, 0, 1, rows, k, r, Pp, parts, st)));
+      else
+        HIPCHK(h, (launch_cross2<T, T>(F, r, 0, F, r, 0, 0, 1, rows, r, r, Pp, parts, st)));
+      (void)blocks;
       return CNMF_OK;
     };
+    const int px = gram_parts(m), py = gram_parts(n);
     if (cf) {
       Span sp(h, ST_ITER, (double)d->iters * 4.0 * (double)(m + n) * k * r);
       // initial Yc^T = R V0^T
-      RUN(row(n, iw.by, nullptr, 0, nullptr, k, aw.Vt, nullptr, nullptr, nullptr, nullptr, 0.0, 2, w.RTb, k,
-              nullptr, iw.PpY));
+      HIPCHK(h, (launch_cross2<T, T>(w.RTb, k, 0, aw.Vt, r, 0, 0, 1, n, k, r, iw.PpY, py, st)));
       for (int it = 0; it < d->iters; ++it) {
-        HIPCHK(h, launch_sum_parts(iw.PpY, iw.by, (int64_t)k * r, iw.S, st));
+        HIPCHK(h, launch_sum_parts(iw.PpY, py, (int64_t)k * r, iw.S, st));
         RUN(half(m, iw.bx, w.Acb, k, aw.U, nullptr, w.Lb, iw.PpX));
-        HIPCHK(h, launch_sum_parts(iw.PpX, iw.bx, (int64_t)k * r, iw.S, st));
+        HIPCHK(h, launch_sum_parts(iw.PpX, px, (int64_t)k * r, iw.S, st));
         RUN(half(n, iw.by, w.BTb, k, aw.Vt, nullptr, w.RTb, iw.PpY));
       }
     } else {
@@ -1331,13 +1336,12 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
       HIPCHK(h, launch_fill(iw.Zop, sizeof(T) * (size_t)m * kk, st));
       HIPCHK(h, (launch_copy2d<T, T>(aw.Vt, r, iw.Xop, kk, n, r, 1.0, st)));
       // initial Gram of V0^T
-      RUN(row(n, iw.by, nullptr, 0, nullptr, r, aw.Vt, nullptr, nullptr, nullptr, nullptr, 0.0, 2, nullptr, r,
-              nullptr, iw.PpY));
+      HIPCHK(h, (launch_cross2<T, T>(aw.Vt, r, 0, aw.Vt, r, 0, 0, 1, n, r, r, iw.PpY, py, st)));
       for (int it = 0; it < d->iters; ++it) {
-        HIPCHK(h, launch_sum_parts(iw.PpY, iw.by, (int64_t)r * r, iw.S, st));
+        HIPCHK(h, launch_sum_parts(iw.PpY, py, (int64_t)r * r, iw.S, st));
         RUN(pass_full<T>(h, A, f.ao, true, iw.Xop, kk, iw.Pn, iw.Ppart));
         RUN(half(m, iw.bx, iw.Pn, kk, aw.U, iw.Zop, nullptr, iw.PpX));
-        HIPCHK(h, launch_sum_parts(iw.PpX, iw.bx, (int64_t)r * r, iw.S, st));
+        HIPCHK(h, launch_sum_parts(iw.PpX, px, (int64_t)r * r, iw.S, st));
         RUN(pass_full<T>(h, A, f.ao, false, iw.Zop, kk, iw.Pt, iw.Ppart));
         RUN(half(n, iw.by, iw.Pt, kk, aw.Vt, iw.Xop, nullptr, iw.PpY));
       }
