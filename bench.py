@@ -314,12 +314,29 @@ def extra_workloads_section(h, lam_c2, inp_c2, w_c2):
     st = {k: (v[0] * 1e3 if not math.isnan(v[0]) else None) for k, v in h.stages().items() if v[2]}
     h.set_timing(False)
     U = f.U.cpu().numpy()
+    # the same solve captured once as a graph and replayed (launch latency
+    # dominates at this size)
+    gph = api.FactorizeGraph(*args, iters=w.iters, lam=lam, phi=lam)
+    for _ in range(3):
+        gph.replay()
+    gph.synchronize()
+    ge0, ge1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ge0.record(gph.stream)
+    for _ in range(10):
+        gph.replay()
+    ge1.record(gph.stream)
+    gph.synchronize()
+    us_graph = ge0.elapsed_time(ge1) * 1e3 / 10
+    same_graph = bool(torch.equal(gph.U, f.U) and torch.equal(gph.V, f.V))
+    gph.close()
     out["plain_fp64_1000x500"] = {
-        "us_per_solve": e0.elapsed_time(e1) * 1e3, "us_per_stage": st,
+        "us_per_solve": e0.elapsed_time(e1) * 1e3, "us_per_solve_graph_replay": us_graph,
+        "graph_replay_identical": same_graph, "us_per_stage": st,
         "rel_diff_U_vs_oracle": float(np.linalg.norm(U - ref["U"]) / np.linalg.norm(ref["U"])),
         "rel_residual": float(f.rel_residual.item()),
         "rel_residual_oracle": O.rel_residual(inp["A"], ref["U"], ref["V"])}
-    log(f"1000x500 FP64: {out['plain_fp64_1000x500']['us_per_solve']:.0f} us per solve")
+    log(f"1000x500 FP64: {out['plain_fp64_1000x500']['us_per_solve']:.0f} us per solve, "
+        f"{us_graph:.0f} us as a graph replay")
     # 20000 x 5000: compressed MU and the uncompressed comparators
     A = torch.as_tensor(inp_c2["A"], device=dev)
     c2 = {}
@@ -725,6 +742,22 @@ def main():
     sketch_flops = 2.0 * w.m * w.n * w.k * (2 * (1 + 2 * w.q) + 1)
     sketch_tflops = sketch_flops / (sketch_ms * 1e-3) / 1e12
 
+    # the same solve captured as a graph and replayed (a context figure; the
+    # headline is the call above)
+    gph = api.FactorizeGraph(A, w.r, w.k, w.q, U1, V1, oml, omr, method="admm", iters=w.iters, lam=lam, phi=lam)
+    gph.replay()
+    gph.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record(gph.stream)
+    for _ in range(args.steps):
+        gph.replay()
+    g1.record(gph.stream)
+    gph.synchronize()
+    graph_ms = g0.elapsed_time(g1) / args.steps
+    graph_same = bool(torch.equal(gph.U, f.U) and torch.equal(gph.V, f.V))
+    gph.close()
+    log(f"graph replay: {graph_ms:.3f} ms/step (identical factors: {graph_same})")
+
     stages = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[2] / args.steps,
                   "gflop_per_step": v[1] / args.steps / 1e9} for k, v in agg.items() if v[2]}
     # dominant kernel: the range-finder pass kernels (A X and A^T Z launches)
@@ -744,7 +777,8 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": w.name, "m": w.m, "n": w.n, "r": w.r, "k": w.k, "q": w.q, "iters": w.iters,
                       "method": "compressed ADMM (two-sided)", "lambda": lam, "rel_residual": res_gpu},
-           "sketch_tflops": sketch_tflops, "sketch_ms": sketch_ms, "stages": stages, "roofline": roofline}
+           "sketch_tflops": sketch_tflops, "sketch_ms": sketch_ms, "stages": stages, "roofline": roofline,
+           "graph_replay": {"ms_per_step": graph_ms, "identical_factors": graph_same}}
 
     if not args.no_extras:
         out["workloads"] = extra_workloads_section(h, lam, inp, w)

@@ -279,6 +279,25 @@ typedef struct {
 cnmf_status cnmf_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
                            cnmf_factorize_out* out);
 
+/* The same factorisation captured once as a HIP graph and replayed: every
+ * launch of one cnmf_factorize call (with these arguments) is recorded on
+ * the handle's stream, with a workspace owned by the graph; each
+ * cnmf_graph_launch then reruns the whole factorisation on the handle's
+ * stream, reading the buffers named at capture (A, U0, V0, the test
+ * matrices) as they are at replay time and writing the same outputs.  For
+ * factorisations short enough that launch latency matters (the iterations
+ * are many small launches).  The buffers must stay allocated while the graph
+ * exists; replays on one handle are ordered like any other call.  Errors:
+ * as cnmf_factorize; CNMF_EINVAL for a handle on the null stream (capture
+ * needs a created stream); CNMF_ENOTSUP for inputs in host memory (they use
+ * a second stream); CNMF_EDEVICE when the runtime refuses the capture. */
+typedef struct cnmf_graph cnmf_graph;
+cnmf_status cnmf_factorize_capture(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
+                                   const cnmf_factorize_out* out, cnmf_graph** graph);
+cnmf_status cnmf_graph_launch(cnmf_graph* graph);
+/* Waits for the handle's stream, then frees the graph and its workspace. */
+cnmf_status cnmf_graph_destroy(cnmf_graph* graph);
+
 /* Separable NMF column selection (Section 4, Alg. SNMF, steps 1-2): left
  * sketch Q of A (or both sides when d->sides == CNMF_BOTH), B = Q^T A, then
  * SPA on the columns of B in FP64: r times pick the column of largest

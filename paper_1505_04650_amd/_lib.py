@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "CNMF_OK", -1: "CNMF_EINVAL", -2: "CNMF_ENOMEM", -3: "CNMF_ED
 EXPORTED = [
     "cnmf_create", "cnmf_destroy", "cnmf_last_error", "cnmf_status_string", "cnmf_version",
     "cnmf_sketch", "cnmf_factorize", "snmf_select", "cnmf_spa", "cnmf_workspace_bytes",
+    "cnmf_factorize_capture", "cnmf_graph_launch", "cnmf_graph_destroy",
     "cnmf_set_timing", "cnmf_stage_ms", "cnmf_range_product", "cnmf_stage_flops", "cnmf_stage_launches",
     "cnmf_range_product_lowp", "cnmf_synchronize", "cnmf_gaussian", "cnmf_srht", "cnmf_spa_noalloc", "snmf_nnls",
     "cnmf_server_start", "cnmf_server_submit", "cnmf_server_poll", "cnmf_server_release",
@@ -120,6 +121,13 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.cnmf_factorize.argtypes = [vp, C.POINTER(cnmf_input), C.POINTER(cnmf_factorize_desc),
                                    C.POINTER(cnmf_factorize_out)]
     lib.cnmf_factorize.restype = st
+    lib.cnmf_factorize_capture.argtypes = [vp, C.POINTER(cnmf_input), C.POINTER(cnmf_factorize_desc),
+                                           C.POINTER(cnmf_factorize_out), C.POINTER(vp)]
+    lib.cnmf_factorize_capture.restype = st
+    lib.cnmf_graph_launch.argtypes = [vp]
+    lib.cnmf_graph_launch.restype = st
+    lib.cnmf_graph_destroy.argtypes = [vp]
+    lib.cnmf_graph_destroy.restype = st
     lib.snmf_select.argtypes = [vp, C.POINTER(cnmf_input), C.POINTER(cnmf_sketch_desc), vp, vp, vp]
     lib.snmf_select.restype = st
     lib.cnmf_spa.argtypes = [vp, vp, st, i64, i64, i64, i32, vp, vp]

@@ -221,6 +221,62 @@ def factorize(A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="adm
     return Factorization(U, V, res, sk)
 
 
+class FactorizeGraph:
+    """One factorisation captured as a HIP graph (cnmf_factorize_capture) on
+    a stream of its own, replayed by replay(): each replay recomputes the
+    factorisation from the current contents of A, U0, V0 (and the test
+    matrices) into U, V and rel_residual.  The arguments are those of
+    factorize(); the tensors are kept alive by the object."""
+
+    def __init__(self, A, r, k, q, U0, V0, omega_left=None, omega_right=None, method="admm", iters=100,
+                 lam=1.0, phi=None, xi=1.0, mu_eps=1e-16, pass_dtype=None, final_dtype=None, seed=0,
+                 test_matrix="gaussian"):
+        if A.device.type != "cuda":
+            raise ValueError("a captured factorisation takes a device A")
+        self.stream = torch.cuda.Stream(device=A.device)
+        self.handle = Handle(A.device.index, stream=self.stream)
+        h = self.handle
+        pass_dtype, final_dtype = _default_prec(A, pass_dtype, final_dtype)
+        m, n = A.shape
+        od = _acc_dtype(A, pass_dtype)
+        dev = A.device
+        self.U = torch.empty((m, r), dtype=od, device=dev)
+        self.V = torch.empty((r, n), dtype=od, device=dev)
+        self.rel_residual = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.U0 = U0.to(device=dev, dtype=torch.float64).contiguous()
+        self.V0 = V0.to(device=dev, dtype=torch.float64).contiguous()
+        self._keep = (A, omega_left, omega_right)
+        torch.cuda.current_stream(dev).synchronize()   # inputs produced elsewhere are ready
+        inp = _input(A)
+        self._inp = inp
+        d = L.cnmf_factorize_desc(_sketch_desc(r, k, q, L.CNMF_BOTH, omega_left, omega_right, pass_dtype,
+                                               final_dtype, seed, test_matrix),
+                                  _METHODS[method], int(iters), float(lam), float(lam if phi is None else phi),
+                                  float(xi), float(mu_eps), _ptr(self.U0), _ptr(self.V0))
+        out = L.cnmf_factorize_out(_ptr(self.U), _ptr(self.V), _ptr(self.rel_residual), L.cnmf_sketch_out())
+        g = C.c_void_p()
+        L.check(h._lib.cnmf_factorize_capture(h.raw, C.byref(inp), C.byref(d), C.byref(out), C.byref(g)), h.raw)
+        self._g = g
+
+    def replay(self):
+        """Enqueue one factorisation on the graph's stream (returns at once)."""
+        L.check(self.handle._lib.cnmf_graph_launch(self._g), self.handle.raw)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "_g", None):
+            self.handle._lib.cnmf_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def select(A, r, k, q, omega_left=None, omega_right=None, sides="left", pass_dtype=None, final_dtype=None,
            want_scores=False, want_B=False, seed=0, block_rows=0, test_matrix="gaussian",
            handle: Handle | None = None):

@@ -1413,6 +1413,15 @@ cnmf_status do_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_factori
 }
 
 template <typename T>
+size_t factorize_ws_bytes(const cnmf_input* A, const cnmf_factorize_desc* d) {
+  FactState<T> f;
+  if (fact_plan<T>(nullptr, d, f) != CNMF_OK) return 0;
+  Arena dry(nullptr);
+  fact_layout<T>(dry, f, A->m, A->n, d, A);
+  return dry.off;
+}
+
+template <typename T>
 cnmf_status do_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, int64_t* K, double* score,
                       void* B_out) {
   std::vector<Pass> passes = plan_passes(d->k, d->q, d->sides, false, d->pass_dtype, d->final_dtype);
@@ -1748,6 +1757,93 @@ cnmf_status cnmf_factorize(cnmf_handle* h, const cnmf_input* A, const cnmf_facto
   timing_reset(h);
   if (A->dtype == CNMF_F64) return do_factorize<double>(h, A, d, out);
   return do_factorize<float>(h, A, d, out);
+}
+
+// A captured factorisation: every launch of one cnmf_factorize call,
+// recorded on the handle's stream into a graph with a workspace of its own.
+struct cnmf_graph {
+  cnmf_handle* h = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipGraphExec_t exec = nullptr;
+};
+
+cnmf_status cnmf_factorize_capture(cnmf_handle* h, const cnmf_input* A, const cnmf_factorize_desc* d,
+                                   const cnmf_factorize_out* out, cnmf_graph** graph) {
+  cnmf_status s = check_input(h, A);
+  if (s != CNMF_OK) return s;
+  s = check_factorize(h, A, d);
+  if (s != CNMF_OK) return s;
+  if (!out || !graph) return fail(h, CNMF_EINVAL, "out and graph are required");
+  if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
+  *graph = nullptr;
+  if (!h->stream) return fail(h, CNMF_EINVAL, "capture needs a handle on a created stream (not the null stream)");
+  if (A->format == CNMF_DENSE_HOST)
+    return fail(h, CNMF_ENOTSUP, "inputs in host memory are streamed on a second stream: not captured");
+  HIPCHK(h, hipSetDevice(h->device));
+  const size_t bytes = std::max<size_t>(
+      A->dtype == CNMF_F64 ? factorize_ws_bytes<double>(A, d) : factorize_ws_bytes<float>(A, d), kAlign);
+  cnmf_graph* g = new cnmf_graph();
+  g->h = h;
+  hipError_t e = hipMalloc((void**)&g->ws, bytes);
+  if (e != hipSuccess) {
+    delete g;
+    return fail(h, CNMF_ENOMEM, "graph workspace hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  g->ws_bytes = bytes;
+  // record into the graph's own workspace (never grown), without timing events
+  char* ws0 = h->ws;
+  const size_t b0 = h->ws_bytes;
+  const bool ext0 = h->ext_ws, tm0 = h->timing;
+  h->ws = g->ws;
+  h->ws_bytes = bytes;
+  h->ext_ws = true;
+  h->timing = false;
+  timing_reset(h);
+  hipGraph_t gr = nullptr;
+  e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    s = A->dtype == CNMF_F64 ? do_factorize<double>(h, A, d, out) : do_factorize<float>(h, A, d, out);
+    hipError_t e2 = hipStreamEndCapture(h->stream, &gr);
+    if (s == CNMF_OK && e2 != hipSuccess) s = fail(h, CNMF_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+  } else {
+    s = fail(h, CNMF_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  h->ws = ws0;
+  h->ws_bytes = b0;
+  h->ext_ws = ext0;
+  h->timing = tm0;
+  if (s == CNMF_OK) {
+    e = hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) s = fail(h, CNMF_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  if (gr) hipGraphDestroy(gr);
+  if (s != CNMF_OK) {
+    (void)hipGetLastError();
+    hipFree(g->ws);
+    delete g;
+    return s;
+  }
+  *graph = g;
+  return CNMF_OK;
+}
+
+cnmf_status cnmf_graph_launch(cnmf_graph* g) {
+  if (!g) return fail(nullptr, CNMF_EINVAL, "graph is NULL");
+  cnmf_handle* h = g->h;
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, hipGraphLaunch(g->exec, h->stream));
+  return CNMF_OK;
+}
+
+cnmf_status cnmf_graph_destroy(cnmf_graph* g) {
+  if (!g) return CNMF_OK;
+  hipSetDevice(g->h->device);
+  hipStreamSynchronize(g->h->stream);
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->ws) hipFree(g->ws);
+  delete g;
+  return CNMF_OK;
 }
 
 cnmf_status snmf_select(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_desc* d, int64_t* K_dev,
