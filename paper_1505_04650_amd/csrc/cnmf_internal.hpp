@@ -94,6 +94,15 @@ struct CholOpts {
 };
 hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double* G, double* Tinv, const CholOpts& o,
                             hipStream_t st);
+// The factor-and-invert step alone on nh summed Grams G (kh x kh each).
+hipError_t launch_chol_tinv(const double* G, int nh, int kh, double* Tinv, const CholOpts& o, hipStream_t st);
+// (S + pen I)^-1 for a symmetric r x r S (r <= 64), FP64: G = sym(S) +
+// pen I, the one-wave Cholesky G = T^T T with T^-1 (launch_chol_tinv; pivots
+// below 1e-300 max diag floored and counted in *floored, which is zeroed
+// first), Minv = T^-1 T^-T.  ok != nullptr: *ok = 1 when max |G Minv - I|
+// <= 1e-8 and nothing was floored, else 0.  G and Tinv: r x r scratch.
+hipError_t launch_spd_inverse(const double* S, int r, double pen, double* G, double* Tinv, double* Minv, int* floored,
+                              int* ok, hipStream_t st);
 // Q64[:, h*kh + c] = sum_{l <= c} Y[:, h*kh + l] Tinv_h[l][c] (FP64), h < nh;
 // columns marked in mask (NULL: none) get entries of Gaussian test matrix
 // id0 + h under `seed`, divided by sqrt(rows).  In place (Q64 == Y) is
@@ -230,8 +239,7 @@ struct RowArgs {
 template <typename T>
 hipError_t launch_nmf_row(const RowArgs& a, int blocks, hipStream_t st);
 // mode 0: G = C^T C (C = S, k x r) -> G+, G-; mode 1: G = S (r x r) -> G+, G-;
-// mode 2: Gp = (S + pen I)^-1 (S the r x r Gram); mode 3: Gp = S^T S (C = S, k x r);
-// mode 4: Gp = S^-1 and *flags = 1 if max |S Gp - I| <= 1e-8 (else 0).
+// mode 3: Gp = S^T S (C = S, k x r).
 hipError_t launch_nmf_small(const double* S, int k, int r, int mode, double pen, double* Gp, double* Gm, int* flags,
                             hipStream_t st);
 

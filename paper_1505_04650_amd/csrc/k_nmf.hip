@@ -211,8 +211,8 @@ template hipError_t launch_nmf_row<double>(const RowArgs&, int, hipStream_t);
 // reduction of the partials into S):
 //   MU, C form:    C = S (k x r), G = C^T C, G+ = max(G, 0), G- = max(-G, 0)
 //   MU, Gram form: G = S (r x r), G+, G-
-//   ADMM:          Minv = (S + pen I)^-1 (S is the Gram, r x r)
 //   ANLS, C form:  G = C^T C (C = S, k x r), unsplit
+// ((Gram + pen I)^-1 of the uncompressed ADMM: launch_spd_inverse below)
 // ---------------------------------------------------------------------------
 constexpr int kSmallNT = 256;
 
@@ -220,7 +220,6 @@ __global__ __launch_bounds__(kSmallNT) void nmf_small_kernel(const double* __res
                                                              double pen, double* __restrict__ Gp,
                                                              double* __restrict__ Gm, int* flags) {
   const int tid = threadIdx.x;
-  extern __shared__ double sm[];
   if (mode == 3) {
     for (int e = tid; e < r * r; e += kSmallNT) {
       const int a = e / r, b = e - a * r;
@@ -256,63 +255,74 @@ __global__ __launch_bounds__(kSmallNT) void nmf_small_kernel(const double* __res
     }
     return;
   }
-  // mode 2: Minv = (S + pen I)^-1 via the blocked Cholesky, then X = I X M^-1
-  // (mode 4: the same with pen = 0, then *flags = 1 when the inverse checks
-  // out, max |S X - I| <= 1e-8 with no floored pivot, else 0)
-  const int NB = (r + 15) / 16, N = 16 * NB, ld = N + 1;
-  double* M = sm;              // N x ld
-  double* TI = M + N * ld;     // NB x 272
-  double* PN = TI + NB * 272;  // 16 x ld
-  double* X = PN + 16 * ld;    // N x ld
-  double* R = X + N * ld;      // N x 17
-  for (int e = tid; e < N * N; e += kSmallNT) {
-    const int i = e / N, j = e - i * N;
-    double v = (i < r && j < r) ? 0.5 * (S[i * r + j] + S[j * r + i]) : 0.0;
-    if (i == j) v += (i < r) ? pen : 1.0;
-    M[i * ld + j] = v;
-    X[i * ld + j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  double mx = 0.0;
-  for (int i = 0; i < r; ++i) mx = fmax(mx, M[i * ld + i]);
-  __shared__ int floored;
-  if (tid == 0) floored = 0;
-  __syncthreads();
-  wg_chol_blocked<kSmallNT>(M, ld, NB, TI, PN, 1e-300 * mx, mode == 4 ? &floored : flags);
-  wg_right_solve_blocked<kSmallNT>(X, N, ld, NB, M, ld, TI, R);
-  for (int e = tid; e < r * r; e += kSmallNT) {
-    const int i = e / r, j = e - i * r;
-    Gp[e] = X[i * ld + j];
-  }
-  if (mode == 4) {
-    __shared__ double worst[kSmallNT];
-    double err = 0.0;
-    for (int e = tid; e < r * r; e += kSmallNT) {
-      const int i = e / r, j = e - i * r;
-      double s = (i == j) ? -1.0 : 0.0;
-      for (int l = 0; l < r; ++l) s = fma(0.5 * (S[i * r + l] + S[l * r + i]), X[l * ld + j], s);
-      err = fmax(err, fabs(s));
-      if (!(s == s)) err = INFINITY;
-    }
-    worst[tid] = err;
-    __syncthreads();
-    for (int w = kSmallNT / 2; w > 0; w >>= 1) {
-      if (tid < w) worst[tid] = fmax(worst[tid], worst[tid + w]);
-      __syncthreads();
-    }
-    if (tid == 0) *flags = (worst[0] <= 1e-8 && floored == 0) ? 1 : 0;
-  }
 }
+
 
 hipError_t launch_nmf_small(const double* S, int k, int r, int mode, double pen, double* Gp, double* Gm, int* flags,
                             hipStream_t st) {
-  size_t sm = 0;
-  if (mode == 2 || mode == 4) {
-    const int NB = (r + 15) / 16, N = 16 * NB, ld = N + 1;
-    sm = ((size_t)N * ld * 2 + (size_t)NB * 272 + 16 * (size_t)ld + (size_t)N * 17) * sizeof(double);
-    hipFuncSetAttribute((const void*)nmf_small_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  if (mode < 0 || mode > 3 || mode == 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(nmf_small_kernel, dim3(1), dim3(kSmallNT), 0, st, S, k, r, mode, pen, Gp, Gm, flags);
+  CNMF_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// (S + pen I)^-1 through the one-wave Cholesky of the orthonormalisation:
+// G = sym(S) + pen I, G = T^T T, Minv = T^-1 T^-T (T^-1 upper triangular),
+// optionally checked against G.
+// ---------------------------------------------------------------------------
+__global__ void spd_prep_kernel(const double* __restrict__ S, int r, double pen, double* __restrict__ G,
+                                int* __restrict__ floored) {
+  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+    const int i = e / r, j = e - i * r;
+    G[e] = 0.5 * (S[i * r + j] + S[j * r + i]) + (i == j ? pen : 0.0);
   }
-  hipLaunchKernelGGL(nmf_small_kernel, dim3(1), dim3(kSmallNT), sm, st, S, k, r, mode, pen, Gp, Gm, flags);
+  if (threadIdx.x == 0) *floored = 0;
+}
+
+__global__ __launch_bounds__(256) void spd_inv_finish_kernel(const double* __restrict__ G,
+                                                             const double* __restrict__ Ti, int r,
+                                                             double* __restrict__ Minv,
+                                                             const int* __restrict__ floored, int* ok) {
+  __shared__ double Ms[64 * 65];
+  __shared__ double worst[256];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < r * r; e += 256) {
+    const int i = e / r, j = e - i * r;
+    double s = 0.0;
+    for (int l = max(i, j); l < r; ++l) s = fma(Ti[i * r + l], Ti[j * r + l], s);
+    Ms[i * 65 + j] = s;
+    Minv[e] = s;
+  }
+  if (!ok) return;
+  __syncthreads();
+  double err = 0.0;
+  for (int e = tid; e < r * r; e += 256) {
+    const int i = e / r, j = e - i * r;
+    double s = (i == j) ? -1.0 : 0.0;
+    for (int l = 0; l < r; ++l) s = fma(G[i * r + l], Ms[l * 65 + j], s);
+    err = (s == s) ? fmax(err, fabs(s)) : INFINITY;
+  }
+  worst[tid] = err;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) worst[tid] = fmax(worst[tid], worst[tid + w]);
+    __syncthreads();
+  }
+  if (tid == 0) *ok = (worst[0] <= 1e-8 && *floored == 0) ? 1 : 0;
+}
+
+hipError_t launch_spd_inverse(const double* S, int r, double pen, double* G, double* Tinv, double* Minv, int* floored,
+                              int* ok, hipStream_t st) {
+  if (r < 1 || r > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(spd_prep_kernel, dim3(1), dim3(256), 0, st, S, r, pen, G, floored);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  CholOpts o{};
+  o.tau = 1e-300;
+  o.unresolved = floored;
+  e = launch_chol_tinv(G, 1, r, Tinv, o, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(spd_inv_finish_kernel, dim3(1), dim3(256), 0, st, G, Tinv, r, Minv, floored, ok);
   CNMF_LAUNCH_CHECK();
 }
 

@@ -509,6 +509,11 @@ hipError_t launch_gram_chol(const double* Gp, int parts, int nh, int kh, double*
   if (kh > 128) return hipErrorInvalidValue;
   hipError_t e = launch_sum_parts(Gp, parts, (int64_t)nh * kh * kh, G, st, o.run_if, nh);
   if (e != hipSuccess) return e;
+  return launch_chol_tinv(G, nh, kh, Tinv, o, st);
+}
+
+hipError_t launch_chol_tinv(const double* G, int nh, int kh, double* Tinv, const CholOpts& o, hipStream_t st) {
+  if (kh > 128 || kh < 1) return hipErrorInvalidValue;
   const int NB = (kh + 15) / 16, N = 16 * NB;
   // kh <= 64: N x (N + 2) + NB x 272 + 128 doubles; kh > 64: 128 x 130 + 8 x 272 + 128
   const size_t smw = kh <= 64 ? ((size_t)N * (N + 2) + (size_t)NB * 272 + 128) * sizeof(double)

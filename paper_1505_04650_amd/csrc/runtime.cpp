@@ -1048,6 +1048,9 @@ struct IterWs {
   double* Gp = nullptr;
   double* Gm = nullptr;
   int* hok = nullptr;     // alternating NNLS: Gm holds a checked G^-1
+  int* floored = nullptr;  // floored pivots of the last small inverse
+  double* Gt = nullptr;    // scratch of the small inverse: sym(S) + pen I and T^-1
+  double* Tinv = nullptr;
   int kk = 16, bx = 1, by = 1;
 };
 
@@ -1074,6 +1077,9 @@ void layout_iter(Arena& a, IterWs<T>& w, int64_t m, int64_t n, int k, int r, boo
   w.Gp = a.take<double>((size_t)r * r);
   w.Gm = a.take<double>((size_t)r * r);
   w.hok = a.take<int>(1);
+  w.floored = a.take<int>(1);
+  w.Gt = a.take<double>((size_t)r * r);
+  w.Tinv = a.take<double>((size_t)r * r);
 }
 
 template <typename T>
@@ -1307,7 +1313,7 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
       an.info = info;
       if (cf) HIPCHK(h, launch_nmf_small(iw.S, k, r, 3, 0.0, iw.Gp, nullptr, nullptr, st));
       // G^-1 and whether it checks out (the rows with few bound variables use it)
-      HIPCHK(h, launch_nmf_small(an.G, r, r, 4, 0.0, iw.Gm, nullptr, iw.hok, st));
+      HIPCHK(h, launch_spd_inverse(an.G, r, 0.0, iw.Gt, iw.Tinv, iw.Gm, iw.floored, iw.hok, st));
       HIPCHK(h, launch_anls_rows<T>(an, st));
       // partial sums of the next C over row slices (FP64 MFMA): B2^T F
       // (k x r) or the Gram F^T F
@@ -1351,6 +1357,17 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
   } else {
     // uncompressed comparators: L = I, R = I, two streaming passes per iteration
     const bool admm = d->method == CNMF_ADMM_FULL;
+    // ADMM: Minv = (Gram + pen I)^-1 into Gp (floored pivots counted in
+    // flags[2]); MU: the Gram's positive and negative parts into Gp, Gm
+    auto small_step = [&](double pen) -> cnmf_status {
+      if (admm) {
+        HIPCHK(h, launch_spd_inverse(iw.S, r, pen, iw.Gt, iw.Tinv, iw.Gp, iw.floored, nullptr, st));
+        HIPCHK(h, launch_add_count(iw.floored, w.flags + 2, st));
+      } else {
+        HIPCHK(h, launch_nmf_small(iw.S, r, r, 1, 0.0, iw.Gp, iw.Gm, nullptr, st));
+      }
+      return CNMF_OK;
+    };
     const int kk = iw.kk;
     Span sp(h, ST_ITER, (double)d->iters * 4.0 * (double)m * n * r);
     HIPCHK(h, launch_fill(iw.Xop, sizeof(T) * (size_t)n * kk, st));
@@ -1361,12 +1378,12 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
             iw.PpY));
     for (int it = 0; it < d->iters; ++it) {
       HIPCHK(h, launch_sum_parts(iw.PpY, iw.by, (int64_t)r * r, iw.S, st));
-      HIPCHK(h, launch_nmf_small(iw.S, r, r, admm ? 2 : 1, d->lambda, iw.Gp, iw.Gm, w.flags + 2, st));
+      RUN(small_step(d->lambda));
       RUN(pass_full<T>(h, A, f.ao, true, iw.Xop, kk, iw.Pn, iw.Ppart));
       RUN(row(m, iw.bx, iw.Pn, kk, nullptr, r, aw.U, admm ? aw.Lam : nullptr, iw.Gp, iw.Gm, iw.Gp, d->lambda,
               admm ? 1 : 0, nullptr, r, iw.Zop, iw.PpX));
       HIPCHK(h, launch_sum_parts(iw.PpX, iw.bx, (int64_t)r * r, iw.S, st));
-      HIPCHK(h, launch_nmf_small(iw.S, r, r, admm ? 2 : 1, d->phi, iw.Gp, iw.Gm, w.flags + 2, st));
+      RUN(small_step(d->phi));
       RUN(pass_full<T>(h, A, f.ao, false, iw.Zop, kk, iw.Pt, iw.Ppart));
       RUN(row(n, iw.by, iw.Pt, kk, nullptr, r, aw.Vt, admm ? aw.Phit : nullptr, iw.Gp, iw.Gm, iw.Gp, d->phi,
               admm ? 1 : 0, nullptr, r, iw.Xop, iw.PpY));

@@ -1,7 +1,6 @@
 // FP64 building blocks for the small (<= 128 x 128) dense steps: fixed-order
-// reduction of per-block partial sums, blocked in-LDS Cholesky factorisations
-// with the inverses of their triangular factors, and a single-wave Cholesky
-// whose products run on the FP64 MFMA.
+// reduction of per-block partial sums and a single-wave Cholesky whose
+// products run on the MFMA.
 #pragma once
 
 #include "cnmf_internal.hpp"
@@ -49,209 +48,6 @@ __device__ __forceinline__ double readlane_d(double x, int lane) {
   int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
   return __hiloint2double(hi, lo);
 }
-
-// ---------------------------------------------------------------------------
-// Blocked SPD factorisation for N = 16 * NB <= 64 (matrices padded with an
-// identity block beyond the true order n, so the factor of the padded
-// matrix is blockdiag(T, I)).
-// ---------------------------------------------------------------------------
-
-// One wave: Cholesky of the 16 x 16 block D (LDS, row stride ldd, full
-// symmetric), D = T^T T.  Writes T (upper, zeros below) over D and the
-// inverse of T (upper) into TI (16 x 17).  Lane i < 16 keeps row i in
-// registers; pivot rows are broadcast with readlane.
-__device__ void wave_diag16(double* D, int ldd, double* TI, double floor_piv, int* flag) {
-  const int lane = threadIdx.x & 63;
-  double m[16];
-#pragma unroll
-  for (int b = 0; b < 16; ++b) m[b] = lane < 16 ? D[lane * ldd + b] : 0.0;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    double d = readlane_d(m[j], j);
-    if (!(d > floor_piv) || !isfinite(d)) {
-      if (lane == 0 && flag) atomicAdd(flag, 1);
-      d = floor_piv > 0.0 ? floor_piv : 1.0;
-    }
-    const double t = sqrt(d);
-    const double it = 1.0 / t;
-    const double f = m[j] * it;
-#pragma unroll
-    for (int b = j + 1; b < 16; ++b) {
-      const double cjb = readlane_d(m[b], j) * it;
-      if (lane > j) m[b] = fma(-f, cjb, m[b]);
-    }
-    if (lane == j) {
-#pragma unroll
-      for (int b = j + 1; b < 16; ++b) m[b] *= it;
-      m[j] = t;
-    }
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int b = 0; b < 16; ++b) D[lane * ldd + b] = b >= lane ? m[b] : 0.0;
-  }
-  // column `lane` of T^-1 from the register rows: x[i] = (delta - sum_{l>i}
-  // T[i][l] x[l]) / T[i][i]; T[i][l] = readlane(m[l], i) is a scalar.
-  double idg = 1.0;
-#pragma unroll
-  for (int i = 0; i < 16; ++i)
-    if (lane == i) idg = 1.0 / m[i];
-  double x[16];
-#pragma unroll
-  for (int i = 15; i >= 0; --i) {
-    double s = (lane == i) ? 1.0 : 0.0;
-#pragma unroll
-    for (int l = i + 1; l < 16; ++l) s = fma(-readlane_d(m[l], i), x[l], s);
-    x[i] = s * readlane_d(idg, i);
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) TI[i * 17 + lane] = x[i];
-  }
-  __builtin_amdgcn_s_waitcnt(0);
-  __builtin_amdgcn_wave_barrier();
-}
-
-// M (N x N, LDS, row stride ldm, full symmetric) = T^T T.  On return the
-// upper block triangle of M holds T (diagonal blocks upper triangular),
-// TI[jb] (16 x 17 each) the inverses of the diagonal blocks.  PN: 16 x ldm
-// LDS scratch.  All NT threads call it; it starts and ends with a barrier.
-template <int NT>
-__device__ void wg_chol_blocked(double* M, int ldm, int NB, double* TI, double* PN, double floor_piv, int* flag) {
-  const int tid = threadIdx.x;
-  const int N = 16 * NB;
-  __syncthreads();
-  for (int jb = 0; jb < NB; ++jb) {
-    const int j0 = 16 * jb, c0 = j0 + 16, rem = N - c0;
-    if (tid < 64) wave_diag16(M + j0 * ldm + j0, ldm, TI + jb * 272, floor_piv, flag);
-    __syncthreads();
-    if (rem > 0) {
-      const double* ti = TI + jb * 272;
-      // panel: T[j0 + i][c] = sum_{l <= i} Tinv[l][i] M[j0 + l][c]
-      for (int e = tid; e < 16 * rem; e += NT) {
-        const int i = e / rem, c = c0 + (e - (e / rem) * rem);
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int l = 0; l < 16; l += 2) {
-          const double t0 = l <= i ? ti[l * 17 + i] : 0.0;
-          const double t1 = l + 1 <= i ? ti[(l + 1) * 17 + i] : 0.0;
-          s0 = fma(t0, M[(j0 + l) * ldm + c], s0);
-          s1 = fma(t1, M[(j0 + l + 1) * ldm + c], s1);
-        }
-        PN[i * ldm + c] = s0 + s1;
-      }
-      __syncthreads();
-      // trailing update (both triangles) and the panel into M's block row
-      for (int e = tid; e < rem * rem; e += NT) {
-        const int x = c0 + e / rem, y = c0 + (e - (e / rem) * rem);
-        if (y >= x) {
-          double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-          for (int i = 0; i < 16; i += 2) {
-            s0 = fma(PN[i * ldm + x], PN[i * ldm + y], s0);
-            s1 = fma(PN[(i + 1) * ldm + x], PN[(i + 1) * ldm + y], s1);
-          }
-          const double s = s0 + s1;
-          M[x * ldm + y] -= s;
-          if (y != x) M[y * ldm + x] -= s;
-        }
-      }
-      for (int e = tid; e < 16 * rem; e += NT) {
-        const int i = e / rem, c = c0 + (e - (e / rem) * rem);
-        M[(j0 + i) * ldm + c] = PN[i * ldm + c];
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// X (rows x N, LDS, row stride ldx) <- X (T^T T)^-1 with T from
-// wg_chol_blocked (upper blocks of M) and the diagonal-block inverses TI.
-// R: rows x 17 LDS scratch.  Starts and ends with a barrier.
-template <int NT>
-__device__ void wg_right_solve_blocked(double* X, int rows, int ldx, int NB, const double* M, int ldm,
-                                       const double* TI, double* R) {
-  const int tid = threadIdx.x;
-  const int N = 16 * NB;
-  __syncthreads();
-  // forward: Z T = X, block column by block column; work item = (row, 4 columns)
-  for (int cb = 0; cb < NB; ++cb) {
-    const int c0 = 16 * cb;
-    for (int e = tid; e < rows * 4; e += NT) {
-      const int i = e >> 2, cq = 4 * (e & 3);
-      const double* xi = X + i * ldx;
-      double s0 = xi[c0 + cq], s1 = xi[c0 + cq + 1], s2 = xi[c0 + cq + 2], s3 = xi[c0 + cq + 3];
-#pragma unroll 8
-      for (int l = 0; l < c0; ++l) {
-        const double xl = xi[l];
-        const double* t = M + l * ldm + c0 + cq;
-        s0 = fma(-xl, t[0], s0);
-        s1 = fma(-xl, t[1], s1);
-        s2 = fma(-xl, t[2], s2);
-        s3 = fma(-xl, t[3], s3);
-      }
-      double* ri = R + i * 17 + cq;
-      ri[0] = s0; ri[1] = s1; ri[2] = s2; ri[3] = s3;
-    }
-    __syncthreads();
-    const double* ti = TI + cb * 272;
-    for (int e = tid; e < rows * 4; e += NT) {
-      const int i = e >> 2, cq = 4 * (e & 3);
-      const double* ri = R + i * 17;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-      for (int l = 0; l < 16; ++l) {
-        const double rl = ri[l];
-        const double* t = ti + l * 17 + cq;   // Tinv upper: zero below the diagonal
-        s0 = fma(rl, t[0], s0);
-        s1 = fma(rl, t[1], s1);
-        s2 = fma(rl, t[2], s2);
-        s3 = fma(rl, t[3], s3);
-      }
-      double* xi = X + i * ldx + c0 + cq;
-      xi[0] = s0; xi[1] = s1; xi[2] = s2; xi[3] = s3;
-    }
-    __syncthreads();
-  }
-  // backward: W T^T = Z
-  for (int cb = NB - 1; cb >= 0; --cb) {
-    const int c0 = 16 * cb;
-    for (int e = tid; e < rows * 4; e += NT) {
-      const int i = e >> 2, cq = 4 * (e & 3);
-      const double* xi = X + i * ldx;
-      double s0 = xi[c0 + cq], s1 = xi[c0 + cq + 1], s2 = xi[c0 + cq + 2], s3 = xi[c0 + cq + 3];
-#pragma unroll 8
-      for (int l = c0 + 16; l < N; ++l) {
-        const double xl = xi[l];
-        s0 = fma(-xl, M[(c0 + cq) * ldm + l], s0);
-        s1 = fma(-xl, M[(c0 + cq + 1) * ldm + l], s1);
-        s2 = fma(-xl, M[(c0 + cq + 2) * ldm + l], s2);
-        s3 = fma(-xl, M[(c0 + cq + 3) * ldm + l], s3);
-      }
-      double* ri = R + i * 17 + cq;
-      ri[0] = s0; ri[1] = s1; ri[2] = s2; ri[3] = s3;
-    }
-    __syncthreads();
-    const double* ti = TI + cb * 272;
-    for (int e = tid; e < rows * 4; e += NT) {
-      const int i = e >> 2, cq = 4 * (e & 3);
-      const double* ri = R + i * 17;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-      for (int l = 0; l < 16; ++l) {
-        const double rl = ri[l];                // W_cb = R Tinv^T: sum_l R[l] Tinv[c][l]
-        s0 = fma(rl, ti[(cq + 0) * 17 + l], s0);
-        s1 = fma(rl, ti[(cq + 1) * 17 + l], s1);
-        s2 = fma(rl, ti[(cq + 2) * 17 + l], s2);
-        s3 = fma(rl, ti[(cq + 3) * 17 + l], s3);
-      }
-      double* xi = X + i * ldx + c0 + cq;
-      xi[0] = s0; xi[1] = s1; xi[2] = s2; xi[3] = s3;
-    }
-    __syncthreads();
-  }
-}
-
 
 // 1 / sqrt(d) for d > 0 in four dependent operations: the hardware estimate
 // y0 (relative error below 2^-24) and one second-order correction
