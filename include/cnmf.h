@@ -143,7 +143,8 @@ cnmf_status cnmf_srht(cnmf_handle* h, uint64_t seed, int32_t matrix_id, int64_t 
  *   CNMF_CSR (2): sparse on the device, compressed rows: rowptr_dev (m + 1
  *     int64 offsets, rowptr[0] = 0, nondecreasing, rowptr[m] = nnz),
  *     colind_dev (nnz int32 column indices in [0, n), ascending within each
- *     row) and the nnz values at data_dev; lda is ignored.  The passes
+ *     row) and the nnz values at data_dev (both may be NULL when nnz = 0);
+ *     lda is ignored.  The passes
  *     multiply with A and A^T directly (the transpose is formed once per
  *     call in the workspace); passes in F32 / F64 only.
  * A is never written.

@@ -205,8 +205,9 @@ cnmf_status check_input(cnmf_handle* h, const cnmf_input* A) {
   if (A->m > INT32_MAX / 2 || A->n > INT32_MAX / 2)
     return fail(h, CNMF_ENOTSUP, "dimensions above 2^30 are not supported");
   if (A->format == CNMF_CSR) {
-    if (!A->rowptr_dev || !A->colind_dev) return fail(h, CNMF_EINVAL, "CSR input needs rowptr_dev and colind_dev");
     if (A->nnz < 0 || A->nnz > INT32_MAX) return fail(h, CNMF_EINVAL, "nnz must be in [0, 2^31)");
+    if (!A->rowptr_dev || (A->nnz > 0 && !A->colind_dev))
+      return fail(h, CNMF_EINVAL, "CSR input needs rowptr_dev and colind_dev");
     if (A->nnz > 0 && !A->data_dev) return fail(h, CNMF_EINVAL, "A->data_dev (the values) is NULL");
     return CNMF_OK;
   }

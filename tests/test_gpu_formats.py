@@ -227,3 +227,27 @@ def test_csr_bad_column_index_is_reported(sparse_case):
         api.synchronize()
     assert e.value.status == L.CNMF_EBREAKDOWN
     api.synchronize()
+
+
+def test_csr_without_nonzeros():
+    """nnz = 0: the products are zero, the fallback completes the bases with
+    Gaussian columns (orthonormal), the factorisation's residual is 0."""
+    m, n, r, k = 300, 200, 4, 10
+    A = torch.sparse_csr_tensor(torch.zeros(m + 1, dtype=torch.int64, device=DEV),
+                                torch.zeros(0, dtype=torch.int64, device=DEV),
+                                torch.zeros(0, dtype=torch.float64, device=DEV), size=(m, n))
+    out = api.sketch(A, r, k, 1, None, None, seed=4)
+    Lg = host(out.L)
+    assert np.abs(Lg.T @ Lg - np.eye(k)).max() < 1e-13
+    assert np.abs(host(out.B)).max() == 0.0
+    U1, V1 = WL.init_factors(0.1, m, n, r, 5)
+    f = api.factorize(A, r, k, 1, dev(U1), dev(V1), None, None, iters=3, lam=1.0, phi=1.0, seed=4)
+    assert float(host(f.rel_residual)[0]) == 0.0
+    api.synchronize()
+
+
+def test_host_block_larger_than_the_matrix(c1):
+    w, inp, sk, _ = c1
+    out = api.sketch(pinned(inp["A"]), w.r, w.k, w.q, dev(inp["Omega_L"]), dev(inp["Omega_R"]),
+                     block_rows=10 ** 6)
+    assert close64(host(out.L), sk["L"])
