@@ -144,8 +144,10 @@ def _sin_max_angle(Q1, Q2):
     return float(torch.linalg.matrix_norm(D, ord=2))
 
 
-def precision_section(h, steps, warmup):
-    """Sketch of the 100000 x 20000 precision workload in FP32, BF16 and FP8."""
+def precision_section(h, steps, warmup, reference=True):
+    """Sketch of the 100000 x 20000 precision workload in FP32, BF16 and FP8
+    (reference=False skips the FP64 reference sketch and the errors against
+    it, for kernel profiles under hardware counters)."""
     import torch
     from paper_1505_04650_amd import api
     w = WL.WORKLOADS["precision_100000x20000"]
@@ -158,12 +160,14 @@ def precision_section(h, steps, warmup):
     oml = torch.randn(w.n, w.k, device=dev, dtype=torch.float64, generator=g)
     omr = torch.randn(w.m, w.k, device=dev, dtype=torch.float64, generator=g)
     norm_a = math.sqrt(sum(float((A[i:i + 8192].double() ** 2).sum()) for i in range(0, w.m, 8192)))
-    t_ref = time.perf_counter()
-    refL, refR, refB, refAt = _fp64_reference_sketch(A, oml, omr, w.q)
-    ref_res, ref_orth = _proj_residual(A, refL, norm_a)
-    torch.cuda.synchronize()
-    log(f"precision: FP64 reference sketch (PyTorch FP64, Householder QR) in {time.perf_counter() - t_ref:.1f} s, "
-        f"projection residual {ref_res:.6e}")
+    refL = refR = refB = refAt = None
+    if reference:
+        t_ref = time.perf_counter()
+        refL, refR, refB, refAt = _fp64_reference_sketch(A, oml, omr, w.q)
+        ref_res, ref_orth = _proj_residual(A, refL, norm_a)
+        torch.cuda.synchronize()
+        log(f"precision: FP64 reference sketch (PyTorch FP64, Householder QR) in {time.perf_counter() - t_ref:.1f} "
+            f"s, projection residual {ref_res:.6e}")
     flops = 2.0 * w.m * w.n * w.k * (2 * (1 + 2 * w.q) + 1)  # two chains of 2q + 1 products, and B
     out = {"workload": w.name, "m": w.m, "n": w.n, "r": w.r, "k": w.k, "q": w.q, "sides": "both",
            "data": "synthetic, generated on the device"}
@@ -193,12 +197,14 @@ def precision_section(h, steps, warmup):
         pass_ms = (pn[0] + pt[0]) / steps
         pres, porth = _proj_residual(A, sk.L, norm_a)
         r_ = w.r
-        vs_ref = {"proj_residual_gap": abs(pres - ref_res),
-                  "orth_err_L": porth,
-                  "sin_angle_L_leading_r": _sin_max_angle(sk.L.double()[:, :r_], refL[:, :r_]),
-                  "sin_angle_R_leading_r": _sin_max_angle(sk.R.double().T[:, :r_].contiguous(), refR.T[:, :r_]),
-                  "rel_err_B": float(torch.linalg.norm(sk.B.double() - refB) / torch.linalg.norm(refB)),
-                  "rel_err_At": float(torch.linalg.norm(sk.At.double() - refAt) / torch.linalg.norm(refAt))}
+        vs_ref = None
+        if reference:
+            vs_ref = {"proj_residual_gap": abs(pres - ref_res),
+                      "orth_err_L": porth,
+                      "sin_angle_L_leading_r": _sin_max_angle(sk.L.double()[:, :r_], refL[:, :r_]),
+                      "sin_angle_R_leading_r": _sin_max_angle(sk.R.double().T[:, :r_].contiguous(), refR.T[:, :r_]),
+                      "rel_err_B": float(torch.linalg.norm(sk.B.double() - refB) / torch.linalg.norm(refB)),
+                      "rel_err_At": float(torch.linalg.norm(sk.At.double() - refAt) / torch.linalg.norm(refAt))}
         out[pd] = {"final_dtype": fd, "sketch_ms": ms, "sketch_tflops": flops / (ms * 1e-3) / 1e12,
                    "pass_ms": pass_ms, "pass_tflops": flops / (pass_ms * 1e-3) / 1e12,
                    "stages_ms": {k: v[0] / steps for k, v in agg.items() if v[2]},
@@ -208,9 +214,10 @@ def precision_section(h, steps, warmup):
     for pd in ("bf16", "fp8"):
         out[pd]["proj_residual_gap_vs_f32"] = abs(out[pd]["proj_residual"] - ref)
         out[pd]["speedup_vs_f32"] = out["f32"]["sketch_ms"] / out[pd]["sketch_ms"]
-    out["fp64_reference"] = {"kind": "PyTorch FP64 on the device (A cast to FP64 per row block, Householder QR "
-                                     "after every product, diag(R) >= 0), the same test matrices",
-                             "proj_residual": ref_res, "orth_err_L": ref_orth}
+    if reference:
+        out["fp64_reference"] = {"kind": "PyTorch FP64 on the device (A cast to FP64 per row block, Householder "
+                                         "QR after every product, diag(R) >= 0), the same test matrices",
+                                 "proj_residual": ref_res, "orth_err_L": ref_orth}
     del A, refL, refR, refB, refAt
     torch.cuda.empty_cache()
     return out
@@ -645,6 +652,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--precision-only", action="store_true",
                     help="only the precision sketches (for kernel profiles); prints that object")
+    ap.add_argument("--no-reference", action="store_true",
+                    help="with --precision-only: skip the FP64 reference sketch (for hardware-counter runs)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads, the attainable peaks and the host information")
@@ -677,7 +686,8 @@ def main():
         log("copy calibration: 3 copies of 1 GiB (read 1 GiB, write 1 GiB each)")
         del src, dst
     if args.precision_only:
-        print(json.dumps({"precision": precision_section(api.default_handle(), max(1, args.steps), args.warmup)}),
+        print(json.dumps({"precision": precision_section(api.default_handle(), max(1, args.steps), args.warmup,
+                                                         reference=not args.no_reference)}),
               flush=True)
         return
     if args.serving_only:

@@ -33,18 +33,22 @@ int choose_splits_n(int m, int n, int kk, int elem_bytes);
 int choose_splits_t(int m, int n, int kk, int elem_bytes);
 
 // Reduced-precision passes (k_lowp.hip).  A copy of A (m x n) and of A^T
-// (n x m) in BF16 or FP8 E4M3; FP8 copies carry one FP32 scale per
-// kFp8Tile x kFp8Tile tile of A (scale[ti * ntj + tj], ntj column tiles),
-// shared by the A^T copy.  Either output pointer may be NULL.
+// (n x m) in BF16 or FP8 E4M3, each padded with zeros to whole
+// kFp8Tile x kFp8Tile tiles (A: lowp_pad(m) rows, ldo >= lowp_pad(n);
+// A^T: lowp_pad(n) rows, ldt >= lowp_pad(m)); FP8 copies carry one FP32
+// power-of-two scale per tile of A (scale[ti * ntj + tj], ntj column
+// tiles), shared by the A^T copy.  Either output pointer may be NULL.
 constexpr int kFp8Tile = 128;
+inline int64_t lowp_pad(int64_t x) { return (x + kFp8Tile - 1) / kFp8Tile * kFp8Tile; }
 hipError_t launch_convert_lowp(const float* A, int64_t lda, int m, int n, __hip_bfloat16* A16, __hip_bfloat16* At16,
                                uint8_t* A8, uint8_t* At8, int64_t ldo, int64_t ldt, float* scale, hipStream_t st);
 // P[s][rows][kk] (FP32) = M (rows x cols, element size es: 2 BF16, 1 FP8,
-// ld ldm) times Xt^T (Xt kk x cols, same type, ld ldx), partial sums over
-// `splits` slices of the column range.  FP8: scale as above; scale_t = 1
-// when M is the A^T copy.
-hipError_t launch_gemm_lowp(int es, const void* M, int64_t ldm, int rows, int cols, const void* Xt, int64_t ldx,
-                            int kk, float* P, int splits, const float* scale, int scale_ld, int scale_t,
+// ld ldm, m_rows >= lowp_pad(rows) rows allocated) times Xt^T (Xt kk x
+// cols, same type, ld ldx), partial sums over `splits` slices of the column
+// range.  ldm, ldx >= lowp_pad(cols); the padding of M and Xt must be zero.
+// FP8: scale as above; scale_t = 1 when M is the A^T copy.
+hipError_t launch_gemm_lowp(int es, const void* M, int64_t ldm, int64_t m_rows, int rows, int cols, const void* Xt,
+                            int64_t ldx, int kk, float* P, int splits, const float* scale, int scale_ld, int scale_t,
                             hipStream_t st);
 int choose_splits_lowp(int rows, int cols, int kk, int es);
 // Columns [c0, c0 + k) of Q (rows x ldq, FP64) -> rows [dr0, dr0 + k) of the

@@ -1,19 +1,25 @@
 // Reduced-precision range-finder passes (BF16, FP8 E4M3 with per-tile
-// scales) on the gfx950 16x16x32 MFMAs with FP32 accumulation.
+// power-of-two scales) on the gfx950 MFMAs with FP32 accumulation: BF16 on
+// the 16x16x32 instruction, FP8 on the scaled 16x16x128 one (twice the FP8
+// rate of the 16x16x32 FP8 instruction), the tile's scale given to the
+// instruction as its block exponent.
 //
 // Layout: the FP32 input A is converted once into a copy of A and a copy of
 // A^T in the pass precision, so every pass is the same "rows of a matrix
-// times a tall operand" kernel reading contiguous rows.  The operand is
-// stored transposed (kk x cols), so each lane's eight K-consecutive operand
-// values are one 16-byte (BF16) or 8-byte (FP8) LDS read.
-// FP8: each 128 x 128 tile of A has its own scale s = max|tile| / 448; the
-// same tile grid serves A^T.  A pass accumulates each 128-column chunk
-// separately and adds s_tile times the chunk product to the accumulator.
+// times a tall operand" kernel reading contiguous rows.  Both copies are
+// padded to whole 128 x 128 tiles (rows and leading dimension), and the
+// padding holds zeros, so a pass reads whole 128-byte row chunks without
+// bounds checks.  The operand is stored transposed (kk x cols, zero beyond
+// the columns), so each lane's K-consecutive operand values are one or two
+// 16-byte loads.
+// FP8: each 128 x 128 tile of A has its own scale s = 2^e, the smallest
+// power of two with max|tile| / s <= 448; the same tile grid serves A^T.
 #include "cnmf_internal.hpp"
 
 namespace cnmf {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ uint8_t to_fp8(float x) {
   // round to nearest even, OCP E4M3 (gfx950 conversion)
@@ -21,11 +27,26 @@ __device__ __forceinline__ uint8_t to_fp8(float x) {
   return (uint8_t)(packed & 0xff);
 }
 
+// Exponent e of the FP8 tile scale 2^e for a tile maximum tmax > 0: with
+// tmax = f 2^t, f in [0.5, 1), tmax / 2^e <= 448 = 0.875 2^9 holds for
+// e = t - 9 when f <= 0.875 and needs e = t - 8 otherwise.  Clamped to
+// [-126, 127] so that the scale is a normal FP32 number (a tile whose
+// maximum is below 448 2^-126 loses its smallest values to FP8 underflow).
+__device__ __forceinline__ int fp8_tile_exponent(float tmax) {
+  int t = 0;
+  const float f = frexpf(tmax, &t);
+  const int e = f <= 0.875f ? t - 9 : t - 8;
+  return min(127, max(-126, e));
+}
+
 // ---------------------------------------------------------------------------
 // FP32 A -> reduced-precision copies of A (ld ldo) and A^T (ld ldt), one
-// workgroup per 128 x 128 tile of A.  BF16: round to nearest even.  FP8:
-// s = max|tile| / 448 (1 for an all-zero tile), element = e4m3(a * (1/s)),
-// s stored in scale[ti * ntj + tj].
+// workgroup per 128 x 128 tile of A.  The grid covers the padded matrix:
+// ceil(m / 128) 128 rows of A (ld ldo >= 128 ceil(n / 128)) and
+// ceil(n / 128) 128 rows of A^T (ld ldt >= 128 ceil(m / 128)); entries
+// outside m x n are written as zeros.  BF16: round to nearest even.  FP8:
+// s = 2^e as above (1 for an all-zero tile), element = e4m3(a * 2^-e), s
+// stored in scale[ti * ntj + tj].
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void convert_lowp_kernel(const float* __restrict__ A, int64_t lda, int m, int n,
                                                            __hip_bfloat16* __restrict__ A16,
@@ -55,7 +76,7 @@ __global__ __launch_bounds__(256) void convert_lowp_kernel(const float* __restri
       const int ii = ty + 2 * s, i = i0 + ii, j = j0 + tx;
       const __hip_bfloat16 q = __float2bfloat16(v[s]);
       t16[ii][tx] = q;
-      if (A16 && i < m && j < n) A16[(int64_t)i * ldo + j] = q;
+      if (A16) A16[(int64_t)i * ldo + j] = q;
     }
   }
   if (want8) {
@@ -66,15 +87,15 @@ __global__ __launch_bounds__(256) void convert_lowp_kernel(const float* __restri
       __syncthreads();
     }
     const float tmax = red[0];
-    const float sc = tmax > 0.0f ? tmax / 448.0f : 1.0f;
-    const float inv = 1.0f / sc;
+    const int e = tmax > 0.0f ? fp8_tile_exponent(tmax) : 0;
+    const float sc = ldexpf(1.0f, e), inv = ldexpf(1.0f, -e);
     if (threadIdx.x == 0) scale[ti * ntj + tj] = sc;
 #pragma unroll
     for (int s = 0; s < TS / 2; ++s) {
       const int ii = ty + 2 * s, i = i0 + ii, j = j0 + tx;
       const uint8_t q = to_fp8(v[s] * inv);
       t8[ii][tx] = q;
-      if (A8 && i < m && j < n) A8[(int64_t)i * ldo + j] = q;
+      if (A8) A8[(int64_t)i * ldo + j] = q;
     }
   }
   __syncthreads();
@@ -82,14 +103,14 @@ __global__ __launch_bounds__(256) void convert_lowp_kernel(const float* __restri
 #pragma unroll 8
     for (int s = 0; s < TS / 2; ++s) {
       const int jj = ty + 2 * s, j = j0 + jj, i = i0 + tx;
-      if (j < n && i < m) At16[(int64_t)j * ldt + i] = t16[tx][jj];
+      At16[(int64_t)j * ldt + i] = t16[tx][jj];
     }
   }
   if (At8) {
 #pragma unroll 8
     for (int s = 0; s < TS / 2; ++s) {
       const int jj = ty + 2 * s, j = j0 + jj, i = i0 + tx;
-      if (j < n && i < m) At8[(int64_t)j * ldt + i] = t8[tx][jj];
+      At8[(int64_t)j * ldt + i] = t8[tx][jj];
     }
   }
 }
@@ -97,6 +118,7 @@ __global__ __launch_bounds__(256) void convert_lowp_kernel(const float* __restri
 hipError_t launch_convert_lowp(const float* A, int64_t lda, int m, int n, __hip_bfloat16* A16, __hip_bfloat16* At16,
                                uint8_t* A8, uint8_t* At8, int64_t ldo, int64_t ldt, float* scale, hipStream_t st) {
   const int ntj = (n + kFp8Tile - 1) / kFp8Tile, nti = (m + kFp8Tile - 1) / kFp8Tile;
+  if (m < 1 || n < 1 || ldo < (int64_t)ntj * kFp8Tile || ldt < (int64_t)nti * kFp8Tile) return hipErrorInvalidValue;
   hipLaunchKernelGGL(convert_lowp_kernel, dim3(ntj, nti), dim3(256), 0, st, A, lda, m, n, A16, At16, A8, At8, ldo,
                      ldt, scale, ntj);
   CNMF_LAUNCH_CHECK();
@@ -104,217 +126,219 @@ hipError_t launch_convert_lowp(const float* A, int64_t lda, int m, int n, __hip_
 
 // ---------------------------------------------------------------------------
 // Y (partials [split][rows][kk], FP32) = M (rows x cols, element size ES,
-// ld ldm) times the operand given transposed as Xt (kk x cols, ld ldx),
-// kk <= 256.
-// Workgroup: 16 RB rows of M (RB row blocks of 16: 128 rows for BF16, 64
-// for FP8, whose per-chunk accumulators double the registers) and all kk
-// output columns;
-// wave w owns output column blocks [w KBW, (w + 1) KBW).  Per chunk of KC
-// columns of M (128 bytes per row): the 64 x KC tile of M is staged in LDS
-// (double buffered) and read by all four waves; each wave loads its own
-// operand rows for the chunk straight into registers (prefetched one chunk
-// ahead).  Operand traffic from L2 per byte of M is kk / (16 RB), LDS reads
-// per byte of M staged are 4.  Lane group g covers K [g KC/4, (g + 1) KC/4) of the chunk, eight
-// K values per MFMA step, the same mapping on both operands.
-// FP8: a chunk is one 128-column scale tile and the workgroup's rows lie in
-// one 128-row tile; the chunk's product is accumulated separately and added
-// to the FP32 accumulator times the tile scale.
+// ldm elements per row) times the operand given transposed as Xt (kk x cols,
+// ld ldx), kk <= 256.
+// Requirements (checked by the launcher where it can): M has m_rows >=
+// 128 ceil(rows / 128) rows, ldm and ldx hold whole 128-byte chunks and at
+// least 128 ceil(cols / 128) columns, the padding of M and of Xt is zero,
+// M, Xt 16-byte aligned.
+//
+// Workgroup: 512 threads, 256 rows of M and all kk output columns, one
+// workgroup per CU.  Wave w owns rows [128 (w / 4), + 128) and output column
+// blocks [(w % 4) KBW, + KBW).  M and Xt are read in chunks of 128 bytes per
+// row (KC = 128 / ES columns).  Every chunk of M (32 KB) and of Xt (kk x 128
+// bytes) goes straight from global memory into LDS (global_load_lds, 16
+// bytes per lane): M through a three-stage ring, issued two chunks ahead,
+// Xt through a two-stage ring, issued one chunk ahead (it comes from L2).
+// Nothing passes through registers on the way, so the only waits for the
+// loads are the explicit ones at the top of each step.  Within a row the
+// 16-byte segment j of a chunk sits in slot j ^ h(row), h(row) = (row & 7)
+// ^ ((row >> 3) & 1), so the fragment reads of 8 consecutive rows use 8
+// distinct slots, and those of 16 consecutive rows 16 distinct 16-byte bank
+// groups of a 256-byte bank line.  Lane group g covers
+// bytes [32 g, 32 g + 32) of a chunk row, the same mapping on both operands
+// (the MFMA's K order is the same for its two inputs, so any common
+// assignment sums the full dot product).
+// FP8: a chunk lies in one 128-column scale tile and a wave's rows in one
+// 128-row tile, so the tile's exponent is the instruction's block scale for
+// A (the operand's scale is 1) and products are accumulated in FP32
+// directly (the instruction adds C at FP32 precision).
 // ---------------------------------------------------------------------------
+typedef uint4 v16;
+
 template <int ES>
 struct Lowp;
 template <>
-struct Lowp<2> {  // BF16
-  typedef bf16x8 opnd;
-  static __device__ __forceinline__ void mma(const opnd& a, const opnd& b, floatx4& c) {
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+struct Lowp<2> {  // BF16: two 16x16x32 steps per 32-byte lane run
+  static __device__ __forceinline__ void mma(const v16 (&a)[2], const v16 (&b)[2], int, floatx4& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[0]), __builtin_bit_cast(bf16x8, b[0]),
+                                                c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[1]), __builtin_bit_cast(bf16x8, b[1]),
+                                                c, 0, 0, 0);
   }
-  // eight K-consecutive elements s of a lane's 32-byte run
-  static __device__ __forceinline__ opnd part(const uint4 (&v)[2], int s) { return __builtin_bit_cast(opnd, v[s]); }
 };
 template <>
-struct Lowp<1> {  // FP8 E4M3
-  typedef long opnd;
-  static __device__ __forceinline__ void mma(const opnd& a, const opnd& b, floatx4& c) {
-    c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+struct Lowp<1> {  // FP8 E4M3: one scaled 16x16x128 step per 32-byte lane run
+  static __device__ __forceinline__ intx8 cat(const v16 (&v)[2]) {
+    return intx8{(int)v[0].x, (int)v[0].y, (int)v[0].z, (int)v[0].w,
+                 (int)v[1].x, (int)v[1].y, (int)v[1].z, (int)v[1].w};
   }
-  static __device__ __forceinline__ opnd part(const uint4 (&v)[2], int s) {
-    const uint4 q = v[s >> 1];
-    const uint2 h = (s & 1) ? uint2{q.z, q.w} : uint2{q.x, q.y};
-    return __builtin_bit_cast(opnd, h);
+  static __device__ __forceinline__ void mma(const v16 (&a)[2], const v16 (&b)[2], int e8a, floatx4& c) {
+    // formats 0 / 0: E4M3 for both inputs; block exponents e8a for A, 127 (2^0) for the operand
+    c = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(a), cat(b), c, 0, 0, 0, e8a, 0, 127);
   }
 };
 
-typedef uint4 v16;
-
-// 32 bytes at p (16-byte aligned when vec), bytes at or beyond `lim` (a
-// byte count from p) read as zero.
-__device__ __forceinline__ void load32(const uint8_t* p, int lim, bool vec, v16 (&d)[2]) {
-  if (vec && lim >= 32) {
-    d[0] = *reinterpret_cast<const v16*>(p);
-    d[1] = *reinterpret_cast<const v16*>(p + 16);
-    return;
-  }
-#pragma unroll
-  for (int v = 0; v < 2; ++v) {
-    uint32_t wd[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      uint32_t val = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int byte = 16 * v + 4 * q + b;
-        if (byte < lim) val |= (uint32_t)p[byte] << (8 * b);
-      }
-      wd[q] = val;
-    }
-    d[v] = v16{wd[0], wd[1], wd[2], wd[3]};
-  }
+// LDS byte address of a pointer into a __shared__ array
+__device__ __forceinline__ uint32_t lds_addr(const uint8_t* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t*)p;
 }
 
-template <int ES, int KB, int RB>
-__global__ __launch_bounds__(256, 2) void gemm_lowp_kernel(const void* __restrict__ Mv, int64_t ldm, int rows,
-                                                           int cols, const void* __restrict__ Xv, int64_t ldx,
+// 16 bytes per lane from global memory into LDS: lane l's bytes land at
+// lds_base + 16 l (lds_base wave-uniform).  Written in asm so that the
+// compiler, which would otherwise wait for every such load in flight before
+// any LDS read, leaves the waiting to the explicit counts of the caller (the
+// instruction writes no registers).
+__device__ __forceinline__ void dma16(const void* gptr, uint32_t lds_base) {
+  asm volatile(
+      "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dwordx4 %0, off"
+      :
+      : "v"(gptr), "s"(lds_base)
+      : "memory", "m0");
+}
+
+constexpr int kLowpRows = 256;      // rows of M per workgroup
+constexpr int kLowpThreads = 512;
+constexpr int kLowpStagesA = 3;     // LDS ring depths (chunks)
+constexpr int kLowpStagesB = 2;
+
+template <int ES, int KB>
+__global__ __launch_bounds__(512, 1) void gemm_lowp_kernel(const uint8_t* M, int64_t ldmb, int64_t m_rows, int rows,
+                                                           int cols, const uint8_t* X, int64_t ldxb,
                                                            float* __restrict__ P, int cols_per_split,
                                                            const float* __restrict__ scale, int scale_ld,
                                                            int scale_transposed) {
-  typedef typename Lowp<ES>::opnd opnd;
-  constexpr bool SCALED = ES == 1;
-  constexpr int KC = 128 / ES;      // chunk columns (128 bytes per row)
-  constexpr int STEPS = KC / 32;    // MFMA steps per chunk
+  constexpr int KC = 128 / ES;        // chunk columns (128 bytes per row)
   constexpr int KK = 16 * KB;
-  constexpr int KBW = (KB + 3) / 4;  // column blocks per wave
-  constexpr int LDA = 128 + 16;      // LDS bytes per staged row
-  static_assert(kFp8Tile % KC == 0 && kFp8Tile % (16 * RB) == 0, "chunks and rows must stay in one scale tile");
-  __shared__ __attribute__((aligned(16))) uint8_t As[2][16 * RB * LDA];
-  const uint8_t* __restrict__ M = (const uint8_t*)Mv;
-  const uint8_t* __restrict__ X = (const uint8_t*)Xv;
+  constexpr int KBW = (KB + 3) / 4;   // column blocks per wave
+  constexpr int SA = kLowpRows * 128; // bytes per ring stage
+  constexpr int SB = KK * 128;
+  constexpr int BI = KK / 8;          // 1 KB DMA instructions per operand chunk
+  static_assert(kFp8Tile % KC == 0 && kFp8Tile == 128, "chunks and wave rows must stay in one scale tile");
+  static_assert(kLowpStagesA * SA + kLowpStagesB * SB <= 160 * 1024, "LDS");
+  __shared__ __attribute__((aligned(16))) uint8_t As[kLowpStagesA * SA];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[kLowpStagesB * SB];
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6;
+  const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 15, g = lane >> 4;
+  const int half = w >> 2, jb0 = (w & 3) * KBW;
   const int split = blockIdx.y;
   const int kbeg = split * cols_per_split;
   const int kend = min(cols, kbeg + cols_per_split);
   const int nchunk = kend > kbeg ? (kend - kbeg + KC - 1) / KC : 0;
-  const int row_blk = blockIdx.x * (16 * RB);
-  const int jb0 = w * KBW;
-  const bool vec_a = ((uintptr_t)M % 16 == 0) && ((ldm * ES) % 16 == 0);
-  const bool vec_x = ((uintptr_t)X % 16 == 0) && ((ldx * ES) % 16 == 0);
+  const int row_blk = blockIdx.x * kLowpRows;
 
-  floatx4 acc[RB][KBW];
-  floatx4 cacc[SCALED ? RB : 1][SCALED ? KBW : 1];
+  floatx4 acc[8][KBW];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+  for (int rb = 0; rb < 8; ++rb)
 #pragma unroll
     for (int jj = 0; jj < KBW; ++jj) acc[rb][jj] = floatx4{0, 0, 0, 0};
 
-  // staging of the M tile: thread t moves 32 bytes of rows t / 4 + 64 q
-  constexpr int SR = RB / 4;
-  const int srow = tid >> 2, sseg = tid & 3;
-  v16 ast[SR][2];
-  auto load_a = [&](int chunk) {
-    const int c0 = kbeg + chunk * KC + sseg * (KC / 4);
-#pragma unroll
-    for (int q = 0; q < SR; ++q) {
-      const int rr = row_blk + srow + 64 * q;
-      const bool ok = rr < rows;
-      const int lim = ok ? (kend - c0) * ES : 0;
-      load32(M + ((int64_t)(ok ? rr : 0) * ldm + c0) * ES, lim, vec_a, ast[q]);
-    }
-  };
-  auto store_a = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < SR; ++q) {
-      uint8_t* p = &As[buf][(srow + 64 * q) * LDA + sseg * 32];
-      *reinterpret_cast<v16*>(p) = ast[q][0];
-      *reinterpret_cast<v16*>(p + 16) = ast[q][1];
-    }
-  };
-  // this wave's operand fragments: lane (lr, g) of column block jj holds
-  // Xt[(jb0 + jj) 16 + lr][chunk cols g KC/4 .. + KC/4)
-  v16 bcur[KBW][2], bnxt[KBW][2];
-  auto load_b = [&](int chunk, v16 (&d)[KBW][2]) {
-    const int c0 = kbeg + chunk * KC + g * (KC / 4);
-    const int lim = (kend - c0) * ES;
-#pragma unroll
-    for (int jj = 0; jj < KBW; ++jj) {
-      if (jb0 + jj < KB) {
-        const uint8_t* p = X + ((int64_t)((jb0 + jj) * 16 + lr) * ldx + c0) * ES;
-        load32(p, lim, vec_x, d[jj]);
-      } else {
-        d[jj][0] = v16{0, 0, 0, 0};
-        d[jj][1] = v16{0, 0, 0, 0};
-      }
-    }
-  };
-
   if (nchunk > 0) {
-    load_a(0);
-    load_b(0, bcur);
-    store_a(0);
-  }
-  __syncthreads();
-  for (int ch = 0; ch < nchunk; ++ch) {
-    const int buf = ch & 1;
-    const bool more = ch + 1 < nchunk;
-    if (more) {
-      load_a(ch + 1);
-      load_b(ch + 1, bnxt);
+    // DMA lane mapping: an instruction moves 8 rows of 128 bytes (1 KB);
+    // lane l writes LDS bytes [16 l, 16 l + 16) of it, i.e. row 8 b + l / 8
+    // (b the instruction's row group), slot l % 8, which holds segment
+    // (l % 8) ^ h(row) = (l % 8) ^ (l / 8) ^ (b & 1)
+    const int drow = lane >> 3, dseg = (lane & 7) ^ drow;
+    // M: wave w moves rows [32 w, 32 w + 32) of a chunk, four instructions;
+    // rows past the allocation (the last tile) re-read its last row, whose
+    // results are not stored
+    const uint8_t* asrc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = min<int64_t>(row_blk + 32 * w + 8 * i + drow, m_rows - 1);
+      asrc[i] = M + r * ldmb + (int64_t)kbeg * ES + (dseg ^ (i & 1)) * 16;  // row group 4 w + i
     }
-    if (SCALED) {
+    // Xt: instruction i (rows 8 i .. 8 i + 7) is issued by wave i % 8
+    const uint8_t* bsrc = X + (int64_t)(8 * w + drow) * ldxb + (int64_t)kbeg * ES + (dseg ^ (w & 1)) * 16;
+    // the destination slot is always one that every wave has finished
+    // reading; past the last chunk the source is clamped to it and the slot
+    // is never read
+    const uint32_t as0 = lds_addr(As), bs0 = lds_addr(Bs);
+    auto issue_a = [&](int chunk) {
+      const int64_t off = (int64_t)min(chunk, nchunk - 1) * 128;
+      const uint32_t dst = as0 + (chunk % kLowpStagesA) * SA + 32 * w * 128;
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+      for (int i = 0; i < 4; ++i) dma16(asrc[i] + off, __builtin_amdgcn_readfirstlane(dst + 8 * i * 128));
+    };
+    auto issue_b = [&](int chunk) {
+      const int64_t off = (int64_t)min(chunk, nchunk - 1) * 128;
+      const uint32_t dst = bs0 + (chunk % kLowpStagesB) * SB + 8 * w * 128;
 #pragma unroll
-        for (int jj = 0; jj < KBW; ++jj) cacc[SCALED ? rb : 0][SCALED ? jj : 0] = floatx4{0, 0, 0, 0};
-    }
+      for (int i = 0; i < (BI + 7) / 8; ++i)
+        if (w + 8 * i < BI)
+          dma16(bsrc + (int64_t)(64 * i) * ldxb + off, __builtin_amdgcn_readfirstlane(dst + 64 * i * 128));
+    };
+    const int tr = (row_blk + 128 * half) / kFp8Tile;
+    // the loop for a wave owning NB column blocks (KBW, KB % KBW or none:
+    // a wave without columns still moves its share of every chunk)
+    auto run = [&](auto nb_const) {
+      constexpr int NB = decltype(nb_const)::value;
+      constexpr int NBA = NB > 0 ? NB : 1;
+      // order of issue: A(0), B(0), A(1) before the loop; step ch issues
+      // B(ch + 1), then A(ch + 2) (asm statements keep their order).  So at
+      // the top of step ch all but the last four DMAs of this wave (A(ch + 1))
+      // have landed, A(ch) and B(ch) among them; the barrier then covers
+      // every wave's share.
+      issue_a(0);
+      issue_b(0);
+      issue_a(1);
+      for (int ch = 0; ch < nchunk; ++ch) {
+        // (a plain barrier: the workgroup fence of __syncthreads would wait
+        // for every DMA in flight)
+        asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory");
+        issue_b(ch + 1);
+        issue_a(ch + 2);
+        if (NB > 0) {
+          int e8a = 127;
+          if (ES == 1) {
+            const int tc = (kbeg + ch * KC) / kFp8Tile;
+            const float sc =
+                scale_transposed ? scale[(int64_t)tc * scale_ld + tr] : scale[(int64_t)tr * scale_ld + tc];
+            e8a = (int)((__float_as_uint(sc) >> 23) & 0xffu);
+          }
+          // fragment reads: lane (lr, g) reads segments 2g and 2g + 1 of
+          // its row (h(16 i + lr) == (lr & 7) ^ (lr >> 3))
+          const int hl = (lr & 7) ^ (lr >> 3);
+          const uint32_t o0 = ((2 * g) ^ hl) << 4, o1 = ((2 * g + 1) ^ hl) << 4;
+          const uint8_t* bst = Bs + (ch % kLowpStagesB) * SB + (jb0 * 16 + lr) * 128;
+          v16 bf[NBA][2];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      v16 af[2];
-      const uint8_t* ap = &As[buf][(rb * 16 + lr) * LDA + g * 32];
-      af[0] = *reinterpret_cast<const v16*>(ap);
-      af[1] = *reinterpret_cast<const v16*>(ap + 16);
+          for (int jj = 0; jj < NB; ++jj) {
+            bf[jj][0] = *reinterpret_cast<const v16*>(bst + jj * 2048 + o0);
+            bf[jj][1] = *reinterpret_cast<const v16*>(bst + jj * 2048 + o1);
+          }
+          const uint8_t* ast = As + (ch % kLowpStagesA) * SA + (128 * half + lr) * 128;
 #pragma unroll
-      for (int s = 0; s < STEPS; ++s) {
-        const opnd a = Lowp<ES>::part(af, s);
+          for (int rb = 0; rb < 8; ++rb) {
+            v16 af[2];
+            af[0] = *reinterpret_cast<const v16*>(ast + rb * 2048 + o0);
+            af[1] = *reinterpret_cast<const v16*>(ast + rb * 2048 + o1);
 #pragma unroll
-        for (int jj = 0; jj < KBW; ++jj) {
-          if (jb0 + jj < KB) {
-            const opnd b = Lowp<ES>::part(bcur[jj], s);
-            if (SCALED)
-              Lowp<ES>::mma(a, b, cacc[SCALED ? rb : 0][SCALED ? jj : 0]);
-            else
-              Lowp<ES>::mma(a, b, acc[rb][jj]);
+            for (int jj = 0; jj < NB; ++jj) Lowp<ES>::mma(af, bf[jj], e8a, acc[rb][jj]);
           }
         }
       }
-    }
-    if (SCALED) {
-      const int tr = row_blk / kFp8Tile, tc = (kbeg + ch * KC) / kFp8Tile;
-      const float sc = scale_transposed ? scale[(int64_t)tc * scale_ld + tr] : scale[(int64_t)tr * scale_ld + tc];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int jj = 0; jj < KBW; ++jj)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            acc[rb][jj][i] = fmaf(sc, cacc[SCALED ? rb : 0][SCALED ? jj : 0][i], acc[rb][jj][i]);
-    }
-    if (more) {
-      store_a(buf ^ 1);
-#pragma unroll
-      for (int jj = 0; jj < KBW; ++jj) {
-        bcur[jj][0] = bnxt[jj][0];
-        bcur[jj][1] = bnxt[jj][1];
-      }
-    }
-    __syncthreads();
+    };
+    const int nb = min(KBW, max(0, KB - jb0));
+    if (nb == KBW)
+      run(std::integral_constant<int, KBW>());
+    else if (KB % KBW != 0 && nb == KB % KBW)
+      run(std::integral_constant<int, (KB % KBW)>());
+    else
+      run(std::integral_constant<int, 0>());
+    // drain the clamped DMAs issued past the last chunk before the wave ends
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
   float* out = P + (int64_t)split * rows * KK;
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+  for (int rb = 0; rb < 8; ++rb)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = row_blk + rb * 16 + 4 * g + i;
+      const int row = row_blk + 128 * half + rb * 16 + 4 * g + i;
       if (row < rows) {
 #pragma unroll
         for (int jj = 0; jj < KBW; ++jj)
@@ -324,34 +348,43 @@ __global__ __launch_bounds__(256, 2) void gemm_lowp_kernel(const void* __restric
 }
 
 int choose_splits_lowp(int rows, int cols, int kk, int es) {
-  // about 3000 workgroups (six rounds of two per CU) for latency hiding, while
-  // the FP32 partials stay below a tenth of the bytes of M read
-  const int tile_rows = es == 2 ? 128 : 64;
-  const int tiles = (rows + tile_rows - 1) / tile_rows;
-  int s = (3072 + tiles - 1) / tiles;
-  const int cap_bytes = (int)std::max<int64_t>(1, (int64_t)cols * es / (10LL * kk * 4));
-  s = std::min(s, cap_bytes);
-  s = std::min(s, std::max(1, cols / 256));
-  return std::max(1, std::min(s, 64));
+  // One workgroup per CU: the launch runs in ceil(W / CUs) rounds for W =
+  // tiles * splits workgroups, each reading 1 / W of M and writing one FP32
+  // partial per row.  Choose the split count (at most 16, at least 256
+  // columns per split) minimising rounds * (bytes per workgroup, partials
+  // included).
+  constexpr int kCUs = 256;
+  const int64_t tiles = (rows + kLowpRows - 1) / kLowpRows;
+  const double mbytes = (double)rows * cols * es, pbytes = (double)rows * kk * 4;
+  int best = 1;
+  double best_t = 0.0;
+  for (int s = 1; s <= 16 && (s == 1 || cols / s >= 256); ++s) {
+    const int64_t wgs = tiles * s;
+    const double t = (double)((wgs + kCUs - 1) / kCUs) * (mbytes + s * pbytes) / (double)wgs;
+    if (s == 1 || t < best_t * 0.999) {
+      best = s;
+      best_t = t;
+    }
+  }
+  return best;
 }
 
 template <int ES, int KB>
-static hipError_t gemm_lowp_kb(const void* M, int64_t ldm, int rows, int cols, const void* Xt, int64_t ldx,
+static hipError_t gemm_lowp_kb(const void* M, int64_t ldm, int64_t m_rows, int rows, int cols, const void* Xt, int64_t ldx,
                                float* P, int splits, const float* scale, int scale_ld, int scale_t, hipStream_t st) {
-  constexpr int RB = ES == 2 ? 8 : 4;
   int per = (cols + splits - 1) / splits;
   per = (per + 127) / 128 * 128;
-  dim3 grid((rows + 16 * RB - 1) / (16 * RB), splits);
-  hipLaunchKernelGGL((gemm_lowp_kernel<ES, KB, RB>), grid, dim3(256), 0, st, M, ldm, rows, cols, Xt, ldx, P, per,
-                     scale, scale_ld, scale_t);
+  dim3 grid((rows + kLowpRows - 1) / kLowpRows, splits);
+  hipLaunchKernelGGL((gemm_lowp_kernel<ES, KB>), grid, dim3(kLowpThreads), 0, st, (const uint8_t*)M, ldm * ES, m_rows,
+                     rows, cols, (const uint8_t*)Xt, ldx * ES, P, per, scale, scale_ld, scale_t);
   CNMF_LAUNCH_CHECK();
 }
 
 template <int ES>
-static hipError_t gemm_lowp_es(const void* M, int64_t ldm, int rows, int cols, const void* Xt, int64_t ldx, int kk,
+static hipError_t gemm_lowp_es(const void* M, int64_t ldm, int64_t m_rows, int rows, int cols, const void* Xt, int64_t ldx, int kk,
                                float* P, int splits, const float* scale, int scale_ld, int scale_t, hipStream_t st) {
 #define CNMF_LOWP_CASE(KB) \
-  case 16 * KB: return gemm_lowp_kb<ES, KB>(M, ldm, rows, cols, Xt, ldx, P, splits, scale, scale_ld, scale_t, st);
+  case 16 * KB: return gemm_lowp_kb<ES, KB>(M, ldm, m_rows, rows, cols, Xt, ldx, P, splits, scale, scale_ld, scale_t, st);
   switch (kk) {
     CNMF_LOWP_CASE(1)
     CNMF_LOWP_CASE(2)
@@ -374,12 +407,18 @@ static hipError_t gemm_lowp_es(const void* M, int64_t ldm, int rows, int cols, c
 #undef CNMF_LOWP_CASE
 }
 
-hipError_t launch_gemm_lowp(int es, const void* M, int64_t ldm, int rows, int cols, const void* Xt, int64_t ldx,
-                            int kk, float* P, int splits, const float* scale, int scale_ld, int scale_t,
+hipError_t launch_gemm_lowp(int es, const void* M, int64_t ldm, int64_t m_rows, int rows, int cols, const void* Xt,
+                            int64_t ldx, int kk, float* P, int splits, const float* scale, int scale_ld, int scale_t,
                             hipStream_t st) {
-  if (es == 2) return gemm_lowp_es<2>(M, ldm, rows, cols, Xt, ldx, kk, P, splits, nullptr, 0, 0, st);
-  if (es == 1) return gemm_lowp_es<1>(M, ldm, rows, cols, Xt, ldx, kk, P, splits, scale, scale_ld, scale_t, st);
-  return hipErrorInvalidValue;
+  if (es != 1 && es != 2) return hipErrorInvalidValue;
+  const int64_t cpad = ((int64_t)cols + 127) / 128 * 128;
+  if (rows < 1 || cols < 1 || splits < 1 || m_rows < lowp_pad(rows) ||
+      ldm < cpad || ldx < cpad || (ldm * es) % 128 != 0 || (ldx * es) % 16 != 0 || (uintptr_t)M % 16 != 0 ||
+      (uintptr_t)Xt % 16 != 0)
+    return hipErrorInvalidValue;
+  if (es == 2) return gemm_lowp_es<2>(M, ldm, m_rows, rows, cols, Xt, ldx, kk, P, splits, nullptr, 0, 0, st);
+  if (!scale) return hipErrorInvalidValue;
+  return gemm_lowp_es<1>(M, ldm, m_rows, rows, cols, Xt, ldx, kk, P, splits, scale, scale_ld, scale_t, st);
 }
 
 // ---------------------------------------------------------------------------

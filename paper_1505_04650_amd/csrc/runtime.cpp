@@ -279,6 +279,7 @@ struct SketchWs {
   int gparts = 0;
   size_t ppart_elems = 0;
   // reduced-precision passes: copies of A (m x ldo) and A^T (n x ldt),
+  // padded with zeros to whole 128 x 128 tiles,
   // FP8 tile scales, transposed operands (kkmax x ldo / kkmax x ldt, 2-byte
   // slots) and their FP8 column scales (A passes [0, 128), A^T [128, 256))
   __hip_bfloat16* A16 = nullptr;
@@ -347,15 +348,15 @@ void layout_sketch(Arena& a, SketchWs<T>& w, int64_t m, int64_t n, int k, const 
   w.Acb = want_ac ? a.take<T>((size_t)m * k) : nullptr;
   w.At = a.take<double>((size_t)k * k);
   if (need16 || need8) {
-    w.ldo = (n + 63) / 64 * 64;
-    w.ldt = (m + 63) / 64 * 64;
+    w.ldo = lowp_pad(n);
+    w.ldt = lowp_pad(m);
     if (need16) {
-      w.A16 = a.take<__hip_bfloat16>((size_t)m * w.ldo);
-      w.At16 = a.take<__hip_bfloat16>((size_t)n * w.ldt);
+      w.A16 = a.take<__hip_bfloat16>((size_t)lowp_pad(m) * w.ldo);
+      w.At16 = a.take<__hip_bfloat16>((size_t)lowp_pad(n) * w.ldt);
     }
     if (need8) {
-      w.A8 = a.take<uint8_t>((size_t)m * w.ldo);
-      w.At8 = a.take<uint8_t>((size_t)n * w.ldt);
+      w.A8 = a.take<uint8_t>((size_t)lowp_pad(m) * w.ldo);
+      w.At8 = a.take<uint8_t>((size_t)lowp_pad(n) * w.ldt);
       w.ntj = (int)((n + kFp8Tile - 1) / kFp8Tile);
       w.tscale = a.take<float>((size_t)w.ntj * ((m + kFp8Tile - 1) / kFp8Tile));
     }
@@ -906,7 +907,8 @@ cnmf_status run_sketch(cnmf_handle* h, const cnmf_input* A, const cnmf_sketch_de
           const int es = lowp_es(p.prec);
           const void* M = es == 2 ? (p.dirN ? (const void*)w.A16 : (const void*)w.At16)
                                   : (p.dirN ? (const void*)w.A8 : (const void*)w.At8);
-          HIPCHK(h, launch_gemm_lowp(es, M, p.dirN ? w.ldo : w.ldt, rows, p.dirN ? n : m, xt_for(p), xt_ld(p), p.kk,
+          HIPCHK(h, launch_gemm_lowp(es, M, p.dirN ? w.ldo : w.ldt, lowp_pad(rows), rows, p.dirN ? n : m, xt_for(p),
+                                     xt_ld(p), p.kk,
                                      splits > 1 ? w.Ppart : w.Y, splits, w.tscale, w.ntj, p.dirN ? 0 : 1, st));
         }
       } else {
@@ -2049,13 +2051,13 @@ cnmf_status cnmf_range_product_lowp(cnmf_handle* h, const cnmf_input* A, int tra
   const int m = (int)A->m, n = (int)A->n, kk = ru16(kx);
   const int rows_out = trans ? n : m, cols = trans ? m : n;
   const int es = lowp_es(pass_dtype);
-  const int64_t ldo = (n + 63) / 64 * 64, ldt = (m + 63) / 64 * 64;
+  const int64_t ldo = lowp_pad(n), ldt = lowp_pad(m);
   const int64_t ldm = trans ? ldt : ldo;
   const int ntj = (n + kFp8Tile - 1) / kFp8Tile, nti = (m + kFp8Tile - 1) / kFp8Tile;
   const int splits = choose_splits_lowp(rows_out, cols, kk, es);
   auto layout = [&](Arena& a, uint8_t** Mc, float** tsc, uint8_t** Xt, float** cs, float** Yp, float** Pp,
                     unsigned long long** cm) {
-    *Mc = a.take<uint8_t>((size_t)es * (trans ? n : m) * ldm);
+    *Mc = a.take<uint8_t>((size_t)es * lowp_pad(rows_out) * ldm);
     *tsc = a.take<float>((size_t)ntj * nti);
     *Xt = a.take<uint8_t>((size_t)es * kk * ldm);
     *cs = a.take<float>(128);
@@ -2082,7 +2084,8 @@ cnmf_status cnmf_range_product_lowp(cnmf_handle* h, const cnmf_input* A, int tra
   HIPCHK(h, launch_fill(Xt, (size_t)es * kk * ldm, st));
   HIPCHK(h, launch_store_lowp(es, X_dev, cols, kx, 0, kx, Xt, ldm, 0, cs, 0, cm, st));
   float* dst = splits > 1 ? Pp : Yp;
-  HIPCHK(h, launch_gemm_lowp(es, Mc, ldm, rows_out, cols, Xt, ldm, kk, dst, splits, tsc, ntj, trans, st));
+  HIPCHK(h, launch_gemm_lowp(es, Mc, ldm, lowp_pad(rows_out), rows_out, cols, Xt, ldm, kk, dst, splits, tsc, ntj,
+                             trans, st));
   if (splits > 1) HIPCHK(h, launch_reduce_splits<float>(Pp, splits, rows_out, kk, Yp, st));
   if (es == 1) HIPCHK(h, launch_unscale_cols(Yp, rows_out, kk, kx, cs, st));
   HIPCHK(h, (launch_copy2d<float, float>(Yp, kk, Y_dev, kx, rows_out, kx, 1.0, st)));

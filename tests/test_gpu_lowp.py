@@ -4,8 +4,8 @@ accumulation, FP64 CholeskyQR2), through the C ABI.
 Two levels:
   * the pass kernel against a host emulation of its rounding: A and the
     operand are rounded exactly as the kernels round them (BF16 round to
-    nearest even; FP8 E4M3 with a per-128x128-tile scale for A and a
-    power-of-two column scale for the operand), the product of the rounded
+    nearest even; FP8 E4M3 with a power-of-two scale per 128x128 tile of A
+    and a power-of-two column scale for the operand), the product of the rounded
     values is taken in FP64, and the GPU's FP32 accumulation must agree to
     a bound derived from the FP32 unit roundoff;
   * the whole sketch / factorisation against the FP64 oracle: the error of
@@ -69,18 +69,26 @@ def e4m3(x):
     return np.sign(x) * r
 
 
+def tile_exponent(tmax):
+    """Smallest e with tmax / 2^e <= 448 (written from that definition: a
+    search from above), clamped to [-126, 127]."""
+    e = 127
+    while e > -126 and tmax / 2.0 ** (e - 1) <= 448.0:
+        e -= 1
+    return e
+
+
 def quant_a_fp8(A32):
-    """A (float32) -> dequantised FP8 copy with per-tile scales."""
+    """A (float32) -> dequantised FP8 copy with per-tile power-of-two scales."""
     m, n = A32.shape
     out = np.empty((m, n), dtype=np.float64)
     for i0 in range(0, m, TILE):
         for j0 in range(0, n, TILE):
             t = A32[i0:i0 + TILE, j0:j0 + TILE]
-            tmax = np.float32(np.abs(t).max())
-            sc = np.float32(tmax / np.float32(448.0)) if tmax > 0 else np.float32(1.0)
-            inv = np.float32(np.float32(1.0) / sc)
-            q = e4m3((t * inv).astype(np.float32))
-            out[i0:i0 + TILE, j0:j0 + TILE] = q * np.float64(sc)
+            tmax = float(np.abs(t).max())
+            e = tile_exponent(tmax) if tmax > 0 else 0
+            q = e4m3(t.astype(np.float64) * 2.0 ** -e)
+            out[i0:i0 + TILE, j0:j0 + TILE] = q * 2.0 ** e
     return out
 
 
@@ -114,13 +122,15 @@ def test_lowp_pass_matches_emulated_rounding(kind, shape):
     W = host(api.range_product_lowp(Ad, dev(Z), trans=True, pass_dtype=kind))
     Aq = bf16(A32) if kind == "bf16" else quant_a_fp8(A32)
     Xq, Zq = quant_x(X, kind), quant_x(Z, kind)
-    # FP32 accumulation: |error| <= c * n * u * (|A| |X|), u = 2^-24; the
-    # per-tile rescaling adds one more rounding per 128 columns.  The FP8
-    # MFMA itself does not add its products exactly: it aligns a group of
-    # products to the group's largest exponent and keeps about 13 bits below
-    # it (measured on gfx950: a product of -110 next to one of 114688 entered
-    # the sum as -104).  The kernel promotes every 128-column chunk into FP32,
-    # so that loss is bounded per chunk; 2^-9 of the chunk's |A| |X| covers it.
+    # FP32 accumulation: |error| <= c * n * u * (|A| |X|), u = 2^-24, plus
+    # one rounding per 128-column chunk.  The FP8 MFMA itself does not add
+    # its products exactly: it aligns a group of products to the group's
+    # largest exponent and keeps about 13 bits below it (measured on gfx950:
+    # a product of -110 next to one of 114688 entered the sum as -104, and
+    # -3.375 next to 114688 vanished), while the accumulator it adds them to
+    # keeps FP32 precision (2^20 + 1 stays exact).  Every 128-column chunk is
+    # one instruction, so that loss is bounded per chunk; 2^-9 of the chunk's
+    # |A| |X| covers it.
     for got, ref, bound in ((Y, Aq @ Xq, np.abs(Aq) @ np.abs(Xq)), (W, Aq.T @ Zq, np.abs(Aq.T) @ np.abs(Zq))):
         kdim = n if got is Y else m
         tol = 4.0 * (kdim + 2 * (kdim // TILE + 1)) * 2.0 ** -24 + (2.0 ** -9 if kind == "fp8" else 0.0)
