@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256, 2) void gemm_t_kernel(const T* __restrict__ A,
   constexpr int KC = 32;
   constexpr int G = KC / 4;
   constexpr int KK = 16 * KB;
-  constexpr int LDZ = KK + 1;
+  constexpr int LDZ = KK + 2;   // group g reads rows g G + s: 8 LDZ = 16 mod 64 words keeps the four groups on distinct banks
   constexpr int ZPER = KC * KK / 256;
   constexpr int CW = 16 * VW;  // columns per wave
   __shared__ T Zs[2][KC * LDZ];
