@@ -159,15 +159,23 @@ __global__ __launch_bounds__(256, 2) void gemm_n_kernel(const T* __restrict__ A,
       load_a(ch + 1, a_nxt);
       load_x(ch + 1);
     }
+    // operand values of step s + 1 are read from LDS while step s's
+    // products issue (the scheduling barrier keeps the reads ahead)
     const T* xs = Xs[buf] + (g * G) * LDX + r;
+    T bb[2][KB];
+#pragma unroll
+    for (int jb = 0; jb < KB; ++jb) bb[0][jb] = xs[jb * 16];
 #pragma unroll
     for (int s = 0; s < G; ++s) {
+      if (s + 1 < G) {
 #pragma unroll
-      for (int jb = 0; jb < KB; ++jb) {
-        T b = xs[s * LDX + jb * 16];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) Mfma<T>::mma(a_cur[rb][s], b, acc[rb][jb]);
+        for (int jb = 0; jb < KB; ++jb) bb[(s + 1) & 1][jb] = xs[(s + 1) * LDX + jb * 16];
       }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int jb = 0; jb < KB; ++jb)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) Mfma<T>::mma(a_cur[rb][s], bb[s & 1][jb], acc[rb][jb]);
     }
     if (more) store_x(buf ^ 1);
     __syncthreads();
@@ -284,15 +292,23 @@ __global__ __launch_bounds__(256, 2) void gemm_t_kernel(const T* __restrict__ A,
       load_a(ch + 1, a_nxt);
       load_z(ch + 1);
     }
+    // operand values of step s + 1 are read from LDS while step s's
+    // products issue (the scheduling barrier keeps the reads ahead)
     const T* zs = Zs[buf] + (g * G) * LDZ + r;
+    T bb[2][KB];
+#pragma unroll
+    for (int jb = 0; jb < KB; ++jb) bb[0][jb] = zs[jb * 16];
 #pragma unroll
     for (int s = 0; s < G; ++s) {
+      if (s + 1 < G) {
 #pragma unroll
-      for (int jb = 0; jb < KB; ++jb) {
-        T b = zs[s * LDZ + jb * 16];
-#pragma unroll
-        for (int e = 0; e < VW; ++e) Mfma<T>::mma(a_cur[s][e], b, acc[e][jb]);
+        for (int jb = 0; jb < KB; ++jb) bb[(s + 1) & 1][jb] = zs[(s + 1) * LDZ + jb * 16];
       }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int jb = 0; jb < KB; ++jb)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) Mfma<T>::mma(a_cur[s][e], bb[s & 1][jb], acc[e][jb]);
     }
     if (more) store_z(buf ^ 1);
     __syncthreads();
