@@ -7,6 +7,7 @@
 // columns; each slice writes its own partial (no atomics), and the partials
 // are summed later in a fixed order, so results are bit-reproducible.
 #include "cnmf_internal.hpp"
+#include "lds_dma.hpp"
 
 namespace cnmf {
 
@@ -202,6 +203,166 @@ __global__ __launch_bounds__(256, 2) void gemm_n_kernel(const T* __restrict__ A,
 }
 
 // ---------------------------------------------------------------------------
+// Y = A X for FP32 A whose rows are 16-byte aligned with n % 4 == 0: both
+// operands stream from global memory into LDS rings (global_load_lds, 16
+// bytes per lane), so the only waits for the loads are the explicit counts
+// at the top of each step and the waves spend their issue slots on the MFMA.
+// Workgroup: 512 threads, 256 rows of A and all KK operand columns, one
+// workgroup per CU; wave w owns rows [128 (w / 4), + 128) and column blocks
+// [(w % 4) KBW, + KBW).  A chunk: 32 columns (128 bytes per row) through a
+// three-stage ring issued two chunks ahead, the 16-byte segment j of a row
+// in slot j ^ h(row), h(row) = (row & 7) ^ ((row >> 3) & 1); X chunk: its 32
+// operand rows (KK floats each) through a two-stage ring, for KK = 64 or 128
+// the segment j of row k in slot j ^ (4 ((k >> 3) & 3)), so that the four
+// lane groups read distinct banks.  Lane (r, g) holds the chunk columns
+// 8 g .. 8 g + 7 of its rows and multiplies them with operand rows 8 g + t in
+// step t (a K permutation both operands share).  Segments of A past the end
+// of the split re-read an in-range segment, and the matching operand rows are
+// zeroed in LDS after they land, so the last chunk needs no other guard.
+// ---------------------------------------------------------------------------
+constexpr int kDmaRows = 256;
+
+template <int KB>
+__global__ __launch_bounds__(512, 1) void gemm_n_dma_kernel(const float* A, int64_t lda, int m, int n,
+                                                            const float* X, float* __restrict__ P,
+                                                            int cols_per_split, int ntiles, int nsplits) {
+  constexpr int KK = 16 * KB, KBW = (KB + 3) / 4;
+  constexpr int SA = kDmaRows * 128;   // bytes per A stage
+  constexpr int SB = 32 * KK * 4;      // bytes per X stage
+  constexpr int RSEG = KK / 4;         // 16-byte segments per operand row
+  constexpr int BI = 32 * RSEG / 64;   // 1 KB DMA instructions per operand chunk
+  constexpr bool SWB = RSEG % 16 == 0;
+  __shared__ __attribute__((aligned(16))) uint8_t As[3 * SA];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[2 * SB];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, g = lane >> 4;
+  const int half = w >> 2, jb0 = (w & 3) * KBW;
+  int tile, split;
+  xcd_tile(ntiles, nsplits, tile, split);
+  const int kbeg = split * cols_per_split;
+  const int kend = min(n, kbeg + cols_per_split);
+  const int nchunk = kend > kbeg ? (kend - kbeg + 31) / 32 : 0;
+  const int row_blk = tile * kDmaRows;
+
+  floatx4 acc[8][KBW];
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+    for (int jj = 0; jj < KBW; ++jj) acc[rb][jj] = floatx4{0, 0, 0, 0};
+
+  if (nchunk > 0) {
+    const uint32_t as0 = lds_addr(As), bs0 = lds_addr(Bs);
+    // A: wave w moves rows [32 w, 32 w + 32) of a chunk, eight per
+    // instruction; lane l: row 8 b + l / 8 (b = 4 w + i), slot l % 8, which
+    // holds segment (l % 8) ^ (l / 8) ^ (b & 1); rows past m re-read row m - 1
+    const int drow = lane >> 3;
+    const float* abase[4];
+    int aseg[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = min(row_blk + 32 * w + 8 * i + drow, m - 1);
+      abase[i] = A + (int64_t)r * lda + kbeg;
+      aseg[i] = (lane & 7) ^ drow ^ (i & 1);
+    }
+    auto issue_a = [&](int chunk) {
+      const int c0 = 32 * min(chunk, nchunk - 1);
+      const uint32_t dst = as0 + (chunk % 3) * SA + 32 * w * 128;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int sg = (kbeg + c0 + 4 * aseg[i] < kend) ? aseg[i] : 0;
+        dma16(abase[i] + c0 + 4 * sg, __builtin_amdgcn_readfirstlane(dst + 8 * i * 128));
+      }
+    };
+    // X: instruction i covers LDS segments [64 i, 64 i + 64) of the stage
+    // and is issued by wave i % 8; operand rows past the end re-read the
+    // chunk's first row (zeroed after landing)
+    auto issue_b = [&](int chunk) {
+      const int c0 = 32 * min(chunk, nchunk - 1);
+      const uint32_t dst0 = bs0 + (chunk % 2) * SB;
+      for (int i = w; i < BI; i += 8) {
+        const int p = 64 * i + lane;
+        const int row = p / RSEG, slot = p - row * RSEG;
+        const int seg = SWB ? (slot ^ (((row >> 3) & 3) << 2)) : slot;
+        const int krow = kbeg + c0 + (kbeg + c0 + row < kend ? row : 0);
+        dma16(X + (int64_t)krow * KK + 4 * seg, __builtin_amdgcn_readfirstlane(dst0 + 64 * i * 16));
+      }
+    };
+    const int hl = (lr & 7) ^ (lr >> 3);
+    const uint32_t o0 = ((2 * g) ^ hl) << 4, o1 = ((2 * g + 1) ^ hl) << 4;
+    auto run = [&](auto nb_const) {
+      constexpr int NB = decltype(nb_const)::value;
+      constexpr int NBA = NB > 0 ? NB : 1;
+      // order of issue: A(0), B(0), A(1); step ch issues B(ch + 1), then
+      // A(ch + 2): at the top of step ch all but this wave's last four DMAs
+      // (A(ch + 1)) have landed
+      issue_a(0);
+      issue_b(0);
+      issue_a(1);
+      for (int ch = 0; ch < nchunk; ++ch) {
+        // (a plain barrier: the fence of __syncthreads would wait for every DMA)
+        asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory");
+        const int valid = min(32, kend - kbeg - 32 * ch);
+        if (valid < 32) {
+          float* bz = reinterpret_cast<float*>(Bs + (ch % 2) * SB);
+          for (int e = tid; e < (32 - valid) * KK; e += 512) bz[valid * KK + e] = 0.0f;
+          __syncthreads();
+        }
+        issue_b(ch + 1);
+        issue_a(ch + 2);
+        if (NB > 0) {
+          const float* bst = reinterpret_cast<const float*>(Bs + (ch % 2) * SB);
+          float bf[NBA][8];
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) {
+            const int col = (jb0 + jj) * 16 + lr;
+            const int slot = SWB ? ((col >> 2) ^ (g << 2)) : (col >> 2);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) bf[jj][t] = bst[(8 * g + t) * KK + 4 * slot + (col & 3)];
+          }
+          const uint8_t* ast = As + (ch % 3) * SA + (128 * half + lr) * 128;
+          float af[8][8];
+#pragma unroll
+          for (int rb = 0; rb < 8; ++rb) {
+            const float4 x0 = *reinterpret_cast<const float4*>(ast + rb * 2048 + o0);
+            const float4 x1 = *reinterpret_cast<const float4*>(ast + rb * 2048 + o1);
+            af[rb][0] = x0.x; af[rb][1] = x0.y; af[rb][2] = x0.z; af[rb][3] = x0.w;
+            af[rb][4] = x1.x; af[rb][5] = x1.y; af[rb][6] = x1.z; af[rb][7] = x1.w;
+          }
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+#pragma unroll
+            for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+              for (int jj = 0; jj < NB; ++jj) Mfma<float>::mma(af[rb][t], bf[jj][t], acc[rb][jj]);
+        }
+      }
+    };
+    const int nb = min(KBW, max(0, KB - jb0));
+    if (nb == KBW)
+      run(std::integral_constant<int, KBW>());
+    else if (KB % KBW != 0 && nb == KB % KBW)
+      run(std::integral_constant<int, (KB % KBW)>());
+    else
+      run(std::integral_constant<int, 0>());
+    // drain the clamped DMAs issued past the last chunk before the wave ends
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+  float* out = P + (int64_t)split * m * KK;
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = row_blk + 128 * half + rb * 16 + 4 * g + i;
+      if (row < m) {
+#pragma unroll
+        for (int jj = 0; jj < KBW; ++jj)
+          if (jb0 + jj < KB) out[(int64_t)row * KK + (jb0 + jj) * 16 + lr] = acc[rb][jj][i];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // W = A^T Z.  MFMA M index = column of A, N = operand column, K = row of A.
 // Lane (r, g) loads VW consecutive columns [4.. of its 16-lane group] of a
 // row: column col_w + VW*r + e belongs to MFMA block e at M index r.  Per K
@@ -380,7 +541,29 @@ static int choose_splits(int tiles, int klen, int min_per_split, int wg_per_cu =
 // operand width makes the register budget spill.
 static constexpr int rb_for(int kb, int elem_bytes) { return (elem_bytes == 4 && kb != 6 && kb != 7) ? 2 : 1; }
 
+// FP32 A X runs the LDS-ring kernel (one 256-row workgroup per CU) when the
+// rows allow it; the split count is chosen for that kernel (any count is
+// valid for the other one, used when A's rows are not 16-byte aligned):
+// minimise rounds * (bytes per workgroup, partials included).
+static int choose_splits_dma(int m, int n, int kk) {
+  const int cus = num_cu();
+  const int64_t tiles = (m + kDmaRows - 1) / kDmaRows;
+  const double abytes = 4.0 * m * n, pbytes = 4.0 * m * kk;
+  int best = 1;
+  double best_t = 0.0;
+  for (int s = 1; s <= 64 && (s == 1 || n / s >= 128); ++s) {
+    const int64_t wgs = tiles * s;
+    const double t = (double)((wgs + cus - 1) / cus) * (abytes + s * pbytes) / (double)wgs;
+    if (s == 1 || t < best_t * 0.999) {
+      best = s;
+      best_t = t;
+    }
+  }
+  return best;
+}
+
 int choose_splits_n(int m, int n, int kk, int elem_bytes) {
+  if (elem_bytes == 4 && kk <= 128 && n % 4 == 0) return choose_splits_dma(m, n, kk);
   int rb = rb_for(kk / 16, elem_bytes);
   int tiles = (m + 64 * rb - 1) / (64 * rb);
   return choose_splits(tiles, n, 512);
@@ -405,9 +588,19 @@ static hipError_t gemm_n_kb(const T* A, int64_t lda, int m, int n, const T* X, T
   constexpr int KC = sizeof(T) == 4 ? 64 : 32;
   int per = (n + splits - 1) / splits;
   per = (per + KC - 1) / KC * KC;
+  bool vec = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(T)) % 16 == 0);
+  if constexpr (sizeof(T) == 4) {
+    if (vec && n % 4 == 0 && (uintptr_t)X % 16 == 0) {
+      int per32 = (n + splits - 1) / splits;
+      per32 = (per32 + 31) / 32 * 32;
+      const int nt = (m + kDmaRows - 1) / kDmaRows;
+      hipLaunchKernelGGL((gemm_n_dma_kernel<KB>), dim3(nt * splits), dim3(512), 0, st, (const float*)A, lda, m, n,
+                         (const float*)X, (float*)P, per32, nt, splits);
+      CNMF_LAUNCH_CHECK();
+    }
+  }
   const int ntiles = (m + 64 * RB - 1) / (64 * RB);
   dim3 grid(ntiles * splits);
-  bool vec = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(T)) % 16 == 0);
   if (vec)
     hipLaunchKernelGGL((gemm_n_kernel<T, KB, RB, true>), grid, dim3(256), 0, st, A, lda, m, n, X, P, per, ntiles,
                        splits);

@@ -15,6 +15,7 @@
 // FP8: each 128 x 128 tile of A has its own scale s = 2^e, the smallest
 // power of two with max|tile| / s <= 448; the same tile grid serves A^T.
 #include "cnmf_internal.hpp"
+#include "lds_dma.hpp"
 
 namespace cnmf {
 
@@ -178,26 +179,6 @@ struct Lowp<1> {  // FP8 E4M3: one scaled 16x16x128 step per 32-byte lane run
     c = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(a), cat(b), c, 0, 0, 0, e8a, 0, 127);
   }
 };
-
-// LDS byte address of a pointer into a __shared__ array
-__device__ __forceinline__ uint32_t lds_addr(const uint8_t* p) {
-  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t*)p;
-}
-
-// 16 bytes per lane from global memory into LDS: lane l's bytes land at
-// lds_base + 16 l (lds_base wave-uniform).  Written in asm so that the
-// compiler, which would otherwise wait for every such load in flight before
-// any LDS read, leaves the waiting to the explicit counts of the caller (the
-// instruction writes no registers).
-__device__ __forceinline__ void dma16(const void* gptr, uint32_t lds_base) {
-  asm volatile(
-      "s_mov_b32 m0, %1\n\t"
-      "s_nop 0\n\t"
-      "global_load_lds_dwordx4 %0, off"
-      :
-      : "v"(gptr), "s"(lds_base)
-      : "memory", "m0");
-}
 
 constexpr int kLowpRows = 256;      // rows of M per workgroup
 constexpr int kLowpThreads = 512;
