@@ -363,6 +363,144 @@ __global__ __launch_bounds__(512, 1) void gemm_n_dma_kernel(const float* A, int6
 }
 
 // ---------------------------------------------------------------------------
+// W = A^T Z for FP32 A with 16-byte aligned rows (n % 4 == 0), the same LDS
+// rings as gemm_n_dma_kernel with the roles of A's dimensions swapped: a
+// workgroup owns 256 columns of A (MFMA M index) and a slice of its rows
+// (K); a chunk is 32 rows of A restricted to the workgroup's columns (1 KB
+// per row, one DMA instruction) and the same 32 rows of Z.  In both stages
+// the 16-byte segment j of chunk row k sits in slot j ^ (4 ((k >> 3) & 3)),
+// so that lane groups g (rows 8 g + t in step t) read distinct banks; lane
+// (r, g) reads one A value per step (column r of its block).  Columns past
+// n re-read the tile's first segment (their results are not stored); rows
+// past the slice re-read its first row and meet zeroed rows of Z.
+// ---------------------------------------------------------------------------
+template <int KB>
+__global__ __launch_bounds__(512, 1) void gemm_t_dma_kernel(const float* A, int64_t lda, int m, int n,
+                                                            const float* Z, float* __restrict__ P,
+                                                            int rows_per_split, int ntiles, int nsplits) {
+  constexpr int KK = 16 * KB, KBW = (KB + 3) / 4;
+  constexpr int SA = 32 * kDmaRows * 4;   // bytes per A stage: 32 rows x 256 columns
+  constexpr int SB = 32 * KK * 4;         // bytes per Z stage
+  constexpr int RSEG = KK / 4;
+  constexpr int BI = 32 * RSEG / 64;
+  constexpr bool SWB = RSEG % 16 == 0;
+  __shared__ __attribute__((aligned(16))) uint8_t As[3 * SA];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[2 * SB];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, g = lane >> 4;
+  const int half = w >> 2, jb0 = (w & 3) * KBW;
+  int tile, split;
+  xcd_tile(ntiles, nsplits, tile, split);
+  const int ibeg = split * rows_per_split;
+  const int iend = min(m, ibeg + rows_per_split);
+  const int nchunk = iend > ibeg ? (iend - ibeg + 31) / 32 : 0;
+  const int col_blk = tile * kDmaRows;
+
+  floatx4 acc[8][KBW];
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+    for (int jj = 0; jj < KBW; ++jj) acc[rb][jj] = floatx4{0, 0, 0, 0};
+
+  if (nchunk > 0) {
+    const uint32_t as0 = lds_addr(As), bs0 = lds_addr(Bs);
+    // A: wave w moves chunk rows 4 w .. 4 w + 3, one 1 KB instruction each;
+    // lane l writes slot l, which holds segment l ^ (4 ((row >> 3) & 3)) of
+    // the row's 256 columns (row >> 3 == w >> 1)
+    const int aseg = lane ^ (((w >> 1) & 3) << 2);
+    const int acol = (col_blk + 4 * aseg + 4 <= n) ? col_blk + 4 * aseg : col_blk;
+    auto issue_a = [&](int chunk) {
+      const int c0 = 32 * min(chunk, nchunk - 1);
+      const uint32_t dst = as0 + (chunk % 3) * SA + 4 * w * 1024;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = ibeg + c0 + 4 * w + i;
+        const int srow = row < iend ? row : ibeg + c0;
+        dma16(A + (int64_t)srow * lda + acol, __builtin_amdgcn_readfirstlane(dst + i * 1024));
+      }
+    };
+    auto issue_b = [&](int chunk) {
+      const int c0 = 32 * min(chunk, nchunk - 1);
+      const uint32_t dst0 = bs0 + (chunk % 2) * SB;
+      for (int i = w; i < BI; i += 8) {
+        const int p = 64 * i + lane;
+        const int row = p / RSEG, slot = p - row * RSEG;
+        const int seg = SWB ? (slot ^ (((row >> 3) & 3) << 2)) : slot;
+        const int krow = ibeg + c0 + (ibeg + c0 + row < iend ? row : 0);
+        dma16(Z + (int64_t)krow * KK + 4 * seg, __builtin_amdgcn_readfirstlane(dst0 + 64 * i * 16));
+      }
+    };
+    auto run = [&](auto nb_const) {
+      constexpr int NB = decltype(nb_const)::value;
+      constexpr int NBA = NB > 0 ? NB : 1;
+      // order of issue as in gemm_n_dma_kernel: the last four DMAs of a
+      // wave at the top of step ch are A(ch + 1)'s
+      issue_a(0);
+      issue_b(0);
+      issue_a(1);
+      for (int ch = 0; ch < nchunk; ++ch) {
+        asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory");
+        const int valid = min(32, iend - ibeg - 32 * ch);
+        if (valid < 32) {
+          float* bz = reinterpret_cast<float*>(Bs + (ch % 2) * SB);
+          for (int e = tid; e < (32 - valid) * KK; e += 512) bz[valid * KK + e] = 0.0f;
+          __syncthreads();
+        }
+        issue_b(ch + 1);
+        issue_a(ch + 2);
+        if (NB > 0) {
+          const float* bst = reinterpret_cast<const float*>(Bs + (ch % 2) * SB);
+          float bf[NBA][8];
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) {
+            const int col = (jb0 + jj) * 16 + lr;
+            const int slot = SWB ? ((col >> 2) ^ (g << 2)) : (col >> 2);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) bf[jj][t] = bst[(8 * g + t) * KK + 4 * slot + (col & 3)];
+          }
+          // lane (lr, g), block rb: column 128 half + 16 rb + lr of the tile
+          const float* ast = reinterpret_cast<const float*>(As + (ch % 3) * SA);
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            float af[8];
+#pragma unroll
+            for (int rb = 0; rb < 8; ++rb) {
+              const int c = 128 * half + 16 * rb + lr;
+              af[rb] = ast[(8 * g + t) * kDmaRows + 4 * ((c >> 2) ^ (g << 2)) + (c & 3)];
+            }
+#pragma unroll
+            for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+              for (int jj = 0; jj < NB; ++jj) Mfma<float>::mma(af[rb], bf[jj][t], acc[rb][jj]);
+          }
+        }
+      }
+    };
+    const int nb = min(KBW, max(0, KB - jb0));
+    if (nb == KBW)
+      run(std::integral_constant<int, KBW>());
+    else if (KB % KBW != 0 && nb == KB % KBW)
+      run(std::integral_constant<int, (KB % KBW)>());
+    else
+      run(std::integral_constant<int, 0>());
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+  float* out = P + (int64_t)split * n * KK;
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int col = col_blk + 128 * half + rb * 16 + 4 * g + i;
+      if (col < n) {
+#pragma unroll
+        for (int jj = 0; jj < KBW; ++jj)
+          if (jb0 + jj < KB) out[(int64_t)col * KK + (jb0 + jj) * 16 + lr] = acc[rb][jj][i];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // W = A^T Z.  MFMA M index = column of A, N = operand column, K = row of A.
 // Lane (r, g) loads VW consecutive columns [4.. of its 16-lane group] of a
 // row: column col_w + VW*r + e belongs to MFMA block e at M index r.  Per K
@@ -575,6 +713,7 @@ int choose_splits_n(int m, int n, int kk, int elem_bytes) {
 static constexpr int t_vw(int kb, int elem_bytes) { return kb > 4 ? 1 : (elem_bytes == 4 ? 4 : 2); }
 
 int choose_splits_t(int m, int n, int kk, int elem_bytes) {
+  if (elem_bytes == 4 && kk <= 128 && n % 4 == 0) return choose_splits_dma(n, m, kk);
   const int kb = kk / 16;
   const int cw = 4 * 16 * t_vw(kb, elem_bytes);
   const int tiles = (n + cw - 1) / cw;
@@ -633,9 +772,17 @@ static hipError_t gemm_t_kb(const T* A, int64_t lda, int m, int n, const T* Z, T
   constexpr int KC = 32;
   int per = (m + splits - 1) / splits;
   per = (per + KC - 1) / KC * KC;
+  bool vec = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(T)) % 16 == 0);
+  if constexpr (sizeof(T) == 4) {
+    if (vec && n % 4 == 0 && (uintptr_t)Z % 16 == 0) {
+      const int nt = (n + kDmaRows - 1) / kDmaRows;
+      hipLaunchKernelGGL((gemm_t_dma_kernel<KB>), dim3(nt * splits), dim3(512), 0, st, (const float*)A, lda, m, n,
+                         (const float*)Z, (float*)P, per, nt, splits);
+      CNMF_LAUNCH_CHECK();
+    }
+  }
   const int ntiles = (n + 64 * VW - 1) / (64 * VW);
   dim3 grid(ntiles * splits);
-  bool vec = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(T)) % 16 == 0);
   if (vec)
     hipLaunchKernelGGL((gemm_t_kernel<T, KB, VW, true>), grid, dim3(256), 0, st, A, lda, m, n, Z, P, per, ntiles,
                        splits);
