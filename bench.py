@@ -778,7 +778,7 @@ def main():
     achieved = pass_fl / (pass_ms * 1e-3) / 1e12 if pass_ms > 0 else None
     roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": (achieved / FP32_PEAK_TFLOPS) if achieved else None, "traffic": pass_traffic(w),
-                "kernel": "gemm_n_kernel + gemm_t_kernel (range-finder passes, FP32 16x16x4 MFMA)",
+                "kernel": "gemm_n_dma_kernel + gemm_t_dma_kernel (range-finder passes, FP32 16x16x4 MFMA)",
                 "avg_launch_ms": pass_ms / pass_n if pass_n else None,
                 "gflop_per_launch": pass_fl / pass_n / 1e9 if pass_n else None}
 
