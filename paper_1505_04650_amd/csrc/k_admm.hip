@@ -593,10 +593,21 @@ __device__ __forceinline__ void admm_solve_chol_nb(const double* __restrict__ Pr
   const CholLayout Ly = chol_layout(k, r);
   double* S = sm + Ly.s_off;
   const int64_t kr = (int64_t)k * r;
-  // S = Yt^T (k x r, zero padded to kp x N)
-  for (int e = threadIdx.x; e < Ly.kp * N; e += NT) {
-    const int i = e / N, j = e - i * N;
-    S[i * Ly.ld + j] = (i < k && j < r) ? (first ? Pred[kr + i * r + j] / phi : XY[kr + i * r + j]) : 0.0;
+  // S = Yt^T (k x r, zero padded to kp x N); eight loads in flight per
+  // thread before their stores (one load-store pair at a time waits on the
+  // L2 latency per element row)
+  for (int e0 = threadIdx.x; e0 < Ly.kp * N; e0 += NT * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + NT * u, i = e / N, j = e - i * N;
+      v[u] = (e < Ly.kp * N && i < k && j < r) ? (first ? Pred[kr + i * r + j] / phi : XY[kr + i * r + j]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + NT * u, i = e / N, j = e - i * N;
+      if (e < Ly.kp * N) S[i * Ly.ld + j] = v[u];
+    }
   }
   __syncthreads();
   // the zero-padded FP32 copies (kp x N per side) after XY feed the row updates
@@ -644,12 +655,21 @@ __device__ __forceinline__ void admm_solve_side_nb(const AdmmHalf& a, double* sm
   const double* XY = a.XY;
   // S = Yt^T for pass 0 (P_V / phi on the first iteration, Alg. 3's
   // initialisation), Xt for pass 1; zero padded to kp x N
-  for (int e = threadIdx.x; e < Ly.kp * N; e += NT) {
-    const int i = e / N, j = e - i * N;
-    double v = 0.0;
-    if (i < k && j < r)
-      v = PASS == 1 ? XY[i * r + j] : (a.first ? a.Pred[kr + i * r + j] / a.phi : XY[kr + i * r + j]);
-    S[i * Ly.ld + j] = v;
+  // (eight loads in flight per thread before their stores, as above)
+  for (int e0 = threadIdx.x; e0 < Ly.kp * N; e0 += NT * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + NT * u, i = e / N, j = e - i * N;
+      v[u] = 0.0;
+      if (e < Ly.kp * N && i < k && j < r)
+        v[u] = PASS == 1 ? XY[i * r + j] : (a.first ? a.Pred[kr + i * r + j] / a.phi : XY[kr + i * r + j]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + NT * u, i = e / N, j = e - i * N;
+      if (e < Ly.kp * N) S[i * Ly.ld + j] = v[u];
+    }
   }
   __syncthreads();
   float* XYf = reinterpret_cast<float*>(a.XY + 2 * kr);

@@ -265,6 +265,30 @@ hipError_t launch_sum_parts(const double* in, int parts, int64_t count, double* 
 // ---------------------------------------------------------------------------
 constexpr int kFacNT = 256;
 
+// M (N x N, ld) = (G + G^T) / 2 for the kh x kh Gram G in global memory,
+// identity outside it.  Eight elements per thread are loaded before any is
+// stored: G was just written and comes from L2, and a load-store pair per
+// element would leave the workgroup waiting on the L2 latency N^2 / 256 times.
+template <int N>
+__device__ __forceinline__ void load_sym_gram(const double* __restrict__ Gh, int kh, double* M, int ld) {
+  constexpr int U = 8;
+  for (int e0 = threadIdx.x; e0 < N * N; e0 += kFacNT * U) {
+    double a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + kFacNT * u, i = e / N, j = e - i * N;
+      const bool ok = e < N * N && i < kh && j < kh;
+      a[u] = ok ? Gh[i * kh + j] : 0.0;
+      b[u] = ok ? Gh[j * kh + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + kFacNT * u, i = e / N, j = e - i * N;
+      if (e < N * N) M[i * ld + j] = (i < kh && j < kh) ? 0.5 * (a[u] + b[u]) : (i == j ? 1.0 : 0.0);
+    }
+  }
+}
+
 // kh <= 64, with the products on the FP64 MFMA: wave 0
 // factors G_h = L L^T (wave_chol_lower: 16-column register panels, MFMA
 // trailing updates, inverses V_b of the diagonal blocks); then wave j forms
@@ -282,10 +306,7 @@ __device__ __forceinline__ void chol_tinv_wave_body(const double* __restrict__ G
   double* W = V + NB * 272;       // 128
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
-  for (int e = tid; e < N * N; e += kFacNT) {
-    const int i = e / N, j = e - i * N;
-    M[i * ld + j] = (i < kh && j < kh) ? 0.5 * (Gh[i * kh + j] + Gh[j * kh + i]) : (i == j ? 1.0 : 0.0);
-  }
+  load_sym_gram<N>(Gh, kh, M, ld);
   __syncthreads();
   if (w == 0) {
     double dg = lane < kh ? M[lane * ld + lane] : 0.0;
@@ -350,10 +371,7 @@ __device__ __forceinline__ void chol_tinv_wave128_body(const double* __restrict_
   double* W = V + 8 * 272;        // 128
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
-  for (int e = tid; e < N * N; e += kFacNT) {
-    const int i = e / N, j = e - i * N;
-    M[i * ld + j] = (i < kh && j < kh) ? 0.5 * (Gh[i * kh + j] + Gh[j * kh + i]) : (i == j ? 1.0 : 0.0);
-  }
+  load_sym_gram<N>(Gh, kh, M, ld);
   __syncthreads();
   double fl = 1.0;
   {
@@ -561,9 +579,22 @@ __global__ __launch_bounds__(256, 2) void apply_mfma_kernel(const TY* __restrict
   for (int sl = 0; sl < nslab; ++sl) {
     const int c0 = sl * SL;
     __syncthreads();
-    for (int e = tid; e < 4 * nsteps * SL; e += 256) {
-      const int l = e / SL, c = e - l * SL;
-      Ts[l * LDT + c] = (l < kh && c0 + c < kh) ? Th[l * kh + c0 + c] : 0.0;
+    // eight loads in flight per thread before their stores (the slab comes
+    // from L2; one load and store at a time left each workgroup waiting on
+    // the L2 latency once per element row)
+    const int lim = 4 * nsteps * SL;
+    for (int e0 = tid; e0 < lim; e0 += 256 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u, l = e / SL, c = e - l * SL;
+        v[u] = (e < lim && l < kh && c0 + c < kh) ? Th[l * kh + c0 + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u, l = e / SL, c = e - l * SL;
+        if (e < lim) Ts[l * LDT + c] = v[u];
+      }
     }
     __syncthreads();
 #pragma unroll
