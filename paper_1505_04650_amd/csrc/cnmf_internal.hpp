@@ -15,6 +15,28 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 // status of its launch so the runtime can map it to CNMF_EDEVICE.
 #define CNMF_LAUNCH_CHECK() return hipGetLastError()
 
+// Block-cooperative staging with up to U loads in flight per thread: for e =
+// first, first + stride, ... < count, load(e) for U elements, then
+// store(e, value) for them.  Staging loops that load and store one element
+// at a time leave every thread waiting on the memory latency once per
+// element it moves.
+template <int U, typename Load, typename Store>
+__device__ __forceinline__ void staged_copy(int count, int first, int stride, Load&& load, Store&& store) {
+  for (int e0 = first; e0 < count; e0 += stride * U) {
+    decltype(load(0)) v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + stride * u;
+      if (e < count) v[u] = load(e);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + stride * u;
+      if (e < count) store(e, v[u]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pass GEMMs (range-finder passes over A)
 // ---------------------------------------------------------------------------

@@ -39,14 +39,12 @@ __global__ __launch_bounds__(256) void nmf_row_kernel(RowArgs a) {
   double* ms = fs + kRowCh * ldr;        // kRowCh x ldr: Mu rows
   double* b2s = ms + kRowCh * ldr;       // kRowCh x (k2 + 1)
   if (a.C)
-    for (int e = tid; e < k1 * r; e += 256) cs[e] = a.C[e];
+    staged_copy<8>(k1 * r, tid, 256, [&](int e) { return a.C[e]; }, [&](int e, double v) { cs[e] = v; });
   if (a.method == 0) {
-    for (int e = tid; e < r * r; e += 256) {
-      gp[e] = a.Gp[e];
-      gm[e] = a.Gm[e];
-    }
+    staged_copy<8>(r * r, tid, 256, [&](int e) { return a.Gp[e]; }, [&](int e, double v) { gp[e] = v; });
+    staged_copy<8>(r * r, tid, 256, [&](int e) { return a.Gm[e]; }, [&](int e, double v) { gm[e] = v; });
   } else if (a.method == 1) {
-    for (int e = tid; e < r * r; e += 256) gp[e] = a.Minv[e];
+    staged_copy<8>(r * r, tid, 256, [&](int e) { return a.Minv[e]; }, [&](int e, double v) { gp[e] = v; });
   }
   const int ta = tid >> 4, tb = tid & 15;
   double acc[8][4];
@@ -63,18 +61,31 @@ __global__ __launch_bounds__(256) void nmf_row_kernel(RowArgs a) {
     const int nr = min(kRowCh, i1 - base);
     const bool have = my_rr < nr;
     __syncthreads();
-    for (int e = tid; e < nr * r; e += 256) {
-      const int rr = e / r, c = e - rr * r;
-      const int64_t off = (int64_t)(base + rr) * a.ldf + c;
-      fs[rr * ldr + c] = (double)F[off];
-      ms[rr * ldr + c] = Mu ? (double)Mu[off] : 0.0;
-      if (!a.C && a.method != 2) zs[rr * ldr + c] = (double)B1[(int64_t)(base + rr) * a.ldb1 + c];
+    {
+      const bool zb = !a.C && a.method != 2;
+      struct V3 {
+        double f, m, z;
+      };
+      staged_copy<4>(
+          nr * r, tid, 256,
+          [&](int e) {
+            const int rr = e / r, c = e - rr * r;
+            const int64_t off = (int64_t)(base + rr) * a.ldf + c;
+            return V3{(double)F[off], Mu ? (double)Mu[off] : 0.0,
+                      zb ? (double)B1[(int64_t)(base + rr) * a.ldb1 + c] : 0.0};
+          },
+          [&](int e, V3 v) {
+            const int rr = e / r, c = e - rr * r;
+            fs[rr * ldr + c] = v.f;
+            ms[rr * ldr + c] = v.m;
+            if (zb) zs[rr * ldr + c] = v.z;
+          });
     }
     if (B2)
-      for (int e = tid; e < nr * k2; e += 256) {
-        const int rr = e / k2, c = e - rr * k2;
-        b2s[rr * (k2 + 1) + c] = (double)B2[(int64_t)(base + rr) * a.ldb2 + c];
-      }
+      staged_copy<8>(
+          nr * k2, tid, 256, [&](int e) { const int rr = e / k2, c = e - rr * k2;
+            return (double)B2[(int64_t)(base + rr) * a.ldb2 + c]; },
+          [&](int e, double v) { const int rr = e / k2, c = e - rr * k2; b2s[rr * (k2 + 1) + c] = v; });
     __syncthreads();
     if (a.C && a.method != 2) {
       // z = B1[i] C

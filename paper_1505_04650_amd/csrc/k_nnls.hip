@@ -269,10 +269,13 @@ __device__ double bpp_wave(const double* Gs, const double* Hs, int r, double c, 
 // G (r x r, row-major, FP64) into LDS, padded to RM x RM with zeros.
 template <int RM>
 __device__ __forceinline__ void stage_gram(double* Gs, const double* __restrict__ G, int r) {
-  for (int e = threadIdx.x; e < RM * RM; e += blockDim.x) {
-    const int i = e / RM, l = e - i * RM;
-    Gs[e] = (i < r && l < r) ? G[i * r + l] : 0.0;
-  }
+  staged_copy<8>(
+      RM * RM, threadIdx.x, blockDim.x,
+      [&](int e) {
+        const int i = e / RM, l = e - i * RM;
+        return (i < r && l < r) ? G[i * r + l] : 0.0;
+      },
+      [&](int e, double v) { Gs[e] = v; });
 }
 
 // Right factor: one wave per column (grid-stride over the columns), cold

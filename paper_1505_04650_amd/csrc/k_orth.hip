@@ -12,6 +12,8 @@
 
 namespace cnmf {
 
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+
 template <typename T>
 __device__ __forceinline__ double to_d(T x) {
   return (double)x;
@@ -71,13 +73,19 @@ __global__ __launch_bounds__(256) void cross_kernel(const TX* __restrict__ X, in
     for (int j = 0; j < KH16; ++j) acc[i][j] = 0.0;
 
   for (int base = i0; base < i1; base += CR) {
-    for (int e = tid; e < CR * KW; e += 256) {
-      int rr = e / KW, c = e - rr * KW;
-      int row = base + rr;
-      bool ok = row < i1;
-      xs[rr][c] = (ok && c < ka) ? to_d(X[(int64_t)row * ldx + xc + c]) : 0.0;
-      ys[rr][c] = (ok && c < kb) ? to_d(Y[(int64_t)row * ldy + yc + c]) : 0.0;
-    }
+    staged_copy<4>(
+        CR * KW, tid, 256,
+        [&](int e) {
+          const int rr = e / KW, c = e - rr * KW, row = base + rr;
+          const bool ok = row < i1;
+          return doublex2{(ok && c < ka) ? to_d(X[(int64_t)row * ldx + xc + c]) : 0.0,
+                          (ok && c < kb) ? to_d(Y[(int64_t)row * ldy + yc + c]) : 0.0};
+        },
+        [&](int e, doublex2 v) {
+          const int rr = e / KW, c = e - rr * KW;
+          xs[rr][c] = v.x;
+          ys[rr][c] = v.y;
+        });
     __syncthreads();
 #pragma unroll 4
     for (int rr = 0; rr < CR; ++rr) {
