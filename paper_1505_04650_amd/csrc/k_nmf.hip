@@ -230,17 +230,23 @@ constexpr int kSmallNT = 256;
 __global__ __launch_bounds__(kSmallNT) void nmf_small_kernel(const double* __restrict__ S, int k, int r, int mode,
                                                              double pen, double* __restrict__ Gp,
                                                              double* __restrict__ Gm, int* flags) {
+  // S (k x r, k <= 128, r <= 64) staged in LDS first, with eight loads in
+  // flight per thread; the products then read LDS in the same order as before
+  __shared__ double Ss[128 * 64];
   const int tid = threadIdx.x;
+  const int cnt = mode == 1 ? r * r : k * r;
+  staged_copy<8>(cnt, tid, kSmallNT, [&](int e) { return S[e]; }, [&](int e, double v) { Ss[e] = v; });
+  __syncthreads();
   if (mode == 3) {
     for (int e = tid; e < r * r; e += kSmallNT) {
       const int a = e / r, b = e - a * r;
       double s0 = 0.0, s1 = 0.0;
       int l = 0;
       for (; l + 1 < k; l += 2) {
-        s0 = fma(S[l * r + a], S[l * r + b], s0);
-        s1 = fma(S[(l + 1) * r + a], S[(l + 1) * r + b], s1);
+        s0 = fma(Ss[l * r + a], Ss[l * r + b], s0);
+        s1 = fma(Ss[(l + 1) * r + a], Ss[(l + 1) * r + b], s1);
       }
-      if (l < k) s0 = fma(S[l * r + a], S[l * r + b], s0);
+      if (l < k) s0 = fma(Ss[l * r + a], Ss[l * r + b], s0);
       Gp[e] = s0 + s1;
     }
     return;
@@ -253,13 +259,13 @@ __global__ __launch_bounds__(kSmallNT) void nmf_small_kernel(const double* __res
         double s0 = 0.0, s1 = 0.0;
         int l = 0;
         for (; l + 1 < k; l += 2) {
-          s0 = fma(S[l * r + a], S[l * r + b], s0);
-          s1 = fma(S[(l + 1) * r + a], S[(l + 1) * r + b], s1);
+          s0 = fma(Ss[l * r + a], Ss[l * r + b], s0);
+          s1 = fma(Ss[(l + 1) * r + a], Ss[(l + 1) * r + b], s1);
         }
-        if (l < k) s0 = fma(S[l * r + a], S[l * r + b], s0);
+        if (l < k) s0 = fma(Ss[l * r + a], Ss[l * r + b], s0);
         g = s0 + s1;
       } else {
-        g = S[e];
+        g = Ss[e];
       }
       Gp[e] = g > 0.0 ? g : 0.0;
       Gm[e] = g < 0.0 ? -g : 0.0;
@@ -271,7 +277,8 @@ __global__ __launch_bounds__(kSmallNT) void nmf_small_kernel(const double* __res
 
 hipError_t launch_nmf_small(const double* S, int k, int r, int mode, double pen, double* Gp, double* Gm, int* flags,
                             hipStream_t st) {
-  if (mode < 0 || mode > 3 || mode == 2) return hipErrorInvalidValue;
+  if (mode < 0 || mode > 3 || mode == 2 || r < 1 || r > 64 || (mode != 1 && (k < 1 || k > 128)))
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(nmf_small_kernel, dim3(1), dim3(kSmallNT), 0, st, S, k, r, mode, pen, Gp, Gm, flags);
   CNMF_LAUNCH_CHECK();
 }
@@ -295,22 +302,29 @@ __global__ __launch_bounds__(256) void spd_inv_finish_kernel(const double* __res
                                                              double* __restrict__ Minv,
                                                              const int* __restrict__ floored, int* ok) {
   __shared__ double Ms[64 * 65];
+  __shared__ double Ts[64 * 64];   // Ti, then G (both r x r, r <= 64)
   __shared__ double worst[256];
   const int tid = threadIdx.x;
+  // operands staged in LDS with eight loads in flight per thread; the sums
+  // read them in the same order as from global memory
+  staged_copy<8>(r * r, tid, 256, [&](int e) { return Ti[e]; }, [&](int e, double v) { Ts[e] = v; });
+  __syncthreads();
   for (int e = tid; e < r * r; e += 256) {
     const int i = e / r, j = e - i * r;
     double s = 0.0;
-    for (int l = max(i, j); l < r; ++l) s = fma(Ti[i * r + l], Ti[j * r + l], s);
+    for (int l = max(i, j); l < r; ++l) s = fma(Ts[i * r + l], Ts[j * r + l], s);
     Ms[i * 65 + j] = s;
     Minv[e] = s;
   }
   if (!ok) return;
   __syncthreads();
+  staged_copy<8>(r * r, tid, 256, [&](int e) { return G[e]; }, [&](int e, double v) { Ts[e] = v; });
+  __syncthreads();
   double err = 0.0;
   for (int e = tid; e < r * r; e += 256) {
     const int i = e / r, j = e - i * r;
     double s = (i == j) ? -1.0 : 0.0;
-    for (int l = 0; l < r; ++l) s = fma(G[i * r + l], Ms[l * 65 + j], s);
+    for (int l = 0; l < r; ++l) s = fma(Ts[i * r + l], Ms[l * 65 + j], s);
     err = (s == s) ? fmax(err, fabs(s)) : INFINITY;
   }
   worst[tid] = err;
