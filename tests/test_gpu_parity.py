@@ -86,6 +86,40 @@ def test_range_product_padded_lda():
     assert rel(Y, host(A) @ host(X)) < 2e-6
 
 
+@pytest.mark.parametrize("shape", [(300, 4100, 128), (513, 2048, 96), (777, 1000, 112), (2000, 516, 60),
+                                   (1200, 3000, 128), (257, 132, 16), (5, 36, 48), (20000, 5000, 120)])
+def test_range_product_fp32_lds_ring_shapes(shape):
+    """FP32 rows that are 16-byte aligned (n % 4 == 0) take the LDS-ring pass
+    kernels: ragged row tiles (256), ragged K chunks (32), every operand
+    width class, several split counts.  Element-wise against the FP64
+    product of the same FP32 inputs, within the FP32 accumulation bound."""
+    m, n, kx = shape
+    g = np.random.default_rng(m * 3 + n + kx)
+    A = g.random((m, n)).astype(np.float32)
+    X = (g.random((n, kx)) - 0.5).astype(np.float32)
+    Z = (g.random((m, kx)) - 0.5).astype(np.float32)
+    Ad = dev(A, torch.float32)
+    Y = host(api.range_product(Ad, dev(X, torch.float32)))
+    W = host(api.range_product(Ad, dev(Z, torch.float32), trans=True))
+    A64, X64, Z64 = A.astype(np.float64), X.astype(np.float64), Z.astype(np.float64)
+    for got, ref, mag, kdim in ((Y, A64 @ X64, np.abs(A64) @ np.abs(X64), n),
+                                (W, A64.T @ Z64, np.abs(A64.T) @ np.abs(Z64), m)):
+        bound = 2.0 * kdim * 2.0 ** -24 * mag + 1e-30
+        assert np.all(np.abs(got - ref) <= bound)
+
+
+def test_range_product_fp32_padded_aligned_lda():
+    """lda > n with 16-byte aligned rows (the LDS-ring kernels read only the
+    first n columns of each row)."""
+    g = np.random.default_rng(6)
+    big = dev(g.standard_normal((300, 264)), torch.float32)
+    A = big[:, :256]   # lda = 264, n = 256
+    X = dev(g.standard_normal((256, 40)), torch.float32)
+    Z = dev(g.standard_normal((300, 40)), torch.float32)
+    assert rel(host(api.range_product(A, X)), host(A) @ host(X)) < 2e-6
+    assert rel(host(api.range_product(A, Z, trans=True)), host(A).T @ host(Z)) < 2e-6
+
+
 # --------------------------------------------------------------------------
 # FP64 path at the 1000 x 500 workload: 1e-10 against the oracle
 # --------------------------------------------------------------------------
