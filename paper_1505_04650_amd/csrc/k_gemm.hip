@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256, 2) void gemm_n_kernel(const T* __restrict__ A,
 // ---------------------------------------------------------------------------
 constexpr int kDmaRows = 256;
 
-template <int KB>
+template <int KB, bool DW16>
 __global__ __launch_bounds__(512, 1) void gemm_n_dma_kernel(const float* A, int64_t lda, int m, int n,
                                                             const float* X, float* __restrict__ P,
                                                             int cols_per_split, int ntiles, int nsplits) {
@@ -265,13 +265,31 @@ __global__ __launch_bounds__(512, 1) void gemm_n_dma_kernel(const float* A, int6
       abase[i] = A + (int64_t)r * lda + kbeg;
       aseg[i] = (lane & 7) ^ drow ^ (i & 1);
     }
+    // without 16-byte aligned rows the same LDS image is written 4 bytes per
+    // lane: instruction j moves chunk rows 32 w + 2 j, + 1 (256 bytes), lane
+    // l row 32 w + 2 j + l / 32, slot (l % 32) / 4, float l % 4 of it, which
+    // holds float l % 4 of segment slot ^ h(row); columns past the end re-read
+    // the chunk's first column
+    const int dhi = lane >> 5, dslot = (lane & 31) >> 2, ddw = lane & 3;
     auto issue_a = [&](int chunk) {
       const int c0 = 32 * min(chunk, nchunk - 1);
       const uint32_t dst = as0 + (chunk % 3) * SA + 32 * w * 128;
+      if constexpr (DW16) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int sg = (kbeg + c0 + 4 * aseg[i] < kend) ? aseg[i] : 0;
-        dma16(abase[i] + c0 + 4 * sg, __builtin_amdgcn_readfirstlane(dst + 8 * i * 128));
+        for (int i = 0; i < 4; ++i) {
+          const int sg = (kbeg + c0 + 4 * aseg[i] < kend) ? aseg[i] : 0;
+          dma16(abase[i] + c0 + 4 * sg, __builtin_amdgcn_readfirstlane(dst + 8 * i * 128));
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int x = 2 * j + dhi;                     // row within the wave's 32
+          const int hrow = (x & 7) ^ ((x >> 3) & 1);     // h of the chunk row (32 w adds no low bits)
+          const int col = 4 * (dslot ^ hrow) + ddw;
+          const int r = min(row_blk + 32 * w + x, m - 1);
+          const int cc = (kbeg + c0 + col < kend) ? col : 0;
+          dma4(A + (int64_t)r * lda + kbeg + c0 + cc, __builtin_amdgcn_readfirstlane(dst + j * 256));
+        }
       }
     };
     // X: instruction i covers LDS segments [64 i, 64 i + 64) of the stage
@@ -294,14 +312,17 @@ __global__ __launch_bounds__(512, 1) void gemm_n_dma_kernel(const float* A, int6
       constexpr int NB = decltype(nb_const)::value;
       constexpr int NBA = NB > 0 ? NB : 1;
       // order of issue: A(0), B(0), A(1); step ch issues B(ch + 1), then
-      // A(ch + 2): at the top of step ch all but this wave's last four DMAs
-      // (A(ch + 1)) have landed
+      // A(ch + 2): at the top of step ch all but this wave's last DMAs of
+      // A(ch + 1) (four, or sixteen 4-byte ones) have landed
       issue_a(0);
       issue_b(0);
       issue_a(1);
       for (int ch = 0; ch < nchunk; ++ch) {
         // (a plain barrier: the fence of __syncthreads would wait for every DMA)
-        asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory");
+        if constexpr (DW16)
+          asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory");
+        else
+          asm volatile("s_waitcnt vmcnt(16)\n\ts_barrier" ::: "memory");
         const int valid = min(32, kend - kbeg - 32 * ch);
         if (valid < 32) {
           float* bz = reinterpret_cast<float*>(Bs + (ch % 2) * SB);
@@ -374,7 +395,7 @@ __global__ __launch_bounds__(512, 1) void gemm_n_dma_kernel(const float* A, int6
 // n re-read the tile's first segment (their results are not stored); rows
 // past the slice re-read its first row and meet zeroed rows of Z.
 // ---------------------------------------------------------------------------
-template <int KB>
+template <int KB, bool DW16>
 __global__ __launch_bounds__(512, 1) void gemm_t_dma_kernel(const float* A, int64_t lda, int m, int n,
                                                             const float* Z, float* __restrict__ P,
                                                             int rows_per_split, int ntiles, int nsplits) {
@@ -410,14 +431,33 @@ __global__ __launch_bounds__(512, 1) void gemm_t_dma_kernel(const float* A, int6
     // the row's 256 columns (row >> 3 == w >> 1)
     const int aseg = lane ^ (((w >> 1) & 3) << 2);
     const int acol = (col_blk + 4 * aseg + 4 <= n) ? col_blk + 4 * aseg : col_blk;
+    // without 16-byte aligned rows, 4 bytes per lane: instruction j moves a
+    // quarter (64 columns, 256 bytes) of chunk row 4 w + j / 4; lane l writes
+    // slot 16 (j % 4) + l / 4, float l % 4, which holds float l % 4 of
+    // segment slot ^ (4 ((row >> 3) & 3)); columns past n re-read the tile's
+    // first column
+    const int asw = ((w >> 1) & 3) << 2;
     auto issue_a = [&](int chunk) {
       const int c0 = 32 * min(chunk, nchunk - 1);
       const uint32_t dst = as0 + (chunk % 3) * SA + 4 * w * 1024;
+      if constexpr (DW16) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = ibeg + c0 + 4 * w + i;
-        const int srow = row < iend ? row : ibeg + c0;
-        dma16(A + (int64_t)srow * lda + acol, __builtin_amdgcn_readfirstlane(dst + i * 1024));
+        for (int i = 0; i < 4; ++i) {
+          const int row = ibeg + c0 + 4 * w + i;
+          const int srow = row < iend ? row : ibeg + c0;
+          dma16(A + (int64_t)srow * lda + acol, __builtin_amdgcn_readfirstlane(dst + i * 1024));
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int i = j >> 2, q = j & 3;
+          const int row = ibeg + c0 + 4 * w + i;
+          const int srow = row < iend ? row : ibeg + c0;
+          const int slot = 16 * q + (lane >> 2);
+          const int col = col_blk + 4 * (slot ^ asw) + (lane & 3);
+          dma4(A + (int64_t)srow * lda + (col < n ? col : col_blk),
+               __builtin_amdgcn_readfirstlane(dst + i * 1024 + q * 256));
+        }
       }
     };
     auto issue_b = [&](int chunk) {
@@ -434,13 +474,16 @@ __global__ __launch_bounds__(512, 1) void gemm_t_dma_kernel(const float* A, int6
     auto run = [&](auto nb_const) {
       constexpr int NB = decltype(nb_const)::value;
       constexpr int NBA = NB > 0 ? NB : 1;
-      // order of issue as in gemm_n_dma_kernel: the last four DMAs of a
-      // wave at the top of step ch are A(ch + 1)'s
+      // order of issue as in gemm_n_dma_kernel: the last DMAs of a wave at
+      // the top of step ch are A(ch + 1)'s (four, or sixteen 4-byte ones)
       issue_a(0);
       issue_b(0);
       issue_a(1);
       for (int ch = 0; ch < nchunk; ++ch) {
-        asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory");
+        if constexpr (DW16)
+          asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory");
+        else
+          asm volatile("s_waitcnt vmcnt(16)\n\ts_barrier" ::: "memory");
         const int valid = min(32, iend - ibeg - 32 * ch);
         if (valid < 32) {
           float* bz = reinterpret_cast<float*>(Bs + (ch % 2) * SB);
@@ -683,6 +726,12 @@ static constexpr int rb_for(int kb, int elem_bytes) { return (elem_bytes == 4 &&
 // rows allow it; the split count is chosen for that kernel (any count is
 // valid for the other one, used when A's rows are not 16-byte aligned):
 // minimise rounds * (bytes per workgroup, partials included).
+// The 4-byte DMA variants (rows that are not 16-byte aligned) move four
+// times as many DMA instructions; on small matrices (where several requests'
+// passes share the GPU in serving) the register-staged kernels, which leave
+// room for other workgroups on a CU, measured faster, so they serve those.
+static bool dw4_worth(int m, int n) { return (int64_t)m * n >= (int64_t)4 << 20; }
+
 static int choose_splits_dma(int m, int n, int kk) {
   const int cus = num_cu();
   const int64_t tiles = (m + kDmaRows - 1) / kDmaRows;
@@ -701,7 +750,7 @@ static int choose_splits_dma(int m, int n, int kk) {
 }
 
 int choose_splits_n(int m, int n, int kk, int elem_bytes) {
-  if (elem_bytes == 4 && kk <= 128 && n % 4 == 0) return choose_splits_dma(m, n, kk);
+  if (elem_bytes == 4 && kk <= 128 && (n % 4 == 0 || dw4_worth(m, n))) return choose_splits_dma(m, n, kk);
   int rb = rb_for(kk / 16, elem_bytes);
   int tiles = (m + 64 * rb - 1) / (64 * rb);
   return choose_splits(tiles, n, 512);
@@ -713,7 +762,7 @@ int choose_splits_n(int m, int n, int kk, int elem_bytes) {
 static constexpr int t_vw(int kb, int elem_bytes) { return kb > 4 ? 1 : (elem_bytes == 4 ? 4 : 2); }
 
 int choose_splits_t(int m, int n, int kk, int elem_bytes) {
-  if (elem_bytes == 4 && kk <= 128 && n % 4 == 0) return choose_splits_dma(n, m, kk);
+  if (elem_bytes == 4 && kk <= 128 && (n % 4 == 0 || dw4_worth(m, n))) return choose_splits_dma(n, m, kk);
   const int kb = kk / 16;
   const int cw = 4 * 16 * t_vw(kb, elem_bytes);
   const int tiles = (n + cw - 1) / cw;
@@ -729,13 +778,20 @@ static hipError_t gemm_n_kb(const T* A, int64_t lda, int m, int n, const T* X, T
   per = (per + KC - 1) / KC * KC;
   bool vec = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(T)) % 16 == 0);
   if constexpr (sizeof(T) == 4) {
-    if (vec && n % 4 == 0 && (uintptr_t)X % 16 == 0) {
+    if ((uintptr_t)X % 16 == 0 && (uintptr_t)A % 4 == 0) {
       int per32 = (n + splits - 1) / splits;
       per32 = (per32 + 31) / 32 * 32;
       const int nt = (m + kDmaRows - 1) / kDmaRows;
-      hipLaunchKernelGGL((gemm_n_dma_kernel<KB>), dim3(nt * splits), dim3(512), 0, st, (const float*)A, lda, m, n,
-                         (const float*)X, (float*)P, per32, nt, splits);
-      CNMF_LAUNCH_CHECK();
+      if (vec && n % 4 == 0) {
+        hipLaunchKernelGGL((gemm_n_dma_kernel<KB, true>), dim3(nt * splits), dim3(512), 0, st, (const float*)A, lda,
+                           m, n, (const float*)X, (float*)P, per32, nt, splits);
+        CNMF_LAUNCH_CHECK();
+      }
+      if (dw4_worth(m, n)) {
+        hipLaunchKernelGGL((gemm_n_dma_kernel<KB, false>), dim3(nt * splits), dim3(512), 0, st, (const float*)A, lda,
+                           m, n, (const float*)X, (float*)P, per32, nt, splits);
+        CNMF_LAUNCH_CHECK();
+      }
     }
   }
   const int ntiles = (m + 64 * RB - 1) / (64 * RB);
@@ -774,11 +830,18 @@ static hipError_t gemm_t_kb(const T* A, int64_t lda, int m, int n, const T* Z, T
   per = (per + KC - 1) / KC * KC;
   bool vec = ((uintptr_t)A % 16 == 0) && ((lda * (int64_t)sizeof(T)) % 16 == 0);
   if constexpr (sizeof(T) == 4) {
-    if (vec && n % 4 == 0 && (uintptr_t)Z % 16 == 0) {
+    if ((uintptr_t)Z % 16 == 0 && (uintptr_t)A % 4 == 0) {
       const int nt = (n + kDmaRows - 1) / kDmaRows;
-      hipLaunchKernelGGL((gemm_t_dma_kernel<KB>), dim3(nt * splits), dim3(512), 0, st, (const float*)A, lda, m, n,
-                         (const float*)Z, (float*)P, per, nt, splits);
-      CNMF_LAUNCH_CHECK();
+      if (vec && n % 4 == 0) {
+        hipLaunchKernelGGL((gemm_t_dma_kernel<KB, true>), dim3(nt * splits), dim3(512), 0, st, (const float*)A, lda,
+                           m, n, (const float*)Z, (float*)P, per, nt, splits);
+        CNMF_LAUNCH_CHECK();
+      }
+      if (dw4_worth(m, n)) {
+        hipLaunchKernelGGL((gemm_t_dma_kernel<KB, false>), dim3(nt * splits), dim3(512), 0, st, (const float*)A, lda,
+                           m, n, (const float*)Z, (float*)P, per, nt, splits);
+        CNMF_LAUNCH_CHECK();
+      }
     }
   }
   const int ntiles = (n + 64 * VW - 1) / (64 * VW);

@@ -29,4 +29,16 @@ __device__ __forceinline__ void dma16(const void* gptr, uint32_t lds_base) {
       : "memory", "m0");
 }
 
+// 4 bytes per lane (no alignment beyond the element's): lane l's bytes land
+// at lds_base + 4 l.
+__device__ __forceinline__ void dma4(const void* gptr, uint32_t lds_base) {
+  asm volatile(
+      "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dword %0, off"
+      :
+      : "v"(gptr), "s"(lds_base)
+      : "memory", "m0");
+}
+
 }  // namespace cnmf
