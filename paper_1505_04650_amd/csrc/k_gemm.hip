@@ -727,9 +727,10 @@ static constexpr int rb_for(int kb, int elem_bytes) { return (elem_bytes == 4 &&
 // valid for the other one, used when A's rows are not 16-byte aligned):
 // minimise rounds * (bytes per workgroup, partials included).
 // The 4-byte DMA variants (rows that are not 16-byte aligned) move four
-// times as many DMA instructions; on small matrices (where several requests'
-// passes share the GPU in serving) the register-staged kernels, which leave
-// room for other workgroups on a CU, measured faster, so they serve those.
+// times as many DMA instructions and hold a whole CU per workgroup; small
+// unaligned matrices (most of the serving mix, where several requests'
+// passes share the GPU) keep the register-staged kernels, which leave room
+// for other workgroups on a CU.
 static bool dw4_worth(int m, int n) { return (int64_t)m * n >= (int64_t)4 << 20; }
 
 static int choose_splits_dma(int m, int n, int kk) {
