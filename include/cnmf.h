@@ -90,7 +90,11 @@ const char* cnmf_status_string(cnmf_status s);
 /* Library version string, e.g. "cnmf-mi355x 0.1". */
 const char* cnmf_version(void);
 /* Wait for the work enqueued on the handle's stream.  Returns CNMF_EDEVICE
- * for an asynchronous HIP fault, CNMF_EBREAKDOWN if a call enqueued since
+ * for an asynchronous HIP fault, or if a compressed-ADMM solve of a
+ * cnmf_factorize enqueued since the previous cnmf_synchronize gave up (after
+ * about two seconds) waiting for the partial sums formed by other
+ * workgroups of its own launch (its factors are then not valid; the count
+ * is cleared), CNMF_EBREAKDOWN if a call enqueued since
  * the previous cnmf_synchronize hit an orthonormalisation breakdown that the
  * fallback could not resolve (see cnmf_sketch_desc) or an alternating-NNLS
  * problem that did not finish (see cnmf_factorize_desc; the count is then

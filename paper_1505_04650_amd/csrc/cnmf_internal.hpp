@@ -179,14 +179,29 @@ size_t admm_solve_lds_bytes(int k, int r);
 struct AdmmHalf {
   AdmmSide s0, s1;
   const double* At;
-  const double* Pred;
+  double* Pred;
   double* XY;
   double* Pp;
   int* flags;
   double lam, phi, xi;
   int k, r, parts0, parts1, rpb0, rpb1;
   int solve, pass, first, uv, side, mode;
+  // nred > 0: the launch also forms the solve's reduced partials (P_V for
+  // pass 1, P_U for pass 0) in nred workgroups placed
+  // between the solve's block and the row-update blocks; each adds one to
+  // *ready after its release, and the solve waits until *ready reaches
+  // ready_target (a count that only grows, cleared before the iterations).
+  // A wait that times out adds one to *wait_fail.
+  unsigned* ready;
+  unsigned ready_target;
+  int nred;
+  int rgroups;   // 16-element groups per reduction workgroup: 1, 2, 4 or 8 (nred = ceil(ceil(k r / 16) / rgroups))
+  int* wait_fail;
 };
+// Groups per reduction workgroup for fused launches beside nuv row-update
+// workgroups: the smallest of 1, 2, 4, 8 that keeps the launch within one
+// workgroup per CU (8 if none does).
+int admm_fused_reduce_groups(int k, int r, int nuv);
 template <typename T>
 hipError_t launch_admm_half(const AdmmHalf& a, hipStream_t st);
 // Fixed-order FP64 sums of the partials of one side (0: P_U into Pred, 1:

@@ -11,10 +11,11 @@
 // P_V, so the big matrices are read once per iteration; admm_reduce_body
 // sums those partials in a fixed order, and the r x r solves are Cholesky
 // factorisations in FP64 in one workgroup.  For one request the iteration
-// runs as two launches plus two reductions (admm_half_kernel): the Yt^T
-// solve beside the U-side row update, then the next Xt solve beside the
-// V-side row update; serving runs both solves and both sides per launch
-// over a batch of requests.
+// runs as two launches (admm_half_kernel): the Yt^T solve beside the U-side
+// row update, then the next Xt solve beside the V-side row update, each
+// launch also summing its solve's partials in workgroups of its own that
+// the solve waits for; serving runs both solves and both sides per launch
+// over a batch of requests, with the sums in a launch before the solves.
 #include "cnmf_internal.hpp"
 #include "small_dense.hpp"
 
@@ -408,12 +409,36 @@ __device__ __forceinline__ void s_chunks(const double* S, int ld, int kp, int c,
   }
 }
 
+// Waits (every lane of the calling wave) until *ready has reached target
+// (modulo 2^32), then acquires at agent scope, so that what the signalling
+// workgroups stored before their release is visible to the wave's loads.
+// The wait is bounded (about two seconds of the constant 100 MHz clock):
+// past that, *wait_fail is incremented and the wave goes on.
+__device__ __forceinline__ void wait_ready(const unsigned* ready, unsigned target, int* wait_fail) {
+  const uint64_t t0 = wall_clock64();
+  bool late = false;
+  while ((int)(__hip_atomic_load(ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+    if (wall_clock64() - t0 > 200000000ull) {
+      late = true;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  if (late && (threadIdx.x & 63) == 0) atomicAdd(wait_fail, 1);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 // One side of the iteration: PASS 0 solves for Xt (S = Yt^T, At), PASS 1
-// for Yt^T (S = Xt, At^T).  Starts after a barrier, ends with one.
+// for Yt^T (S = Xt, At^T).  Starts after a barrier, ends with one.  With
+// ready != nullptr the reduced partials P are produced by other workgroups
+// of the same launch: the waves that read P (the right-hand sides) first
+// wait for *ready to reach target.
 template <int NB, int PASS>
 __device__ __forceinline__ void chol_side(const double* __restrict__ At, const double* __restrict__ P, int k, int r,
                                           double pen, double* __restrict__ out, float* __restrict__ outf,
-                                          int* flags, const CholLayout& Ly, double* sm) {
+                                          int* flags, const CholLayout& Ly, double* sm,
+                                          const unsigned* ready = nullptr, unsigned target = 0,
+                                          int* wait_fail = nullptr) {
   constexpr int KS = kCholMaxK / 4;
   constexpr int N = 16 * NB;
   const int ld = Ly.ld, kp = Ly.kp, KB16 = Ly.KB16;
@@ -452,6 +477,7 @@ __device__ __forceinline__ void chol_side(const double* __restrict__ At, const d
   } else {
     // (b) strips of RHS into E (kp x ld, row xr = 16 rb + c): the lane's At
     // and P values are loaded up front, then RHS^T tiles = S^T At^T (+ P^T)
+    if (ready) wait_ready(ready, target, wait_fail);
     for (int rb = w - 1; rb < KB16; rb += 3) {
       const int xr = 16 * rb + c;
       double at[KS];
@@ -673,10 +699,12 @@ __device__ __forceinline__ void admm_solve_side_nb(const AdmmHalf& a, double* sm
   }
   __syncthreads();
   float* XYf = reinterpret_cast<float*>(a.XY + 2 * kr);
+  const unsigned* ready = a.nred > 0 ? a.ready : nullptr;
   if constexpr (PASS == 0)
-    chol_side<NB, 0>(a.At, a.Pred, k, r, a.lam, a.XY, XYf, a.flags, Ly, sm);
+    chol_side<NB, 0>(a.At, a.Pred, k, r, a.lam, a.XY, XYf, a.flags, Ly, sm, ready, a.ready_target, a.wait_fail);
   else
-    chol_side<NB, 1>(a.At, a.Pred + kr, k, r, a.phi, a.XY + kr, XYf + Ly.kp * N, a.flags, Ly, sm);
+    chol_side<NB, 1>(a.At, a.Pred + kr, k, r, a.phi, a.XY + kr, XYf + Ly.kp * N, a.flags, Ly, sm, ready,
+                     a.ready_target, a.wait_fail);
 }
 
 template <int PASS>
@@ -689,6 +717,20 @@ __device__ __forceinline__ void admm_solve_side(const AdmmHalf& a, double* sm) {
   }
 }
 
+static_assert(kSolveNT == kRedNT, "the half kernel's reduction blocks run the reduction with its block size");
+
+// Reduction workgroup b of a fused launch: the element groups
+// [b G, b G + G) of the solve's side (P_V for pass 1, P_U for pass 0), each
+// element summed exactly as by admm_reduce_body.
+template <int G, typename T>
+__device__ __forceinline__ void fused_reduce(const AdmmHalf& a, int b, double* sm) {
+  const int64_t kr = (int64_t)a.k * a.r;
+  const bool vside = a.pass == 1;
+  const T* P = reinterpret_cast<const T*>(a.Pp) + (vside ? (int64_t)a.parts0 * kr : 0);
+  block_sum_parts_groups<kRedNT, kRedEPB, G, T>(P, vside ? a.parts1 : a.parts0, kr, kr,
+                                                (int64_t)b * G * kRedEPB, a.Pred + (vside ? kr : 0), sm);
+}
+
 template <typename T, int CH>
 __global__ __launch_bounds__(kSolveNT) void admm_half_kernel(AdmmHalf a) {
   extern __shared__ double sm[];
@@ -699,7 +741,21 @@ __global__ __launch_bounds__(kSolveNT) void admm_half_kernel(AdmmHalf a) {
       admm_solve_side<1>(a, sm);
     return;
   }
-  const int b = (int)blockIdx.x - (a.solve ? 1 : 0);
+  int b = (int)blockIdx.x - (a.solve ? 1 : 0);
+  if (b < a.nred) {
+    // the fixed-order sums of the solve's partials (P_V for the Yt^T
+    // solve, P_U for Xt), rgroups groups of 16 elements, then a release and
+    // one count on *ready
+    switch (a.rgroups) {
+      case 1: fused_reduce<1, T>(a, b, sm); break;
+      case 2: fused_reduce<2, T>(a, b, sm); break;
+      case 4: fused_reduce<4, T>(a, b, sm); break;
+      default: fused_reduce<8, T>(a, b, sm); break;
+    }
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(a.ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  b -= a.nred;
   admm_uv_body<T, CH>(a.s0, a.s1, a.parts0, a.side ? a.parts0 + b : b, a.XY, a.k, a.r, a.xi, a.mode, a.Pp,
                       a.rpb0, a.rpb1, reinterpret_cast<char*>(sm));
 }
@@ -708,18 +764,26 @@ template <typename T>
 hipError_t launch_admm_half(const AdmmHalf& a, hipStream_t st) {
   const int k = a.k, r = a.r;
   if (r > 64 || k > kCholMaxK || a.parts0 < 1 || a.parts1 < 1 || (!a.solve && !a.uv)) return hipErrorInvalidValue;
+  // fused reductions: exactly the solve side's blocks, a counter and a
+  // failure word, and only beside a solve (which is what waits for them)
+  const int nbh_ = (int)(((int64_t)k * r + kRedEPB - 1) / kRedEPB);
+  const bool pow2 = a.rgroups == 1 || a.rgroups == 2 || a.rgroups == 4 || a.rgroups == 8;
+  if (a.nred != 0 && (!pow2 || a.nred != (nbh_ + a.rgroups - 1) / a.rgroups || !a.solve || a.first || !a.ready ||
+                      !a.wait_fail))
+    return hipErrorInvalidValue;
+  const size_t red_lds = a.nred ? (size_t)a.rgroups * kRedNT * sizeof(double) : 0;
   const size_t solve_lds = a.solve ? chol_layout(k, r).total * sizeof(double) : 0;
   if (solve_lds > 160 * 1024) return hipErrorInvalidValue;
   const int nuv = a.side ? a.parts1 : a.parts0;
   const int KP = (k + 15) / 16 * 16, RP = (r + 15) / 16 * 16;
   auto lds = [&](int ch) { return ((size_t)KP * (RP + 1) + (size_t)ch * (KP + 1) + (size_t)ch * (RP + 1)) * sizeof(T); };
-  const dim3 grid((a.uv ? nuv : 0) + (a.solve ? 1 : 0));
+  const dim3 grid((a.uv ? nuv : 0) + (a.solve ? 1 : 0) + a.nred);
   if (lds(64) <= 160 * 1024) {
-    const size_t sm = std::max(solve_lds, lds(64));
+    const size_t sm = std::max({solve_lds, lds(64), red_lds});
     hipFuncSetAttribute((const void*)admm_half_kernel<T, 64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     hipLaunchKernelGGL((admm_half_kernel<T, 64>), grid, dim3(kSolveNT), sm, st, a);
   } else {
-    const size_t sm = std::max(solve_lds, lds(32));
+    const size_t sm = std::max({solve_lds, lds(32), red_lds});
     hipFuncSetAttribute((const void*)admm_half_kernel<T, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     hipLaunchKernelGGL((admm_half_kernel<T, 32>), grid, dim3(kSolveNT), sm, st, a);
   }
@@ -727,6 +791,22 @@ hipError_t launch_admm_half(const AdmmHalf& a, hipStream_t st) {
 }
 template hipError_t launch_admm_half<float>(const AdmmHalf&, hipStream_t);
 template hipError_t launch_admm_half<double>(const AdmmHalf&, hipStream_t);
+
+int admm_fused_reduce_groups(int k, int r, int nuv) {
+  static int cus = 0;   // compute units of the device (queried once; 256 if the query fails)
+  if (cus == 0) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    cus = hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess &&
+                  p.multiProcessorCount > 0
+              ? p.multiProcessorCount
+              : 256;
+  }
+  const int nbh = (int)(((int64_t)k * r + kRedEPB - 1) / kRedEPB);
+  int g = 1;
+  while (g < 8 && 1 + (nbh + g - 1) / g + nuv > cus) g *= 2;
+  return g;
+}
 
 // The fixed-order sums of one side's partials (side 0: P_U, 1: P_V, 2: both).
 template <typename T>

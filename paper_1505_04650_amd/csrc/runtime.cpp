@@ -1258,21 +1258,37 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
     }
     H.first = 0;
     H.uv = 1;
+    // From here on each solve's reduced partials are formed inside its own
+    // launch (by workgroups beside the solve, which waits for their count
+    // on aw.counter[0]; cleared by the prologue); P_V of the first Yt^T
+    // solve is the one reduced above.
+    const int nbh = (int)(((int64_t)k * r + 15) / 16);
+    H.rgroups = admm_fused_reduce_groups(k, r, std::max(aw.parts0, aw.parts1));
+    const int nred = (nbh + H.rgroups - 1) / H.rgroups;
+    unsigned signals = 0;
+    H.ready = aw.counter;
+    H.wait_fail = h->unresolved_dev + 1;
     for (int it = 0; it < d->iters; ++it) {
       const bool last = it + 1 == d->iters;
       H.mode = last ? 2 : 1;
-      // Yt^T of this iteration beside the U-side row update (which needs Xt only)
+      // Yt^T of this iteration (with P_V of the previous V-side row update)
+      // beside the U-side row update (which needs Xt only)
       H.solve = 1;
       H.pass = 1;
       H.side = 0;
+      H.nred = it > 0 ? nred : 0;
+      signals += (unsigned)H.nred;
+      H.ready_target = signals;
       HIPCHK(h, launch_admm_half<T>(H, st));
-      if (!last) HIPCHK(h, launch_admm_reduce<T>(aw.Pp, aw.parts0, aw.parts1, k, r, 0, aw.Pred, st));
-      // the next iteration's Xt beside the V-side row update
+      // the next iteration's Xt (with P_U of the U-side row update just
+      // issued) beside the V-side row update
       H.solve = last ? 0 : 1;
       H.pass = 0;
       H.side = 1;
+      H.nred = last ? 0 : nred;
+      signals += (unsigned)H.nred;
+      H.ready_target = signals;
       HIPCHK(h, launch_admm_half<T>(H, st));
-      if (!last) HIPCHK(h, launch_admm_reduce<T>(aw.Pp, aw.parts0, aw.parts1, k, r, 1, aw.Pred, st));
     }
   } else if (d->method == CNMF_MU) {
     Span sp(h, ST_ITER, (double)d->iters * (4.0 * (double)(m + n) * k * r + 4.0 * (double)(m + n) * r * r));
@@ -1640,8 +1656,17 @@ cnmf_status cnmf_synchronize(cnmf_handle* h) {
   if (!h) return fail(nullptr, CNMF_EINVAL, "handle is NULL");
   HIPCHK(h, hipSetDevice(h->device));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  int unres = 0;
-  HIPCHK(h, hipMemcpy(&unres, h->unresolved_dev, sizeof(int), hipMemcpyDeviceToHost));
+  int words[2] = {0, 0};
+  HIPCHK(h, hipMemcpy(words, h->unresolved_dev, sizeof(words), hipMemcpyDeviceToHost));
+  const int unres = words[0];
+  if (words[1]) {
+    HIPCHK(h, launch_fill(h->unresolved_dev + 1, sizeof(int), h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return fail(h, CNMF_EDEVICE,
+                "%d ADMM solve(s) gave up waiting for the partial sums of their own launch (the device did not "
+                "run the launch's other workgroups within two seconds); the factors are not valid",
+                words[1]);
+  }
   if (unres) {
     HIPCHK(h, launch_fill(h->unresolved_dev, sizeof(int), h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));

@@ -43,6 +43,59 @@ __device__ __forceinline__ void block_sum_parts(const TI* __restrict__ in, int n
   __syncthreads();
 }
 
+// G consecutive element ranges of block_sum_parts at once: range q covers
+// the elements [e0 + q EPB, e0 + (q + 1) EPB).  Each element is summed in
+// exactly block_sum_parts's order (same chains, same tree), so the results
+// are bit for bit those of G separate calls; the loads of the G ranges are
+// issued together, so the block waits for the memory latency once per step
+// rather than G times.  red: G NT doubles of LDS.
+template <int NT, int EPB, int G, typename TI = double>
+__device__ __forceinline__ void block_sum_parts_groups(const TI* __restrict__ in, int nparts, int64_t stride,
+                                                       int64_t count, int64_t e0, double* __restrict__ out,
+                                                       double* red) {
+  constexpr int PG = NT / EPB;
+  const int tid = threadIdx.x;
+  const int el = tid % EPB, pg = tid / EPB;
+  double s[G][4];
+  bool ok[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    ok[q] = e0 + q * EPB + el < count;
+    s[q][0] = s[q][1] = s[q][2] = s[q][3] = 0.0;
+  }
+  int p = pg;
+  for (; p + 3 * PG < nparts; p += 4 * PG) {
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+      if (ok[q]) {
+        const int64_t e = e0 + q * EPB + el;
+        s[q][0] += (double)in[(int64_t)p * stride + e];
+        s[q][1] += (double)in[(int64_t)(p + PG) * stride + e];
+        s[q][2] += (double)in[(int64_t)(p + 2 * PG) * stride + e];
+        s[q][3] += (double)in[(int64_t)(p + 3 * PG) * stride + e];
+      }
+  }
+  for (; p < nparts; p += PG)
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+      if (ok[q]) s[q][0] += (double)in[(int64_t)p * stride + e0 + q * EPB + el];
+#pragma unroll
+  for (int q = 0; q < G; ++q) red[q * NT + tid] = (s[q][0] + s[q][1]) + (s[q][2] + s[q][3]);
+  __syncthreads();
+#pragma unroll
+  for (int w = PG / 2; w > 0; w >>= 1) {
+    if (pg < w)
+#pragma unroll
+      for (int q = 0; q < G; ++q) red[q * NT + tid] += red[q * NT + tid + w * EPB];
+    __syncthreads();
+  }
+  if (pg == 0)
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+      if (ok[q]) out[e0 + q * EPB + el] = red[q * NT + el];
+  __syncthreads();
+}
+
 __device__ __forceinline__ double readlane_d(double x, int lane) {
   int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
   int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
