@@ -681,18 +681,19 @@ __device__ __forceinline__ void admm_solve_side_nb(const AdmmHalf& a, double* sm
   const double* XY = a.XY;
   // S = Yt^T for pass 0 (P_V / phi on the first iteration, Alg. 3's
   // initialisation), Xt for pass 1; zero padded to kp x N
-  // (eight loads in flight per thread before their stores, as above)
-  for (int e0 = threadIdx.x; e0 < Ly.kp * N; e0 += NT * 8) {
-    double v[8];
+  // (sixteen loads in flight per thread before their stores: one memory
+  // round trip for k, r <= 64, where S is 64 x 64 after padding)
+  for (int e0 = threadIdx.x; e0 < Ly.kp * N; e0 += NT * 16) {
+    double v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int e = e0 + NT * u, i = e / N, j = e - i * N;
       v[u] = 0.0;
       if (e < Ly.kp * N && i < k && j < r)
         v[u] = PASS == 1 ? XY[i * r + j] : (a.first ? a.Pred[kr + i * r + j] / a.phi : XY[kr + i * r + j]);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int e = e0 + NT * u, i = e / N, j = e - i * N;
       if (e < Ly.kp * N) S[i * Ly.ld + j] = v[u];
     }
