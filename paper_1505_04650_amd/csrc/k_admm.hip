@@ -794,15 +794,16 @@ template hipError_t launch_admm_half<float>(const AdmmHalf&, hipStream_t);
 template hipError_t launch_admm_half<double>(const AdmmHalf&, hipStream_t);
 
 int admm_fused_reduce_groups(int k, int r, int nuv) {
-  static int cus = 0;   // compute units of the device (queried once; 256 if the query fails)
-  if (cus == 0) {
+  // compute units of the device current at the first call (queried once,
+  // thread-safe; 256 if the query fails); only the group count depends on it
+  static const int cus = [] {
     int dev = 0;
     hipDeviceProp_t p;
-    cus = hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess &&
-                  p.multiProcessorCount > 0
-              ? p.multiProcessorCount
-              : 256;
-  }
+    return hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess &&
+                   p.multiProcessorCount > 0
+               ? p.multiProcessorCount
+               : 256;
+  }();
   const int nbh = (int)(((int64_t)k * r + kRedEPB - 1) / kRedEPB);
   int g = 1;
   while (g < 8 && 1 + (nbh + g - 1) / g + nuv > cus) g *= 2;

@@ -1663,8 +1663,9 @@ cnmf_status cnmf_synchronize(cnmf_handle* h) {
     HIPCHK(h, launch_fill(h->unresolved_dev + 1, sizeof(int), h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return fail(h, CNMF_EDEVICE,
-                "%d ADMM solve(s) gave up waiting for the partial sums of their own launch (the device did not "
-                "run the launch's other workgroups within two seconds); the factors are not valid",
+                "ADMM solves gave up waiting for the partial sums of their own launch %d time(s) (counted per "
+                "waiting wave: the device did not run the launch's other workgroups within two seconds); the "
+                "factors are not valid",
                 words[1]);
   }
   if (unres) {
