@@ -195,12 +195,13 @@ struct AdmmHalf {
   unsigned* ready;
   unsigned ready_target;
   int nred;
-  int rgroups;   // 16-element groups per reduction workgroup: 1, 2, 4 or 8 (nred = ceil(ceil(k r / 16) / rgroups))
+  int rgroups;   // 16-element groups per reduction workgroup: 1, 2 or 4 (nred = ceil(ceil(k r / 16) / rgroups))
   int* wait_fail;
 };
 // Groups per reduction workgroup for fused launches beside nuv row-update
-// workgroups: the smallest of 1, 2, 4, 8 that keeps the launch within one
-// workgroup per CU (8 if none does).
+// workgroups: the smallest of 1, 2, 4 that keeps the launch within one
+// workgroup per CU, or 0 (sum in separate launches) if none does or the
+// sum workgroups would be too slow to finish before the solve needs them.
 int admm_fused_reduce_groups(int k, int r, int nuv);
 template <typename T>
 hipError_t launch_admm_half(const AdmmHalf& a, hipStream_t st);

@@ -750,8 +750,7 @@ __global__ __launch_bounds__(kSolveNT) void admm_half_kernel(AdmmHalf a) {
     switch (a.rgroups) {
       case 1: fused_reduce<1, T>(a, b, sm); break;
       case 2: fused_reduce<2, T>(a, b, sm); break;
-      case 4: fused_reduce<4, T>(a, b, sm); break;
-      default: fused_reduce<8, T>(a, b, sm); break;
+      default: fused_reduce<4, T>(a, b, sm); break;
     }
     if (threadIdx.x == 0) __hip_atomic_fetch_add(a.ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     return;
@@ -768,7 +767,7 @@ hipError_t launch_admm_half(const AdmmHalf& a, hipStream_t st) {
   // fused reductions: exactly the solve side's blocks, a counter and a
   // failure word, and only beside a solve (which is what waits for them)
   const int nbh_ = (int)(((int64_t)k * r + kRedEPB - 1) / kRedEPB);
-  const bool pow2 = a.rgroups == 1 || a.rgroups == 2 || a.rgroups == 4 || a.rgroups == 8;
+  const bool pow2 = a.rgroups == 1 || a.rgroups == 2 || a.rgroups == 4;
   if (a.nred != 0 && (!pow2 || a.nred != (nbh_ + a.rgroups - 1) / a.rgroups || !a.solve || a.first || !a.ready ||
                       !a.wait_fail))
     return hipErrorInvalidValue;
@@ -806,7 +805,13 @@ int admm_fused_reduce_groups(int k, int r, int nuv) {
   }();
   const int nbh = (int)(((int64_t)k * r + kRedEPB - 1) / kRedEPB);
   int g = 1;
-  while (g < 8 && 1 + (nbh + g - 1) / g + nuv > cus) g *= 2;
+  while (g < 4 && 1 + (nbh + g - 1) / g + nuv > cus) g *= 2;
+  if (1 + (nbh + g - 1) / g + nuv > cus) return 0;
+  // a sum workgroup that loads more than about 640 partial rows (groups x
+  // parts) finishes after the solve needs its sums: separate launches then
+  // cost less (20000 x 5000: 2 x 157 and 4 x 157 faster fused, 8 x 157
+  // slower; 40000 x 30000 with 235 parts: 8 groups slower)
+  if (g * nuv > 640) return 0;
   return g;
 }
 

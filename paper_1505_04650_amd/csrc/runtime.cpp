@@ -1259,12 +1259,14 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
     H.first = 0;
     H.uv = 1;
     // From here on each solve's reduced partials are formed inside its own
-    // launch (by workgroups beside the solve, which waits for their count
-    // on aw.counter[0]; cleared by the prologue); P_V of the first Yt^T
-    // solve is the one reduced above.
+    // launch where that pays (by workgroups beside the solve, which waits
+    // for their count on aw.counter[0]; cleared by the prologue), else by
+    // separate launches after each half; both sum in the same order.  P_V
+    // of the first Yt^T solve is the one reduced above.
     const int nbh = (int)(((int64_t)k * r + 15) / 16);
     H.rgroups = admm_fused_reduce_groups(k, r, std::max(aw.parts0, aw.parts1));
-    const int nred = (nbh + H.rgroups - 1) / H.rgroups;
+    const bool fuse = H.rgroups > 0;
+    const int nred = fuse ? (nbh + H.rgroups - 1) / H.rgroups : 0;
     unsigned signals = 0;
     H.ready = aw.counter;
     H.wait_fail = h->unresolved_dev + 1;
@@ -1280,6 +1282,7 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
       signals += (unsigned)H.nred;
       H.ready_target = signals;
       HIPCHK(h, launch_admm_half<T>(H, st));
+      if (!fuse && !last) HIPCHK(h, launch_admm_reduce<T>(aw.Pp, aw.parts0, aw.parts1, k, r, 0, aw.Pred, st));
       // the next iteration's Xt (with P_U of the U-side row update just
       // issued) beside the V-side row update
       H.solve = last ? 0 : 1;
@@ -1289,6 +1292,7 @@ cnmf_status fact_iterations(cnmf_handle* h, const cnmf_input* A, const cnmf_fact
       signals += (unsigned)H.nred;
       H.ready_target = signals;
       HIPCHK(h, launch_admm_half<T>(H, st));
+      if (!fuse && !last) HIPCHK(h, launch_admm_reduce<T>(aw.Pp, aw.parts0, aw.parts1, k, r, 1, aw.Pred, st));
     }
   } else if (d->method == CNMF_MU) {
     Span sp(h, ST_ITER, (double)d->iters * (4.0 * (double)(m + n) * k * r + 4.0 * (double)(m + n) * r * r));

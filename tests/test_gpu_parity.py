@@ -161,14 +161,15 @@ def test_factorize_admm_fp64_parity(c1):
 # 240 64-row sweeps on one side, so its row-update blocks take two sweeps
 # each (129 blocks of 128 rows, the last one ragged).  Each launch of the
 # iteration also sums its solve's partials in workgroups of its own, with 1,
-# 2, 4 or 8 groups of 16 elements each, the fewest that keep the launch
-# within one workgroup per CU on a 256-CU device: one group for the small
-# shapes, two for r 64 / k 74 and up, and with 240 row-update blocks
-# (15360 rows) four for r 20 / k 40 and eight for r 32 / k 60.
+# 2 or 4 groups of 16 elements each, the fewest that keep the launch within
+# one workgroup per CU on a 256-CU device: one group for the small shapes,
+# two for r 64 / k 74 and up, four at 20000 rows with r 48 / k 80; with 240
+# row-update blocks (15360 rows) the sums are too slow beside the solve and
+# run as separate launches instead.
 @pytest.mark.parametrize("m,n,r,k", [(420, 300, 5, 9), (500, 400, 37, 47), (500, 400, 48, 80), (500, 400, 64, 74),
                                      (500, 400, 20, 100), (500, 400, 64, 112), (500, 400, 48, 128),
-                                     (16437, 150, 10, 20), (150, 16437, 12, 22), (150, 15360, 20, 40),
-                                     (15360, 150, 32, 60)])
+                                     (16437, 150, 10, 20), (150, 16437, 12, 22), (20000, 150, 48, 80),
+                                     (150, 15360, 20, 40), (15360, 150, 32, 60)])
 def test_factorize_admm_fp64_solve_shapes(m, n, r, k):
     A = WL.nmf_matrix(m, n, r, 0.05, seed=31 + r, dtype=np.float64)
     g = np.random.default_rng(41 + k)
