@@ -14,8 +14,10 @@
 // runs as two launches (admm_half_kernel): the Yt^T solve beside the U-side
 // row update, then the next Xt solve beside the V-side row update, each
 // launch also summing its solve's partials in workgroups of its own that
-// the solve waits for; serving runs both solves and both sides per launch
-// over a batch of requests, with the sums in a launch before the solves.
+// the solve waits for (where they fit beside it and finish in time; else
+// the sums are separate launches after each half); serving runs both solves
+// and both sides per launch over a batch of requests, with the sums in a
+// launch before the solves.
 #include "cnmf_internal.hpp"
 #include "small_dense.hpp"
 
